@@ -1,0 +1,57 @@
+"""Susceptibility, dielectric function and loss function from the Lanczos
+coefficients (Sec. 2.5, eqs. resolvent_Liouvillian_Lanczos_q, post_processing,
+resolvent_Liouvillian_Lanczos_2_for_chi; Sec. 2.1 eq.
+def_inv_microscopic_diel_tensor; Sec. 3.3 for the Lorentzian broadening).
+
+    (omega + i eta - T_M) x = e_1          T_M symmetric tridiagonal, zero
+                                           diagonal, off-diagonals beta_2..beta_M
+    chi(omega) = (4/Omega) beta_1 sum_j z_j x_j
+    eps^-1     = 1 + 4 pi chi / |Q|^2,   loss = -Im eps^-1,   eps = 1/eps^-1
+
+The prefactor reading: (z, x) with the normalised start vector must be
+multiplied by the start norm beta_1; 4/Omega collects the spin factor 2, the
+SBR factor 2 of the response density and the per-volume normalisation of the
+orbitals.  It is pinned by the independent-particle sum over states and by the
+first-moment (f-sum) closed form.
+
+Each frequency is solved by LU with partial pivoting on the band matrix
+(LAPACK gbsv through scipy.linalg.solve_banded).
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.linalg as sla
+
+
+def chi_from_coefficients(beta, z, omega, eta, volume, m=None):
+    beta = np.asarray(beta, dtype=np.float64)
+    z = np.asarray(z, dtype=np.complex128)
+    m = len(beta) if m is None else int(m)
+    if m == 0:
+        # no Lanczos vector: the right-hand side vanished, chi = 0
+        return np.zeros(len(omega), dtype=np.complex128)
+    off = beta[1:m]
+    out = np.empty(len(omega), dtype=np.complex128)
+    rhs = np.zeros(m, dtype=np.complex128)
+    rhs[0] = 1.0
+    ab = np.zeros((3, m), dtype=np.complex128)
+    ab[0, 1:] = -off
+    ab[2, :-1] = -off
+    for i, w in enumerate(np.asarray(omega, dtype=np.float64)):
+        ab[1, :] = w + 1j * eta
+        x = sla.solve_banded((1, 1), ab, rhs)
+        out[i] = np.sum(z[:m] * x)
+    return (4.0 / volume) * beta[0] * out
+
+
+def dielectric(chi, qcart):
+    """eps^-1, loss = -Im eps^-1 and eps = 1/eps^-1 (a scalar inverse)."""
+    q2 = float(np.dot(qcart, qcart))
+    eps_inv = 1.0 + 4.0 * np.pi * np.asarray(chi) / q2
+    return eps_inv, -eps_inv.imag, 1.0 / eps_inv
+
+
+def spectrum(beta, z, omega, eta, volume, qcart, m=None):
+    chi = chi_from_coefficients(beta, z, omega, eta, volume, m)
+    eps_inv, loss, eps = dielectric(chi, qcart)
+    return chi, eps_inv, loss, eps

@@ -1,0 +1,149 @@
+"""The synthetic workloads: named, seeded instances with their run parameters.
+
+  cfg1  simple-cubic a=10.0 bohr, 24^3 grid (ecut 6 Ha), two Gaussian wells
+        (depth 2 Ha, sigma 1.2 bohr), no projectors, 4 bands, Gamma only,
+        q = (0.1,0,0) 2pi/a, exchange-only ALDA, 200 Lanczos steps.
+  cfg2  simple-cubic a=10.26 bohr, 48^3 grid (ecut 25 Ha = 50 Ry), 8 wells on
+        the diamond sites of the conventional cell, s+p projectors per atom
+        (32 in total), 16 bands, 8 k on a 2x2x2 mesh with a seeded shift,
+        q = 0.2 (2pi/a) along [100], Perdew-Zunger ALDA, 1000 Lanczos steps.
+  cfg3  cfg2 run in mixed precision (3000 steps).
+  micro small cells for brute-force diagonalisation of the explicit Liouvillian.
+  free  free electrons (V=0): one closed shell of 7 bands, Gamma only,
+        q = (0.1,0,0) b, G0 = (1,0,0).
+
+Every instance is a deterministic function of its name; results are cached
+as .npz under $LZ_SYNTH_CACHE (default /tmp/lz_synth_cache).
+"""
+from __future__ import annotations
+
+import hashlib
+import json
+import os
+
+import numpy as np
+
+from .system import SystemArrays, build_system, mp_kpoints
+
+_VERSION = "v4"
+
+OMEGA_GRID = dict(w0=0.0, w1=2.0, n=2000, eta=0.01)
+
+CONFIGS = {
+    "cfg1": dict(steps=200, **OMEGA_GRID),
+    "cfg2": dict(steps=1000, **OMEGA_GRID),
+    "cfg3": dict(steps=3000, **OMEGA_GRID),
+}
+
+DIAMOND_SITES = np.array([
+    [0, 0, 0], [0, .5, .5], [.5, 0, .5], [.5, .5, 0],
+    [.25, .25, .25], [.25, .75, .75], [.75, .25, .75], [.75, .75, .25]])
+
+
+def _positions(seed, nat, at, dmin=3.0):
+    """Uniform fractional positions with every pair at least dmin apart
+    (minimum image)."""
+    rng = np.random.default_rng(seed)
+    while True:
+        f = rng.random((nat, 3))
+        ok = True
+        for i in range(nat):
+            for j in range(i + 1, nat):
+                d = f[i] - f[j]
+                d -= np.round(d)
+                if np.linalg.norm(d @ at) < dmin:
+                    ok = False
+        if ok:
+            return f
+
+
+def _spec(name: str, **kw) -> dict:
+    if name == "cfg1":
+        a = 10.0
+        at = np.eye(3) * a
+        # seed 16 is the first seed (counting from 1) whose gap
+        # eps_{5,k+q} - eps_{4,k} reaches 0.02 Ha for this well model
+        seed = kw.get("seed", 16)
+        return dict(at=at, nr=(24, 24, 24), ecut=6.0, tau_frac=_positions(seed, 2, at),
+                    depth=2.0, width=1.2, nbnd=4, kpts=[[0.0, 0.0, 0.0]],
+                    q=[0.1 * 2 * np.pi / a, 0.0, 0.0], xc="x", kb=None)
+    if name in ("cfg2", "cfg3"):
+        a = 10.26
+        at = np.eye(3) * a
+        rng = np.random.default_rng(2)
+        radii = rng.uniform(0.8, 1.2, (8, 2))
+        dkb = np.stack([rng.uniform(3.0, 8.0, 8), rng.uniform(0.1, 0.5, 8)], axis=1)
+        shift = rng.random(3)
+        qf = kw.get("qfrac", 0.2)
+        return dict(at=at, nr=(48, 48, 48), ecut=25.0, tau_frac=DIAMOND_SITES,
+                    depth=4.0, width=1.2, nbnd=16, kpts=mp_kpoints(at, (2, 2, 2), shift),
+                    q=[qf * 2 * np.pi / a, 0.0, 0.0], xc="pz",
+                    kb=dict(radii=radii, dkb=dkb))
+    if name == "cfg2lo":
+        # cfg2 geometry at a low cutoff: the same physics on a 32^3 grid,
+        # small enough for the oracle to run hundreds of steps in seconds
+        a = 10.26
+        at = np.eye(3) * a
+        rng = np.random.default_rng(2)
+        radii = rng.uniform(0.8, 1.2, (8, 2))
+        dkb = np.stack([rng.uniform(3.0, 8.0, 8), rng.uniform(0.1, 0.5, 8)], axis=1)
+        shift = rng.random(3)
+        nk = kw.get("nk", 2)
+        return dict(at=at, nr=(32, 32, 32), ecut=8.0, tau_frac=DIAMOND_SITES,
+                    depth=4.0, width=1.2, nbnd=16, kpts=mp_kpoints(at, (2, 2, 2), shift)[:nk],
+                    q=[0.2 * 2 * np.pi / a, 0.0, 0.0], xc="pz",
+                    kb=dict(radii=radii, dkb=dkb))
+    if name == "micro":
+        # a tiny gapped cell: two wells, s+p projectors, two bands, two k
+        a = 6.0
+        at = np.array([[a, 0, 0], [0.3, a * 1.05, 0], [0.2, -0.4, a * 0.95]])
+        seed = kw.get("seed", 5)
+        rng = np.random.default_rng(seed)
+        radii = rng.uniform(0.8, 1.2, (2, 2))
+        dkb = np.stack([rng.uniform(0.5, 1.5, 2), rng.uniform(0.1, 0.5, 2)], axis=1)
+        use_kb = kw.get("kb", True)
+        nk = kw.get("nk", 2)
+        ks = mp_kpoints(at, (2, 1, 1), rng.random(3))[:nk]
+        return dict(at=at, nr=(12, 12, 12), ecut=kw.get("ecut", 2.2),
+                    tau_frac=np.array([[0.1, 0.2, 0.15], [0.55, 0.6, 0.7]]),
+                    depth=3.0, width=1.0, nbnd=kw.get("nbnd", 2), kpts=ks,
+                    q=[0.17, 0.05, -0.03], g0=kw.get("g0", (0, 0, 0)), xc=kw.get("xc", "pz"),
+                    kb=dict(radii=radii, dkb=dkb) if use_kb else None,
+                    kq_basis=kw.get("kq_basis", "sphere"))
+    if name == "free":
+        a = 8.0
+        at = np.eye(3) * a
+        b = 2 * np.pi / a
+        return dict(at=at, nr=(16, 16, 16), ecut=kw.get("ecut", 4.5), tau_frac=np.zeros((0, 3)),
+                    depth=0.0, width=1.0, nbnd=7, kpts=[[0.0, 0.0, 0.0]],
+                    q=[0.1 * b, 0.0, 0.0], g0=kw.get("g0", (1, 0, 0)), xc=kw.get("xc", "x"), kb=None)
+    raise KeyError(name)
+
+
+def _cache_path(name, kw):
+    d = os.environ.get("LZ_SYNTH_CACHE", "/tmp/lz_synth_cache")
+    key = hashlib.sha1(json.dumps([_VERSION, name, sorted(kw.items())], default=str).encode()).hexdigest()[:16]
+    return d, os.path.join(d, f"{name}_{key}.npz")
+
+
+_FIELDS = ["nr", "at", "q", "g0", "xk", "wk", "npw_k", "npw_kq", "nl_k", "nl_kq", "evc_k",
+           "evc_kq", "et_k", "vloc_r", "fxc_r", "vkb_kq", "dkb", "et_kq", "n0_r"]
+
+
+def config_system(name: str, use_cache: bool = True, **kw) -> SystemArrays:
+    d, path = _cache_path(name, kw)
+    if use_cache and os.path.exists(path):
+        z = np.load(path, allow_pickle=False)
+        s = SystemArrays(**{f: z[f] for f in _FIELDS}, ecut=float(z["ecut"]))
+        s.info = json.loads(str(z["info"]))
+        return s
+    spec = _spec(name, **kw)
+    s = build_system(**spec)
+    s.info["name"] = name
+    if use_cache:
+        os.makedirs(d, exist_ok=True)
+        tmp = path + f".tmp{os.getpid()}.npz"
+        np.savez(tmp, **{f: getattr(s, f) for f in _FIELDS}, ecut=s.ecut,
+                 info=json.dumps(s.info, default=lambda o: o.tolist() if hasattr(o, "tolist") else str(o)))
+        os.replace(tmp, path)
+    return s

@@ -1,0 +1,81 @@
+"""Pins of the spectrum step (Sec. 2.5 post-processing, Sec. 2.1 dielectric
+function) and of the first-moment (f-sum) closed form (Sec. 2.1, Sec. 3.3)."""
+import numpy as np
+import pytest
+
+from oracle import closed_forms, lanczos, spectrum
+from oracle.liouvillian import Liouvillian
+from synth import config_system
+
+
+def _random_coefficients(m, seed):
+    rng = np.random.default_rng(seed)
+    beta = rng.uniform(0.2, 2.0, m)
+    z = np.zeros(m, dtype=np.complex128)
+    z[1::2] = rng.standard_normal(len(z[1::2]))
+    return beta, z
+
+
+def test_banded_solve_equals_dense_inverse():
+    beta, z = _random_coefficients(37, 1)
+    om = np.linspace(-1, 4, 57)
+    eta, vol = 0.03, 123.0
+    chi = spectrum.chi_from_coefficients(beta, z, om, eta, vol)
+    t = np.diag(beta[1:], 1) + np.diag(beta[1:], -1)
+    ref = np.array([(4 / vol) * beta[0] * (z @ np.linalg.inv((w + 1j * eta) * np.eye(37) - t))[0] for w in om])
+    # (z, (w-T)^-1 e1) = z^T x with x the first column; T symmetric
+    ref = np.array([(4 / vol) * beta[0] * (z @ np.linalg.inv((w + 1j * eta) * np.eye(37) - t)[:, 0]) for w in om])
+    assert np.abs(chi - ref).max() < 1e-12 * np.abs(ref).max()
+
+
+def test_spectral_representation():
+    """chi = (4/Omega) beta_1 sum_l (z.s_l) s_l[0] / (w~ - theta_l)."""
+    beta, z = _random_coefficients(24, 2)
+    t = np.diag(beta[1:], 1) + np.diag(beta[1:], -1)
+    th, s = np.linalg.eigh(t)
+    om = np.linspace(0, 3, 31)
+    ref = np.array([(4 / 10.0) * beta[0] * np.sum((z @ s) * s[0] / (w + 0.1j - th)) for w in om])
+    chi = spectrum.chi_from_coefficients(beta, z, om, 0.1, 10.0)
+    assert np.abs(chi - ref).max() < 1e-12 * np.abs(ref).max()
+
+
+def test_truncation_uses_leading_coefficients():
+    beta, z = _random_coefficients(40, 3)
+    om = np.linspace(0, 2, 11)
+    a = spectrum.chi_from_coefficients(beta, z, om, 0.05, 5.0, m=20)
+    b = spectrum.chi_from_coefficients(beta[:20], z[:20], om, 0.05, 5.0)
+    assert np.array_equal(a, b)
+
+
+def test_dielectric_identities():
+    chi = np.array([0.01 - 0.02j, -0.3 + 0.0j, 0.2 - 0.5j])
+    q = np.array([0.1, 0.05, 0.0])
+    ei, loss, eps = spectrum.dielectric(chi, q)
+    assert np.allclose(ei, 1 + 4 * np.pi * chi / (q @ q))
+    assert np.allclose(eps * ei, 1.0)
+    # -Im eps^-1 = Im eps / |eps|^2 (Sec. 2.1)
+    assert np.allclose(loss, eps.imag / np.abs(eps) ** 2)
+
+
+@pytest.mark.parametrize("g0", [(0, 0, 0), (1, 0, 0), (1, 1, 0)])
+def test_first_moment_closed_form(g0):
+    """<y, D y>_w for local potentials equals N_b Q^2/2 + velocity term -
+    valence-valence term, when the k+q basis holds the G0-shifted k sphere."""
+    s = config_system("micro", kb=False, kq_basis="union", g0=g0)
+    L = Liouvillian(s)
+    y = L.rhs()
+    m = L.inner(y, L.apply_D(y)).real
+    ref = closed_forms.first_moment(s)
+    assert abs(m - ref) < 1e-12 * abs(ref)
+
+
+@pytest.mark.parametrize("approx", ["ipa", "tddft"])
+def test_high_frequency_tail_is_first_moment(approx):
+    """chi(w) w^2 -> (4/Omega) <y, D y>_w for any K and any M >= 2."""
+    s = config_system("micro", kb=False, kq_basis="union", g0=(1, 0, 0))
+    L = Liouvillian(s, approx)
+    r = lanczos.run(L, 12)
+    w = np.array([1e4, 1e5])
+    chi = spectrum.chi_from_coefficients(r.beta, r.z, w, 0.0, L.cell.omega)
+    ref = 4.0 / L.cell.omega * closed_forms.first_moment(s)
+    assert np.allclose((chi * w ** 2).real, ref, rtol=1e-6)
