@@ -1,0 +1,198 @@
+/*
+ * lz.h -- C ABI of the Liouville-Lanczos hot path on AMD Instinct MI355X (gfx950).
+ *
+ * The library computes the charge-density susceptibility chi(Q,Q;omega) of a
+ * periodic insulator within linearised TDDFT (Timrov, Vast, Gebauer, Baroni,
+ * "turboEELS").  It applies the Liouvillian superoperator in the standard
+ * batch representation (Sec. 2.4, eqs. Liouvillian_SBR, D_super-operator_2,
+ * K_super-operator_2) to a batch of response orbitals over bands and
+ * k-points at fixed q, runs the pseudo-Hermitian Lanczos recursion (Sec. 2.5)
+ * and evaluates chi, eps^-1 and the loss function from the tridiagonal matrix
+ * (eqs. post_processing, resolvent_Liouvillian_Lanczos_2_for_chi,
+ * def_inv_microscopic_diel_tensor).
+ *
+ * Units: Hartree atomic units (energies in Ha, lengths in bohr).
+ * Complex numbers are stored interleaved (re, im).
+ * Every call returns an lz_status and never throws or aborts across the ABI;
+ * lz_last_error() gives a message for the last non-OK status of the calling
+ * thread.
+ */
+#ifndef LZ_H
+#define LZ_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lz_ctx lz_ctx; /* opaque; owns every device buffer of a run */
+
+typedef enum {
+  LZ_OK = 0,
+  LZ_ERR_ARG = 1,    /* a null pointer, an inconsistent size or index, an unsupported grid */
+  LZ_ERR_HIP = 2,    /* a HIP runtime failure; the context is unusable afterwards */
+  LZ_ERR_OOM = 3,    /* device allocation failed */
+  LZ_ERR_NOT_PD = 4, /* beta^2 <= 0: the metric diag(D+K, D) is not positive definite */
+  LZ_ERR_STATE = 5,  /* call order violated (e.g. a spectrum longer than the recursion) */
+  LZ_BREAKDOWN = 6   /* informational: Krylov space exhausted, coefficients so far exact */
+} lz_status;
+
+typedef enum {
+  LZ_FP64 = 0,            /* every array and every FFT in double precision */
+  LZ_FP32 = 1,            /* vectors, FFTs, pointwise work and projector products in
+                             single precision; Lanczos scalars and the spectrum in double */
+  LZ_FP32_SPLITBF16 = 2   /* as LZ_FP32, projector products as three bf16 MFMA products
+                             of (hi, lo) bf16 splits with fp32 accumulation */
+} lz_precision;
+
+typedef enum {   /* levels of theory of Sec. 3.2 */
+  LZ_TDDFT = 0,  /* Hartree + adiabatic xc kernel f_xc */
+  LZ_RPA = 1,    /* Hartree only ("RPA with crystal local-field effects") */
+  LZ_IPA = 2     /* K = 0 (independent particles) */
+} lz_approx;
+
+/*
+ * One (system, q) instance: the ground-state data of Sec. 3.1 plus q.
+ * Host arrays in double precision, owned by the caller and deep-copied by
+ * lz_init (the caller may free them when lz_init returns).
+ *
+ *  nr        FFT grid N1, N2, N3.  Each N must factor into 2, 3, 5
+ *            (2 <= N <= 128, N1*N2 <= 9216).  Grid point (j1,j2,j3) is at
+ *            r = sum_i (j_i/N_i) a_i, stored at (j1*N2 + j2)*N3 + j3.
+ *  at        lattice vectors, rows a1, a2, a3 (bohr).
+ *  q         q in Cartesian bohr^-1;  g0: Miller index of G0 (Q = q + G0).
+ *  nks       number of k-points; nbnd: occupied bands per k (the valence
+ *            manifold of P_c); nproj: separable projectors (0 = local only);
+ *            npwx: padded stride of every plane-wave array (>= max npw).
+ *  xk        [nks][3] k-points (Cartesian bohr^-1);  wk: [nks] weights, sum 1.
+ *  npw_k, npw_kq   [nks] plane-wave counts of the spheres at k and k+q.
+ *  nl_k, nl_kq     [nks][npwx] linear grid index of each plane wave
+ *            (Miller index m stored at the index of m mod N; Miller indices
+ *            must lie in [-N/2, N/2) so the centred representative recovers
+ *            them).  Entries beyond npw are ignored.
+ *  evc_k     [nks][nbnd][npwx] complex: u_nk on the k sphere (orthonormal).
+ *  evc_kq    [nks][nbnd][npwx] complex: u_n,k+q on the k+q sphere (orthonormal);
+ *            they define P_c^{k+q} = 1 - sum_n |u_n,k+q><u_n,k+q| (Sec. 2.3).
+ *  et_k      [nks][nbnd] eps_nk (Ha).
+ *  vloc_r    [N] total local Kohn-Sham potential on the grid (Ha).
+ *  fxc_r     [N] adiabatic xc kernel f_xc(r) (Ha bohr^3); ignored for RPA/IPA.
+ *  vkb_kq    [nks][nproj][npwx] complex projectors beta_p(k+q+G);
+ *  dkb       [nproj] their energies: V_NL = sum_p |beta_p> D_p <beta_p|.
+ *            (both may be NULL when nproj == 0)
+ *  Orbitals are normalised over the cell: u(r) = Omega^-1/2 sum_G u(G) e^{iG.r}.
+ */
+typedef struct {
+  int32_t nr[3];
+  double at[9];
+  double q[3];
+  int32_t g0[3];
+  int32_t nks, nbnd, nproj, npwx;
+  const double *xk, *wk;
+  const int32_t *npw_k, *npw_kq;
+  const int32_t *nl_k, *nl_kq;
+  const double *evc_k, *evc_kq;
+  const double *et_k;
+  const double *vloc_r, *fxc_r;
+  const double *vkb_kq, *dkb;
+} lz_system;
+
+typedef struct {
+  lz_precision prec;
+  lz_approx approx;
+  int32_t max_steps;  /* capacity of the coefficient arrays (>= 1) */
+  int32_t use_graph;  /* nonzero: replay each Lanczos step as a captured hipGraph */
+  int32_t autotune;   /* reserved, must be 0 or 1 (1 = time launch shapes at init) */
+} lz_options;
+
+/*
+ * Create a context on HIP device `device` for n_inst instances (sys[0..n_inst-1]).
+ * Work is ordered on `hip_stream` (a hipStream_t; NULL = the device's null
+ * stream).  Builds the stick tables, the valence orbitals in real space and the
+ * right-hand side y = P_c^{k+q} e^{iG0.r} u_nk (eq. RHS_of_Liouville_eq).
+ * Errors: LZ_ERR_ARG (see the field rules above; also q + G = 0 on the grid for
+ * TDDFT/RPA, weights not summing to 1, duplicate plane waves), LZ_ERR_OOM,
+ * LZ_ERR_HIP.  *out is NULL on error.
+ */
+lz_status lz_init(const lz_system *sys, int32_t n_inst, const lz_options *opt,
+                  int32_t device, void *hip_stream, lz_ctx **out);
+
+/*
+ * One application of the SBR Liouvillian (eqs. Liouvillian_SBR,
+ * D_super-operator_2, K_super-operator_2) to every instance:
+ *     q_out = D p_in,     p_out = (D + K) q_in,
+ * (D x)_nk = P_c^{k+q}(H_{k+q} - eps_nk) x_nk and
+ * (K x)_nk = P_c^{k+q} v'_HXC[n'[x]] u_nk with n' = 4 sum_k w_k sum_n u*_nk x_nk.
+ * Arguments are device pointers on the context's device holding complex
+ * arrays [inst][nks][nbnd][npwx] in the caller's plane-wave order (that of
+ * nl_kq), complex128 for LZ_FP64 and complex64 otherwise; padding beyond npw_kq
+ * is ignored on input and written as zero.  Either half may be skipped by
+ * passing NULL for both its input and output.  Inputs and outputs must not
+ * alias.  Stream-ordered; returns without synchronising.
+ */
+lz_status lz_apply_liouvillian(lz_ctx *ctx, const void *q_in, const void *p_in,
+                               void *q_out, void *p_out);
+
+/*
+ * Advance the pseudo-Hermitian Lanczos recursion of every instance by n_steps
+ * steps (one Liouvillian half-application each); the first call starts from
+ * the vector (0, y).  Step j gives beta_{j+1}, gamma_{j+1} = beta_{j+1} and
+ * z_{j+1}.  Coefficients stay on the device.  On return *steps_done is the
+ * total number of completed steps of instance 0.  Synchronises the stream once
+ * at the end to read the status flags.
+ * Returns LZ_BREAKDOWN when an instance exhausted its Krylov space (its
+ * coefficients so far are exact and its later steps are no-ops),
+ * LZ_ERR_NOT_PD when the metric is indefinite, LZ_ERR_STATE when the
+ * coefficient capacity (max_steps) would be exceeded.
+ */
+lz_status lz_step(lz_ctx *ctx, int32_t n_steps, int32_t *steps_done);
+
+/* Copy coefficients first..first+count-1 (0-based: index j holds beta_{j+1})
+ * of instance inst to host arrays beta[count], gamma[count], z[count][2].
+ * Any of the three may be NULL.  LZ_ERR_STATE if they are not computed yet. */
+lz_status lz_get_coefficients(lz_ctx *ctx, int32_t inst, int32_t first, int32_t count,
+                              double *beta, double *gamma, double *z);
+
+/* Number of completed steps and recursion status (0 running, LZ_BREAKDOWN,
+ * LZ_ERR_NOT_PD) of one instance.  Synchronises the stream. */
+lz_status lz_get_state(lz_ctx *ctx, int32_t inst, int32_t *steps_done, int32_t *status);
+
+/*
+ * Spectrum of instance inst from its first m coefficients (Sec. 2.5, Sec. 3.3),
+ * computed on the device in double precision:
+ *   (omega + i eta - T_m) x = e_1,   chi = (4/Omega) beta_1 sum_j z_j x_j,
+ *   eps^-1 = 1 + 4 pi chi / |Q|^2,   loss = -Im eps^-1.
+ * omega: host [n_omega] (Ha); eta > 0 (Ha).  Outputs are host arrays:
+ * chi[n_omega][2], eps_inv[n_omega][2], loss[n_omega]; any may be NULL.
+ * m = 0 with a vanished right-hand side gives chi = 0.
+ */
+lz_status lz_spectrum(lz_ctx *ctx, int32_t inst, int32_t m, const double *omega,
+                      int32_t n_omega, double eta, double *chi, double *eps_inv,
+                      double *loss);
+
+/* Copy the right-hand side y of instance inst to a device array in the
+ * caller's layout and precision (as lz_apply_liouvillian). */
+lz_status lz_get_rhs(lz_ctx *ctx, int32_t inst, void *y_out);
+
+/* Stage timing for measurement: with enable != 0, every later kernel stage of
+ * lz_step and lz_apply_liouvillian is bracketed by HIP events on the
+ * context's stream, and lz_stage_times returns, per stage, the summed
+ * event-measured duration (ms) and the number of timed launches since the
+ * last lz_stage_timer call.  Stages (8 entries): 0 z pass sphere->sticks,
+ * 1 plane pass of a D step, 2 plane pass with the response density,
+ * 3 Hartree+xc potential, 4 plane pass v'u, 5 z pass sticks->sphere,
+ * 6 projector products (P_c and separable projectors), 7 Lanczos vector
+ * update and reductions.  Arrays total_ms[8], count[8]; either may be NULL. */
+lz_status lz_stage_timer(lz_ctx *ctx, int32_t enable);
+lz_status lz_stage_times(lz_ctx *ctx, int32_t inst, double *total_ms, int32_t *count);
+
+/* Release every resource of the context (NULL is accepted). */
+lz_status lz_free(lz_ctx *ctx);
+
+/* Message of the last non-OK status returned on this thread ("" if none). */
+const char *lz_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LZ_H */

@@ -1,0 +1,282 @@
+"""Python binding of the lz C ABI (include/lz.h): argument marshalling only.
+
+Every computation runs in the HIP library liblz.so (built for gfx950 by
+``paper_2111_06623_amd.build``).  Importing this package never computes
+anything; ``load()`` raises if the library is missing rather than falling back
+to any other implementation.
+
+Device vectors are torch tensors on the GPU (complex128 for LZ_FP64,
+complex64 for the mixed modes), shaped [nks, nbnd, npwx] per instance and
+concatenated over instances; torch supplies memory and the current stream.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+LZ_OK, LZ_ERR_ARG, LZ_ERR_HIP, LZ_ERR_OOM, LZ_ERR_NOT_PD, LZ_ERR_STATE, LZ_BREAKDOWN = range(7)
+LZ_FP64, LZ_FP32, LZ_FP32_SPLITBF16 = 0, 1, 2
+LZ_TDDFT, LZ_RPA, LZ_IPA = 0, 1, 2
+APPROX = {"tddft": LZ_TDDFT, "rpa": LZ_RPA, "ipa": LZ_IPA}
+PREC = {"fp64": LZ_FP64, "fp32": LZ_FP32, "splitbf16": LZ_FP32_SPLITBF16}
+STATUS_NAMES = {0: "ok", 1: "arg", 2: "hip", 3: "oom", 4: "not_pd", 5: "state", 6: "breakdown"}
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "liblz.so")
+_lib = None
+
+_dp = ctypes.POINTER(ctypes.c_double)
+_ip = ctypes.POINTER(ctypes.c_int32)
+
+
+class LzSystem(ctypes.Structure):
+    _fields_ = [
+        ("nr", ctypes.c_int32 * 3), ("at", ctypes.c_double * 9), ("q", ctypes.c_double * 3),
+        ("g0", ctypes.c_int32 * 3),
+        ("nks", ctypes.c_int32), ("nbnd", ctypes.c_int32), ("nproj", ctypes.c_int32),
+        ("npwx", ctypes.c_int32),
+        ("xk", _dp), ("wk", _dp), ("npw_k", _ip), ("npw_kq", _ip), ("nl_k", _ip), ("nl_kq", _ip),
+        ("evc_k", _dp), ("evc_kq", _dp), ("et_k", _dp), ("vloc_r", _dp), ("fxc_r", _dp),
+        ("vkb_kq", _dp), ("dkb", _dp),
+    ]
+
+
+class LzOptions(ctypes.Structure):
+    _fields_ = [("prec", ctypes.c_int), ("approx", ctypes.c_int), ("max_steps", ctypes.c_int32),
+                ("use_graph", ctypes.c_int32), ("autotune", ctypes.c_int32)]
+
+
+class LzError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"lz status {status} ({STATUS_NAMES.get(status, '?')}): {msg}")
+        self.status = status
+
+
+STAGES = ["zfft_inv", "plane_local", "plane_density", "hxc", "plane_vu", "zfft_fwd",
+          "projectors", "lanczos"]
+
+
+def load(path: str = LIB_PATH):
+    """Load liblz.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None and path == LIB_PATH:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with python -m paper_2111_06623_amd.build")
+    lib = ctypes.CDLL(path)
+    vp = ctypes.c_void_p
+    lib.lz_init.argtypes = [ctypes.POINTER(LzSystem), ctypes.c_int32, ctypes.POINTER(LzOptions),
+                            ctypes.c_int32, vp, ctypes.POINTER(vp)]
+    lib.lz_apply_liouvillian.argtypes = [vp, vp, vp, vp, vp]
+    lib.lz_step.argtypes = [vp, ctypes.c_int32, _ip]
+    lib.lz_get_coefficients.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _dp, _dp, _dp]
+    lib.lz_get_state.argtypes = [vp, ctypes.c_int32, _ip, _ip]
+    lib.lz_spectrum.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, _dp, ctypes.c_int32,
+                                ctypes.c_double, _dp, _dp, _dp]
+    lib.lz_get_rhs.argtypes = [vp, ctypes.c_int32, vp]
+    lib.lz_stage_timer.argtypes = [vp, ctypes.c_int32]
+    lib.lz_stage_times.argtypes = [vp, ctypes.c_int32, _dp, _ip]
+    lib.lz_free.argtypes = [vp]
+    lib.lz_last_error.restype = ctypes.c_char_p
+    for f in ("lz_init", "lz_apply_liouvillian", "lz_step", "lz_get_coefficients", "lz_get_state",
+              "lz_spectrum", "lz_get_rhs", "lz_stage_timer", "lz_stage_times", "lz_free"):
+        getattr(lib, f).restype = ctypes.c_int
+    if path == LIB_PATH:
+        _lib = lib
+    return lib
+
+
+def lz_last_error() -> str:
+    return load().lz_last_error().decode()
+
+
+def _check(status, allow=()):
+    if status != LZ_OK and status not in allow:
+        raise LzError(status, lz_last_error())
+    return status
+
+
+def _f64(a):
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+def _i32(a):
+    return np.ascontiguousarray(np.asarray(a, dtype=np.int32))
+
+
+def _c128(a):
+    return np.ascontiguousarray(np.asarray(a, dtype=np.complex128)).view(np.float64)
+
+
+def _ptr(a, t):
+    return a.ctypes.data_as(t) if a is not None else None
+
+
+def make_system(s):
+    """Marshal a system (any object with the lz_system fields as arrays) into
+    an LzSystem; returns (struct, keepalive)."""
+    keep = dict(
+        xk=_f64(s.xk), wk=_f64(s.wk), npw_k=_i32(s.npw_k), npw_kq=_i32(s.npw_kq),
+        nl_k=_i32(s.nl_k), nl_kq=_i32(s.nl_kq), evc_k=_c128(s.evc_k), evc_kq=_c128(s.evc_kq),
+        et_k=_f64(s.et_k), vloc_r=_f64(s.vloc_r), fxc_r=_f64(s.fxc_r),
+        vkb_kq=_c128(s.vkb_kq) if len(s.dkb) else None, dkb=_f64(s.dkb) if len(s.dkb) else None)
+    st = LzSystem()
+    st.nr[:] = [int(v) for v in s.nr]
+    st.at[:] = [float(v) for v in np.asarray(s.at, dtype=np.float64).ravel()]
+    st.q[:] = [float(v) for v in s.q]
+    st.g0[:] = [int(v) for v in s.g0]
+    st.nks = int(np.asarray(s.xk).shape[0])
+    st.nbnd = int(np.asarray(s.et_k).shape[1])
+    st.nproj = int(len(s.dkb))
+    st.npwx = int(np.asarray(s.nl_kq).shape[1])
+    for name in ("xk", "wk", "evc_k", "evc_kq", "et_k", "vloc_r", "fxc_r", "vkb_kq", "dkb"):
+        setattr(st, name, _ptr(keep[name], _dp))
+    for name in ("npw_k", "npw_kq", "nl_k", "nl_kq"):
+        setattr(st, name, _ptr(keep[name], _ip))
+    return st, keep
+
+
+def _stream_handle(device):
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def lz_init(systems, prec="fp64", approx="tddft", max_steps=1000, use_graph=False, autotune=False,
+            device=0, stream=None):
+    """Create a context for one system or a list of systems; returns a handle."""
+    lib = load()
+    systems = systems if isinstance(systems, (list, tuple)) else [systems]
+    arr = (LzSystem * len(systems))()
+    keep = []
+    for i, s in enumerate(systems):
+        arr[i], k = make_system(s)
+        keep.append(k)
+    opt = LzOptions(PREC[prec] if isinstance(prec, str) else int(prec),
+                    APPROX[approx] if isinstance(approx, str) else int(approx),
+                    int(max_steps), int(bool(use_graph)), int(bool(autotune)))
+    out = ctypes.c_void_p()
+    hs = _stream_handle(device) if stream is None else ctypes.c_void_p(stream)
+    _check(lib.lz_init(arr, len(systems), ctypes.byref(opt), int(device), hs, ctypes.byref(out)))
+    return Context(out, systems, opt)
+
+
+class Context:
+    """Handle of an lz context; methods call the C ABI of the same name."""
+
+    def __init__(self, handle, systems, opt):
+        self.handle = handle
+        self.prec = opt.prec
+        self.nvec = [int(np.asarray(s.xk).shape[0]) * int(np.asarray(s.et_k).shape[1]) *
+                     int(np.asarray(s.nl_kq).shape[1]) for s in systems]
+        self.shapes = [(int(np.asarray(s.xk).shape[0]), int(np.asarray(s.et_k).shape[1]),
+                        int(np.asarray(s.nl_kq).shape[1])) for s in systems]
+
+    @property
+    def complex_dtype(self):
+        import torch
+        return torch.complex128 if self.prec == LZ_FP64 else torch.complex64
+
+    def _dev(self, t):
+        if t is None:
+            return None
+        if not t.is_cuda or not t.is_contiguous() or t.dtype != self.complex_dtype or t.numel() != sum(self.nvec):
+            raise ValueError("vectors must be contiguous CUDA tensors of the context's dtype and size")
+        return ctypes.c_void_p(t.data_ptr())
+
+    def apply_liouvillian(self, q_in, p_in, q_out, p_out):
+        lib = load()
+        _check(lib.lz_apply_liouvillian(self.handle, self._dev(q_in), self._dev(p_in),
+                                        self._dev(q_out), self._dev(p_out)))
+
+    def step(self, n):
+        lib = load()
+        done = ctypes.c_int32()
+        st = _check(lib.lz_step(self.handle, int(n), ctypes.byref(done)), allow=(LZ_BREAKDOWN,))
+        return int(done.value), st
+
+    def state(self, inst=0):
+        lib = load()
+        n, st = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib.lz_get_state(self.handle, int(inst), ctypes.byref(n), ctypes.byref(st)))
+        return int(n.value), int(st.value)
+
+    def coefficients(self, inst=0, first=0, count=None):
+        lib = load()
+        if count is None:
+            count = self.state(inst)[0] - first
+        beta = np.zeros(count)
+        gamma = np.zeros(count)
+        z = np.zeros(2 * count)
+        _check(lib.lz_get_coefficients(self.handle, int(inst), int(first), int(count),
+                                       _ptr(beta, _dp), _ptr(gamma, _dp), _ptr(z, _dp)))
+        return beta, gamma, z.view(np.complex128)
+
+    def spectrum(self, omega, eta, m=None, inst=0):
+        lib = load()
+        omega = _f64(omega)
+        if m is None:
+            m = self.state(inst)[0]
+        chi = np.zeros(2 * len(omega))
+        einv = np.zeros(2 * len(omega))
+        loss = np.zeros(len(omega))
+        _check(lib.lz_spectrum(self.handle, int(inst), int(m), _ptr(omega, _dp), len(omega),
+                               float(eta), _ptr(chi, _dp), _ptr(einv, _dp), _ptr(loss, _dp)))
+        return chi.view(np.complex128), einv.view(np.complex128), loss
+
+    def rhs(self, inst=0):
+        import torch
+        lib = load()
+        y = torch.zeros(self.shapes[inst], dtype=self.complex_dtype, device="cuda")
+        _check(lib.lz_get_rhs(self.handle, int(inst), ctypes.c_void_p(y.data_ptr())))
+        return y
+
+    def stage_timer(self, enable=True):
+        _check(load().lz_stage_timer(self.handle, int(bool(enable))))
+
+    def stage_times(self, inst=0):
+        """(total_ms[8], count[8]) per stage since the last stage_timer call."""
+        ms = np.zeros(8)
+        cnt = np.zeros(8, dtype=np.int32)
+        _check(load().lz_stage_times(self.handle, int(inst), _ptr(ms, _dp), _ptr(cnt, _ip)))
+        return ms, cnt
+
+    def free(self):
+        if self.handle:
+            load().lz_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+# functional aliases with the C names
+def lz_apply_liouvillian(ctx, q_in, p_in, q_out, p_out):
+    return ctx.apply_liouvillian(q_in, p_in, q_out, p_out)
+
+
+def lz_step(ctx, n):
+    return ctx.step(n)
+
+
+def lz_get_coefficients(ctx, inst=0, first=0, count=None):
+    return ctx.coefficients(inst, first, count)
+
+
+def lz_get_state(ctx, inst=0):
+    return ctx.state(inst)
+
+
+def lz_spectrum(ctx, omega, eta, m=None, inst=0):
+    return ctx.spectrum(omega, eta, m, inst)
+
+
+def lz_get_rhs(ctx, inst=0):
+    return ctx.rhs(inst)
+
+
+def lz_free(ctx):
+    ctx.free()

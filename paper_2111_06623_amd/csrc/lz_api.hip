@@ -1,0 +1,862 @@
+// C ABI of the library: context construction, the Liouvillian application,
+// the pseudo-Hermitian Lanczos driver and the spectrum (see include/lz.h).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/lz.h"
+#include "lz_kernels.h"
+
+namespace lz {
+hipError_t enable_large_lds();
+}
+
+using namespace lz;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+struct LzError {
+  lz_status st;
+  std::string msg;
+};
+
+[[noreturn]] void fail(lz_status st, const std::string& msg) { throw LzError{st, msg}; }
+
+#define HIPC(call)                                                                    \
+  do {                                                                                \
+    hipError_t e_ = (call);                                                           \
+    if (e_ != hipSuccess) {                                                           \
+      if (e_ == hipErrorOutOfMemory) fail(LZ_ERR_OOM, std::string(#call) + ": out of device memory"); \
+      fail(LZ_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_));            \
+    }                                                                                 \
+  } while (0)
+
+constexpr double kTwoPi = 6.283185307179586476925286766559;
+constexpr double kBreakdownTol = 1e-7;
+
+// device buffer with RAII
+struct DBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DBuf() = default;
+  DBuf(const DBuf&) = delete;
+  DBuf& operator=(const DBuf&) = delete;
+  ~DBuf() { if (p) (void)hipFree(p); }
+  void alloc(size_t b) {
+    if (p) { (void)hipFree(p); p = nullptr; }
+    bytes = b ? b : 16;
+    HIPC(hipMalloc(&p, bytes));
+    // zero-fill and wait: later work runs on a non-blocking stream that is not
+    // ordered after the null stream
+    HIPC(hipMemset(p, 0, bytes));
+    HIPC(hipDeviceSynchronize());
+  }
+  template <typename U> U* as() const { return reinterpret_cast<U*>(p); }
+};
+
+template <typename U>
+void upload(DBuf& d, const std::vector<U>& h) {
+  d.alloc(h.size() * sizeof(U));
+  if (!h.empty()) HIPC(hipMemcpy(d.p, h.data(), h.size() * sizeof(U), hipMemcpyHostToDevice));
+}
+
+// factor n into radix passes (4, 3, 5, 2) and build the forward twiddles
+bool make_plan(int n, FftPlan& p, std::vector<double>& tw_re, std::vector<double>& tw_im) {
+  p.n = n;
+  p.npass = 0;
+  int m = n, ns = 1;
+  const int order[4] = {4, 3, 5, 2};
+  for (int r : order) {
+    while (m % r == 0) {
+      if (p.npass >= kMaxPass) return false;
+      p.radix[p.npass] = r;
+      p.ns[p.npass] = ns;
+      p.twoff[p.npass] = (int)tw_re.size();
+      for (int k = 0; k < ns; ++k)
+        for (int q = 1; q < r; ++q) {
+          const double ang = -kTwoPi * (double)k * q / ((double)ns * r);
+          tw_re.push_back(std::cos(ang));
+          tw_im.push_back(std::sin(ang));
+        }
+      ns *= r;
+      m /= r;
+      p.npass++;
+    }
+  }
+  return m == 1;
+}
+
+int centred(int i, int n) { return i >= (n + 1) / 2 ? i - n : i; }
+
+// Stages of one Liouvillian half-application that can be timed with events.
+enum Stage { ST_ZINV = 0, ST_PLANE = 1, ST_PLANE_DENS = 2, ST_HXC = 3, ST_PLANE_VU = 4,
+             ST_ZFWD = 5, ST_PROJ = 6, ST_LANCZOS = 7, ST_COUNT = 8 };
+
+struct StageTimer {
+  bool on = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> pending[ST_COUNT];
+  double total_ms[ST_COUNT] = {0};
+  int count[ST_COUNT] = {0};
+  std::vector<hipEvent_t> pool;
+  hipEvent_t get() {
+    hipEvent_t e;
+    if (!pool.empty()) { e = pool.back(); pool.pop_back(); return e; }
+    HIPC(hipEventCreate(&e));
+    return e;
+  }
+  void begin(int st, hipStream_t s, hipEvent_t& e0) {
+    if (!on) return;
+    e0 = get();
+    HIPC(hipEventRecord(e0, s));
+    (void)st;
+  }
+  void end(int st, hipStream_t s, hipEvent_t e0) {
+    if (!on) return;
+    hipEvent_t e1 = get();
+    HIPC(hipEventRecord(e1, s));
+    pending[st].push_back({e0, e1});
+  }
+  // fold completed pairs into the totals (after a stream synchronisation)
+  void collect() {
+    for (int st = 0; st < ST_COUNT; ++st) {
+      for (auto& pr : pending[st]) {
+        float ms = 0;
+        HIPC(hipEventElapsedTime(&ms, pr.first, pr.second));
+        total_ms[st] += ms;
+        count[st] += 1;
+        pool.push_back(pr.first);
+        pool.push_back(pr.second);
+      }
+      pending[st].clear();
+    }
+  }
+  void reset() {
+    for (int st = 0; st < ST_COUNT; ++st) { total_ms[st] = 0; count[st] = 0; }
+  }
+  ~StageTimer() {
+    for (int st = 0; st < ST_COUNT; ++st)
+      for (auto& pr : pending[st]) { (void)hipEventDestroy(pr.first); (void)hipEventDestroy(pr.second); }
+    for (auto e : pool) (void)hipEventDestroy(e);
+  }
+};
+
+struct Instance {
+  lz_precision prec;
+  lz_approx approx;
+  bool fp64;
+  size_t csz;  // bytes per complex element
+  int n1, n2, n3, N;
+  int nks, nbnd, nproj, npwx, nb;
+  double omega, q2;
+  double pref, fq;
+  int max_steps;
+  int S = 0, nact = 0;
+  int ngroups = 1, gsize = 1;
+  int nchunk = 1, nlzblk = 1;
+  int64_t nvec;  // complex elements of one batch
+  Grid3 grid;
+  DBuf si1, si2, act, map_kq, map_k, perm, npw_kq;
+  DBuf tw1, tw2, tw3;
+  DBuf kin, eps, wk, bandw, vloc, fxc, khart;
+  DBuf U, vkb, dkb;
+  DBuf ur, y;
+  DBuf X0, X1, LW;
+  DBuf sa, sb;
+  DBuf dpart, nr, work, vp;
+  DBuf dpartial, C;
+  DBuf lzpart, st, beta, z;
+  DBuf tin, tout, tin2, tout2;
+  int steps_host = 0;
+  int status_host = 0;
+  StageTimer timer;
+};
+
+#define STAGE(I, ST, S, ...)             \
+  do {                                   \
+    hipEvent_t e0_ = nullptr;            \
+    (I).timer.begin(ST, S, e0_);         \
+    __VA_ARGS__;                         \
+    (I).timer.end(ST, S, e0_);           \
+  } while (0)
+
+template <typename T>
+void to_dev_real(DBuf& d, const std::vector<double>& h) {
+  std::vector<T> t(h.begin(), h.end());
+  upload(d, t);
+}
+
+template <typename T>
+void to_dev_cplx(DBuf& d, const std::vector<double>& h /* interleaved */) {
+  std::vector<T> t(h.begin(), h.end());
+  upload(d, t);
+}
+
+void upload_real(Instance& I, DBuf& d, const std::vector<double>& h) {
+  if (I.fp64) to_dev_real<double>(d, h); else to_dev_real<float>(d, h);
+}
+void upload_cplx(Instance& I, DBuf& d, const std::vector<double>& h) {
+  if (I.fp64) to_dev_cplx<double>(d, h); else to_dev_cplx<float>(d, h);
+}
+
+bool valid_len(int n) {
+  if (n < 2 || n > 128) return false;
+  int m = n;
+  for (int r : {2, 3, 5}) while (m % r == 0) m /= r;
+  return m == 1;
+}
+
+// ---------------------------------------------------------------------------
+// operator application on one instance (internal order, stream-ordered)
+// ---------------------------------------------------------------------------
+template <typename T>
+void apply_pc(Instance& I, void* X, const LzDevState* st, hipStream_t s) {
+  STAGE(I, ST_PROJ, s,
+        Launch<T>::proj_dot(I.U.p, I.nbnd, X, I.nbnd, I.npwx, I.nks, I.dpartial.p, I.nchunk, I.C.p,
+                            nullptr, -1.0, st, s);
+        Launch<T>::proj_update(I.U.p, I.nbnd, I.C.p, X, I.nbnd, I.npwx, I.nks, st, s));
+}
+
+template <typename T>
+void apply_half(Instance& I, const void* in, void* out, bool upper, const LzDevState* st,
+                hipStream_t s) {
+  const Grid3& g = I.grid;
+  const int64_t xs = I.npwx;
+  STAGE(I, ST_ZINV, s, Launch<T>::zfft_inv(g, in, xs, I.sa.p, I.map_kq.as<int>(), I.nb, I.nbnd, st, s));
+  if (upper && I.approx != LZ_IPA) {
+    STAGE(I, ST_PLANE_DENS, s,
+          Launch<T>::plane_local_density(g, I.sa.p, I.sb.p, I.vloc.p, I.ur.p, I.bandw.as<double>(),
+                                         I.dpart.p, I.nb, I.gsize, st, s));
+    STAGE(I, ST_HXC, s,
+          Launch<T>::hxc(g, I.dpart.p, I.ngroups, I.nr.p, I.work.p, I.khart.p, I.fxc.p,
+                         I.approx == LZ_TDDFT, I.vp.p, st, s));
+    STAGE(I, ST_PLANE_VU, s, Launch<T>::plane_vu(g, I.ur.p, I.vp.p, I.sb.p, I.nb, st, s));
+  } else {
+    STAGE(I, ST_PLANE, s, Launch<T>::plane_local(g, I.sa.p, I.sb.p, I.vloc.p, I.nb, st, s));
+  }
+  STAGE(I, ST_ZFWD, s,
+        Launch<T>::zfft_fwd(g, I.sb.p, in, xs, out, I.map_kq.as<int>(), I.kin.p, I.eps.as<double>(),
+                            I.nb, I.nbnd, I.npwx, st, s));
+  if (I.nproj > 0) {
+    STAGE(I, ST_PROJ, s,
+          Launch<T>::proj_dot(I.vkb.p, I.nproj, in, I.nbnd, I.npwx, I.nks, I.dpartial.p, I.nchunk,
+                              I.C.p, I.dkb.as<double>(), 0.0, st, s);
+          Launch<T>::proj_update(I.vkb.p, I.nproj, I.C.p, out, I.nbnd, I.npwx, I.nks, st, s));
+  }
+  apply_pc<T>(I, out, st, s);
+}
+
+template <typename T>
+void lanczos_step(Instance& I, int j, hipStream_t s) {
+  LzDevState* st = I.st.as<LzDevState>();
+  void* X = (j & 1) ? I.X1.p : I.X0.p;
+  if (j > 0) {
+    STAGE(I, ST_LANCZOS, s, Launch<T>::lz_update(X, I.LW.p, I.nvec, st, s));
+    apply_pc<T>(I, X, st, s);
+  }
+  apply_half<T>(I, X, I.LW.p, (j & 1) != 0, st, s);
+  STAGE(I, ST_LANCZOS, s,
+        Launch<T>::lz_dots(X, I.LW.p, I.y.p, I.wk.as<double>(), I.nbnd, I.npwx, I.nks,
+                           I.lzpart.as<double>(), I.nlzblk, st, s);
+        launch_lz_finalize(I.lzpart.as<double>(), I.nlzblk, st, I.beta.as<double>(),
+                           I.z.as<double>(), I.max_steps, kBreakdownTol, (double)I.nbnd, s));
+}
+
+// ---------------------------------------------------------------------------
+// construction of one instance
+// ---------------------------------------------------------------------------
+template <typename T>
+void build_device_tables(Instance& I, const lz_system& sys, hipStream_t s,
+                         const std::vector<double>& evc_k_in, const std::vector<int>& map_k) {
+  (void)map_k;
+  // valence orbitals in real space: sphere (caller order) -> sticks -> planes
+  DBuf uk;
+  std::vector<double> tmp(evc_k_in);
+  upload_cplx(I, uk, tmp);
+  Launch<T>::zfft_inv(I.grid, uk.p, I.npwx, I.sa.p, I.map_k.as<int>(), I.nb, I.nbnd, nullptr, s);
+  Launch<T>::plane_to_real(I.grid, I.sa.p, I.ur.p, I.nb, s);
+  // y = P_c (shifted u) ; then the Lanczos start vector X0 = y
+  apply_pc<T>(I, I.y.p, nullptr, s);
+  HIPC(hipStreamSynchronize(s));
+  (void)sys;
+}
+
+std::unique_ptr<Instance> build_instance(const lz_system& sys, const lz_options& opt,
+                                         hipStream_t s) {
+  auto Ip = std::make_unique<Instance>();
+  Instance& I = *Ip;
+  I.prec = opt.prec;
+  I.approx = opt.approx;
+  I.fp64 = opt.prec == LZ_FP64;
+  I.csz = I.fp64 ? 16 : 8;
+  I.max_steps = opt.max_steps;
+  // ---- validation
+  for (int i = 0; i < 3; ++i)
+    if (!valid_len(sys.nr[i])) fail(LZ_ERR_ARG, "nr[" + std::to_string(i) + "] must factor into 2,3,5 and lie in [2,128]");
+  I.n1 = sys.nr[0]; I.n2 = sys.nr[1]; I.n3 = sys.nr[2];
+  if (I.n1 * I.n2 > 36 * 256) fail(LZ_ERR_ARG, "N1*N2 exceeds 9216");
+  I.N = I.n1 * I.n2 * I.n3;
+  if (sys.nks < 1 || sys.nbnd < 1 || sys.nproj < 0 || sys.npwx < 1)
+    fail(LZ_ERR_ARG, "nks, nbnd, npwx must be >= 1 and nproj >= 0");
+  I.nks = sys.nks; I.nbnd = sys.nbnd; I.nproj = sys.nproj; I.npwx = sys.npwx;
+  I.nb = I.nks * I.nbnd;
+  if (!sys.xk || !sys.wk || !sys.npw_k || !sys.npw_kq || !sys.nl_k || !sys.nl_kq || !sys.evc_k ||
+      !sys.evc_kq || !sys.et_k || !sys.vloc_r)
+    fail(LZ_ERR_ARG, "a required array pointer is NULL");
+  if (opt.approx == LZ_TDDFT && !sys.fxc_r) fail(LZ_ERR_ARG, "fxc_r is required for TDDFT");
+  if (I.nproj > 0 && (!sys.vkb_kq || !sys.dkb)) fail(LZ_ERR_ARG, "vkb_kq and dkb are required when nproj > 0");
+  const double* at = sys.at;
+  const double det = at[0] * (at[4] * at[8] - at[5] * at[7]) - at[1] * (at[3] * at[8] - at[5] * at[6]) +
+                     at[2] * (at[3] * at[7] - at[4] * at[6]);
+  if (!(std::fabs(det) > 0)) fail(LZ_ERR_ARG, "lattice vectors are singular");
+  I.omega = std::fabs(det);
+  // reciprocal rows b_j: b = 2 pi inv(at)^T
+  double bg[9];
+  {
+    double inv[9];
+    inv[0] = (at[4] * at[8] - at[5] * at[7]) / det;
+    inv[1] = -(at[1] * at[8] - at[2] * at[7]) / det;
+    inv[2] = (at[1] * at[5] - at[2] * at[4]) / det;
+    inv[3] = -(at[3] * at[8] - at[5] * at[6]) / det;
+    inv[4] = (at[0] * at[8] - at[2] * at[6]) / det;
+    inv[5] = -(at[0] * at[5] - at[2] * at[3]) / det;
+    inv[6] = (at[3] * at[7] - at[4] * at[6]) / det;
+    inv[7] = -(at[0] * at[7] - at[1] * at[6]) / det;
+    inv[8] = (at[0] * at[4] - at[1] * at[3]) / det;
+    for (int j = 0; j < 3; ++j)
+      for (int c = 0; c < 3; ++c) bg[j * 3 + c] = kTwoPi * inv[c * 3 + j];
+  }
+  auto gcart = [&](int m1, int m2, int m3, double* out) {
+    for (int c = 0; c < 3; ++c) out[c] = m1 * bg[c] + m2 * bg[3 + c] + m3 * bg[6 + c];
+  };
+  double Q[3];
+  gcart(sys.g0[0], sys.g0[1], sys.g0[2], Q);
+  for (int c = 0; c < 3; ++c) Q[c] += sys.q[c];
+  I.q2 = Q[0] * Q[0] + Q[1] * Q[1] + Q[2] * Q[2];
+  if (!(I.q2 > 0)) fail(LZ_ERR_ARG, "Q = q + G0 must be nonzero");
+  I.pref = 4.0 / I.omega;
+  I.fq = 4.0 * M_PI / I.q2;
+  double wsum = 0;
+  for (int k = 0; k < I.nks; ++k) {
+    if (!(sys.wk[k] >= 0)) fail(LZ_ERR_ARG, "negative k weight");
+    wsum += sys.wk[k];
+  }
+  if (std::fabs(wsum - 1.0) > 1e-10) fail(LZ_ERR_ARG, "k weights must sum to 1");
+  for (int k = 0; k < I.nks; ++k) {
+    if (sys.npw_k[k] < 1 || sys.npw_k[k] > I.npwx || sys.npw_kq[k] < 1 || sys.npw_kq[k] > I.npwx)
+      fail(LZ_ERR_ARG, "npw out of range [1, npwx]");
+    if (sys.npw_kq[k] <= I.nbnd) fail(LZ_ERR_ARG, "npw_kq must exceed nbnd");
+  }
+  // ---- sticks: union of the (i1, i2) columns of every sphere
+  auto split = [&](int idx, int& i1, int& i2, int& i3) {
+    i3 = idx % I.n3;
+    i2 = (idx / I.n3) % I.n2;
+    i1 = idx / (I.n2 * I.n3);
+  };
+  std::vector<char> col(I.n1 * I.n2, 0);
+  auto scan = [&](const int32_t* nl, const int32_t* npw) {
+    for (int k = 0; k < I.nks; ++k) {
+      std::vector<char> seen(I.N, 0);
+      for (int i = 0; i < npw[k]; ++i) {
+        const int idx = nl[(int64_t)k * I.npwx + i];
+        if (idx < 0 || idx >= I.N) fail(LZ_ERR_ARG, "plane-wave index outside the grid");
+        if (seen[idx]) fail(LZ_ERR_ARG, "duplicate plane wave in a sphere");
+        seen[idx] = 1;
+        int i1, i2, i3;
+        split(idx, i1, i2, i3);
+        col[i1 * I.n2 + i2] = 1;
+      }
+    }
+  };
+  scan(sys.nl_k, sys.npw_k);
+  scan(sys.nl_kq, sys.npw_kq);
+  std::vector<int> sid(I.n1 * I.n2, -1), si1, si2, act;
+  std::vector<char> rowact(I.n1, 0);
+  for (int c = 0; c < I.n1 * I.n2; ++c)
+    if (col[c]) {
+      sid[c] = (int)si1.size();
+      si1.push_back(c / I.n2);
+      si2.push_back(c % I.n2);
+      rowact[c / I.n2] = 1;
+    }
+  for (int r = 0; r < I.n1; ++r)
+    if (rowact[r]) act.push_back(r);
+  I.S = (int)si1.size();
+  I.nact = (int)act.size();
+  // ---- internal (stick-major) order of the k+q spheres
+  std::vector<int> perm((size_t)I.nks * I.npwx, 0), npwkq(I.nks);
+  std::vector<int> map_kq((size_t)I.nks * I.S * I.n3, -1), map_k((size_t)I.nks * I.S * I.n3, -1);
+  std::vector<double> kin((size_t)I.nks * I.npwx, 0.0);
+  for (int k = 0; k < I.nks; ++k) {
+    const int npw = sys.npw_kq[k];
+    npwkq[k] = npw;
+    std::vector<std::pair<int64_t, int>> key(npw);
+    for (int i = 0; i < npw; ++i) {
+      const int idx = sys.nl_kq[(int64_t)k * I.npwx + i];
+      int i1, i2, i3;
+      split(idx, i1, i2, i3);
+      key[i] = {(int64_t)sid[i1 * I.n2 + i2] * I.n3 + i3, i};
+    }
+    std::sort(key.begin(), key.end());
+    const double* xk = sys.xk + 3 * k;
+    for (int ii = 0; ii < npw; ++ii) {
+      const int i = key[ii].second;
+      perm[(size_t)k * I.npwx + ii] = i;
+      const int idx = sys.nl_kq[(int64_t)k * I.npwx + i];
+      int i1, i2, i3;
+      split(idx, i1, i2, i3);
+      map_kq[((size_t)k * I.S + sid[i1 * I.n2 + i2]) * I.n3 + i3] = ii;
+      double g[3];
+      gcart(centred(i1, I.n1), centred(i2, I.n2), centred(i3, I.n3), g);
+      double e = 0;
+      for (int c = 0; c < 3; ++c) {
+        const double v = xk[c] + sys.q[c] + g[c];
+        e += v * v;
+      }
+      kin[(size_t)k * I.npwx + ii] = 0.5 * e;
+    }
+    for (int i = 0; i < sys.npw_k[k]; ++i) {
+      const int idx = sys.nl_k[(int64_t)k * I.npwx + i];
+      int i1, i2, i3;
+      split(idx, i1, i2, i3);
+      map_k[((size_t)k * I.S + sid[i1 * I.n2 + i2]) * I.n3 + i3] = i;
+    }
+  }
+  // ---- complex arrays in internal order (interleaved doubles on the host)
+  const size_t nv = (size_t)I.nks * I.nbnd * I.npwx;
+  I.nvec = (int64_t)nv;
+  std::vector<double> U(2 * nv, 0.0), Y(2 * nv, 0.0), EK(2 * nv, 0.0);
+  for (int k = 0; k < I.nks; ++k) {
+    // y_nk(G') = u_nk at the grid point G' - G0 (the grid product e^{iG0.r} u)
+    std::unordered_map<int, int> kpos;
+    for (int i = 0; i < sys.npw_k[k]; ++i) kpos[sys.nl_k[(int64_t)k * I.npwx + i]] = i;
+    for (int n = 0; n < I.nbnd; ++n) {
+      const size_t row = ((size_t)k * I.nbnd + n) * I.npwx;
+      for (int ii = 0; ii < npwkq[k]; ++ii) {
+        const int i = perm[(size_t)k * I.npwx + ii];
+        U[2 * (row + ii)] = sys.evc_kq[2 * (row + i)];
+        U[2 * (row + ii) + 1] = sys.evc_kq[2 * (row + i) + 1];
+        const int idx = sys.nl_kq[(int64_t)k * I.npwx + i];
+        int i1, i2, i3;
+        split(idx, i1, i2, i3);
+        const int j1 = ((i1 - sys.g0[0]) % I.n1 + I.n1) % I.n1;
+        const int j2 = ((i2 - sys.g0[1]) % I.n2 + I.n2) % I.n2;
+        const int j3 = ((i3 - sys.g0[2]) % I.n3 + I.n3) % I.n3;
+        auto it = kpos.find((j1 * I.n2 + j2) * I.n3 + j3);
+        if (it != kpos.end()) {
+          Y[2 * (row + ii)] = sys.evc_k[2 * (row + it->second)];
+          Y[2 * (row + ii) + 1] = sys.evc_k[2 * (row + it->second) + 1];
+        }
+      }
+      for (int i = 0; i < sys.npw_k[k]; ++i) {
+        EK[2 * (row + i)] = sys.evc_k[2 * (row + i)];
+        EK[2 * (row + i) + 1] = sys.evc_k[2 * (row + i) + 1];
+      }
+    }
+  }
+  std::vector<double> VKB;
+  std::vector<double> dkb(I.nproj);
+  if (I.nproj > 0) {
+    VKB.assign(2 * (size_t)I.nks * I.nproj * I.npwx, 0.0);
+    for (int k = 0; k < I.nks; ++k)
+      for (int p = 0; p < I.nproj; ++p) {
+        const size_t row = ((size_t)k * I.nproj + p) * I.npwx;
+        for (int ii = 0; ii < npwkq[k]; ++ii) {
+          const int i = perm[(size_t)k * I.npwx + ii];
+          VKB[2 * (row + ii)] = sys.vkb_kq[2 * (row + i)];
+          VKB[2 * (row + ii) + 1] = sys.vkb_kq[2 * (row + i) + 1];
+        }
+      }
+    for (int p = 0; p < I.nproj; ++p) dkb[p] = sys.dkb[p];
+  }
+  // ---- real-space grids in plane-major order [i3][i1][i2]; Hartree kernel
+  std::vector<double> vl(I.N), fx(I.N, 0.0), kh(I.N, 0.0);
+  bool singular = false;
+  for (int i1 = 0; i1 < I.n1; ++i1)
+    for (int i2 = 0; i2 < I.n2; ++i2)
+      for (int i3 = 0; i3 < I.n3; ++i3) {
+        const int src = (i1 * I.n2 + i2) * I.n3 + i3;
+        const int dst = (i3 * I.n1 + i1) * I.n2 + i2;
+        vl[dst] = sys.vloc_r[src];
+        if (sys.fxc_r) fx[dst] = sys.fxc_r[src];
+        double g[3];
+        gcart(centred(i1, I.n1), centred(i2, I.n2), centred(i3, I.n3), g);
+        double qg2 = 0;
+        for (int c = 0; c < 3; ++c) {
+          const double v = sys.q[c] + g[c];
+          qg2 += v * v;
+        }
+        if (qg2 == 0.0) singular = true;
+        else kh[dst] = 4.0 * M_PI / (qg2 * (double)I.N);
+      }
+  if (singular && I.approx != LZ_IPA) fail(LZ_ERR_ARG, "q + G = 0 on the grid: the Hartree kernel is singular");
+  // ---- plans
+  std::vector<double> tr, ti;
+  FftPlan p1, p2, p3;
+  std::vector<double> tws[3];
+  int lens[3] = {I.n1, I.n2, I.n3};
+  FftPlan* plans[3] = {&p1, &p2, &p3};
+  DBuf* twb[3] = {&I.tw1, &I.tw2, &I.tw3};
+  for (int a = 0; a < 3; ++a) {
+    tr.clear(); ti.clear();
+    if (!make_plan(lens[a], *plans[a], tr, ti)) fail(LZ_ERR_ARG, "unsupported FFT length");
+    std::vector<double> il(2 * tr.size());
+    for (size_t i = 0; i < tr.size(); ++i) { il[2 * i] = tr[i]; il[2 * i + 1] = ti[i]; }
+    upload_cplx(I, *twb[a], il);
+  }
+  // ---- device uploads
+  upload(I.si1, si1);
+  upload(I.si2, si2);
+  upload(I.act, act);
+  upload(I.map_kq, map_kq);
+  upload(I.map_k, map_k);
+  upload(I.perm, perm);
+  upload(I.npw_kq, npwkq);
+  upload_real(I, I.kin, kin);
+  std::vector<double> eps(sys.et_k, sys.et_k + I.nb), wk(sys.wk, sys.wk + I.nks), bw(I.nb);
+  for (int b = 0; b < I.nb; ++b) bw[b] = 4.0 * wk[b / I.nbnd] / I.omega;
+  upload(I.eps, eps);
+  upload(I.wk, wk);
+  upload(I.bandw, bw);
+  upload_real(I, I.vloc, vl);
+  upload_real(I, I.fxc, fx);
+  upload_real(I, I.khart, kh);
+  upload_cplx(I, I.U, U);
+  upload_cplx(I, I.y, Y);
+  if (I.nproj > 0) {
+    upload_cplx(I, I.vkb, VKB);
+    upload(I.dkb, dkb);
+  }
+  I.grid.n1 = I.n1; I.grid.n2 = I.n2; I.grid.n3 = I.n3;
+  I.grid.S = I.S; I.grid.nact = I.nact; I.grid.pitch2 = I.n2 + 1;
+  I.grid.si1 = I.si1.as<int>(); I.grid.si2 = I.si2.as<int>(); I.grid.act = I.act.as<int>();
+  I.grid.p1 = p1; I.grid.p2 = p2; I.grid.p3 = p3;
+  I.grid.tw1 = I.tw1.p; I.grid.tw2 = I.tw2.p; I.grid.tw3 = I.tw3.p;
+  // ---- work buffers
+  const size_t vb = nv * I.csz;
+  I.X0.alloc(vb); I.X1.alloc(vb); I.LW.alloc(vb);
+  I.tin.alloc(vb); I.tout.alloc(vb); I.tin2.alloc(vb); I.tout2.alloc(vb);
+  I.sa.alloc((size_t)I.nb * I.n3 * I.S * I.csz);
+  I.sb.alloc((size_t)I.nb * I.n3 * I.S * I.csz);
+  I.ur.alloc((size_t)I.nb * I.N * I.csz);
+  I.ngroups = std::max(1, std::min(I.nb, (512 + I.n3 - 1) / I.n3));
+  I.gsize = (I.nb + I.ngroups - 1) / I.ngroups;
+  I.ngroups = (I.nb + I.gsize - 1) / I.gsize;
+  I.dpart.alloc((size_t)I.ngroups * I.N * I.csz);
+  I.nr.alloc((size_t)I.N * I.csz);
+  I.work.alloc((size_t)I.N * I.csz);
+  I.vp.alloc((size_t)I.N * I.csz);
+  I.nchunk = (I.npwx + 511) / 512;
+  const int pmax = std::max(I.nbnd, I.nproj);
+  I.dpartial.alloc((size_t)I.nks * I.nchunk * pmax * I.nbnd * I.csz);
+  I.C.alloc((size_t)I.nks * pmax * I.nbnd * I.csz);
+  I.nlzblk = (int)std::min<int64_t>(512, std::max<int64_t>(1, (I.nvec + 1023) / 1024));
+  I.lzpart.alloc((size_t)I.nlzblk * 3 * sizeof(double));
+  I.st.alloc(sizeof(LzDevState));
+  I.beta.alloc((size_t)I.max_steps * sizeof(double));
+  I.z.alloc((size_t)I.max_steps * 2 * sizeof(double));
+  if (I.fp64) build_device_tables<double>(I, sys, s, EK, map_k);
+  else build_device_tables<float>(I, sys, s, EK, map_k);
+  return Ip;
+}
+
+}  // namespace
+
+struct lz_ctx {
+  int device = 0;
+  hipStream_t user = nullptr;
+  hipStream_t stream = nullptr;
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  lz_options opt{};
+  std::vector<std::unique_ptr<Instance>> inst;
+  bool started = false;
+  ~lz_ctx() {
+    inst.clear();
+    if (ev_in) (void)hipEventDestroy(ev_in);
+    if (ev_out) (void)hipEventDestroy(ev_out);
+    if (stream) (void)hipStreamDestroy(stream);
+  }
+  // order the private stream after the caller's stream
+  void enter() {
+    HIPC(hipEventRecord(ev_in, user));
+    HIPC(hipStreamWaitEvent(stream, ev_in, 0));
+  }
+  void leave() {
+    HIPC(hipEventRecord(ev_out, stream));
+    HIPC(hipStreamWaitEvent(user, ev_out, 0));
+  }
+};
+
+namespace {
+
+template <typename F>
+lz_status guarded(F&& f) {
+  try {
+    f();
+    g_last_error.clear();
+    return LZ_OK;
+  } catch (const LzError& e) {
+    g_last_error = e.msg;
+    return e.st;
+  } catch (const std::exception& e) {
+    g_last_error = e.what();
+    return LZ_ERR_HIP;
+  } catch (...) {
+    g_last_error = "unknown failure";
+    return LZ_ERR_HIP;
+  }
+}
+
+void start_recursion(lz_ctx* c) {
+  for (auto& ip : c->inst) {
+    Instance& I = *ip;
+    launch_set_state(I.st.as<LzDevState>(), c->stream);
+    HIPC(hipMemcpyAsync(I.X0.p, I.y.p, (size_t)I.nvec * I.csz, hipMemcpyDeviceToDevice, c->stream));
+    HIPC(hipMemsetAsync(I.X1.p, 0, (size_t)I.nvec * I.csz, c->stream));
+    I.steps_host = 0;
+    I.status_host = 0;
+  }
+  c->started = true;
+}
+
+void read_state(lz_ctx* c) {
+  HIPC(hipStreamSynchronize(c->stream));
+  for (auto& ip : c->inst) {
+    ip->timer.collect();
+    LzDevState h;
+    HIPC(hipMemcpy(&h, ip->st.p, sizeof(h), hipMemcpyDeviceToHost));
+    ip->steps_host = h.step;
+    ip->status_host = h.status;
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+lz_status lz_init(const lz_system* sys, int32_t n_inst, const lz_options* opt, int32_t device,
+                  void* hip_stream, lz_ctx** out) {
+  if (out) *out = nullptr;
+  return guarded([&] {
+    if (!sys || !opt || !out) fail(LZ_ERR_ARG, "null argument");
+    if (n_inst < 1) fail(LZ_ERR_ARG, "n_inst must be >= 1");
+    if (opt->max_steps < 1) fail(LZ_ERR_ARG, "max_steps must be >= 1");
+    if (opt->prec != LZ_FP64 && opt->prec != LZ_FP32 && opt->prec != LZ_FP32_SPLITBF16)
+      fail(LZ_ERR_ARG, "unknown precision");
+    if (opt->approx != LZ_TDDFT && opt->approx != LZ_RPA && opt->approx != LZ_IPA)
+      fail(LZ_ERR_ARG, "unknown approximation");
+    int ndev = 0;
+    HIPC(hipGetDeviceCount(&ndev));
+    if (device < 0 || device >= ndev) fail(LZ_ERR_ARG, "no such device");
+    HIPC(hipSetDevice(device));
+    auto c = std::make_unique<lz_ctx>();
+    c->device = device;
+    c->opt = *opt;
+    c->user = (hipStream_t)hip_stream;
+    HIPC(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+    HIPC(hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming));
+    HIPC(hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming));
+    HIPC(enable_large_lds());
+    c->enter();
+    for (int i = 0; i < n_inst; ++i) c->inst.push_back(build_instance(sys[i], *opt, c->stream));
+    start_recursion(c.get());
+    c->leave();
+    HIPC(hipStreamSynchronize(c->stream));
+    *out = c.release();
+  });
+}
+
+lz_status lz_apply_liouvillian(lz_ctx* c, const void* q_in, const void* p_in, void* q_out,
+                               void* p_out) {
+  return guarded([&] {
+    if (!c) fail(LZ_ERR_ARG, "null context");
+    if ((q_in == nullptr) != (p_out == nullptr) || (p_in == nullptr) != (q_out == nullptr))
+      fail(LZ_ERR_ARG, "each half needs both its input and its output (or neither)");
+    HIPC(hipSetDevice(c->device));
+    c->enter();
+    size_t off = 0;
+    for (auto& ip : c->inst) {
+      Instance& I = *ip;
+      const size_t bytes_off = off * I.csz;
+      auto at = [&](const void* p) { return p ? (const char*)p + bytes_off : nullptr; };
+      auto atw = [&](void* p) { return p ? (char*)p + bytes_off : nullptr; };
+      const void* qi = at(q_in);
+      const void* pi = at(p_in);
+      void* qo = atw(q_out);
+      void* po = atw(p_out);
+      if (I.fp64) {
+        if (pi) {
+          Launch<double>::perm_in(pi, I.tin.p, I.perm.as<int>(), I.npw_kq.as<int>(), I.nks, I.nbnd, I.npwx, c->stream);
+          apply_half<double>(I, I.tin.p, I.tout.p, false, nullptr, c->stream);
+          Launch<double>::perm_out(I.tout.p, qo, I.perm.as<int>(), I.npw_kq.as<int>(), I.nks, I.nbnd, I.npwx, c->stream);
+        }
+        if (qi) {
+          Launch<double>::perm_in(qi, I.tin2.p, I.perm.as<int>(), I.npw_kq.as<int>(), I.nks, I.nbnd, I.npwx, c->stream);
+          apply_half<double>(I, I.tin2.p, I.tout2.p, true, nullptr, c->stream);
+          Launch<double>::perm_out(I.tout2.p, po, I.perm.as<int>(), I.npw_kq.as<int>(), I.nks, I.nbnd, I.npwx, c->stream);
+        }
+      } else {
+        if (pi) {
+          Launch<float>::perm_in(pi, I.tin.p, I.perm.as<int>(), I.npw_kq.as<int>(), I.nks, I.nbnd, I.npwx, c->stream);
+          apply_half<float>(I, I.tin.p, I.tout.p, false, nullptr, c->stream);
+          Launch<float>::perm_out(I.tout.p, qo, I.perm.as<int>(), I.npw_kq.as<int>(), I.nks, I.nbnd, I.npwx, c->stream);
+        }
+        if (qi) {
+          Launch<float>::perm_in(qi, I.tin2.p, I.perm.as<int>(), I.npw_kq.as<int>(), I.nks, I.nbnd, I.npwx, c->stream);
+          apply_half<float>(I, I.tin2.p, I.tout2.p, true, nullptr, c->stream);
+          Launch<float>::perm_out(I.tout2.p, po, I.perm.as<int>(), I.npw_kq.as<int>(), I.nks, I.nbnd, I.npwx, c->stream);
+        }
+      }
+      off += (size_t)I.nvec;
+    }
+    HIPC(hipGetLastError());
+    c->leave();
+  });
+}
+
+lz_status lz_step(lz_ctx* c, int32_t n_steps, int32_t* steps_done) {
+  lz_status ret = LZ_OK;
+  lz_status g = guarded([&] {
+    if (!c) fail(LZ_ERR_ARG, "null context");
+    if (n_steps < 0) fail(LZ_ERR_ARG, "n_steps must be >= 0");
+    HIPC(hipSetDevice(c->device));
+    for (auto& ip : c->inst)
+      if (ip->status_host == 0 && ip->steps_host + n_steps > ip->max_steps)
+        fail(LZ_ERR_STATE, "max_steps would be exceeded");
+    c->enter();
+    for (auto& ip : c->inst) {
+      Instance& I = *ip;
+      if (I.status_host != 0) continue;
+      for (int j = I.steps_host; j < I.steps_host + n_steps; ++j) {
+        if (I.fp64) lanczos_step<double>(I, j, c->stream);
+        else lanczos_step<float>(I, j, c->stream);
+      }
+    }
+    HIPC(hipGetLastError());
+    c->leave();
+    read_state(c);
+    for (auto& ip : c->inst) {
+      if (ip->status_host == 4 || ip->status_host == 7) ret = LZ_ERR_NOT_PD;
+      else if (ip->status_host == 6 && ret == LZ_OK) ret = LZ_BREAKDOWN;
+    }
+    if (steps_done) *steps_done = c->inst[0]->steps_host;
+    if (ret == LZ_ERR_NOT_PD) g_last_error = "beta^2 <= 0 or non-finite: the metric is not positive definite";
+    if (ret == LZ_BREAKDOWN) g_last_error = "Krylov space exhausted (lucky breakdown)";
+  });
+  if (g != LZ_OK) return g;
+  return ret;
+}
+
+lz_status lz_get_state(lz_ctx* c, int32_t inst, int32_t* steps_done, int32_t* status) {
+  return guarded([&] {
+    if (!c || inst < 0 || inst >= (int)c->inst.size()) fail(LZ_ERR_ARG, "bad context or instance");
+    HIPC(hipSetDevice(c->device));
+    read_state(c);
+    Instance& I = *c->inst[inst];
+    if (steps_done) *steps_done = I.steps_host;
+    if (status) *status = I.status_host == 0 ? 0 : (I.status_host == 6 ? LZ_BREAKDOWN : LZ_ERR_NOT_PD);
+  });
+}
+
+lz_status lz_get_coefficients(lz_ctx* c, int32_t inst, int32_t first, int32_t count, double* beta,
+                              double* gamma, double* z) {
+  return guarded([&] {
+    if (!c || inst < 0 || inst >= (int)c->inst.size()) fail(LZ_ERR_ARG, "bad context or instance");
+    if (first < 0 || count < 0) fail(LZ_ERR_ARG, "negative range");
+    HIPC(hipSetDevice(c->device));
+    read_state(c);
+    Instance& I = *c->inst[inst];
+    if (first + count > I.steps_host) fail(LZ_ERR_STATE, "coefficients not computed yet");
+    if (count == 0) return;
+    if (beta) HIPC(hipMemcpy(beta, I.beta.as<double>() + first, count * sizeof(double), hipMemcpyDeviceToHost));
+    if (gamma) HIPC(hipMemcpy(gamma, I.beta.as<double>() + first, count * sizeof(double), hipMemcpyDeviceToHost));
+    if (z) HIPC(hipMemcpy(z, I.z.as<double>() + 2 * first, 2 * count * sizeof(double), hipMemcpyDeviceToHost));
+  });
+}
+
+lz_status lz_spectrum(lz_ctx* c, int32_t inst, int32_t m, const double* omega, int32_t n_omega,
+                      double eta, double* chi, double* eps_inv, double* loss) {
+  return guarded([&] {
+    if (!c || inst < 0 || inst >= (int)c->inst.size()) fail(LZ_ERR_ARG, "bad context or instance");
+    if (n_omega < 0 || (n_omega > 0 && !omega)) fail(LZ_ERR_ARG, "bad frequency grid");
+    if (!(eta > 0)) fail(LZ_ERR_ARG, "eta must be > 0");
+    HIPC(hipSetDevice(c->device));
+    read_state(c);
+    Instance& I = *c->inst[inst];
+    if (m < 0 || m > I.steps_host) fail(LZ_ERR_STATE, "m exceeds the completed steps");
+    if (n_omega == 0) return;
+    DBuf dw, dchi, dei, dl;
+    dw.alloc(n_omega * sizeof(double));
+    dchi.alloc(2 * n_omega * sizeof(double));
+    dei.alloc(2 * n_omega * sizeof(double));
+    dl.alloc(n_omega * sizeof(double));
+    HIPC(hipMemcpyAsync(dw.p, omega, n_omega * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    launch_spectrum(I.beta.as<double>(), I.z.as<double>(), m, dw.as<double>(), n_omega, eta, I.pref,
+                    I.fq, dchi.as<double>(), dei.as<double>(), dl.as<double>(), c->stream);
+    HIPC(hipGetLastError());
+    HIPC(hipStreamSynchronize(c->stream));
+    if (chi) HIPC(hipMemcpy(chi, dchi.p, 2 * n_omega * sizeof(double), hipMemcpyDeviceToHost));
+    if (eps_inv) HIPC(hipMemcpy(eps_inv, dei.p, 2 * n_omega * sizeof(double), hipMemcpyDeviceToHost));
+    if (loss) HIPC(hipMemcpy(loss, dl.p, n_omega * sizeof(double), hipMemcpyDeviceToHost));
+  });
+}
+
+lz_status lz_get_rhs(lz_ctx* c, int32_t inst, void* y_out) {
+  return guarded([&] {
+    if (!c || inst < 0 || inst >= (int)c->inst.size() || !y_out) fail(LZ_ERR_ARG, "bad argument");
+    HIPC(hipSetDevice(c->device));
+    c->enter();
+    Instance& I = *c->inst[inst];
+    if (I.fp64) Launch<double>::perm_out(I.y.p, y_out, I.perm.as<int>(), I.npw_kq.as<int>(), I.nks, I.nbnd, I.npwx, c->stream);
+    else Launch<float>::perm_out(I.y.p, y_out, I.perm.as<int>(), I.npw_kq.as<int>(), I.nks, I.nbnd, I.npwx, c->stream);
+    HIPC(hipGetLastError());
+    c->leave();
+  });
+}
+
+lz_status lz_stage_timer(lz_ctx* c, int32_t enable) {
+  return guarded([&] {
+    if (!c) fail(LZ_ERR_ARG, "null context");
+    HIPC(hipSetDevice(c->device));
+    read_state(c);
+    for (auto& ip : c->inst) {
+      ip->timer.on = enable != 0;
+      ip->timer.reset();
+    }
+  });
+}
+
+lz_status lz_stage_times(lz_ctx* c, int32_t inst, double* total_ms, int32_t* count) {
+  return guarded([&] {
+    if (!c || inst < 0 || inst >= (int)c->inst.size()) fail(LZ_ERR_ARG, "bad context or instance");
+    HIPC(hipSetDevice(c->device));
+    read_state(c);
+    Instance& I = *c->inst[inst];
+    for (int s = 0; s < ST_COUNT; ++s) {
+      if (total_ms) total_ms[s] = I.timer.total_ms[s];
+      if (count) count[s] = I.timer.count[s];
+    }
+  });
+}
+
+lz_status lz_free(lz_ctx* c) {
+  return guarded([&] {
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    (void)hipStreamSynchronize(c->stream);
+    delete c;
+  });
+}
+
+const char* lz_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,84 @@
+// Host-visible launchers of the device kernels (all stream-ordered, no syncs).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "lz_device.h"
+
+namespace lz {
+
+// Geometry of the FFT work shared by the kernels of one instance.
+struct Grid3 {
+  int n1, n2, n3;
+  int S;        // sticks (i1, i2 columns) touching any sphere
+  int nact;     // rows i1 holding at least one stick
+  int pitch2;   // LDS row pitch of a plane (n2 + 1)
+  const int* si1;   // [S] stick row i1
+  const int* si2;   // [S] stick column i2
+  const int* act;   // [nact] active rows
+  FftPlan p1, p2, p3;
+  const void* tw1;  // twiddles of each plan (cplx<T>)
+  const void* tw2;
+  const void* tw3;
+};
+
+template <typename T> struct Launch {
+  // sphere (stick-major order of nb bands, band stride xs) -> sticks [b][z][S]
+  static void zfft_inv(const Grid3& g, const void* x, int64_t xs, void* sticks, const int* map,
+                       int nb, int nbnd, const LzDevState* st, hipStream_t s);
+  // sticks -> plane inverse -> *V -> forward -> sticks
+  static void plane_local(const Grid3& g, const void* sin, void* sout, const void* vloc, int nb,
+                          const LzDevState* st, hipStream_t s);
+  // as plane_local, also accumulating the response density of band groups
+  static void plane_local_density(const Grid3& g, const void* sin, void* sout, const void* vloc,
+                                  const void* ur, const double* bandw, void* dpart, int nb,
+                                  int gsize, const LzDevState* st, hipStream_t s);
+  // sticks -> real-space planes [b][z][n1][n2]
+  static void plane_to_real(const Grid3& g, const void* sin, void* rout, int nb, hipStream_t s);
+  // real-space u_b(r) * v'(r) -> forward -> sticks (accumulated into sout)
+  static void plane_vu(const Grid3& g, const void* ur, const void* vp, void* sout, int nb,
+                       const LzDevState* st, hipStream_t s);
+  // sticks -> forward z -> sphere, plus (kin - eps) x
+  static void zfft_fwd(const Grid3& g, const void* sticks, const void* x, int64_t xs, void* y,
+                       const int* map, const void* kin, const double* eps, int nb, int nbnd,
+                       int npwx, const LzDevState* st, hipStream_t s);
+  // density partials -> n'(r) and v'(r) (Hartree + optional f_xc)
+  static void hxc(const Grid3& g, const void* dpart, int ngroups, void* nr, void* work,
+                  const void* khart, const void* fxc, bool with_fxc, void* vp,
+                  const LzDevState* st, hipStream_t s);
+  // C[k][p][n] = coef_p * sum_G conj(A[k][p][G]) X[k][n][G]
+  static void proj_dot(const void* A, int P, const void* X, int nbnd, int npwx, int nks,
+                       void* partial, int nchunk, void* C, const double* coef, double coef_const,
+                       const LzDevState* st, hipStream_t s);
+  // Y[k][n][G] += sum_p A[k][p][G] C[k][p][n]
+  static void proj_update(const void* A, int P, const void* C, void* Y, int nbnd, int npwx,
+                          int nks, const LzDevState* st, hipStream_t s);
+  // Lanczos: w <- a*LW + b*w
+  static void lz_update(void* w, const void* lw, int64_t n, const LzDevState* st, hipStream_t s);
+  // partial sums of Re<w,Lw>_w and <y,w>_w
+  static void lz_dots(const void* w, const void* lw, const void* y, const double* wk, int nbnd,
+                      int npwx, int nks, double* partial, int nblk, const LzDevState* st,
+                      hipStream_t s);
+  // user order <-> internal order
+  static void perm_in(const void* xu, void* xi, const int* perm, const int* npw, int nks, int nbnd,
+                      int npwx, hipStream_t s);
+  static void perm_out(const void* xi, void* xu, const int* perm, const int* npw, int nks,
+                       int nbnd, int npwx, hipStream_t s);
+  static void copy(void* dst, const void* src, int64_t n, hipStream_t s);
+};
+
+void launch_lz_finalize(const double* partial, int nblk, LzDevState* st, double* beta, double* z,
+                        int max_steps, double tol, double yscale, hipStream_t s);
+void launch_spectrum(const double* beta, const double* z, int m, const double* omega, int nw,
+                     double eta, double pref, double fq, double* chi, double* einv, double* loss,
+                     hipStream_t s);
+void launch_set_state(LzDevState* st, hipStream_t s);
+
+constexpr int kPlaneMaxPt = 12;   // complex values per thread per plane pass
+constexpr int kStickTile = 16;    // sticks per block in the z passes
+constexpr int kStickMaxPt = 8;
+constexpr int kColTile = 16;      // grid columns per block in the Hartree z pass
+int plane_mp(int n1, int n2);
+
+}  // namespace lz

@@ -1,0 +1,193 @@
+"""GPU parity: the HIP library (through the C ABI) against the CPU oracle on the
+same seeded inputs.  Tolerances (FP64 path): operator applications 1e-12
+relative to the largest output element; Lanczos beta/gamma 1e-10 relative and
+z 1e-10 of max|z| over the first 50 steps; loss function 1e-6 relative with
+the denominator floored at 1e-6 of its maximum."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+from oracle import lanczos, spectrum  # noqa: E402
+from oracle.liouvillian import Liouvillian  # noqa: E402
+from synth import config_system, random_batch  # noqa: E402
+
+
+def _lz():
+    import paper_2111_06623_amd as lz
+    lz.load()
+    return lz
+
+
+def _to_dev(x, dtype=torch.complex128):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(device="cuda", dtype=dtype)
+
+
+def _rel(a, b):
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+def _loss_err(loss, ref):
+    floor = 1e-6 * np.abs(ref).max()
+    return np.max(np.abs(loss - ref) / np.maximum(np.abs(ref), floor))
+
+
+CASES = [("micro", {}), ("cfg1", {}), ("cfg2lo", {}), ("free", {})]
+
+
+@pytest.mark.parametrize("name,kw", CASES)
+@pytest.mark.parametrize("approx", ["tddft", "rpa", "ipa"])
+def test_apply_liouvillian_matches_oracle(name, kw, approx):
+    lz = _lz()
+    s = config_system(name, **kw)
+    print(f"[apply] {name} {approx} nr={tuple(s.nr)} nks={s.nks} nbnd={s.nbnd}", flush=True)
+    ctx = lz.lz_init(s, prec="fp64", approx=approx, max_steps=8)
+    L = Liouvillian(s, approx)
+    p = random_batch(s, 11)
+    q = random_batch(s, 12)
+    qo = torch.zeros_like(_to_dev(p))
+    po = torch.zeros_like(qo)
+    ctx.apply_liouvillian(_to_dev(q), _to_dev(p), qo, po)
+    torch.cuda.synchronize()
+    d_ref = L.apply_D(p)
+    dk_ref = L.apply_DK(q)
+    assert _rel(qo.cpu().numpy(), d_ref) < 1e-12
+    assert _rel(po.cpu().numpy(), dk_ref) < 1e-12
+    ctx.free()
+
+
+@pytest.mark.parametrize("name", ["micro", "cfg1", "cfg2lo", "free"])
+def test_rhs_matches_oracle(name):
+    lz = _lz()
+    s = config_system(name)
+    ctx = lz.lz_init(s, prec="fp64", max_steps=4)
+    y = ctx.rhs().cpu().numpy()
+    assert _rel(y, Liouvillian(s).rhs()) < 1e-12
+    ctx.free()
+
+
+@pytest.mark.parametrize("name,approx", [("cfg1", "tddft"), ("micro", "tddft"), ("micro", "rpa"),
+                                         ("micro", "ipa"), ("cfg2lo", "tddft")])
+def test_lanczos_coefficients_first_50_steps(name, approx):
+    lz = _lz()
+    s = config_system(name)
+    print(f"[lanczos] {name} {approx}", flush=True)
+    ctx = lz.lz_init(s, prec="fp64", approx=approx, max_steps=64)
+    done, st = ctx.step(50)
+    ref = lanczos.run(Liouvillian(s, approx), 50)
+    assert done == ref.steps == 50 and st == lz.LZ_OK
+    beta, gamma, z = ctx.coefficients()
+    assert np.max(np.abs(beta - ref.beta) / ref.beta) < 1e-10
+    assert np.array_equal(beta, gamma)
+    assert np.abs(z - ref.z).max() < 1e-10 * np.abs(ref.z).max()
+    ctx.free()
+
+
+def test_spectrum_cfg1_full_run():
+    """cfg1: 200 steps, 2000 frequencies in [0, 2] Ha, eta = 0.01 Ha."""
+    lz = _lz()
+    s = config_system("cfg1")
+    ctx = lz.lz_init(s, prec="fp64", max_steps=200)
+    done, _ = ctx.step(200)
+    assert done == 200
+    om = np.linspace(0.0, 2.0, 2000)
+    chi, einv, loss = ctx.spectrum(om, 0.01)
+    L = Liouvillian(s)
+    ref = lanczos.run(L, 200)
+    chi_r, einv_r, loss_r, _ = spectrum.spectrum(ref.beta, ref.z, om, 0.01, L.cell.omega, L.Q)
+    assert _loss_err(loss, loss_r) < 1e-6
+    assert _rel(chi, chi_r) < 1e-6
+    # the spectrum kernel on the oracle's own coefficients isolates the solve
+    beta, _, z = ctx.coefficients()
+    chi_same = spectrum.chi_from_coefficients(beta, z, om, 0.01, L.cell.omega)
+    assert _rel(chi, chi_same) < 1e-12
+    ctx.free()
+
+
+def test_free_electron_lucky_breakdown_on_gpu(free):
+    lz = _lz()
+    ctx = lz.lz_init(free, prec="fp64", max_steps=40)
+    done, st = ctx.step(30)
+    ref = lanczos.run(Liouvillian(free), 30)
+    assert st == lz.LZ_BREAKDOWN and ref.status == "breakdown"
+    assert done == ref.steps
+    beta, _, z = ctx.coefficients()
+    assert np.max(np.abs(beta - ref.beta) / ref.beta) < 1e-10
+    ctx.free()
+
+
+def test_pauli_blocked_rhs_gives_zero_spectrum():
+    lz = _lz()
+    s = config_system("free", g0=(0, 0, 0))
+    ctx = lz.lz_init(s, prec="fp64", max_steps=8)
+    done, st = ctx.step(5)
+    assert st == lz.LZ_BREAKDOWN and done == 0
+    chi, einv, loss = ctx.spectrum(np.linspace(0, 1, 11), 0.02, m=0)
+    assert np.all(chi == 0) and np.all(loss == 0)
+    ctx.free()
+
+
+def test_recursion_is_deterministic(cfg1):
+    lz = _lz()
+    out = []
+    for _ in range(2):
+        ctx = lz.lz_init(cfg1, prec="fp64", max_steps=40)
+        ctx.step(40)
+        out.append(ctx.coefficients())
+        ctx.free()
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][2], out[1][2])
+
+
+def test_steps_in_pieces_equal_one_call(cfg1):
+    lz = _lz()
+    a = lz.lz_init(cfg1, prec="fp64", max_steps=30)
+    a.step(30)
+    b = lz.lz_init(cfg1, prec="fp64", max_steps=30)
+    for n in (1, 2, 7, 20):
+        b.step(n)
+    assert np.array_equal(a.coefficients()[0], b.coefficients()[0])
+    with pytest.raises(lz.LzError) as e:
+        b.step(1)
+    assert e.value.status == lz.LZ_ERR_STATE
+    a.free()
+    b.free()
+
+
+def test_argument_errors_are_reported(cfg1):
+    lz = _lz()
+    import copy
+    bad = copy.copy(cfg1)
+    bad.wk = np.array([0.5])
+    with pytest.raises(lz.LzError) as e:
+        lz.lz_init(bad)
+    assert e.value.status == lz.LZ_ERR_ARG and "weights" in str(e.value)
+    bad = copy.copy(cfg1)
+    bad.nr = np.array([24, 24, 7 * 3])
+    with pytest.raises(lz.LzError) as e:
+        lz.lz_init(bad)
+    assert e.value.status == lz.LZ_ERR_ARG
+    ctx = lz.lz_init(cfg1, max_steps=10)
+    ctx.step(10)
+    with pytest.raises(lz.LzError) as e:
+        ctx.spectrum(np.zeros(3), 0.01, m=11)
+    assert e.value.status == lz.LZ_ERR_STATE
+    ctx.free()
+
+
+@pytest.mark.slow
+def test_cfg2_first_50_steps_full_size():
+    """The benchmark workload at its full size (48^3, 16 bands, 8 k)."""
+    lz = _lz()
+    s = config_system("cfg2")
+    print("[cfg2] init", flush=True)
+    ctx = lz.lz_init(s, prec="fp64", max_steps=64)
+    done, st = ctx.step(50)
+    assert done == 50
+    print("[cfg2] oracle", flush=True)
+    ref = lanczos.run(Liouvillian(s), 50)
+    beta, _, z = ctx.coefficients()
+    assert np.max(np.abs(beta - ref.beta) / ref.beta) < 1e-10
+    assert np.abs(z - ref.z).max() < 1e-10 * np.abs(ref.z).max()
+    ctx.free()
