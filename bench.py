@@ -71,28 +71,35 @@ def run_gpu(s, prec, steps, warmup):
                 stage_ms=ms, stage_cnt=cnt)
 
 
-def stage_bytes(s, prec):
-    """Algorithmic HBM bytes per launch of each stage (one launch covers every
-    band of the instance)."""
+def stage_bytes(s, prec, ngroups):
+    """Algorithmic HBM bytes of one launch of each stage (a launch covers every
+    band of the instance): each array the stage must touch, read or written
+    once.  c = bytes per complex, r = bytes per real; nb bands, S sticks,
+    N grid points, npw the summed sphere sizes over bands and k-points."""
     import numpy as np
     c = 16 if prec == "fp64" else 8
     r = c // 2
     nb = s.nks * s.nbnd
     n1, n2, n3 = (int(v) for v in s.nr)
-    ncol = set()
+    cols = set()
     for k in range(s.nks):
         for nl, npw in ((s.nl_k[k], s.npw_k[k]), (s.nl_kq[k], s.npw_kq[k])):
-            idx = np.asarray(nl[:npw])
-            ncol.update((idx // n3).tolist())
-    S = len(ncol)
+            cols.update((np.asarray(nl[:npw]) // n3).tolist())
+    S = len(cols)
     npw = int(np.sum(s.npw_kq)) * s.nbnd
     N = n1 * n2 * n3
+    sticks = nb * n3 * S * c
+    pc = 2 * s.nks * s.nbnd * int(np.mean(s.npw_kq)) * c + 3 * npw * c
     return {
-        "zfft_inv": npw * c + nb * n3 * S * c,
-        "plane_local": 2 * nb * n3 * S * c + N * r,
-        "zfft_fwd": nb * n3 * S * c + 2 * npw * c + npw * r,
-        "sticks_S": S,
-    }
+        "zfft_inv": npw * c + sticks,
+        "plane_local": 2 * sticks + N * r,
+        "plane_density": 2 * sticks + nb * N * c + N * r + ngroups * N * c,
+        "hxc": ngroups * N * c + 7 * N * c + 2 * N * r,
+        "plane_vu": nb * N * c + N * c + 2 * sticks,
+        "zfft_fwd": sticks + 2 * npw * c + s.nks * int(np.mean(s.npw_kq)) * r,
+        "projectors": pc,
+        "lanczos": 3 * npw * c,
+    }, S
 
 
 def cpu_baseline(s, budget_s):
@@ -156,9 +163,13 @@ def main():
                   for i in range(8)}
     totals = {names[i]: float(r["stage_ms"][i]) for i in range(8)}
     dom = max(totals, key=totals.get)
-    nbytes = stage_bytes(s, head)
+    ngroups = max(1, min(s.nks * s.nbnd, -(-1024 // int(s.nr[2]))))
+    gsize = -(-(s.nks * s.nbnd) // ngroups)
+    ngroups = -(-(s.nks * s.nbnd) // gsize)
+    nbytes, nsticks = stage_bytes(s, head, ngroups)
+    gbs = {k: round(nbytes[k] / (per_launch[k] * 1e-3) / 1e9, 1) for k in nbytes if per_launch.get(k, 0) > 0}
     roof = None
-    if dom in nbytes and per_launch[dom] > 0:
+    if per_launch.get(dom, 0) > 0:
         ach = nbytes[dom] / (per_launch[dom] * 1e-3) / 1e9
         roof = {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1), "peak": 8000.0,
                 "unit": "GB/s", "frac": round(ach / 8000.0, 4), "traffic": None,
@@ -174,6 +185,8 @@ def main():
                    "precision": head, "lanczos_steps_timed": 2 * a.steps},
         "roofline": roof,
         "stage_ms_per_launch": {k: round(v, 5) for k, v in per_launch.items()},
+        "stage_ms_per_apply": {k: round(totals[k] / 10.0, 5) for k in totals},
+        "stage_algorithmic_GBps": gbs,
         "spectrum_ms": round(1e3 * r["t_spec"], 3),
     }
     if "fp64" in res and "fp32" in res:

@@ -13,11 +13,8 @@
 #include <vector>
 
 #include "../../include/lz.h"
+#include "lz_fft_ct.h"
 #include "lz_kernels.h"
-
-namespace lz {
-hipError_t enable_large_lds();
-}
 
 using namespace lz;
 
@@ -75,6 +72,25 @@ bool make_plan(int n, FftPlan& p, std::vector<double>& tw_re, std::vector<double
   p.n = n;
   p.npass = 0;
   int m = n, ns = 1;
+  if (ct_supported(n)) {
+    // the radix list the compile-time kernels were built with
+    for (int q = 0; q < ct_npass(n); ++q) {
+      const int r = ct_radix(n, q);
+      p.radix[p.npass] = r;
+      p.ns[p.npass] = ns;
+      p.twoff[p.npass] = (int)tw_re.size();
+      for (int k = 0; k < ns; ++k)
+        for (int t = 1; t < r; ++t) {
+          const double ang = -kTwoPi * (double)k * t / ((double)ns * r);
+          tw_re.push_back(std::cos(ang));
+          tw_im.push_back(std::sin(ang));
+        }
+      ns *= r;
+      m /= r;
+      p.npass++;
+    }
+    return m == 1;
+  }
   const int order[4] = {4, 3, 5, 2};
   for (int r : order) {
     while (m % r == 0) {
@@ -162,18 +178,21 @@ struct Instance {
   int max_steps;
   int S = 0, nact = 0;
   int ngroups = 1, gsize = 1;
-  int nchunk = 1, nlzblk = 1;
+  int ptot = 0;                // rows of the stacked projector array [U; beta]
+  int chunk = 32, nchunk = 1;  // split of the projector products over G
+  int nlzblk = 1;              // blocks of the output update (Lanczos partial sums)
   int64_t nvec;  // complex elements of one batch
   Grid3 grid;
   DBuf si1, si2, act, map_kq, map_k, perm, npw_kq;
   DBuf tw1, tw2, tw3;
   DBuf kin, eps, wk, bandw, vloc, fxc, khart;
   DBuf U, vkb, dkb;
+  DBuf Aio, Mkb, Rin, Cin, Rout, Cout;
   DBuf ur, y;
   DBuf X0, X1, LW;
   DBuf sa, sb;
   DBuf dpart, nr, work, vp;
-  DBuf dpartial, C;
+  DBuf dpartial;
   DBuf lzpart, st, beta, z;
   DBuf tin, tout, tin2, tout2;
   int steps_host = 0;
@@ -218,55 +237,95 @@ bool valid_len(int n) {
 // ---------------------------------------------------------------------------
 // operator application on one instance (internal order, stream-ordered)
 // ---------------------------------------------------------------------------
+// Input side of an application: R = [U; beta]^H x, the coefficients of the
+// separable term D (beta^H P_c x) and, with project, x <- P_c x.  With lw the
+// Lanczos update x <- a lw + b x is formed first (fused into the dot when one
+// block spans every row and band).
 template <typename T>
-void apply_pc(Instance& I, void* X, const LzDevState* st, hipStream_t s) {
+void input_side(Instance& I, void* x, const void* lw, bool project, const LzDevState* st,
+                hipStream_t s) {
+  const bool fuse = lw != nullptr && LaunchLin<T>::dot_single_tile(I.ptot, I.nbnd);
+  if (lw != nullptr && !fuse)
+    STAGE(I, ST_LANCZOS, s, LaunchLin<T>::lz_update(x, lw, I.nvec, st, s));
   STAGE(I, ST_PROJ, s,
-        Launch<T>::proj_dot(I.U.p, I.nbnd, X, I.nbnd, I.npwx, I.nks, I.dpartial.p, I.nchunk, I.C.p,
-                            nullptr, -1.0, st, s);
-        Launch<T>::proj_update(I.U.p, I.nbnd, I.C.p, X, I.nbnd, I.npwx, I.nks, st, s));
+        LaunchLin<T>::proj_dot(I.Aio.p, I.ptot, I.ptot, x, fuse ? lw : nullptr, I.nbnd, I.npwx,
+                               I.nks, I.chunk, I.nchunk, I.dpartial.p, I.Rin.p, st, s);
+        LaunchLin<T>::coef_in(I.Rin.p, I.Mkb.p, I.dkb.as<double>(), I.nbnd, I.nproj, I.nks,
+                              !project, I.Cin.p, st, s));
+  if (project)
+    STAGE(I, ST_PROJ, s,
+          LaunchLin<T>::proj_update(x, I.Aio.p, I.nbnd, I.ptot, I.Cin.p, I.ptot, I.nbnd, I.npwx,
+                                    I.nks, nullptr, nullptr, nullptr, nullptr, st, s));
 }
 
+// Output side: out <- P_c (out + beta D B), as out + [U; beta] C_out with
+// C_out = [-(U^H out + M^H D B); D B]; with lzpart also the Lanczos sums of
+// (x, out, y) per block.
 template <typename T>
-void apply_half(Instance& I, const void* in, void* out, bool upper, const LzDevState* st,
+void output_side(Instance& I, void* out, const void* x, double* lzpart, const LzDevState* st,
+                 hipStream_t s) {
+  STAGE(I, ST_PROJ, s,
+        LaunchLin<T>::proj_dot(I.Aio.p, I.nbnd, I.ptot, out, nullptr, I.nbnd, I.npwx, I.nks,
+                               I.chunk, I.nchunk, I.dpartial.p, I.Rout.p, st, s);
+        LaunchLin<T>::coef_out(I.Rout.p, I.Cin.p, I.Mkb.p, I.nbnd, I.nproj, I.nks, I.Cout.p, st, s);
+        LaunchLin<T>::proj_update(out, I.Aio.p, I.ptot, I.ptot, I.Cout.p, I.ptot, I.nbnd, I.npwx,
+                                  I.nks, x, I.y.p, I.wk.as<double>(), lzpart, st, s));
+}
+
+// FFT part of one half-application: out = (H_loc - eps) in (+ v'u for an
+// upper vector), before the projector terms.
+template <typename T>
+void apply_core(Instance& I, const void* in, void* out, bool upper, const LzDevState* st,
                 hipStream_t s) {
   const Grid3& g = I.grid;
   const int64_t xs = I.npwx;
-  STAGE(I, ST_ZINV, s, Launch<T>::zfft_inv(g, in, xs, I.sa.p, I.map_kq.as<int>(), I.nb, I.nbnd, st, s));
+  STAGE(I, ST_ZINV, s, LaunchFft<T>::zfft_inv(g, in, xs, I.sa.p, I.map_kq.as<int>(), I.nb, I.nbnd, st, s));
   if (upper && I.approx != LZ_IPA) {
     STAGE(I, ST_PLANE_DENS, s,
-          Launch<T>::plane_local_density(g, I.sa.p, I.sb.p, I.vloc.p, I.ur.p, I.bandw.as<double>(),
-                                         I.dpart.p, I.nb, I.gsize, st, s));
+          LaunchFft<T>::plane_local_density(g, I.sa.p, I.sb.p, I.vloc.p, I.ur.p,
+                                            I.bandw.as<double>(), I.dpart.p, I.nb, I.gsize, st, s));
     STAGE(I, ST_HXC, s,
-          Launch<T>::hxc(g, I.dpart.p, I.ngroups, I.nr.p, I.work.p, I.khart.p, I.fxc.p,
-                         I.approx == LZ_TDDFT, I.vp.p, st, s));
-    STAGE(I, ST_PLANE_VU, s, Launch<T>::plane_vu(g, I.ur.p, I.vp.p, I.sb.p, I.nb, st, s));
+          LaunchFft<T>::hxc(g, I.dpart.p, I.ngroups, I.nr.p, I.work.p, I.khart.p, I.fxc.p,
+                            I.approx == LZ_TDDFT, I.vp.p, st, s));
+    STAGE(I, ST_PLANE_VU, s, LaunchFft<T>::plane_vu(g, I.ur.p, I.vp.p, I.sb.p, I.nb, st, s));
   } else {
-    STAGE(I, ST_PLANE, s, Launch<T>::plane_local(g, I.sa.p, I.sb.p, I.vloc.p, I.nb, st, s));
+    STAGE(I, ST_PLANE, s, LaunchFft<T>::plane_local(g, I.sa.p, I.sb.p, I.vloc.p, I.nb, st, s));
   }
   STAGE(I, ST_ZFWD, s,
-        Launch<T>::zfft_fwd(g, I.sb.p, in, xs, out, I.map_kq.as<int>(), I.kin.p, I.eps.as<double>(),
-                            I.nb, I.nbnd, I.npwx, st, s));
-  if (I.nproj > 0) {
-    STAGE(I, ST_PROJ, s,
-          Launch<T>::proj_dot(I.vkb.p, I.nproj, in, I.nbnd, I.npwx, I.nks, I.dpartial.p, I.nchunk,
-                              I.C.p, I.dkb.as<double>(), 0.0, st, s);
-          Launch<T>::proj_update(I.vkb.p, I.nproj, I.C.p, out, I.nbnd, I.npwx, I.nks, st, s));
-  }
-  apply_pc<T>(I, out, st, s);
+        LaunchFft<T>::zfft_fwd(g, I.sb.p, in, xs, out, I.map_kq.as<int>(), I.kin.p,
+                               I.eps.as<double>(), I.nb, I.nbnd, I.npwx, st, s));
 }
 
+// One operator application on a vector the caller owns: D (lower) or D+K
+// (upper) with P_c on the output only.
+template <typename T>
+void apply_half(Instance& I, void* in, void* out, bool upper, hipStream_t s) {
+  input_side<T>(I, in, nullptr, false, nullptr, s);
+  apply_core<T>(I, in, out, upper, nullptr, s);
+  output_side<T>(I, out, nullptr, nullptr, nullptr, s);
+}
+
+// P_c on a vector (set-up of the right-hand side)
+template <typename T>
+void project_c(Instance& I, void* x, hipStream_t s) {
+  LaunchLin<T>::proj_dot(I.Aio.p, I.nbnd, I.ptot, x, nullptr, I.nbnd, I.npwx, I.nks, I.chunk,
+                         I.nchunk, I.dpartial.p, I.Rin.p, nullptr, s);
+  LaunchLin<T>::coef_in(I.Rin.p, I.Mkb.p, I.dkb.as<double>(), I.nbnd, 0, I.nks, false, I.Cin.p,
+                        nullptr, s);
+  LaunchLin<T>::proj_update(x, I.Aio.p, I.nbnd, I.ptot, I.Cin.p, I.nbnd, I.nbnd, I.npwx, I.nks,
+                            nullptr, nullptr, nullptr, nullptr, nullptr, s);
+}
+
+// Lanczos step j: w_j = a LW + b w_{j-2} (j > 0), w_j <- P_c w_j, LW = L w_j,
+// then beta_{j+1}, z_{j+1} from the fused sums.
 template <typename T>
 void lanczos_step(Instance& I, int j, hipStream_t s) {
   LzDevState* st = I.st.as<LzDevState>();
   void* X = (j & 1) ? I.X1.p : I.X0.p;
-  if (j > 0) {
-    STAGE(I, ST_LANCZOS, s, Launch<T>::lz_update(X, I.LW.p, I.nvec, st, s));
-    apply_pc<T>(I, X, st, s);
-  }
-  apply_half<T>(I, X, I.LW.p, (j & 1) != 0, st, s);
+  input_side<T>(I, X, j > 0 ? I.LW.p : nullptr, j > 0, st, s);
+  apply_core<T>(I, X, I.LW.p, (j & 1) != 0, st, s);
+  output_side<T>(I, I.LW.p, X, I.lzpart.as<double>(), st, s);
   STAGE(I, ST_LANCZOS, s,
-        Launch<T>::lz_dots(X, I.LW.p, I.y.p, I.wk.as<double>(), I.nbnd, I.npwx, I.nks,
-                           I.lzpart.as<double>(), I.nlzblk, st, s);
         launch_lz_finalize(I.lzpart.as<double>(), I.nlzblk, st, I.beta.as<double>(),
                            I.z.as<double>(), I.max_steps, kBreakdownTol, (double)I.nbnd, s));
 }
@@ -275,19 +334,21 @@ void lanczos_step(Instance& I, int j, hipStream_t s) {
 // construction of one instance
 // ---------------------------------------------------------------------------
 template <typename T>
-void build_device_tables(Instance& I, const lz_system& sys, hipStream_t s,
-                         const std::vector<double>& evc_k_in, const std::vector<int>& map_k) {
-  (void)map_k;
+void build_device_tables(Instance& I, hipStream_t s, const std::vector<double>& evc_k_in) {
   // valence orbitals in real space: sphere (caller order) -> sticks -> planes
   DBuf uk;
-  std::vector<double> tmp(evc_k_in);
-  upload_cplx(I, uk, tmp);
-  Launch<T>::zfft_inv(I.grid, uk.p, I.npwx, I.sa.p, I.map_k.as<int>(), I.nb, I.nbnd, nullptr, s);
-  Launch<T>::plane_to_real(I.grid, I.sa.p, I.ur.p, I.nb, s);
-  // y = P_c (shifted u) ; then the Lanczos start vector X0 = y
-  apply_pc<T>(I, I.y.p, nullptr, s);
+  upload_cplx(I, uk, evc_k_in);
+  LaunchFft<T>::zfft_inv(I.grid, uk.p, I.npwx, I.sa.p, I.map_k.as<int>(), I.nb, I.nbnd, nullptr, s);
+  LaunchFft<T>::plane_to_real(I.grid, I.sa.p, I.ur.p, I.nb, s);
+  // M = beta^H U per k (fixed overlaps of the separable projectors)
+  if (I.nproj > 0) {
+    const void* beta = (const char*)I.Aio.p + (size_t)I.nbnd * I.npwx * I.csz;
+    LaunchLin<T>::proj_dot(beta, I.nproj, I.ptot, I.U.p, nullptr, I.nbnd, I.npwx, I.nks, I.chunk,
+                           I.nchunk, I.dpartial.p, I.Mkb.p, nullptr, s);
+  }
+  // y = P_c (shifted u)
+  project_c<T>(I, I.y.p, s);
   HIPC(hipStreamSynchronize(s));
-  (void)sys;
 }
 
 std::unique_ptr<Instance> build_instance(const lz_system& sys, const lz_options& opt,
@@ -532,10 +593,22 @@ std::unique_ptr<Instance> build_instance(const lz_system& sys, const lz_options&
   upload_real(I, I.khart, kh);
   upload_cplx(I, I.U, U);
   upload_cplx(I, I.y, Y);
-  if (I.nproj > 0) {
-    upload_cplx(I, I.vkb, VKB);
-    upload(I.dkb, dkb);
+  // stacked rows per k: U (nbnd rows) then beta (nproj rows)
+  I.ptot = I.nbnd + I.nproj;
+  {
+    std::vector<double> A(2 * (size_t)I.nks * I.ptot * I.npwx, 0.0);
+    for (int k = 0; k < I.nks; ++k) {
+      for (int n = 0; n < I.nbnd; ++n)
+        std::memcpy(&A[2 * (((size_t)k * I.ptot + n) * I.npwx)], &U[2 * (((size_t)k * I.nbnd + n) * I.npwx)],
+                    2 * sizeof(double) * I.npwx);
+      for (int p = 0; p < I.nproj; ++p)
+        std::memcpy(&A[2 * (((size_t)k * I.ptot + I.nbnd + p) * I.npwx)],
+                    &VKB[2 * (((size_t)k * I.nproj + p) * I.npwx)], 2 * sizeof(double) * I.npwx);
+    }
+    upload_cplx(I, I.Aio, A);
   }
+  if (I.nproj > 0) upload(I.dkb, dkb);
+  else I.dkb.alloc(sizeof(double));
   I.grid.n1 = I.n1; I.grid.n2 = I.n2; I.grid.n3 = I.n3;
   I.grid.S = I.S; I.grid.nact = I.nact; I.grid.pitch2 = I.n2 + 1;
   I.grid.si1 = I.si1.as<int>(); I.grid.si2 = I.si2.as<int>(); I.grid.act = I.act.as<int>();
@@ -548,24 +621,30 @@ std::unique_ptr<Instance> build_instance(const lz_system& sys, const lz_options&
   I.sa.alloc((size_t)I.nb * I.n3 * I.S * I.csz);
   I.sb.alloc((size_t)I.nb * I.n3 * I.S * I.csz);
   I.ur.alloc((size_t)I.nb * I.N * I.csz);
-  I.ngroups = std::max(1, std::min(I.nb, (512 + I.n3 - 1) / I.n3));
+  // band groups of the density pass: about four blocks per compute unit
+  I.ngroups = std::max(1, std::min(I.nb, (1024 + I.n3 - 1) / I.n3));
   I.gsize = (I.nb + I.ngroups - 1) / I.ngroups;
   I.ngroups = (I.nb + I.gsize - 1) / I.gsize;
   I.dpart.alloc((size_t)I.ngroups * I.N * I.csz);
   I.nr.alloc((size_t)I.N * I.csz);
   I.work.alloc((size_t)I.N * I.csz);
   I.vp.alloc((size_t)I.N * I.csz);
-  I.nchunk = (I.npwx + 511) / 512;
-  const int pmax = std::max(I.nbnd, I.nproj);
-  I.dpartial.alloc((size_t)I.nks * I.nchunk * pmax * I.nbnd * I.csz);
-  I.C.alloc((size_t)I.nks * pmax * I.nbnd * I.csz);
-  I.nlzblk = (int)std::min<int64_t>(512, std::max<int64_t>(1, (I.nvec + 1023) / 1024));
+  I.chunk = kProjChunk;
+  I.nchunk = (I.npwx + I.chunk - 1) / I.chunk;
+  I.dpartial.alloc((size_t)I.nks * I.nchunk * I.ptot * I.nbnd * I.csz);
+  I.Rin.alloc((size_t)I.nks * I.ptot * I.nbnd * I.csz);
+  I.Cin.alloc((size_t)I.nks * I.ptot * I.nbnd * I.csz);
+  I.Rout.alloc((size_t)I.nks * I.nbnd * I.nbnd * I.csz);
+  I.Cout.alloc((size_t)I.nks * I.ptot * I.nbnd * I.csz);
+  I.Mkb.alloc((size_t)I.nks * std::max(1, I.nproj) * I.nbnd * I.csz);
+  I.nlzblk = I.fp64 ? LaunchLin<double>::update_blocks(I.nbnd, I.npwx, I.nks)
+                    : LaunchLin<float>::update_blocks(I.nbnd, I.npwx, I.nks);
   I.lzpart.alloc((size_t)I.nlzblk * 3 * sizeof(double));
   I.st.alloc(sizeof(LzDevState));
   I.beta.alloc((size_t)I.max_steps * sizeof(double));
   I.z.alloc((size_t)I.max_steps * 2 * sizeof(double));
-  if (I.fp64) build_device_tables<double>(I, sys, s, EK, map_k);
-  else build_device_tables<float>(I, sys, s, EK, map_k);
+  if (I.fp64) build_device_tables<double>(I, s, EK);
+  else build_device_tables<float>(I, s, EK);
   return Ip;
 }
 
@@ -665,7 +744,8 @@ lz_status lz_init(const lz_system* sys, int32_t n_inst, const lz_options* opt, i
     HIPC(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
     HIPC(hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming));
     HIPC(hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming));
-    HIPC(enable_large_lds());
+    HIPC(enable_large_lds_fft<double>());
+    HIPC(enable_large_lds_fft<float>());
     c->enter();
     for (int i = 0; i < n_inst; ++i) c->inst.push_back(build_instance(sys[i], *opt, c->stream));
     start_recursion(c.get());
@@ -695,25 +775,25 @@ lz_status lz_apply_liouvillian(lz_ctx* c, const void* q_in, const void* p_in, vo
       void* po = atw(p_out);
       if (I.fp64) {
         if (pi) {
-          Launch<double>::perm_in(pi, I.tin.p, I.perm.as<int>(), I.npw_kq.as<int>(), I.nks, I.nbnd, I.npwx, c->stream);
-          apply_half<double>(I, I.tin.p, I.tout.p, false, nullptr, c->stream);
-          Launch<double>::perm_out(I.tout.p, qo, I.perm.as<int>(), I.npw_kq.as<int>(), I.nks, I.nbnd, I.npwx, c->stream);
+          LaunchLin<double>::perm_in(pi, I.tin.p, I.perm.as<int>(), I.npw_kq.as<int>(), I.nks, I.nbnd, I.npwx, c->stream);
+          apply_half<double>(I, I.tin.p, I.tout.p, false, c->stream);
+          LaunchLin<double>::perm_out(I.tout.p, qo, I.perm.as<int>(), I.npw_kq.as<int>(), I.nks, I.nbnd, I.npwx, c->stream);
         }
         if (qi) {
-          Launch<double>::perm_in(qi, I.tin2.p, I.perm.as<int>(), I.npw_kq.as<int>(), I.nks, I.nbnd, I.npwx, c->stream);
-          apply_half<double>(I, I.tin2.p, I.tout2.p, true, nullptr, c->stream);
-          Launch<double>::perm_out(I.tout2.p, po, I.perm.as<int>(), I.npw_kq.as<int>(), I.nks, I.nbnd, I.npwx, c->stream);
+          LaunchLin<double>::perm_in(qi, I.tin2.p, I.perm.as<int>(), I.npw_kq.as<int>(), I.nks, I.nbnd, I.npwx, c->stream);
+          apply_half<double>(I, I.tin2.p, I.tout2.p, true, c->stream);
+          LaunchLin<double>::perm_out(I.tout2.p, po, I.perm.as<int>(), I.npw_kq.as<int>(), I.nks, I.nbnd, I.npwx, c->stream);
         }
       } else {
         if (pi) {
-          Launch<float>::perm_in(pi, I.tin.p, I.perm.as<int>(), I.npw_kq.as<int>(), I.nks, I.nbnd, I.npwx, c->stream);
-          apply_half<float>(I, I.tin.p, I.tout.p, false, nullptr, c->stream);
-          Launch<float>::perm_out(I.tout.p, qo, I.perm.as<int>(), I.npw_kq.as<int>(), I.nks, I.nbnd, I.npwx, c->stream);
+          LaunchLin<float>::perm_in(pi, I.tin.p, I.perm.as<int>(), I.npw_kq.as<int>(), I.nks, I.nbnd, I.npwx, c->stream);
+          apply_half<float>(I, I.tin.p, I.tout.p, false, c->stream);
+          LaunchLin<float>::perm_out(I.tout.p, qo, I.perm.as<int>(), I.npw_kq.as<int>(), I.nks, I.nbnd, I.npwx, c->stream);
         }
         if (qi) {
-          Launch<float>::perm_in(qi, I.tin2.p, I.perm.as<int>(), I.npw_kq.as<int>(), I.nks, I.nbnd, I.npwx, c->stream);
-          apply_half<float>(I, I.tin2.p, I.tout2.p, true, nullptr, c->stream);
-          Launch<float>::perm_out(I.tout2.p, po, I.perm.as<int>(), I.npw_kq.as<int>(), I.nks, I.nbnd, I.npwx, c->stream);
+          LaunchLin<float>::perm_in(qi, I.tin2.p, I.perm.as<int>(), I.npw_kq.as<int>(), I.nks, I.nbnd, I.npwx, c->stream);
+          apply_half<float>(I, I.tin2.p, I.tout2.p, true, c->stream);
+          LaunchLin<float>::perm_out(I.tout2.p, po, I.perm.as<int>(), I.npw_kq.as<int>(), I.nks, I.nbnd, I.npwx, c->stream);
         }
       }
       off += (size_t)I.nvec;
@@ -816,8 +896,8 @@ lz_status lz_get_rhs(lz_ctx* c, int32_t inst, void* y_out) {
     HIPC(hipSetDevice(c->device));
     c->enter();
     Instance& I = *c->inst[inst];
-    if (I.fp64) Launch<double>::perm_out(I.y.p, y_out, I.perm.as<int>(), I.npw_kq.as<int>(), I.nks, I.nbnd, I.npwx, c->stream);
-    else Launch<float>::perm_out(I.y.p, y_out, I.perm.as<int>(), I.npw_kq.as<int>(), I.nks, I.nbnd, I.npwx, c->stream);
+    if (I.fp64) LaunchLin<double>::perm_out(I.y.p, y_out, I.perm.as<int>(), I.npw_kq.as<int>(), I.nks, I.nbnd, I.npwx, c->stream);
+    else LaunchLin<float>::perm_out(I.y.p, y_out, I.perm.as<int>(), I.npw_kq.as<int>(), I.nks, I.nbnd, I.npwx, c->stream);
     HIPC(hipGetLastError());
     c->leave();
   });

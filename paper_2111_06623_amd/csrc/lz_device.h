@@ -53,7 +53,9 @@ struct FftPlan {
   int twoff[kMaxPass];
 };
 
-// radix-R DFT of v[0..R-1] in place; DIR = -1 forward (exp(-i..)), +1 inverse
+// radix-R DFT of v[0..R-1] in place; DIR = -1 forward (exp(-i..)), +1 inverse.
+// Radices 8 and 16 (compile-time plans only) are defined in lz_fft_ct.h; the
+// runtime plans of the general form use 4, 3, 5 and 2.
 template <typename T, int R, int DIR> struct Dft;
 
 template <typename T, int DIR> struct Dft<T, 2, DIR> {

@@ -1,0 +1,741 @@
+// FFT-based kernels of the Liouvillian application (Secs. 2.3-2.4 of the
+// turboEELS paper): the local part of H_{k+q}, the response density, the
+// Hartree + ALDA response potential and v'u.  Included by one translation unit
+// per precision.
+//
+// Data layouts (per instance):
+//   sphere vectors   [k][band][npwx] complex, plane waves in stick-major order
+//                    (sorted by stick, then by z index): one stick is a run;
+//   sticks           [band][z][S] complex after the z-direction transform;
+//   real-space grids plane-major [z][i1][i2].
+// A band's 3-D transform is a z pass over the S sticks that touch the sphere
+// (about a fifth of the N1*N2 columns) and a 2-D pass per z-plane held in
+// LDS, in which only the rows carrying a stick are transformed along i2.
+//
+// Every kernel has two forms selected by the template argument N: N > 0 is
+// the compile-time form for cubic grids N^3 with a plan in lz_fft_ct.h, N = 0
+// the general form driven by runtime plans.  Both run 256 threads per block.
+// Every reduction has a fixed order, so repeated runs are bitwise identical.
+#pragma once
+#include "lz_fft_ct.h"
+#include "lz_kernels.h"
+
+namespace lz {
+
+template <typename T>
+__device__ __forceinline__ cplx<T> czero() { return mk<T>(T(0), T(0)); }
+
+struct PlaneArgs {
+  int n1, n2, n3, S, nact, pitch;
+  const int* si1;
+  const int* si2;
+  const int* act;
+  FftPlan p1, p2;
+};
+
+// LDS of a plane kernel: plane [n1][n2+1], then (compile-time form) the
+// twiddle table and the list of active rows.
+template <typename T, int N>
+struct PlaneShm {
+  cplx<T>* plane;
+  const cplx<T>* tw;  // compile-time form: LDS copy; general form: unused
+  const int* act;     // active rows (LDS copy in the compile-time form)
+  __device__ __forceinline__ PlaneShm(unsigned char* raw, const PlaneArgs& a, const void* twg,
+                                      int tid) {
+    plane = reinterpret_cast<cplx<T>*>(raw);
+    if constexpr (N > 0) {
+      constexpr int P = N + 1;
+      cplx<T>* t = plane + N * P;
+      int* r = reinterpret_cast<int*>(t + ct_twsize(N));
+      const cplx<T>* tg = reinterpret_cast<const cplx<T>*>(twg);
+      for (int i = tid; i < ct_twsize(N); i += 256) t[i] = tg[i];
+      for (int i = tid; i < a.nact; i += 256) r[i] = a.act[i];
+      tw = t;
+      act = r;
+    } else {
+      tw = nullptr;
+      act = a.act;
+    }
+  }
+};
+
+template <typename T, int N>
+__host__ __device__ constexpr size_t plane_shm_bytes_ct() {
+  return (size_t)(N * (N + 1) + ct_twsize(N)) * sizeof(cplx<T>) + (size_t)N * sizeof(int);
+}
+
+// 1-D transforms of a plane: rows listed in act (along i2) or all columns
+// (along i1); for the general form tw1/tw2 are the runtime tables.
+template <typename T, int N, int MP, int DIR>
+__device__ __forceinline__ void plane_rows(const PlaneShm<T, N>& sh, const PlaneArgs& a, int nrows,
+                                           bool listed, const cplx<T>* tw2, int tid) {
+  if constexpr (N > 0) {
+    if (listed) ct_fft<T, N, DIR, N>(sh.plane, LayRows<N + 1>{sh.act}, nrows, sh.tw, tid);
+    else ct_fft<T, N, DIR, N>(sh.plane, LayRowsAll<N + 1>{}, nrows, sh.tw, tid);
+  } else {
+    fft_lds<T, MP, DIR>(sh.plane, Lay{1, a.pitch, listed ? sh.act : nullptr}, a.p2, nrows, tw2, tid, 256);
+  }
+}
+
+template <typename T, int N, int MP, int DIR>
+__device__ __forceinline__ void plane_cols(const PlaneShm<T, N>& sh, const PlaneArgs& a,
+                                           const cplx<T>* tw1, int tid) {
+  if constexpr (N > 0) {
+    ct_fft<T, N, DIR, N>(sh.plane, LayCols<N + 1>{}, N, sh.tw, tid);
+  } else {
+    fft_lds<T, MP, DIR>(sh.plane, Lay{a.pitch, 1, nullptr}, a.p1, a.n2, tw1, tid, 256);
+  }
+}
+
+template <typename T, int N>
+__device__ __forceinline__ void plane_zero_scatter(const PlaneShm<T, N>& sh, const PlaneArgs& a,
+                                                   const cplx<T>* __restrict__ src, int tid) {
+  const int n1 = N > 0 ? N : a.n1;
+  const int pitch = N > 0 ? N + 1 : a.pitch;
+  for (int t = tid; t < n1 * pitch; t += 256) sh.plane[t] = czero<T>();
+  __syncthreads();
+  for (int s = tid; s < a.S; s += 256) sh.plane[a.si1[s] * pitch + a.si2[s]] = src[s];
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// z pass, inverse: sphere -> sticks
+// ---------------------------------------------------------------------------
+template <typename T, int N>
+__device__ __forceinline__ void stick_fft(cplx<T>* lds, int pitch, const FftPlan& pz, int nst,
+                                          const cplx<T>* tw, int tid, int dir) {
+  if constexpr (N > 0) {
+    if (dir > 0) ct_fft<T, N, +1, kStickTile>(lds, LayRowsAll<N + 1>{}, nst, tw, tid);
+    else ct_fft<T, N, -1, kStickTile>(lds, LayRowsAll<N + 1>{}, nst, tw, tid);
+  } else {
+    if (dir > 0) fft_lds<T, kStickMaxPt, +1>(lds, Lay{1, pitch, nullptr}, pz, nst, tw, tid, 256);
+    else fft_lds<T, kStickMaxPt, -1>(lds, Lay{1, pitch, nullptr}, pz, nst, tw, tid, 256);
+  }
+}
+
+// twiddles of the z plan: LDS copy behind the stick tile (compile-time form)
+template <typename T, int N>
+__device__ __forceinline__ const cplx<T>* stick_tw(cplx<T>* lds, const cplx<T>* twg, int tid) {
+  if constexpr (N > 0) {
+    cplx<T>* t = lds + kStickTile * (N + 1);
+    for (int i = tid; i < ct_twsize(N); i += 256) t[i] = twg[i];
+    return t;
+  } else {
+    return twg;
+  }
+}
+
+template <typename T, int N>
+__global__ __launch_bounds__(256) void k_zfft_inv(const cplx<T>* __restrict__ x, int64_t xs,
+                                                  cplx<T>* __restrict__ out,
+                                                  const int* __restrict__ map, int S, int n3_rt,
+                                                  int nbnd, FftPlan pz,
+                                                  const cplx<T>* __restrict__ twg,
+                                                  const LzDevState* st) {
+  if (st && st->status) return;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw);
+  const int n3 = N > 0 ? N : n3_rt;
+  const int b = blockIdx.y;
+  const int k = b / nbnd;
+  const int s0 = blockIdx.x * kStickTile;
+  const int nst = min(kStickTile, S - s0);
+  const int pitch = n3 + 1;
+  const int tid = threadIdx.x;
+  const cplx<T>* tw = stick_tw<T, N>(lds, twg, tid);
+  const cplx<T>* xb = x + b * xs;
+  const int* mp = map + ((int64_t)k * S + s0) * n3;
+  for (int t = tid; t < nst * n3; t += 256) {
+    const int ls = t / n3, z = t - ls * n3;
+    const int idx = mp[ls * n3 + z];
+    lds[ls * pitch + z] = idx >= 0 ? xb[idx] : czero<T>();
+  }
+  __syncthreads();
+  stick_fft<T, N>(lds, pitch, pz, nst, tw, tid, +1);
+  cplx<T>* ob = out + (int64_t)b * n3 * S + s0;
+  for (int t = tid; t < nst * n3; t += 256) {
+    const int z = t / nst, ls = t - z * nst;
+    ob[(int64_t)z * S + ls] = lds[ls * pitch + z];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// z pass, forward: sticks -> sphere; y = x_fft/N + (kin - eps) x
+// ---------------------------------------------------------------------------
+template <typename T, int N>
+__global__ __launch_bounds__(256) void k_zfft_fwd(const cplx<T>* __restrict__ sticks,
+                                                  const cplx<T>* __restrict__ x, int64_t xs,
+                                                  cplx<T>* __restrict__ y,
+                                                  const int* __restrict__ map,
+                                                  const T* __restrict__ kin,
+                                                  const double* __restrict__ eps, int S, int n3_rt,
+                                                  int nbnd, int npwx, T scale, FftPlan pz,
+                                                  const cplx<T>* __restrict__ twg,
+                                                  const LzDevState* st) {
+  if (st && st->status) return;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw);
+  const int n3 = N > 0 ? N : n3_rt;
+  const int b = blockIdx.y;
+  const int k = b / nbnd;
+  const int s0 = blockIdx.x * kStickTile;
+  const int nst = min(kStickTile, S - s0);
+  const int pitch = n3 + 1;
+  const int tid = threadIdx.x;
+  const cplx<T>* tw = stick_tw<T, N>(lds, twg, tid);
+  const cplx<T>* sb = sticks + (int64_t)b * n3 * S + s0;
+  for (int t = tid; t < nst * n3; t += 256) {
+    const int z = t / nst, ls = t - z * nst;
+    lds[ls * pitch + z] = sb[(int64_t)z * S + ls];
+  }
+  __syncthreads();
+  stick_fft<T, N>(lds, pitch, pz, nst, tw, tid, -1);
+  const int* mp = map + ((int64_t)k * S + s0) * n3;
+  const cplx<T>* xb = x + b * xs;
+  cplx<T>* yb = y + b * xs;
+  const T* kb = kin + (int64_t)k * npwx;
+  const T e = T(eps[b]);
+  for (int t = tid; t < nst * n3; t += 256) {
+    const int ls = t / n3, z = t - ls * n3;
+    const int idx = mp[ls * n3 + z];
+    if (idx >= 0) {
+      const cplx<T> f = lds[ls * pitch + z];
+      const cplx<T> xv = xb[idx];
+      const T d = kb[idx] - e;
+      yb[idx] = mk<T>(f.x * scale + d * xv.x, f.y * scale + d * xv.y);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// plane pass of a D step: x(r) = IFFT2 sticks, (V x)(r), FFT2 -> sticks
+// ---------------------------------------------------------------------------
+template <typename T, int N, int MP>
+__global__ __launch_bounds__(256) void k_plane_local(const cplx<T>* __restrict__ sin,
+                                                     cplx<T>* __restrict__ sout,
+                                                     const T* __restrict__ vloc, PlaneArgs a,
+                                                     const cplx<T>* __restrict__ tw1,
+                                                     const cplx<T>* __restrict__ tw2,
+                                                     const LzDevState* st) {
+  if (st && st->status) return;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int tid = threadIdx.x;
+  PlaneShm<T, N> sh(smem_raw, a, tw1, tid);
+  const int n1 = N > 0 ? N : a.n1, n2 = N > 0 ? N : a.n2, n3 = N > 0 ? N : a.n3;
+  const int pitch = N > 0 ? N + 1 : a.pitch;
+  const int z = blockIdx.x, b = blockIdx.y;
+  const int64_t so = ((int64_t)b * n3 + z) * a.S;
+  plane_zero_scatter<T, N>(sh, a, sin + so, tid);
+  plane_rows<T, N, MP, +1>(sh, a, a.nact, true, tw2, tid);
+  plane_cols<T, N, MP, +1>(sh, a, tw1, tid);
+  const T* vz = vloc + (int64_t)z * n1 * n2;
+  for (int p = tid; p < n1 * n2; p += 256) {
+    const int i1 = p / n2, i2 = p - i1 * n2;
+    cplx<T>& c = sh.plane[i1 * pitch + i2];
+    c = cscale<T>(c, vz[p]);
+  }
+  __syncthreads();
+  plane_cols<T, N, MP, -1>(sh, a, tw1, tid);
+  plane_rows<T, N, MP, -1>(sh, a, a.nact, true, tw2, tid);
+  for (int s = tid; s < a.S; s += 256) sout[so + s] = sh.plane[a.si1[s] * pitch + a.si2[s]];
+}
+
+// ---------------------------------------------------------------------------
+// plane pass of a D+K step: as above for a group of bands, accumulating the
+// response density  n'(r) += (4 w_k / Omega) conj(u_b(r)) x_b(r)  (raw values
+// of u and x, i.e. without the Omega^-1/2 factors, which bandw absorbs).
+// ---------------------------------------------------------------------------
+template <typename T, int N, int MP>
+__global__ __launch_bounds__(256) void k_plane_local_density(
+    const cplx<T>* __restrict__ sin, cplx<T>* __restrict__ sout, const T* __restrict__ vloc,
+    const cplx<T>* __restrict__ ur, const double* __restrict__ bandw, cplx<T>* __restrict__ dpart,
+    int nb, int gsize, PlaneArgs a, const cplx<T>* __restrict__ tw1,
+    const cplx<T>* __restrict__ tw2, const LzDevState* st) {
+  if (st && st->status) return;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int tid = threadIdx.x;
+  PlaneShm<T, N> sh(smem_raw, a, tw1, tid);
+  const int n1 = N > 0 ? N : a.n1, n2 = N > 0 ? N : a.n2, n3 = N > 0 ? N : a.n3;
+  const int pitch = N > 0 ? N + 1 : a.pitch;
+  constexpr int ACC = N > 0 ? (N * N + 255) / 256 : MP;
+  const int z = blockIdx.x, g = blockIdx.y;
+  const int np = n1 * n2;
+  const T* vz = vloc + (int64_t)z * np;
+  cplx<T> acc[ACC];
+#pragma unroll
+  for (int i = 0; i < ACC; ++i) acc[i] = czero<T>();
+  const int b0 = g * gsize, b1 = min(nb, b0 + gsize);
+  for (int b = b0; b < b1; ++b) {
+    const int64_t so = ((int64_t)b * n3 + z) * a.S;
+    plane_zero_scatter<T, N>(sh, a, sin + so, tid);
+    plane_rows<T, N, MP, +1>(sh, a, a.nact, true, tw2, tid);
+    plane_cols<T, N, MP, +1>(sh, a, tw1, tid);
+    const cplx<T>* ub = ur + ((int64_t)b * n3 + z) * np;
+    const T wb = T(bandw[b]);
+#pragma unroll
+    for (int i = 0; i < ACC; ++i) {
+      const int p = tid + i * 256;
+      if (p < np) {
+        const int i1 = p / n2, i2 = p - i1 * n2;
+        cplx<T>& c = sh.plane[i1 * pitch + i2];
+        const cplx<T> d = cmulc<T>(ub[p], c);
+        acc[i].x += wb * d.x;
+        acc[i].y += wb * d.y;
+        c = cscale<T>(c, vz[p]);
+      }
+    }
+    __syncthreads();
+    plane_cols<T, N, MP, -1>(sh, a, tw1, tid);
+    plane_rows<T, N, MP, -1>(sh, a, a.nact, true, tw2, tid);
+    for (int s = tid; s < a.S; s += 256) sout[so + s] = sh.plane[a.si1[s] * pitch + a.si2[s]];
+    __syncthreads();
+  }
+  cplx<T>* dp = dpart + ((int64_t)g * n3 + z) * np;
+#pragma unroll
+  for (int i = 0; i < ACC; ++i) {
+    const int p = tid + i * 256;
+    if (p < np) dp[p] = acc[i];
+  }
+}
+
+// sticks -> real-space plane (set-up: valence orbitals in real space)
+template <typename T, int N, int MP>
+__global__ __launch_bounds__(256) void k_plane_to_real(const cplx<T>* __restrict__ sin,
+                                                       cplx<T>* __restrict__ rout, PlaneArgs a,
+                                                       const cplx<T>* __restrict__ tw1,
+                                                       const cplx<T>* __restrict__ tw2) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int tid = threadIdx.x;
+  PlaneShm<T, N> sh(smem_raw, a, tw1, tid);
+  const int n1 = N > 0 ? N : a.n1, n2 = N > 0 ? N : a.n2, n3 = N > 0 ? N : a.n3;
+  const int pitch = N > 0 ? N + 1 : a.pitch;
+  const int z = blockIdx.x, b = blockIdx.y;
+  const int np = n1 * n2;
+  plane_zero_scatter<T, N>(sh, a, sin + ((int64_t)b * n3 + z) * a.S, tid);
+  plane_rows<T, N, MP, +1>(sh, a, a.nact, true, tw2, tid);
+  plane_cols<T, N, MP, +1>(sh, a, tw1, tid);
+  cplx<T>* ro = rout + ((int64_t)b * n3 + z) * np;
+  for (int p = tid; p < np; p += 256) {
+    const int i1 = p / n2, i2 = p - i1 * n2;
+    ro[p] = sh.plane[i1 * pitch + i2];
+  }
+}
+
+// v'(r) u_b(r) -> FFT2 -> added to the sticks of the same band
+template <typename T, int N, int MP>
+__global__ __launch_bounds__(256) void k_plane_vu(const cplx<T>* __restrict__ ur,
+                                                  const cplx<T>* __restrict__ vp,
+                                                  cplx<T>* __restrict__ sout, PlaneArgs a,
+                                                  const cplx<T>* __restrict__ tw1,
+                                                  const cplx<T>* __restrict__ tw2,
+                                                  const LzDevState* st) {
+  if (st && st->status) return;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int tid = threadIdx.x;
+  PlaneShm<T, N> sh(smem_raw, a, tw1, tid);
+  const int n1 = N > 0 ? N : a.n1, n2 = N > 0 ? N : a.n2, n3 = N > 0 ? N : a.n3;
+  const int pitch = N > 0 ? N + 1 : a.pitch;
+  const int z = blockIdx.x, b = blockIdx.y;
+  const int np = n1 * n2;
+  const cplx<T>* ub = ur + ((int64_t)b * n3 + z) * np;
+  const cplx<T>* vz = vp + (int64_t)z * np;
+  for (int p = tid; p < np; p += 256) {
+    const int i1 = p / n2, i2 = p - i1 * n2;
+    sh.plane[i1 * pitch + i2] = cmul<T>(ub[p], vz[p]);
+  }
+  __syncthreads();
+  plane_cols<T, N, MP, -1>(sh, a, tw1, tid);
+  plane_rows<T, N, MP, -1>(sh, a, a.nact, true, tw2, tid);
+  const int64_t so = ((int64_t)b * n3 + z) * a.S;
+  for (int s = tid; s < a.S; s += 256) {
+    const cplx<T> v = sh.plane[a.si1[s] * pitch + a.si2[s]];
+    sout[so + s] = cadd<T>(sout[so + s], v);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// response Hartree + xc potential of one instance
+// ---------------------------------------------------------------------------
+// (1) n'(r) = sum over band groups (fixed order); 2-D forward transform
+template <typename T, int N, int MP>
+__global__ __launch_bounds__(256) void k_hxc_planes_fwd(const cplx<T>* __restrict__ dpart,
+                                                        int ngroups, cplx<T>* __restrict__ nr,
+                                                        cplx<T>* __restrict__ work, PlaneArgs a,
+                                                        const cplx<T>* __restrict__ tw1,
+                                                        const cplx<T>* __restrict__ tw2,
+                                                        const LzDevState* st) {
+  if (st && st->status) return;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int tid = threadIdx.x;
+  PlaneShm<T, N> sh(smem_raw, a, tw1, tid);
+  const int n1 = N > 0 ? N : a.n1, n2 = N > 0 ? N : a.n2, n3 = N > 0 ? N : a.n3;
+  const int pitch = N > 0 ? N + 1 : a.pitch;
+  const int z = blockIdx.x;
+  const int np = n1 * n2;
+  const int64_t plane = (int64_t)n3 * np;
+  for (int p = tid; p < np; p += 256) {
+    cplx<T> s = czero<T>();
+    for (int g = 0; g < ngroups; ++g) s = cadd<T>(s, dpart[g * plane + (int64_t)z * np + p]);
+    nr[(int64_t)z * np + p] = s;
+    const int i1 = p / n2, i2 = p - i1 * n2;
+    sh.plane[i1 * pitch + i2] = s;
+  }
+  __syncthreads();
+  plane_cols<T, N, MP, -1>(sh, a, tw1, tid);
+  plane_rows<T, N, MP, -1>(sh, a, n1, false, tw2, tid);
+  for (int p = tid; p < np; p += 256) {
+    const int i1 = p / n2, i2 = p - i1 * n2;
+    work[(int64_t)z * np + p] = sh.plane[i1 * pitch + i2];
+  }
+}
+
+// (2) along z: forward, times 4 pi / (|q+G|^2 N), inverse
+template <typename T, int N>
+__global__ __launch_bounds__(256) void k_hxc_z(cplx<T>* __restrict__ work,
+                                               const T* __restrict__ khart, int np, int n3_rt,
+                                               FftPlan pz, const cplx<T>* __restrict__ twg,
+                                               const LzDevState* st) {
+  if (st && st->status) return;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw);
+  const int n3 = N > 0 ? N : n3_rt;
+  const int c0 = blockIdx.x * kColTile;
+  const int nc = min(kColTile, np - c0);
+  const int pitch = n3 + 1;
+  const int tid = threadIdx.x;
+  const cplx<T>* tw = stick_tw<T, N>(lds, twg, tid);
+  for (int t = tid; t < nc * n3; t += 256) {
+    const int z = t / nc, c = t - z * nc;
+    lds[c * pitch + z] = work[(int64_t)z * np + c0 + c];
+  }
+  __syncthreads();
+  stick_fft<T, N>(lds, pitch, pz, nc, tw, tid, -1);
+  for (int t = tid; t < nc * n3; t += 256) {
+    const int z = t / nc, c = t - z * nc;
+    cplx<T>& v = lds[c * pitch + z];
+    v = cscale<T>(v, khart[(int64_t)z * np + c0 + c]);
+  }
+  __syncthreads();
+  stick_fft<T, N>(lds, pitch, pz, nc, tw, tid, +1);
+  for (int t = tid; t < nc * n3; t += 256) {
+    const int z = t / nc, c = t - z * nc;
+    work[(int64_t)z * np + c0 + c] = lds[c * pitch + z];
+  }
+}
+
+// (3) 2-D inverse transform, v'(r) = v_H(r) + f_xc(r) n'(r)
+template <typename T, int N, int MP>
+__global__ __launch_bounds__(256) void k_hxc_planes_inv(const cplx<T>* __restrict__ work,
+                                                        const cplx<T>* __restrict__ nr,
+                                                        const T* __restrict__ fxc, int with_fxc,
+                                                        cplx<T>* __restrict__ vp, PlaneArgs a,
+                                                        const cplx<T>* __restrict__ tw1,
+                                                        const cplx<T>* __restrict__ tw2,
+                                                        const LzDevState* st) {
+  if (st && st->status) return;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int tid = threadIdx.x;
+  PlaneShm<T, N> sh(smem_raw, a, tw1, tid);
+  const int n1 = N > 0 ? N : a.n1, n2 = N > 0 ? N : a.n2;
+  const int pitch = N > 0 ? N + 1 : a.pitch;
+  const int z = blockIdx.x;
+  const int np = n1 * n2;
+  for (int p = tid; p < np; p += 256) {
+    const int i1 = p / n2, i2 = p - i1 * n2;
+    sh.plane[i1 * pitch + i2] = work[(int64_t)z * np + p];
+  }
+  __syncthreads();
+  plane_rows<T, N, MP, +1>(sh, a, n1, false, tw2, tid);
+  plane_cols<T, N, MP, +1>(sh, a, tw1, tid);
+  for (int p = tid; p < np; p += 256) {
+    const int i1 = p / n2, i2 = p - i1 * n2;
+    cplx<T> v = sh.plane[i1 * pitch + i2];
+    if (with_fxc) {
+      const cplx<T> n = nr[(int64_t)z * np + p];
+      const T f = fxc[(int64_t)z * np + p];
+      v.x += f * n.x;
+      v.y += f * n.y;
+    }
+    vp[(int64_t)z * np + p] = v;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// response potential on compile-time grids: the 3-D transform of the single
+// density grid runs as line passes of kLineTile lines per block (N^2/8
+// blocks per pass instead of N plane blocks), i2 and i1 here, z in k_hxc_z.
+// ---------------------------------------------------------------------------
+constexpr int kLineTile = 8;
+
+// n'(r) = sum over band groups (fixed order); forward transform along i2
+template <typename T, int N>
+__global__ __launch_bounds__(256) void k_hxc_l2_fwd(const cplx<T>* __restrict__ dpart, int ngroups,
+                                                    cplx<T>* __restrict__ nr,
+                                                    cplx<T>* __restrict__ work,
+                                                    const cplx<T>* __restrict__ twg,
+                                                    const LzDevState* st) {
+  if (st && st->status) return;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw);
+  constexpr int P = N + 1;
+  constexpr int64_t NG = (int64_t)N * N * N;
+  const int tid = threadIdx.x;
+  const cplx<T>* tw = stick_tw<T, N>(lds, twg, tid);
+  const int64_t l0 = (int64_t)blockIdx.x * kLineTile;
+  for (int t = tid; t < kLineTile * N; t += 256) {
+    const int ll = t / N, i = t - ll * N;
+    const int64_t idx = (l0 + ll) * N + i;
+    cplx<T> v = czero<T>();
+    for (int g = 0; g < ngroups; ++g) v = cadd<T>(v, dpart[g * NG + idx]);
+    nr[idx] = v;
+    lds[ll * P + i] = v;
+  }
+  __syncthreads();
+  ct_fft<T, N, -1, kStickTile>(lds, LayRowsAll<P>{}, kLineTile, tw, tid);
+  for (int t = tid; t < kLineTile * N; t += 256) {
+    const int ll = t / N, i = t - ll * N;
+    work[(l0 + ll) * N + i] = lds[ll * P + i];
+  }
+}
+
+// transform along i1 (lines (z, i2), stride N), in place
+template <typename T, int N, int DIR>
+__global__ __launch_bounds__(256) void k_hxc_l1(cplx<T>* __restrict__ work,
+                                                const cplx<T>* __restrict__ twg,
+                                                const LzDevState* st) {
+  if (st && st->status) return;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw);
+  constexpr int P = N + 1;
+  constexpr int TPZ = N / kLineTile;
+  const int tid = threadIdx.x;
+  const cplx<T>* tw = stick_tw<T, N>(lds, twg, tid);
+  const int z = blockIdx.x / TPZ;
+  const int i20 = (blockIdx.x - z * TPZ) * kLineTile;
+  cplx<T>* base = work + (int64_t)z * N * N + i20;
+  for (int t = tid; t < kLineTile * N; t += 256) {
+    const int i1 = t / kLineTile, ll = t - i1 * kLineTile;
+    lds[ll * P + i1] = base[i1 * N + ll];
+  }
+  __syncthreads();
+  ct_fft<T, N, DIR, kStickTile>(lds, LayRowsAll<P>{}, kLineTile, tw, tid);
+  for (int t = tid; t < kLineTile * N; t += 256) {
+    const int i1 = t / kLineTile, ll = t - i1 * kLineTile;
+    base[i1 * N + ll] = lds[ll * P + i1];
+  }
+}
+
+// inverse along i2, then v'(r) = v_H(r) + f_xc(r) n'(r)
+template <typename T, int N>
+__global__ __launch_bounds__(256) void k_hxc_l2_inv(const cplx<T>* __restrict__ work,
+                                                    const cplx<T>* __restrict__ nr,
+                                                    const T* __restrict__ fxc, int with_fxc,
+                                                    cplx<T>* __restrict__ vp,
+                                                    const cplx<T>* __restrict__ twg,
+                                                    const LzDevState* st) {
+  if (st && st->status) return;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw);
+  constexpr int P = N + 1;
+  const int tid = threadIdx.x;
+  const cplx<T>* tw = stick_tw<T, N>(lds, twg, tid);
+  const int64_t l0 = (int64_t)blockIdx.x * kLineTile;
+  for (int t = tid; t < kLineTile * N; t += 256) {
+    const int ll = t / N, i = t - ll * N;
+    lds[ll * P + i] = work[(l0 + ll) * N + i];
+  }
+  __syncthreads();
+  ct_fft<T, N, +1, kStickTile>(lds, LayRowsAll<P>{}, kLineTile, tw, tid);
+  for (int t = tid; t < kLineTile * N; t += 256) {
+    const int ll = t / N, i = t - ll * N;
+    const int64_t idx = (l0 + ll) * N + i;
+    cplx<T> v = lds[ll * P + i];
+    if (with_fxc) {
+      const cplx<T> n = nr[idx];
+      const T f = fxc[idx];
+      v.x += f * n.x;
+      v.y += f * n.y;
+    }
+    vp[idx] = v;
+  }
+}
+
+template <typename T, int N>
+static void hxc_lines(const Grid3& g, const void* dpart, int ngroups, void* nr, void* work,
+                      const void* khart, const void* fxc, bool with_fxc, void* vp,
+                      const LzDevState* st, hipStream_t s) {
+  const int nlb = N * N / kLineTile;
+  const size_t ll = (size_t)(kStickTile * (N + 1) + ct_twsize(N)) * sizeof(cplx<T>);
+  const cplx<T>* tw = (const cplx<T>*)g.tw1;
+  hipLaunchKernelGGL((k_hxc_l2_fwd<T, N>), dim3(nlb), dim3(256), ll, s, (const cplx<T>*)dpart,
+                     ngroups, (cplx<T>*)nr, (cplx<T>*)work, tw, st);
+  hipLaunchKernelGGL((k_hxc_l1<T, N, -1>), dim3(nlb), dim3(256), ll, s, (cplx<T>*)work, tw, st);
+  hipLaunchKernelGGL((k_hxc_z<T, N>), dim3(N * N / kColTile), dim3(256), ll, s, (cplx<T>*)work,
+                     (const T*)khart, N * N, N, g.p3, tw, st);
+  hipLaunchKernelGGL((k_hxc_l1<T, N, +1>), dim3(nlb), dim3(256), ll, s, (cplx<T>*)work, tw, st);
+  hipLaunchKernelGGL((k_hxc_l2_inv<T, N>), dim3(nlb), dim3(256), ll, s, (const cplx<T>*)work,
+                     (const cplx<T>*)nr, (const T*)fxc, with_fxc ? 1 : 0, (cplx<T>*)vp, tw, st);
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+static inline PlaneArgs plane_args(const Grid3& g) {
+  PlaneArgs a;
+  a.n1 = g.n1; a.n2 = g.n2; a.n3 = g.n3; a.S = g.S; a.nact = g.nact; a.pitch = g.pitch2;
+  a.si1 = g.si1; a.si2 = g.si2; a.act = g.act; a.p1 = g.p1; a.p2 = g.p2;
+  return a;
+}
+
+// compile-time size of a grid (0 = general form)
+static inline int ct_size(const Grid3& g) {
+  return (g.n1 == g.n2 && g.n2 == g.n3 && ct_supported(g.n1)) ? g.n1 : 0;
+}
+
+template <typename T> static size_t plane_lds(const Grid3& g) {
+  const int n = ct_size(g);
+  switch (n) {
+    case 24: return plane_shm_bytes_ct<T, 24>();
+    case 32: return plane_shm_bytes_ct<T, 32>();
+    case 48: return plane_shm_bytes_ct<T, 48>();
+    case 64: return plane_shm_bytes_ct<T, 64>();
+    default: return (size_t)g.n1 * g.pitch2 * sizeof(cplx<T>);
+  }
+}
+template <typename T> static size_t stick_lds(const Grid3& g) {
+  const int n = ct_size(g);
+  return (size_t)(kStickTile * (g.n3 + 1) + (n ? ct_twsize(n) : 0)) * sizeof(cplx<T>);
+}
+
+// dispatch a plane kernel on (N, MP)
+#define LZ_PLANE_LAUNCH(KERN, T, G, GRID, LDS, STREAM, ...)                                     \
+  do {                                                                                          \
+    switch (ct_size(G)) {                                                                       \
+      case 24: hipLaunchKernelGGL((KERN<T, 24, 0>), GRID, dim3(256), LDS, STREAM, __VA_ARGS__); break; \
+      case 32: hipLaunchKernelGGL((KERN<T, 32, 0>), GRID, dim3(256), LDS, STREAM, __VA_ARGS__); break; \
+      case 48: hipLaunchKernelGGL((KERN<T, 48, 0>), GRID, dim3(256), LDS, STREAM, __VA_ARGS__); break; \
+      case 64: hipLaunchKernelGGL((KERN<T, 64, 0>), GRID, dim3(256), LDS, STREAM, __VA_ARGS__); break; \
+      default:                                                                                  \
+        switch (plane_mp((G).n1, (G).n2)) {                                                     \
+          case 12: hipLaunchKernelGGL((KERN<T, 0, 12>), GRID, dim3(256), LDS, STREAM, __VA_ARGS__); break; \
+          case 24: hipLaunchKernelGGL((KERN<T, 0, 24>), GRID, dim3(256), LDS, STREAM, __VA_ARGS__); break; \
+          default: hipLaunchKernelGGL((KERN<T, 0, 36>), GRID, dim3(256), LDS, STREAM, __VA_ARGS__); break; \
+        }                                                                                       \
+    }                                                                                           \
+  } while (0)
+
+#define LZ_STICK_LAUNCH(KERN, T, G, GRID, LDS, STREAM, ...)                                   \
+  do {                                                                                        \
+    switch (ct_size(G)) {                                                                     \
+      case 24: hipLaunchKernelGGL((KERN<T, 24>), GRID, dim3(256), LDS, STREAM, __VA_ARGS__); break; \
+      case 32: hipLaunchKernelGGL((KERN<T, 32>), GRID, dim3(256), LDS, STREAM, __VA_ARGS__); break; \
+      case 48: hipLaunchKernelGGL((KERN<T, 48>), GRID, dim3(256), LDS, STREAM, __VA_ARGS__); break; \
+      case 64: hipLaunchKernelGGL((KERN<T, 64>), GRID, dim3(256), LDS, STREAM, __VA_ARGS__); break; \
+      default: hipLaunchKernelGGL((KERN<T, 0>), GRID, dim3(256), LDS, STREAM, __VA_ARGS__); break; \
+    }                                                                                         \
+  } while (0)
+
+template <typename T>
+void LaunchFft<T>::zfft_inv(const Grid3& g, const void* x, int64_t xs, void* sticks,
+                            const int* map, int nb, int nbnd, const LzDevState* st, hipStream_t s) {
+  dim3 grid((g.S + kStickTile - 1) / kStickTile, nb);
+  LZ_STICK_LAUNCH(k_zfft_inv, T, g, grid, stick_lds<T>(g), s, (const cplx<T>*)x, xs,
+                  (cplx<T>*)sticks, map, g.S, g.n3, nbnd, g.p3, (const cplx<T>*)g.tw3, st);
+}
+
+template <typename T>
+void LaunchFft<T>::zfft_fwd(const Grid3& g, const void* sticks, const void* x, int64_t xs, void* y,
+                            const int* map, const void* kin, const double* eps, int nb, int nbnd,
+                            int npwx, const LzDevState* st, hipStream_t s) {
+  dim3 grid((g.S + kStickTile - 1) / kStickTile, nb);
+  const T scale = T(1.0 / ((double)g.n1 * g.n2 * g.n3));
+  LZ_STICK_LAUNCH(k_zfft_fwd, T, g, grid, stick_lds<T>(g), s, (const cplx<T>*)sticks,
+                  (const cplx<T>*)x, xs, (cplx<T>*)y, map, (const T*)kin, eps, g.S, g.n3, nbnd,
+                  npwx, scale, g.p3, (const cplx<T>*)g.tw3, st);
+}
+
+template <typename T>
+void LaunchFft<T>::plane_local(const Grid3& g, const void* sin, void* sout, const void* vloc,
+                               int nb, const LzDevState* st, hipStream_t s) {
+  LZ_PLANE_LAUNCH(k_plane_local, T, g, dim3(g.n3, nb), plane_lds<T>(g), s, (const cplx<T>*)sin,
+                  (cplx<T>*)sout, (const T*)vloc, plane_args(g), (const cplx<T>*)g.tw1,
+                  (const cplx<T>*)g.tw2, st);
+}
+
+template <typename T>
+void LaunchFft<T>::plane_local_density(const Grid3& g, const void* sin, void* sout,
+                                       const void* vloc, const void* ur, const double* bandw,
+                                       void* dpart, int nb, int gsize, const LzDevState* st,
+                                       hipStream_t s) {
+  const int ng = (nb + gsize - 1) / gsize;
+  LZ_PLANE_LAUNCH(k_plane_local_density, T, g, dim3(g.n3, ng), plane_lds<T>(g), s,
+                  (const cplx<T>*)sin, (cplx<T>*)sout, (const T*)vloc, (const cplx<T>*)ur, bandw,
+                  (cplx<T>*)dpart, nb, gsize, plane_args(g), (const cplx<T>*)g.tw1,
+                  (const cplx<T>*)g.tw2, st);
+}
+
+template <typename T>
+void LaunchFft<T>::plane_to_real(const Grid3& g, const void* sin, void* rout, int nb,
+                                 hipStream_t s) {
+  LZ_PLANE_LAUNCH(k_plane_to_real, T, g, dim3(g.n3, nb), plane_lds<T>(g), s, (const cplx<T>*)sin,
+                  (cplx<T>*)rout, plane_args(g), (const cplx<T>*)g.tw1, (const cplx<T>*)g.tw2);
+}
+
+template <typename T>
+void LaunchFft<T>::plane_vu(const Grid3& g, const void* ur, const void* vp, void* sout, int nb,
+                            const LzDevState* st, hipStream_t s) {
+  LZ_PLANE_LAUNCH(k_plane_vu, T, g, dim3(g.n3, nb), plane_lds<T>(g), s, (const cplx<T>*)ur,
+                  (const cplx<T>*)vp, (cplx<T>*)sout, plane_args(g), (const cplx<T>*)g.tw1,
+                  (const cplx<T>*)g.tw2, st);
+}
+
+template <typename T>
+void LaunchFft<T>::hxc(const Grid3& g, const void* dpart, int ngroups, void* nr, void* work,
+                       const void* khart, const void* fxc, bool with_fxc, void* vp,
+                       const LzDevState* st, hipStream_t s) {
+  switch (ct_size(g)) {
+    case 24: return hxc_lines<T, 24>(g, dpart, ngroups, nr, work, khart, fxc, with_fxc, vp, st, s);
+    case 32: return hxc_lines<T, 32>(g, dpart, ngroups, nr, work, khart, fxc, with_fxc, vp, st, s);
+    case 48: return hxc_lines<T, 48>(g, dpart, ngroups, nr, work, khart, fxc, with_fxc, vp, st, s);
+    case 64: return hxc_lines<T, 64>(g, dpart, ngroups, nr, work, khart, fxc, with_fxc, vp, st, s);
+    default: break;
+  }
+  const int np = g.n1 * g.n2;
+  LZ_PLANE_LAUNCH(k_hxc_planes_fwd, T, g, dim3(g.n3), plane_lds<T>(g), s, (const cplx<T>*)dpart,
+                  ngroups, (cplx<T>*)nr, (cplx<T>*)work, plane_args(g), (const cplx<T>*)g.tw1,
+                  (const cplx<T>*)g.tw2, st);
+  const size_t zl = (size_t)(kColTile * (g.n3 + 1) + (ct_size(g) ? ct_twsize(ct_size(g)) : 0)) *
+                    sizeof(cplx<T>);
+  LZ_STICK_LAUNCH(k_hxc_z, T, g, dim3((np + kColTile - 1) / kColTile), zl, s, (cplx<T>*)work,
+                  (const T*)khart, np, g.n3, g.p3, (const cplx<T>*)g.tw3, st);
+  LZ_PLANE_LAUNCH(k_hxc_planes_inv, T, g, dim3(g.n3), plane_lds<T>(g), s, (const cplx<T>*)work,
+                  (const cplx<T>*)nr, (const T*)fxc, with_fxc ? 1 : 0, (cplx<T>*)vp,
+                  plane_args(g), (const cplx<T>*)g.tw1, (const cplx<T>*)g.tw2, st);
+}
+
+// Kernels whose LDS may exceed the default dynamic limit opt in once.
+template <typename T>
+hipError_t enable_large_lds_fft() {
+  const int big = 160 * 1024;
+#define LZ_LDS_ATTR(KERN)                                                                     \
+  {                                                                                           \
+    const void* fns[] = {(const void*)KERN<T, 0, 12>, (const void*)KERN<T, 0, 24>,            \
+                         (const void*)KERN<T, 0, 36>, (const void*)KERN<T, 24, 0>,            \
+                         (const void*)KERN<T, 32, 0>, (const void*)KERN<T, 48, 0>,            \
+                         (const void*)KERN<T, 64, 0>};                                        \
+    for (const void* f : fns) {                                                               \
+      hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, big); \
+      if (e != hipSuccess) return e;                                                          \
+    }                                                                                         \
+  }
+  LZ_LDS_ATTR(k_plane_local)
+  LZ_LDS_ATTR(k_plane_local_density)
+  LZ_LDS_ATTR(k_plane_to_real)
+  LZ_LDS_ATTR(k_plane_vu)
+  LZ_LDS_ATTR(k_hxc_planes_fwd)
+  LZ_LDS_ATTR(k_hxc_planes_inv)
+#undef LZ_LDS_ATTR
+  return hipSuccess;
+}
+
+}  // namespace lz

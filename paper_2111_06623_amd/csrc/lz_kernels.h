@@ -23,7 +23,7 @@ struct Grid3 {
   const void* tw3;
 };
 
-template <typename T> struct Launch {
+template <typename T> struct LaunchFft {
   // sphere (stick-major order of nb bands, band stride xs) -> sticks [b][z][S]
   static void zfft_inv(const Grid3& g, const void* x, int64_t xs, void* sticks, const int* map,
                        int nb, int nbnd, const LzDevState* st, hipStream_t s);
@@ -47,19 +47,28 @@ template <typename T> struct Launch {
   static void hxc(const Grid3& g, const void* dpart, int ngroups, void* nr, void* work,
                   const void* khart, const void* fxc, bool with_fxc, void* vp,
                   const LzDevState* st, hipStream_t s);
-  // C[k][p][n] = coef_p * sum_G conj(A[k][p][G]) X[k][n][G]
-  static void proj_dot(const void* A, int P, const void* X, int nbnd, int npwx, int nks,
-                       void* partial, int nchunk, void* C, const double* coef, double coef_const,
+};
+
+template <typename T> struct LaunchLin {
+  // R[k][p][n] = sum_G conj(A[k][p][G]) X[k][n][G], rows p < P of A (a_rows per k);
+  // with LW != null the dot first forms X <- a*LW + b*X (state coefficients)
+  static void proj_dot(const void* A, int P, int a_rows, void* X, const void* LW, int nbnd,
+                       int npwx, int nks, int chunk, int nchunk, void* partial, void* R,
                        const LzDevState* st, hipStream_t s);
-  // Y[k][n][G] += sum_p A[k][p][G] C[k][p][n]
-  static void proj_update(const void* A, int P, const void* C, void* Y, int nbnd, int npwx,
-                          int nks, const LzDevState* st, hipStream_t s);
+  static bool dot_single_tile(int P, int nbnd);
+  // update coefficients from the reduced overlaps (see lz_linalg.hip)
+  static void coef_in(const void* R, const void* M, const double* dkb, int nbnd, int nproj,
+                      int nks, bool skip_pc, void* C, const LzDevState* st, hipStream_t s);
+  static void coef_out(const void* Rout, const void* Cin, const void* M, int nbnd, int nproj,
+                       int nks, void* C, const LzDevState* st, hipStream_t s);
+  // Y[k][n][G] += sum_{p<P} A[k][p][G] C[k][p][n]; with lzpart the Lanczos
+  // sums of (X, Y, y) per block (update_blocks of them)
+  static void proj_update(void* Y, const void* A, int P, int a_rows, const void* C, int c_rows,
+                          int nbnd, int npwx, int nks, const void* X, const void* y,
+                          const double* wk, double* lzpart, const LzDevState* st, hipStream_t s);
+  static int update_blocks(int nbnd, int npwx, int nks);
   // Lanczos: w <- a*LW + b*w
   static void lz_update(void* w, const void* lw, int64_t n, const LzDevState* st, hipStream_t s);
-  // partial sums of Re<w,Lw>_w and <y,w>_w
-  static void lz_dots(const void* w, const void* lw, const void* y, const double* wk, int nbnd,
-                      int npwx, int nks, double* partial, int nblk, const LzDevState* st,
-                      hipStream_t s);
   // user order <-> internal order
   static void perm_in(const void* xu, void* xi, const int* perm, const int* npw, int nks, int nbnd,
                       int npwx, hipStream_t s);
@@ -68,6 +77,8 @@ template <typename T> struct Launch {
   static void copy(void* dst, const void* src, int64_t n, hipStream_t s);
 };
 
+template <typename T> hipError_t enable_large_lds_fft();
+
 void launch_lz_finalize(const double* partial, int nblk, LzDevState* st, double* beta, double* z,
                         int max_steps, double tol, double yscale, hipStream_t s);
 void launch_spectrum(const double* beta, const double* z, int m, const double* omega, int nw,
@@ -75,10 +86,10 @@ void launch_spectrum(const double* beta, const double* z, int m, const double* o
                      hipStream_t s);
 void launch_set_state(LzDevState* st, hipStream_t s);
 
-constexpr int kPlaneMaxPt = 12;   // complex values per thread per plane pass
 constexpr int kStickTile = 16;    // sticks per block in the z passes
 constexpr int kStickMaxPt = 8;
 constexpr int kColTile = 16;      // grid columns per block in the Hartree z pass
 int plane_mp(int n1, int n2);
+constexpr int kProjChunk = 64;  // plane waves per block of a projector product
 
 }  // namespace lz

@@ -1,0 +1,588 @@
+// Linear-algebra kernels of the Liouvillian application and of the
+// pseudo-Hermitian Lanczos recursion (Secs. 2.3-2.5 of the turboEELS paper):
+// projector products (P_c and separable projectors), Lanczos vector updates
+// and deterministic reductions, the spectrum solve, and layout permutations.
+#include "lz_kernels.h"
+
+namespace lz {
+
+// complex values per thread of a 256-thread plane pass (general form)
+int plane_mp(int n1, int n2) {
+  const int np = n1 * n2;
+  if (np <= 12 * 256) return 12;
+  if (np <= 24 * 256) return 24;
+  return 36;
+}
+
+template <typename T>
+__device__ __forceinline__ cplx<T> czero() { return mk<T>(T(0), T(0)); }
+
+// ---------------------------------------------------------------------------
+// Projector products.  Per k the rows of A are the valence orbitals U_{k+q}
+// (nbnd rows, P_c = 1 - U U^H) followed by the separable projectors beta
+// (nproj rows, V_NL = beta D beta^H), all on the k+q sphere.
+//
+//   dot     R[k][p][n]  = sum_G conj(A[k][p][G]) X[k][n][G]   (split over G,
+//                         partials summed in a fixed order by k_proj_reduce)
+//   coef    small per-k matrices turning R into update coefficients
+//   update  Y[k][n][G] += sum_p A[k][p][G] C[k][p][n]
+//
+// With S = U^H w, B' = beta^H w and M = beta^H U (fixed), the projector of
+// the separable term acting on P_c w is beta^H P_c w = B' - M S, and the
+// valence overlap of beta D B is U^H beta D B = M^H (D B); one pass over w
+// and one over the output then give P_c w, V_NL P_c w and P_c of the output.
+// ---------------------------------------------------------------------------
+constexpr int kDotK = 32;  // G per LDS tile
+
+// Block: 256 threads as 16 x 16; thread (ty, tx) owns outputs
+// (p0 + ty + 16 i, n0 + tx + 16 j), i < TPI, j < TNJ; one block covers
+// `chunk` plane waves of one k.  UPD: the block first forms the Lanczos
+// vector w = a*LW + b*X of its plane waves and writes it back to X (the
+// host uses UPD only when one block spans every row and band of a chunk).
+template <typename T, int TPI, int TNJ, bool UPD>
+__global__ __launch_bounds__(256) void k_proj_dot(const cplx<T>* __restrict__ A, int P,
+                                                  int a_rows, cplx<T>* X,
+                                                  const cplx<T>* __restrict__ LW, int nbnd,
+                                                  int npwx, int chunk, int nchunk,
+                                                  cplx<T>* __restrict__ partial,
+                                                  const LzDevState* st) {
+  if (st && st->status) return;
+  constexpr int TP = 16 * TPI, TN = 16 * TNJ;
+  __shared__ cplx<T> As[TP][kDotK + 1];
+  __shared__ cplx<T> Xs[TN][kDotK + 1];
+  const int ntn = (nbnd + TN - 1) / TN;
+  const int p0 = (blockIdx.x / ntn) * TP;
+  const int n0 = (blockIdx.x % ntn) * TN;
+  const int ci = blockIdx.y, k = blockIdx.z;
+  const int tid = threadIdx.x;
+  const int ty = tid / 16, tx = tid % 16;
+  T ua = T(0), ub = T(0);
+  if constexpr (UPD) {
+    ua = T(st->a);
+    ub = T(st->b);
+  }
+  cplx<T> acc[TPI][TNJ];
+#pragma unroll
+  for (int i = 0; i < TPI; ++i)
+#pragma unroll
+    for (int j = 0; j < TNJ; ++j) acc[i][j] = czero<T>();
+  const cplx<T>* Ak = A + (int64_t)k * a_rows * npwx;
+  cplx<T>* Xk = X + (int64_t)k * nbnd * npwx;
+  const cplx<T>* Lk = UPD ? LW + (int64_t)k * nbnd * npwx : nullptr;
+  const int g_end = min(npwx, (ci + 1) * chunk);
+  for (int g0 = ci * chunk; g0 < g_end; g0 += kDotK) {
+    for (int t = tid; t < TP * kDotK; t += 256) {
+      const int r = t / kDotK, c = t - r * kDotK;
+      const int g = g0 + c, p = p0 + r;
+      As[r][c] = (p < P && g < g_end) ? Ak[(int64_t)p * npwx + g] : czero<T>();
+    }
+    for (int t = tid; t < TN * kDotK; t += 256) {
+      const int r = t / kDotK, c = t - r * kDotK;
+      const int g = g0 + c, n = n0 + r;
+      cplx<T> v = czero<T>();
+      if (n < nbnd && g < g_end) {
+        const int64_t o = (int64_t)n * npwx + g;
+        v = Xk[o];
+        if constexpr (UPD) {
+          const cplx<T> l = Lk[o];
+          v = mk<T>(ua * l.x + ub * v.x, ua * l.y + ub * v.y);
+          Xk[o] = v;
+        }
+      }
+      Xs[r][c] = v;
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int c = 0; c < kDotK; ++c) {
+      cplx<T> a[TPI], x[TNJ];
+#pragma unroll
+      for (int i = 0; i < TPI; ++i) a[i] = As[ty + 16 * i][c];
+#pragma unroll
+      for (int j = 0; j < TNJ; ++j) x[j] = Xs[tx + 16 * j][c];
+#pragma unroll
+      for (int i = 0; i < TPI; ++i)
+#pragma unroll
+        for (int j = 0; j < TNJ; ++j) acc[i][j] = cadd<T>(acc[i][j], cmulc<T>(a[i], x[j]));
+    }
+    __syncthreads();
+  }
+  cplx<T>* out = partial + ((int64_t)k * nchunk + ci) * P * nbnd;
+#pragma unroll
+  for (int i = 0; i < TPI; ++i)
+#pragma unroll
+    for (int j = 0; j < TNJ; ++j) {
+      const int p = p0 + ty + 16 * i, n = n0 + tx + 16 * j;
+      if (p < P && n < nbnd) out[p * nbnd + n] = acc[i][j];
+    }
+}
+
+// R[k][i] = sum over chunks, accumulated in double in a fixed order: block
+// (16 outputs) x (16 lanes); lane l sums chunks l, l+16, ..., then the 16
+// lane sums are added in lane order.
+template <typename T>
+__global__ __launch_bounds__(256) void k_proj_reduce(const cplx<T>* __restrict__ partial,
+                                                     int nchunk, int PN, cplx<T>* __restrict__ R,
+                                                     const LzDevState* st) {
+  if (st && st->status) return;
+  __shared__ double rx[16][17], ry[16][17];
+  const int k = blockIdx.y;
+  const int o = threadIdx.x % 16, lane = threadIdx.x / 16;
+  const int i = blockIdx.x * 16 + o;
+  const cplx<T>* pk = partial + (int64_t)k * nchunk * PN;
+  double sx = 0.0, sy = 0.0;
+  if (i < PN) {
+#pragma unroll 4
+    for (int c = lane; c < nchunk; c += 16) {
+      const cplx<T> v = pk[(int64_t)c * PN + i];
+      sx += double(v.x);
+      sy += double(v.y);
+    }
+  }
+  rx[o][lane] = sx;
+  ry[o][lane] = sy;
+  __syncthreads();
+  if (lane == 0 && i < PN) {
+    double ax = 0.0, ay = 0.0;
+    for (int l = 0; l < 16; ++l) {
+      ax += rx[o][l];
+      ay += ry[o][l];
+    }
+    R[(int64_t)k * PN + i] = mk<T>(T(ax), T(ay));
+  }
+}
+
+// input side: R = [S; B'] (rows nbnd + nproj).  C_in = [-S; D (B' - M S)];
+// with skip_pc (the start vector, or an operator application on a vector the
+// caller did not project) S is not applied: C_in = [0; D B'].
+template <typename T>
+__global__ __launch_bounds__(256) void k_coef_in(const cplx<T>* __restrict__ R,
+                                                 const cplx<T>* __restrict__ M,
+                                                 const double* __restrict__ dkb, int nbnd,
+                                                 int nproj, int skip_pc, cplx<T>* __restrict__ C,
+                                                 const LzDevState* st) {
+  if (st && st->status) return;
+  const int k = blockIdx.y;
+  const int P = nbnd + nproj;
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= P * nbnd) return;
+  const int p = i / nbnd, n = i - p * nbnd;
+  const cplx<T>* Rk = R + (int64_t)k * P * nbnd;
+  cplx<T> out;
+  if (p < nbnd) {
+    out = skip_pc ? czero<T>() : mk<T>(-Rk[i].x, -Rk[i].y);
+  } else {
+    const int q = p - nbnd;
+    double ax = double(Rk[i].x), ay = double(Rk[i].y);
+    if (!skip_pc) {
+      const cplx<T>* Mq = M + ((int64_t)k * nproj + q) * nbnd;
+#pragma unroll 4
+      for (int m = 0; m < nbnd; ++m) {
+        const cplx<T> mm = Mq[m], s = Rk[m * nbnd + n];
+        ax -= double(mm.x) * double(s.x) - double(mm.y) * double(s.y);
+        ay -= double(mm.x) * double(s.y) + double(mm.y) * double(s.x);
+      }
+    }
+    const double d = dkb[q];
+    out = mk<T>(T(d * ax), T(d * ay));
+  }
+  C[(int64_t)k * P * nbnd + i] = out;
+}
+
+// output side: Rout = U^H Y (nbnd x nbnd), DB = rows nbnd.. of C_in.
+//   C_out = [-(Rout + M^H DB); DB]
+template <typename T>
+__global__ __launch_bounds__(256) void k_coef_out(const cplx<T>* __restrict__ Rout,
+                                                  const cplx<T>* __restrict__ Cin,
+                                                  const cplx<T>* __restrict__ M, int nbnd,
+                                                  int nproj, cplx<T>* __restrict__ C,
+                                                  const LzDevState* st) {
+  if (st && st->status) return;
+  const int k = blockIdx.y;
+  const int P = nbnd + nproj;
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= P * nbnd) return;
+  const int p = i / nbnd, n = i - p * nbnd;
+  const cplx<T>* Ck = Cin + (int64_t)k * P * nbnd;
+  cplx<T> out;
+  if (p < nbnd) {
+    const cplx<T> r = Rout[((int64_t)k * nbnd + p) * nbnd + n];
+    double ax = double(r.x), ay = double(r.y);
+#pragma unroll 4
+    for (int q = 0; q < nproj; ++q) {
+      const cplx<T> mm = M[((int64_t)k * nproj + q) * nbnd + p];   // conj taken below
+      const cplx<T> db = Ck[(nbnd + q) * nbnd + n];
+      ax += double(mm.x) * double(db.x) + double(mm.y) * double(db.y);
+      ay += double(mm.x) * double(db.y) - double(mm.y) * double(db.x);
+    }
+    out = mk<T>(T(-ax), T(-ay));
+  } else {
+    out = Ck[i];
+  }
+  C[(int64_t)k * P * nbnd + i] = out;
+}
+
+// Y[k][n][G] += sum_{p<P} A[k][p][G] C[k][p][n]; with DOTS the block also
+// accumulates the Lanczos sums of its elements,
+//   s0 = sum w_k Re(conj(X) Y_new),  s1 + i s2 = sum w_k conj(y) X,
+// into lzpart[block] (fixed order inside the block).
+template <typename T, int NBT, bool DOTS>
+__global__ __launch_bounds__(256) void k_proj_update(
+    cplx<T>* __restrict__ Y, const cplx<T>* __restrict__ A, int P, int a_rows,
+    const cplx<T>* __restrict__ C, int c_rows, int nbnd, int npwx,
+    const cplx<T>* __restrict__ X, const cplx<T>* __restrict__ yv, const double* __restrict__ wk,
+    double* __restrict__ lzpart, const LzDevState* st) {
+  if (st && st->status) return;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cplx<T>* Cs = reinterpret_cast<cplx<T>*>(smem_raw);  // [P][NBT]
+  __shared__ double red[3][256];
+  const int k = blockIdx.z;
+  const int n0 = blockIdx.y * NBT;
+  const int nbt = min(NBT, nbnd - n0);
+  const cplx<T>* Ck = C + (int64_t)k * c_rows * nbnd;
+  for (int t = threadIdx.x; t < P * NBT; t += 256) {
+    const int p = t / NBT, j = t - p * NBT;
+    Cs[t] = j < nbt ? Ck[p * nbnd + n0 + j] : czero<T>();
+  }
+  __syncthreads();
+  const int g = blockIdx.x * 256 + threadIdx.x;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+  if (g < npwx) {
+    const cplx<T>* Ak = A + (int64_t)k * a_rows * npwx;
+    cplx<T> acc[NBT];
+#pragma unroll
+    for (int j = 0; j < NBT; ++j) acc[j] = czero<T>();
+#pragma unroll 4
+    for (int p = 0; p < P; ++p) {
+      const cplx<T> a = Ak[(int64_t)p * npwx + g];
+#pragma unroll
+      for (int j = 0; j < NBT; ++j) acc[j] = cadd<T>(acc[j], cmul<T>(a, Cs[p * NBT + j]));
+    }
+    const int64_t kb = (int64_t)k * nbnd * npwx;
+    const double w = DOTS ? wk[k] : 0.0;
+#pragma unroll
+    for (int j = 0; j < NBT; ++j) {
+      if (j < nbt) {
+        const int64_t o = kb + (int64_t)(n0 + j) * npwx + g;
+        cplx<T> yv_new = cadd<T>(Y[o], acc[j]);
+        Y[o] = yv_new;
+        if constexpr (DOTS) {
+          const cplx<T> xv = X[o], rv = yv[o];
+          s0 += w * (double(xv.x) * double(yv_new.x) + double(xv.y) * double(yv_new.y));
+          s1 += w * (double(rv.x) * double(xv.x) + double(rv.y) * double(xv.y));
+          s2 += w * (double(rv.x) * double(xv.y) - double(rv.y) * double(xv.x));
+        }
+      }
+    }
+  }
+  if constexpr (DOTS) {
+    red[0][threadIdx.x] = s0;
+    red[1][threadIdx.x] = s1;
+    red[2][threadIdx.x] = s2;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+      if (threadIdx.x < h) {
+        red[0][threadIdx.x] += red[0][threadIdx.x + h];
+        red[1][threadIdx.x] += red[1][threadIdx.x + h];
+        red[2][threadIdx.x] += red[2][threadIdx.x + h];
+      }
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+      const int blk = (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+      lzpart[3 * blk + 0] = red[0][0];
+      lzpart[3 * blk + 1] = red[1][0];
+      lzpart[3 * blk + 2] = red[2][0];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Lanczos vectors and scalars
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_lz_update(cplx<T>* __restrict__ w, const cplx<T>* __restrict__ lw, int64_t n,
+                            const LzDevState* st) {
+  if (st->status) return;
+  const T a = T(st->a), b = T(st->b);
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const cplx<T> l = lw[i], v = w[i];
+    w[i] = mk<T>(a * l.x + b * v.x, a * l.y + b * v.y);
+  }
+}
+
+constexpr int kDotThreads = 256;
+
+// Sum the partials and take the scalar decisions of one Lanczos step:
+//   j = st->step; b2 = Re<w_j, L w_j>_w; beta_{j+1} = sqrt(b2);
+//   z_{j+1} = <y, w_j>_w / beta_{j+1} for odd j (upper vector), else 0.
+// Step 0 (w_0 = y) first checks for a vanished right-hand side.
+__global__ __launch_bounds__(256) void k_lz_finalize(const double* __restrict__ partial, int nblk,
+                              LzDevState* __restrict__ st, double* __restrict__ beta,
+                              double* __restrict__ z, int max_steps, double tol, double yscale) {
+  __shared__ double red[3][kDotThreads];
+  if (st->status) return;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+  for (int i = threadIdx.x; i < nblk; i += kDotThreads) {
+    s0 += partial[i * 3 + 0];
+    s1 += partial[i * 3 + 1];
+    s2 += partial[i * 3 + 2];
+  }
+  red[0][threadIdx.x] = s0;
+  red[1][threadIdx.x] = s1;
+  red[2][threadIdx.x] = s2;
+  __syncthreads();
+  for (int h = kDotThreads / 2; h > 0; h >>= 1) {
+    if (threadIdx.x < h) {
+      red[0][threadIdx.x] += red[0][threadIdx.x + h];
+      red[1][threadIdx.x] += red[1][threadIdx.x + h];
+      red[2][threadIdx.x] += red[2][threadIdx.x + h];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x != 0) return;
+  const double b2 = red[0][0], zr = red[1][0], zi = red[2][0];
+  const int j = st->step;
+  if (j >= max_steps) { st->status = 5; return; }
+  if (!isfinite(b2) || !isfinite(zr) || !isfinite(zi)) { st->status = 7; return; }
+  if (j == 0) {
+    if (zr <= tol * tol * yscale) { st->status = 6; return; }  // y = 0: chi vanishes
+    if (b2 <= 0.0) { st->status = 4; return; }
+    const double bt = sqrt(b2);
+    beta[0] = bt;
+    z[0] = 0.0;
+    z[1] = 0.0;
+    st->a = 1.0 / bt;
+    st->b = 0.0;
+    st->beta_prev = bt;
+    st->step = 1;
+    return;
+  }
+  const double bm = st->bmax;
+  if (b2 < -(tol * bm) * (tol * bm) || (b2 <= 0.0 && bm == 0.0)) { st->status = 4; return; }
+  if (b2 <= (tol * bm) * (tol * bm)) { st->status = 6; return; }
+  const double bt = sqrt(b2);
+  beta[j] = bt;
+  if (j & 1) {
+    z[2 * j] = zr / bt;
+    z[2 * j + 1] = zi / bt;
+  } else {
+    z[2 * j] = 0.0;
+    z[2 * j + 1] = 0.0;
+  }
+  st->bmax = bm > bt ? bm : bt;
+  st->a = 1.0 / bt;
+  st->b = -bt / st->beta_prev;
+  st->beta_prev = bt;
+  st->step = j + 1;
+}
+
+__global__ __launch_bounds__(256) void k_set_state(LzDevState* st) {
+  st->step = 0;
+  st->status = 0;
+  st->bmax = 0.0;
+  st->a = 0.0;
+  st->b = 0.0;
+  st->beta_prev = 0.0;
+}
+
+// ---------------------------------------------------------------------------
+// caller order <-> internal stick-major order
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_perm_in(const cplx<T>* __restrict__ xu, cplx<T>* __restrict__ xi,
+                          const int* __restrict__ perm, const int* __restrict__ npw, int nbnd,
+                          int npwx) {
+  const int b = blockIdx.y, k = b / nbnd;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= npwx) return;
+  const int64_t o = (int64_t)b * npwx;
+  xi[o + i] = i < npw[k] ? xu[o + perm[(int64_t)k * npwx + i]] : czero<T>();
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_perm_out(const cplx<T>* __restrict__ xi, cplx<T>* __restrict__ xu,
+                           const int* __restrict__ perm, const int* __restrict__ npw, int nbnd,
+                           int npwx) {
+  const int b = blockIdx.y, k = b / nbnd;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= npwx) return;
+  const int64_t o = (int64_t)b * npwx;
+  if (i < npw[k]) xu[o + perm[(int64_t)k * npwx + i]] = xi[o + i];
+  else xu[o + i] = czero<T>();
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_copy(cplx<T>* __restrict__ d, const cplx<T>* __restrict__ s, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    d[i] = s[i];
+}
+
+// ---------------------------------------------------------------------------
+// spectrum: one thread per frequency.  chi needs (z, (w~ - T)^-1 e_1), which
+// for symmetric T equals the first component of (w~ - T)^-1 z; eliminating
+// from the last row upwards, x_j = c_j x_{j-1} + d_j with
+//   den_j = w~ - beta_{j+1} c_{j+1},  c_j = beta_j / den_j,
+//   d_j = (z_j + beta_{j+1} d_{j+1}) / den_j,   x_1 = d_1.
+// |Im den_j| >= eta keeps every division away from zero.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double2 zdiv(double2 a, double2 b) {
+  const double d = b.x * b.x + b.y * b.y;
+  return make_double2((a.x * b.x + a.y * b.y) / d, (a.y * b.x - a.x * b.y) / d);
+}
+
+__global__ __launch_bounds__(256) void k_spectrum(const double* __restrict__ beta, const double* __restrict__ z, int m,
+                           const double* __restrict__ omega, int nw, double eta, double pref,
+                           double fq, double* __restrict__ chi, double* __restrict__ einv,
+                           double* __restrict__ loss) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nw) return;
+  const double2 wt = make_double2(omega[i], eta);
+  double2 c = make_double2(0.0, 0.0), d = make_double2(0.0, 0.0);
+  for (int j = m; j >= 1; --j) {
+    const double bnext = j < m ? beta[j] : 0.0;  // beta_{j+1}
+    const double2 den = make_double2(wt.x - bnext * c.x, wt.y - bnext * c.y);
+    const double2 num = make_double2(z[2 * (j - 1)] + bnext * d.x, z[2 * (j - 1) + 1] + bnext * d.y);
+    d = zdiv(num, den);
+    c = zdiv(make_double2(beta[j - 1], 0.0), den);
+  }
+  double2 ch = make_double2(0.0, 0.0);
+  if (m > 0) ch = make_double2(pref * beta[0] * d.x, pref * beta[0] * d.y);
+  chi[2 * i] = ch.x;
+  chi[2 * i + 1] = ch.y;
+  einv[2 * i] = 1.0 + fq * ch.x;
+  einv[2 * i + 1] = fq * ch.y;
+  loss[i] = -fq * ch.y;
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+template <typename T>
+void LaunchLin<T>::proj_dot(const void* A, int P, int a_rows, void* X, const void* LW, int nbnd,
+                            int npwx, int nks, int chunk, int nchunk, void* partial, void* R,
+                            const LzDevState* st, hipStream_t s) {
+  const int tpi = P <= 16 ? 1 : P <= 32 ? 2 : P <= 48 ? 3 : 4;
+  const int tnj = nbnd <= 16 ? 1 : 2;
+  const int tiles = ((P + 16 * tpi - 1) / (16 * tpi)) * ((nbnd + 16 * tnj - 1) / (16 * tnj));
+  const bool upd = LW != nullptr;
+  dim3 grid(tiles, nchunk, nks);
+#define LZ_DOT(TPI, TNJ)                                                                       \
+  if (upd)                                                                                     \
+    hipLaunchKernelGGL((k_proj_dot<T, TPI, TNJ, true>), grid, dim3(256), 0, s, (const cplx<T>*)A, \
+                       P, a_rows, (cplx<T>*)X, (const cplx<T>*)LW, nbnd, npwx, chunk, nchunk,  \
+                       (cplx<T>*)partial, st);                                                 \
+  else                                                                                         \
+    hipLaunchKernelGGL((k_proj_dot<T, TPI, TNJ, false>), grid, dim3(256), 0, s, (const cplx<T>*)A, \
+                       P, a_rows, (cplx<T>*)X, nullptr, nbnd, npwx, chunk, nchunk,             \
+                       (cplx<T>*)partial, st);
+  if (tnj == 1) {
+    if (tpi == 1) { LZ_DOT(1, 1) } else if (tpi == 2) { LZ_DOT(2, 1) } else if (tpi == 3) { LZ_DOT(3, 1) } else { LZ_DOT(4, 1) }
+  } else {
+    if (tpi == 1) { LZ_DOT(1, 2) } else if (tpi == 2) { LZ_DOT(2, 2) } else if (tpi == 3) { LZ_DOT(3, 2) } else { LZ_DOT(4, 2) }
+  }
+#undef LZ_DOT
+  const int pn = P * nbnd;
+  hipLaunchKernelGGL(k_proj_reduce<T>, dim3((pn + 15) / 16, nks), dim3(256), 0, s,
+                     (const cplx<T>*)partial, nchunk, pn, (cplx<T>*)R, st);
+}
+
+template <typename T>
+bool LaunchLin<T>::dot_single_tile(int P, int nbnd) {
+  const int tpi = P <= 16 ? 1 : P <= 32 ? 2 : P <= 48 ? 3 : 4;
+  const int tnj = nbnd <= 16 ? 1 : 2;
+  return P <= 16 * tpi && nbnd <= 16 * tnj;
+}
+
+template <typename T>
+void LaunchLin<T>::coef_in(const void* R, const void* M, const double* dkb, int nbnd, int nproj,
+                           int nks, bool skip_pc, void* C, const LzDevState* st, hipStream_t s) {
+  const int pn = (nbnd + nproj) * nbnd;
+  hipLaunchKernelGGL(k_coef_in<T>, dim3((pn + 255) / 256, nks), dim3(256), 0, s,
+                     (const cplx<T>*)R, (const cplx<T>*)M, dkb, nbnd, nproj, skip_pc ? 1 : 0,
+                     (cplx<T>*)C, st);
+}
+
+template <typename T>
+void LaunchLin<T>::coef_out(const void* Rout, const void* Cin, const void* M, int nbnd, int nproj,
+                            int nks, void* C, const LzDevState* st, hipStream_t s) {
+  const int pn = (nbnd + nproj) * nbnd;
+  hipLaunchKernelGGL(k_coef_out<T>, dim3((pn + 255) / 256, nks), dim3(256), 0, s,
+                     (const cplx<T>*)Rout, (const cplx<T>*)Cin, (const cplx<T>*)M, nbnd, nproj,
+                     (cplx<T>*)C, st);
+}
+
+// bands per block of the update: few, so that a launch has many blocks
+static int upd_bands(int nbnd) { return nbnd <= 4 ? 4 : nbnd <= 32 ? 4 : 8; }
+
+template <typename T>
+int LaunchLin<T>::update_blocks(int nbnd, int npwx, int nks) {
+  const int nbt = upd_bands(nbnd);
+  return ((npwx + 255) / 256) * ((nbnd + nbt - 1) / nbt) * nks;
+}
+
+template <typename T>
+void LaunchLin<T>::proj_update(void* Y, const void* A, int P, int a_rows, const void* C,
+                               int c_rows, int nbnd, int npwx, int nks, const void* X,
+                               const void* y, const double* wk, double* lzpart,
+                               const LzDevState* st, hipStream_t s) {
+  const int nbt = upd_bands(nbnd);
+  dim3 grid((npwx + 255) / 256, (nbnd + nbt - 1) / nbt, nks);
+  const size_t lds = (size_t)P * nbt * sizeof(cplx<T>);
+  const bool dots = lzpart != nullptr;
+#define LZ_UPD(NBT, DOTS)                                                                        \
+  hipLaunchKernelGGL((k_proj_update<T, NBT, DOTS>), grid, dim3(256), lds, s, (cplx<T>*)Y,        \
+                     (const cplx<T>*)A, P, a_rows, (const cplx<T>*)C, c_rows, nbnd, npwx,        \
+                     (const cplx<T>*)X, (const cplx<T>*)y, wk, lzpart, st);
+  if (nbt == 4) { if (dots) { LZ_UPD(4, true) } else { LZ_UPD(4, false) } }
+  else { if (dots) { LZ_UPD(8, true) } else { LZ_UPD(8, false) } }
+#undef LZ_UPD
+}
+
+template <typename T>
+void LaunchLin<T>::lz_update(void* w, const void* lw, int64_t n, const LzDevState* st, hipStream_t s) {
+  hipLaunchKernelGGL(k_lz_update<T>, dim3(1024), dim3(256), 0, s, (cplx<T>*)w,
+                     (const cplx<T>*)lw, n, st);
+}
+
+template <typename T>
+void LaunchLin<T>::perm_in(const void* xu, void* xi, const int* perm, const int* npw, int nks,
+                        int nbnd, int npwx, hipStream_t s) {
+  hipLaunchKernelGGL(k_perm_in<T>, dim3((npwx + 255) / 256, nks * nbnd), dim3(256), 0, s,
+                     (const cplx<T>*)xu, (cplx<T>*)xi, perm, npw, nbnd, npwx);
+}
+
+template <typename T>
+void LaunchLin<T>::perm_out(const void* xi, void* xu, const int* perm, const int* npw, int nks,
+                         int nbnd, int npwx, hipStream_t s) {
+  hipLaunchKernelGGL(k_perm_out<T>, dim3((npwx + 255) / 256, nks * nbnd), dim3(256), 0, s,
+                     (const cplx<T>*)xi, (cplx<T>*)xu, perm, npw, nbnd, npwx);
+}
+
+template <typename T>
+void LaunchLin<T>::copy(void* dst, const void* src, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_copy<T>, dim3(1024), dim3(256), 0, s, (cplx<T>*)dst, (const cplx<T>*)src, n);
+}
+
+void launch_lz_finalize(const double* partial, int nblk, LzDevState* st, double* beta, double* z,
+                        int max_steps, double tol, double yscale, hipStream_t s) {
+  hipLaunchKernelGGL(k_lz_finalize, dim3(1), dim3(kDotThreads), 0, s, partial, nblk, st, beta, z,
+                     max_steps, tol, yscale);
+}
+
+void launch_spectrum(const double* beta, const double* z, int m, const double* omega, int nw,
+                     double eta, double pref, double fq, double* chi, double* einv, double* loss,
+                     hipStream_t s) {
+  hipLaunchKernelGGL(k_spectrum, dim3((nw + 63) / 64), dim3(64), 0, s, beta, z, m, omega, nw, eta,
+                     pref, fq, chi, einv, loss);
+}
+
+void launch_set_state(LzDevState* st, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_state, dim3(1), dim3(1), 0, s, st);
+}
+
+template struct LaunchLin<double>;
+template struct LaunchLin<float>;
+
+}  // namespace lz
