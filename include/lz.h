@@ -147,6 +147,11 @@ lz_status lz_apply_liouvillian(lz_ctx *ctx, const void *q_in, const void *p_in,
  */
 lz_status lz_step(lz_ctx *ctx, int32_t n_steps, int32_t *steps_done);
 
+/* Restart the recursion of every instance from (0, y), keeping the context
+ * (tables, orbitals, y).  Later lz_step calls overwrite the coefficients from
+ * index 0.  Stream-ordered. */
+lz_status lz_reset(lz_ctx *ctx);
+
 /* Copy coefficients first..first+count-1 (0-based: index j holds beta_{j+1})
  * of instance inst to host arrays beta[count], gamma[count], z[count][2].
  * Any of the three may be NULL.  LZ_ERR_STATE if they are not computed yet. */
@@ -160,7 +165,8 @@ lz_status lz_get_state(lz_ctx *ctx, int32_t inst, int32_t *steps_done, int32_t *
 /*
  * Spectrum of instance inst from its first m coefficients (Sec. 2.5, Sec. 3.3),
  * computed on the device in double precision:
- *   (omega + i eta - T_m) x = e_1,   chi = (4/Omega) beta_1 sum_j z_j x_j,
+ *   (omega + i eta - T_m) x = e_1,   chi = (4/Omega) beta_1 sum_j Re(z_j) x_j,
+ * (z_j is real in exact arithmetic; its rounding-level imaginary part is dropped),
  *   eps^-1 = 1 + 4 pi chi / |Q|^2,   loss = -Im eps^-1.
  * omega: host [n_omega] (Ha); eta > 0 (Ha).  Outputs are host arrays:
  * chi[n_omega][2], eps_inv[n_omega][2], loss[n_omega]; any may be NULL.

@@ -8,6 +8,10 @@ def_inv_microscopic_diel_tensor; Sec. 3.3 for the Lorentzian broadening).
     chi(omega) = (4/Omega) beta_1 sum_j z_j x_j
     eps^-1     = 1 + 4 pi chi / |Q|^2,   loss = -Im eps^-1,   eps = 1/eps^-1
 
+z_j is real in exact arithmetic: it is <y, (D(D+K))^i D y>_w up to the
+normalisations, a palindromic product of Hermitian operators.  The sum uses
+Re z_j, dropping the rounding-level imaginary part.
+
 The prefactor reading: (z, x) with the normalised start vector must be
 multiplied by the start norm beta_1; 4/Omega collects the spin factor 2, the
 SBR factor 2 of the response density and the per-volume normalisation of the
@@ -25,7 +29,7 @@ import scipy.linalg as sla
 
 def chi_from_coefficients(beta, z, omega, eta, volume, m=None):
     beta = np.asarray(beta, dtype=np.float64)
-    z = np.asarray(z, dtype=np.complex128)
+    z = np.asarray(z, dtype=np.complex128).real
     m = len(beta) if m is None else int(m)
     if m == 0:
         # no Lanczos vector: the right-hand side vanished, chi = 0

@@ -75,12 +75,13 @@ def load(path: str = LIB_PATH):
     lib.lz_spectrum.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, _dp, ctypes.c_int32,
                                 ctypes.c_double, _dp, _dp, _dp]
     lib.lz_get_rhs.argtypes = [vp, ctypes.c_int32, vp]
+    lib.lz_reset.argtypes = [vp]
     lib.lz_stage_timer.argtypes = [vp, ctypes.c_int32]
     lib.lz_stage_times.argtypes = [vp, ctypes.c_int32, _dp, _ip]
     lib.lz_free.argtypes = [vp]
     lib.lz_last_error.restype = ctypes.c_char_p
     for f in ("lz_init", "lz_apply_liouvillian", "lz_step", "lz_get_coefficients", "lz_get_state",
-              "lz_spectrum", "lz_get_rhs", "lz_stage_timer", "lz_stage_times", "lz_free"):
+              "lz_spectrum", "lz_get_rhs", "lz_reset", "lz_stage_timer", "lz_stage_times", "lz_free"):
         getattr(lib, f).restype = ctypes.c_int
     if path == LIB_PATH:
         _lib = lib
@@ -195,6 +196,10 @@ class Context:
         st = _check(lib.lz_step(self.handle, int(n), ctypes.byref(done)), allow=(LZ_BREAKDOWN,))
         return int(done.value), st
 
+    def reset(self):
+        """Restart the recursion from (0, y) (lz_reset)."""
+        _check(load().lz_reset(self.handle))
+
     def state(self, inst=0):
         lib = load()
         n, st = ctypes.c_int32(), ctypes.c_int32()
@@ -264,6 +269,10 @@ def lz_step(ctx, n):
 
 def lz_get_coefficients(ctx, inst=0, first=0, count=None):
     return ctx.coefficients(inst, first, count)
+
+
+def lz_reset(ctx):
+    return ctx.reset()
 
 
 def lz_get_state(ctx, inst=0):

@@ -803,6 +803,17 @@ lz_status lz_apply_liouvillian(lz_ctx* c, const void* q_in, const void* p_in, vo
   });
 }
 
+lz_status lz_reset(lz_ctx* c) {
+  return guarded([&] {
+    if (!c) fail(LZ_ERR_ARG, "null context");
+    HIPC(hipSetDevice(c->device));
+    c->enter();
+    start_recursion(c);
+    HIPC(hipGetLastError());
+    c->leave();
+  });
+}
+
 lz_status lz_step(lz_ctx* c, int32_t n_steps, int32_t* steps_done) {
   lz_status ret = LZ_OK;
   lz_status g = guarded([&] {

@@ -420,7 +420,7 @@ __global__ __launch_bounds__(256) void k_copy(cplx<T>* __restrict__ d, const cpl
 }
 
 // ---------------------------------------------------------------------------
-// spectrum: one thread per frequency.  chi needs (z, (w~ - T)^-1 e_1), which
+// spectrum: one thread per frequency.  chi needs (Re z, (w~ - T)^-1 e_1), which
 // for symmetric T equals the first component of (w~ - T)^-1 z; eliminating
 // from the last row upwards, x_j = c_j x_{j-1} + d_j with
 //   den_j = w~ - beta_{j+1} c_{j+1},  c_j = beta_j / den_j,
@@ -443,7 +443,8 @@ __global__ __launch_bounds__(256) void k_spectrum(const double* __restrict__ bet
   for (int j = m; j >= 1; --j) {
     const double bnext = j < m ? beta[j] : 0.0;  // beta_{j+1}
     const double2 den = make_double2(wt.x - bnext * c.x, wt.y - bnext * c.y);
-    const double2 num = make_double2(z[2 * (j - 1)] + bnext * d.x, z[2 * (j - 1) + 1] + bnext * d.y);
+    // z_j is real in exact arithmetic; its rounding-level imaginary part is dropped
+    const double2 num = make_double2(z[2 * (j - 1)] + bnext * d.x, bnext * d.y);
     d = zdiv(num, den);
     c = zdiv(make_double2(beta[j - 1], 0.0), den);
   }

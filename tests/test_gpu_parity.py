@@ -191,3 +191,36 @@ def test_cfg2_first_50_steps_full_size():
     assert np.max(np.abs(beta - ref.beta) / ref.beta) < 1e-10
     assert np.abs(z - ref.z).max() < 1e-10 * np.abs(ref.z).max()
     ctx.free()
+
+
+def test_reset_restarts_the_recursion(cfg1):
+    lz = _lz()
+    ctx = lz.lz_init(cfg1, prec="fp64", max_steps=40)
+    ctx.step(30)
+    first = ctx.coefficients()
+    ctx.reset()
+    assert ctx.state()[0] == 0
+    ctx.step(30)
+    again = ctx.coefficients()
+    assert np.array_equal(first[0], again[0]) and np.array_equal(first[2], again[2])
+    ctx.free()
+
+
+@pytest.mark.parametrize("name,steps", [("cfg1", 150), ("cfg2lo", 150)])
+def test_mixed_precision_tracks_the_oracle(name, steps):
+    """FP32 bulk with FP64 scalars: beta within 1e-5 over the first 50 steps and
+    the loss function of the whole recursion within 1e-4 (floored)."""
+    lz = _lz()
+    s = config_system(name)
+    ctx = lz.lz_init(s, prec="fp32", max_steps=steps + 2)
+    done, _ = ctx.step(steps)
+    assert done == steps
+    beta, _, z = ctx.coefficients()
+    L = Liouvillian(s)
+    ref = lanczos.run(L, steps)
+    assert np.max(np.abs(beta[:50] - ref.beta[:50]) / ref.beta[:50]) < 1e-5
+    om = np.linspace(0.0, 2.0, 2000)
+    _, _, loss = ctx.spectrum(om, 0.01)
+    _, _, loss_r, _ = spectrum.spectrum(ref.beta, ref.z, om, 0.01, L.cell.omega, L.Q)
+    assert _loss_err(loss, loss_r) < 1e-4
+    ctx.free()
