@@ -43,6 +43,8 @@ def _args():
                     help="steps of one recursion (the mixed path tracks FP64 to 1e-4 up to ~350)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--graph", action="store_true",
+                    help="replay pairs of steps as captured graphs (measured no faster than eager)")
     return ap.parse_args()
 
 
@@ -67,13 +69,13 @@ def run_jobs(ctx, nsteps, M, om):
     return last
 
 
-def run_gpu(s, prec, applies, warmup, M):
+def run_gpu(s, prec, applies, warmup, M, graph):
     import numpy as np
     import torch
 
     import paper_2111_06623_amd as lz
     om = np.linspace(*OMEGA)
-    ctx = lz.lz_init(s, prec=prec, max_steps=max(M, 32) + 2)
+    ctx = lz.lz_init(s, prec=prec, max_steps=max(M, 32) + 2, use_graph=graph)
     run_jobs(ctx, 2 * warmup, M, om)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -179,7 +181,7 @@ def main():
     for p in precs:
         _log(f"[bench] gpu {p}: warmup {a.warmup}, timed {a.steps} applies, "
              f"recursions of {a.lanczos_steps} steps")
-        res[p] = run_gpu(s, p, a.steps, a.warmup, a.lanczos_steps)
+        res[p] = run_gpu(s, p, a.steps, a.warmup, a.lanczos_steps, a.graph)
         _log(f"[bench] gpu {p}: {res[p]['applies'] / res[p]['elapsed']:.1f} applies/s")
     rate = {p: res[p]["applies"] / res[p]["elapsed"] for p in res}
     gate = None
@@ -219,6 +221,7 @@ def main():
         "config": {"workload": "cfg2: SC a=10.26 bohr, 48^3 grid, ecut 25 Ha, 8 wells + 32 s/p "
                                "projectors, 16 bands, 8 k-points, q=0.2(2pi/a)[100], PZ-ALDA",
                    "precision": head, "lanczos_steps_per_recursion": a.lanczos_steps,
+                   "graph": a.graph,
                    "spectrum": "2000 frequencies in [0, 2] Ha, eta 0.01 Ha"},
         "roofline": roof,
         "stage_ms_per_launch": {k: round(v, 5) for k, v in per_launch.items()},

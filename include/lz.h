@@ -101,7 +101,9 @@ typedef struct {
   lz_precision prec;
   lz_approx approx;
   int32_t max_steps;  /* capacity of the coefficient arrays (>= 1) */
-  int32_t use_graph;  /* nonzero: replay each Lanczos step as a captured hipGraph */
+  int32_t use_graph;  /* nonzero: lz_step replays every pair of steps after the first as one
+                         captured hipGraph (built on first use; not while the stage timer is
+                         on); results are bitwise identical to the eager launches */
   int32_t autotune;   /* reserved, must be 0 or 1 (1 = time launch shapes at init) */
 } lz_options;
 

@@ -198,6 +198,10 @@ struct Instance {
   int steps_host = 0;
   int status_host = 0;
   StageTimer timer;
+  hipGraphExec_t gpair = nullptr;  // captured pair of steps (odd, even), built on first use
+  ~Instance() {
+    if (gpair) (void)hipGraphExecDestroy(gpair);
+  }
 };
 
 #define STAGE(I, ST, S, ...)             \
@@ -328,6 +332,30 @@ void lanczos_step(Instance& I, int j, hipStream_t s) {
   STAGE(I, ST_LANCZOS, s,
         launch_lz_finalize(I.lzpart.as<double>(), I.nlzblk, st, I.beta.as<double>(),
                            I.z.as<double>(), I.max_steps, kBreakdownTol, (double)I.nbnd, s));
+}
+
+// Capture one odd step (D+K on the upper vector) and the following even step
+// (D on the lower vector) as a graph.  Every step after the first has one of
+// these two forms: the kernels read the step number and the update
+// coefficients from the device state, so the same graph serves every pair.
+void build_pair_graph(Instance& I, hipStream_t s) {
+  hipGraph_t g = nullptr;
+  HIPC(hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed));
+  if (I.fp64) {
+    lanczos_step<double>(I, 1, s);
+    lanczos_step<double>(I, 2, s);
+  } else {
+    lanczos_step<float>(I, 1, s);
+    lanczos_step<float>(I, 2, s);
+  }
+  const hipError_t e = hipStreamEndCapture(s, &g);
+  if (e != hipSuccess || g == nullptr) fail(LZ_ERR_HIP, std::string("graph capture: ") + hipGetErrorString(e));
+  const hipError_t ei = hipGraphInstantiate(&I.gpair, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (ei != hipSuccess) {
+    I.gpair = nullptr;
+    fail(LZ_ERR_HIP, std::string("graph instantiation: ") + hipGetErrorString(ei));
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -827,9 +855,19 @@ lz_status lz_step(lz_ctx* c, int32_t n_steps, int32_t* steps_done) {
     for (auto& ip : c->inst) {
       Instance& I = *ip;
       if (I.status_host != 0) continue;
-      for (int j = I.steps_host; j < I.steps_host + n_steps; ++j) {
-        if (I.fp64) lanczos_step<double>(I, j, c->stream);
-        else lanczos_step<float>(I, j, c->stream);
+      const bool graphs = c->opt.use_graph != 0 && !I.timer.on;
+      const int end = I.steps_host + n_steps;
+      int j = I.steps_host;
+      while (j < end) {
+        if (graphs && (j & 1) && j + 1 < end) {
+          if (!I.gpair) build_pair_graph(I, c->stream);
+          HIPC(hipGraphLaunch(I.gpair, c->stream));
+          j += 2;
+        } else {
+          if (I.fp64) lanczos_step<double>(I, j, c->stream);
+          else lanczos_step<float>(I, j, c->stream);
+          ++j;
+        }
       }
     }
     HIPC(hipGetLastError());

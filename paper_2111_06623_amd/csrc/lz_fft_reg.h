@@ -1,0 +1,150 @@
+// Register-resident FFTs of whole lines for the cubic grid lengths of the
+// production workloads (24, 32, 48, 64).  One thread holds one line of N
+// complex values and transforms it without any data exchange: N = R1 * R2
+// with R1 in {8, 16} and R2 in {3, 4} is split as a Cooley-Tukey pair,
+//   X[k1 + R1 k2] = sum_n2 W_N^{n2 k1} W_R2^{n2 k2} sum_n1 x[R2 n1 + n2] W_R1^{n1 k1},
+// every index and twiddle being a compile-time constant.  Twiddles are
+// rotations by multiples of 2 pi / 192 (192 is the least common multiple of
+// the four lengths), applied as an exact quarter-turn times a rotation by
+// less than pi/2 taken from a table of cosines.
+#pragma once
+#include <type_traits>
+
+#include "lz_fft_ct.h"
+
+namespace lz {
+
+// cos(2 pi j / 192), j = 0..48
+constexpr double kCos192[49] = {
+    1.000000000000000000000, 0.999464587476365644430, 0.997858923238603506738,
+    0.995184726672196886245, 0.991444861373810411145, 0.986643332084879004747,
+    0.980785280403230449126, 0.973876979277333648150, 0.965925826289068286750,
+    0.956940335732208864936, 0.946930129495105664256, 0.935905926757325700292,
+    0.923879532511286756128, 0.910863824921175818573, 0.896872741532688303894,
+    0.881921264348355029713, 0.866025403784438646764, 0.849202181526578887649,
+    0.831469612302545237079, 0.812846684591615216579, 0.793353340291235164580,
+    0.773010453362736960811, 0.751839807478977396408, 0.729864072697835657350,
+    0.707106781186547524401, 0.683592302022871280513, 0.659345815100068868425,
+    0.634393284163645498215, 0.608761429008720639416, 0.582477696867802149197,
+    0.555570233019602224743, 0.528067850650367995873, 0.500000000000000000000,
+    0.471396736825997648556, 0.442288690219001281995, 0.412707029804394737048,
+    0.382683432365089771728, 0.352250047921233506532, 0.321439465303161580701,
+    0.290284677254462367636, 0.258819045102520762349, 0.227076263034373207586,
+    0.195090322016128267848, 0.162895473394588739481, 0.130526192220051591548,
+    0.098017140329560601994, 0.065403129230143066815, 0.032719082821776142064,
+    0.0};
+
+template <int N> struct RegSplit;
+template <> struct RegSplit<12> { static constexpr int R1 = 4, R2 = 3; };
+template <> struct RegSplit<16> { static constexpr int R1 = 16, R2 = 1; };
+template <> struct RegSplit<24> { static constexpr int R1 = 8, R2 = 3; };
+template <> struct RegSplit<32> { static constexpr int R1 = 8, R2 = 4; };
+template <> struct RegSplit<48> { static constexpr int R1 = 16, R2 = 3; };
+template <> struct RegSplit<64> { static constexpr int R1 = 16, R2 = 4; };
+
+template <int N> constexpr bool reg_fft_supported() {
+  return N == 24 || N == 32 || N == 48 || N == 64;
+}
+
+// compile-time loop: f(std::integral_constant<int, I>) for I in [B, E)
+template <int B, int E, typename F>
+__device__ __forceinline__ void sfor(F&& f) {
+  if constexpr (B < E) {
+    f(std::integral_constant<int, B>{});
+    sfor<B + 1, E>(f);
+  }
+}
+
+// a * exp(DIR 2 pi i J / 192)
+template <typename T, int J, int DIR>
+__device__ __forceinline__ cplx<T> w192(cplx<T> a) {
+  constexpr int j = ((J % 192) + 192) % 192;
+  constexpr int quarter = j / 48, r = j % 48;
+  if constexpr (r != 0) {
+    const T c = T(kCos192[r]);
+    const T s = T(DIR * kCos192[48 - r]);
+    a = mk<T>(a.x * c - a.y * s, a.x * s + a.y * c);
+  }
+  if constexpr (quarter == 1) return mul_i<T>(a, DIR);
+  if constexpr (quarter == 2) return mk<T>(-a.x, -a.y);
+  if constexpr (quarter == 3) return mul_i<T>(a, -DIR);
+  return a;
+}
+
+// In-place transform of x (natural order in and out); DIR = -1 forward
+// (exp(-i ..)), +1 inverse, unnormalised.
+template <typename T, int N, int DIR>
+__device__ __forceinline__ void reg_fft(cplx<T> (&x)[N]) {
+  constexpr int R1 = RegSplit<N>::R1, R2 = RegSplit<N>::R2;
+  if constexpr (R2 == 1) {
+    Dft<T, N, DIR>::run(x);
+  } else {
+    cplx<T> y[R2][R1];
+    sfor<0, R2>([&](auto n2c) {
+      constexpr int n2 = decltype(n2c)::value;
+      cplx<T> a[R1];
+#pragma unroll
+      for (int n1 = 0; n1 < R1; ++n1) a[n1] = x[R2 * n1 + n2];
+      Dft<T, R1, DIR>::run(a);
+      sfor<0, R1>([&](auto k1c) {
+        constexpr int k1 = decltype(k1c)::value;
+        y[n2][k1] = w192<T, (192 / N) * n2 * k1, DIR>(a[k1]);
+      });
+    });
+#pragma unroll
+    for (int k1 = 0; k1 < R1; ++k1) {
+      cplx<T> b[R2];
+#pragma unroll
+      for (int n2 = 0; n2 < R2; ++n2) b[n2] = y[n2][k1];
+      Dft<T, R2, DIR>::run(b);
+#pragma unroll
+      for (int k2 = 0; k2 < R2; ++k2) x[k1 + R1 * k2] = b[k2];
+    }
+  }
+}
+
+// Value held by the partner lane (lane ^ 1) of a lane pair.
+__device__ __forceinline__ float pair_swap(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xF, 0xF, false));
+}
+__device__ __forceinline__ double pair_swap(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0xB1, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0xB1, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+template <typename T>
+__device__ __forceinline__ cplx<T> pair_swap(cplx<T> v) {
+  return mk<T>(pair_swap(v.x), pair_swap(v.y));
+}
+
+// Length-N transform shared by a lane pair (h = lane & 1), each lane holding
+// N/2 values: a radix-2 step across the pair and a register transform of
+// length N/2 on each lane.
+//   pair_fft_dit: in x[j] = v[2 j + h], out x[k] = V[h N/2 + k]
+//   pair_fft_dif: in x[k] = v[h N/2 + k], out x[j] = V[2 j + h]
+template <typename T, int N, int DIR>
+__device__ __forceinline__ void pair_fft_dit(cplx<T> (&x)[N / 2], int h) {
+  constexpr int M = N / 2;
+  reg_fft<T, M, DIR>(x);
+  sfor<0, M>([&](auto kc) {
+    constexpr int k = decltype(kc)::value;
+    const cplx<T> t = w192<T, (192 / N) * k, DIR>(x[k]);
+    const cplx<T> own = h ? t : x[k];
+    const cplx<T> other = pair_swap<T>(own);
+    x[k] = h ? csub<T>(other, own) : cadd<T>(own, other);
+  });
+}
+
+template <typename T, int N, int DIR>
+__device__ __forceinline__ void pair_fft_dif(cplx<T> (&x)[N / 2], int h) {
+  constexpr int M = N / 2;
+  sfor<0, M>([&](auto kc) {
+    constexpr int k = decltype(kc)::value;
+    const cplx<T> other = pair_swap<T>(x[k]);
+    const cplx<T> b = w192<T, (192 / N) * k, DIR>(csub<T>(other, x[k]));
+    x[k] = h ? b : cadd<T>(x[k], other);
+  });
+  reg_fft<T, M, DIR>(x);
+}
+
+}  // namespace lz

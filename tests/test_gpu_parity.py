@@ -224,3 +224,31 @@ def test_mixed_precision_tracks_the_oracle(name, steps):
     _, _, loss_r, _ = spectrum.spectrum(ref.beta, ref.z, om, 0.01, L.cell.omega, L.Q)
     assert _loss_err(loss, loss_r) < 1e-4
     ctx.free()
+
+
+@pytest.mark.parametrize("name,prec", [("cfg1", "fp64"), ("cfg2lo", "fp32")])
+def test_graph_replay_equals_eager(name, prec):
+    """Pairs of steps replayed from a captured graph, interleaved with eager
+    steps and with operator applications on the same context, give the
+    coefficients of the eager recursion bit for bit, on every replay."""
+    lz = _lz()
+    s = config_system(name)
+    eager = lz.lz_init(s, prec=prec, max_steps=64)
+    eager.step(41)
+    ref = eager.coefficients()
+    eager.free()
+    dt = torch.complex128 if prec == "fp64" else torch.complex64
+    p = _to_dev(random_batch(s, 3), dt)
+    g = lz.lz_init(s, prec=prec, max_steps=64, use_graph=True)
+    for rep in range(3):
+        g.reset()
+        for n in (1, 6, 3, 31):
+            g.step(n)
+            qo = torch.zeros_like(p)
+            po = torch.zeros_like(p)
+            g.apply_liouvillian(p, p, qo, po)
+            torch.cuda.synchronize()
+        got = g.coefficients()
+        print(f"[graph] {name} {prec} replay {rep}", flush=True)
+        assert np.array_equal(got[0], ref[0]) and np.array_equal(got[2], ref[2])
+    g.free()
