@@ -182,16 +182,18 @@ lz_status lz_spectrum(lz_ctx *ctx, int32_t inst, int32_t m, const double *omega,
  * caller's layout and precision (as lz_apply_liouvillian). */
 lz_status lz_get_rhs(lz_ctx *ctx, int32_t inst, void *y_out);
 
-/* Stage timing for measurement: with enable != 0, every later kernel stage of
- * lz_step and lz_apply_liouvillian is bracketed by HIP events on the
- * context's stream, and lz_stage_times returns, per stage, the summed
- * event-measured duration (ms) and the number of timed launches since the
- * last lz_stage_timer call.  Stages (8 entries): 0 z pass sphere->sticks,
+/* Stage timing for measurement: `mask` selects stages by bit (bit s = stage
+ * s; -1 = all, 0 = off).  Every later launch of a selected stage in lz_step
+ * and lz_apply_liouvillian is bracketed by HIP events on the context's
+ * stream, and lz_stage_times returns, per stage, the summed event-measured
+ * duration (ms) and the number of timed launches since the last
+ * lz_stage_timer call.  Stages (8 entries): 0 z pass sphere->sticks,
  * 1 plane pass of a D step, 2 plane pass with the response density,
  * 3 Hartree+xc potential, 4 plane pass v'u, 5 z pass sticks->sphere,
  * 6 projector products (P_c and separable projectors), 7 Lanczos vector
- * update and reductions.  Arrays total_ms[8], count[8]; either may be NULL. */
-lz_status lz_stage_timer(lz_ctx *ctx, int32_t enable);
+ * update and reductions.  Stages 0, 1, 2, 4 and 5 are one kernel launch
+ * each.  Arrays total_ms[8], count[8]; either may be NULL. */
+lz_status lz_stage_timer(lz_ctx *ctx, int32_t mask);
 lz_status lz_stage_times(lz_ctx *ctx, int32_t inst, double *total_ms, int32_t *count);
 
 /* Release every resource of the context (NULL is accepted). */

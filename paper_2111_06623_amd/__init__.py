@@ -236,8 +236,13 @@ class Context:
         _check(lib.lz_get_rhs(self.handle, int(inst), ctypes.c_void_p(y.data_ptr())))
         return y
 
-    def stage_timer(self, enable=True):
-        _check(load().lz_stage_timer(self.handle, int(bool(enable))))
+    def stage_timer(self, enable=True, stages=None):
+        """Time every stage (enable), none, or only the stages named in
+        `stages` (names from STAGES) with HIP events (lz_stage_timer)."""
+        mask = 0
+        if enable:
+            mask = -1 if stages is None else sum(1 << STAGES.index(n) for n in stages)
+        _check(load().lz_stage_timer(self.handle, int(mask)))
 
     def stage_times(self, inst=0):
         """(total_ms[8], count[8]) per stage since the last stage_timer call."""

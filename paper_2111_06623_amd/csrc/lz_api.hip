@@ -120,6 +120,7 @@ enum Stage { ST_ZINV = 0, ST_PLANE = 1, ST_PLANE_DENS = 2, ST_HXC = 3, ST_PLANE_
 
 struct StageTimer {
   bool on = false;
+  uint32_t mask = 0;  // stages timed (bit s = stage s)
   std::vector<std::pair<hipEvent_t, hipEvent_t>> pending[ST_COUNT];
   double total_ms[ST_COUNT] = {0};
   int count[ST_COUNT] = {0};
@@ -130,14 +131,14 @@ struct StageTimer {
     HIPC(hipEventCreate(&e));
     return e;
   }
+  bool timed(int st) const { return on && ((mask >> st) & 1u); }
   void begin(int st, hipStream_t s, hipEvent_t& e0) {
-    if (!on) return;
+    if (!timed(st)) return;
     e0 = get();
     HIPC(hipEventRecord(e0, s));
-    (void)st;
   }
   void end(int st, hipStream_t s, hipEvent_t e0) {
-    if (!on) return;
+    if (!timed(st)) return;
     hipEvent_t e1 = get();
     HIPC(hipEventRecord(e1, s));
     pending[st].push_back({e0, e1});
@@ -952,13 +953,14 @@ lz_status lz_get_rhs(lz_ctx* c, int32_t inst, void* y_out) {
   });
 }
 
-lz_status lz_stage_timer(lz_ctx* c, int32_t enable) {
+lz_status lz_stage_timer(lz_ctx* c, int32_t mask) {
   return guarded([&] {
     if (!c) fail(LZ_ERR_ARG, "null context");
     HIPC(hipSetDevice(c->device));
     read_state(c);
     for (auto& ip : c->inst) {
-      ip->timer.on = enable != 0;
+      ip->timer.mask = (uint32_t)mask & ((1u << ST_COUNT) - 1u);
+      ip->timer.on = ip->timer.mask != 0;
       ip->timer.reset();
     }
   });
