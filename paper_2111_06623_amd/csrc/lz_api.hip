@@ -185,6 +185,7 @@ struct Instance {
   int64_t nvec;  // complex elements of one batch
   Grid3 grid;
   DBuf si1, si2, act, map_kq, map_k, perm, npw_kq;
+  DBuf soff_f;
   DBuf tw1, tw2, tw3;
   DBuf kin, eps, wk, bandw, vloc, fxc, khart;
   DBuf U, vkb, dkb;
@@ -643,6 +644,17 @@ std::unique_ptr<Instance> build_instance(const lz_system& sys, const lz_options&
   I.grid.si1 = I.si1.as<int>(); I.grid.si2 = I.si2.as<int>(); I.grid.act = I.act.as<int>();
   I.grid.p1 = p1; I.grid.p2 = p2; I.grid.p3 = p3;
   I.grid.tw1 = I.tw1.p; I.grid.tw2 = I.tw2.p; I.grid.tw3 = I.tw3.p;
+  // row tables of the register-line plane kernels (cubic grids up to 64)
+  I.grid.soff_f = nullptr;
+  for (int i = 0; i < 64; ++i) I.grid.slot[i] = -1;
+  if (I.n1 == I.n2 && I.n2 == I.n3 && I.n1 <= 64) {
+    const int pitch = I.n1 + 1;
+    for (int a = 0; a < I.nact; ++a) I.grid.slot[act[a]] = (signed char)a;
+    std::vector<int> sf(I.S);
+    for (int t = 0; t < I.S; ++t) sf[t] = si1[t] * pitch + si2[t];
+    upload(I.soff_f, sf);
+    I.grid.soff_f = I.soff_f.as<int>();
+  }
   // ---- work buffers
   const size_t vb = nv * I.csz;
   I.X0.alloc(vb); I.X1.alloc(vb); I.LW.alloc(vb);
@@ -653,6 +665,14 @@ std::unique_ptr<Instance> build_instance(const lz_system& sys, const lz_options&
   // band groups of the density pass: about four blocks per compute unit
   I.ngroups = std::max(1, std::min(I.nb, (1024 + I.n3 - 1) / I.n3));
   I.gsize = (I.nb + I.ngroups - 1) / I.ngroups;
+  {
+    // the register-line kernel takes the bands of a group kRegPlaneThreads/N at a time
+    const int rn = I.fp64 ? reg_plane_size<double>(I.grid) : reg_plane_size<float>(I.grid);
+    if (rn) {
+      const int npb = 192 / rn;
+      I.gsize = (I.gsize + npb - 1) / npb * npb;
+    }
+  }
   I.ngroups = (I.nb + I.gsize - 1) / I.gsize;
   I.dpart.alloc((size_t)I.ngroups * I.N * I.csz);
   I.nr.alloc((size_t)I.N * I.csz);
@@ -666,8 +686,8 @@ std::unique_ptr<Instance> build_instance(const lz_system& sys, const lz_options&
   I.Rout.alloc((size_t)I.nks * I.nbnd * I.nbnd * I.csz);
   I.Cout.alloc((size_t)I.nks * I.ptot * I.nbnd * I.csz);
   I.Mkb.alloc((size_t)I.nks * std::max(1, I.nproj) * I.nbnd * I.csz);
-  I.nlzblk = I.fp64 ? LaunchLin<double>::update_blocks(I.nbnd, I.npwx, I.nks)
-                    : LaunchLin<float>::update_blocks(I.nbnd, I.npwx, I.nks);
+  I.nlzblk = I.fp64 ? LaunchLin<double>::update_blocks(I.ptot, I.nbnd, I.npwx, I.nks)
+                    : LaunchLin<float>::update_blocks(I.ptot, I.nbnd, I.npwx, I.nks);
   I.lzpart.alloc((size_t)I.nlzblk * 3 * sizeof(double));
   I.st.alloc(sizeof(LzDevState));
   I.beta.alloc((size_t)I.max_steps * sizeof(double));

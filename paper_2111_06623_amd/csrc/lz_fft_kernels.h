@@ -19,6 +19,7 @@
 #pragma once
 #include "lz_fft_ct.h"
 #include "lz_kernels.h"
+#include "lz_plane_reg.h"
 
 namespace lz {
 
@@ -592,6 +593,43 @@ static inline int ct_size(const Grid3& g) {
   return (g.n1 == g.n2 && g.n2 == g.n3 && ct_supported(g.n1)) ? g.n1 : 0;
 }
 
+// size N of the register-line plane kernels for this grid (0 = not used)
+template <typename T>
+int reg_plane_size(const Grid3& g) {
+  if (!g.soff_f) return 0;
+  switch (ct_size(g)) {
+    case 24: return reg_plane_ok<T, 24>() ? 24 : 0;
+    case 32: return reg_plane_ok<T, 32>() ? 32 : 0;
+    case 48: return reg_plane_ok<T, 48>() ? 48 : 0;
+    case 64: return reg_plane_ok<T, 64>() ? 64 : 0;
+    default: return 0;
+  }
+}
+template int reg_plane_size<double>(const Grid3&);
+template int reg_plane_size<float>(const Grid3&);
+
+static inline RegPlaneArgs reg_args(const Grid3& g) {
+  RegPlaneArgs a;
+  a.S = g.S;
+  a.nact = g.nact;
+  a.soff = g.soff_f;
+  a.act = g.act;
+  for (int i = 0; i < 64; ++i) a.slot[i] = g.slot[i];
+  return a;
+}
+
+#define LZ_REG_LAUNCH(KERN, T, N, GRID, LDS, STREAM, ...)                                      \
+  do {                                                                                         \
+    if constexpr (reg_plane_ok<T, 48>()) {                                                     \
+      switch (N) {                                                                             \
+        case 24: hipLaunchKernelGGL((KERN<T, 24>), GRID, dim3(kRegPlaneThreads), LDS, STREAM, __VA_ARGS__); break; \
+        case 32: hipLaunchKernelGGL((KERN<T, 32>), GRID, dim3(kRegPlaneThreads), LDS, STREAM, __VA_ARGS__); break; \
+        case 48: hipLaunchKernelGGL((KERN<T, 48>), GRID, dim3(kRegPlaneThreads), LDS, STREAM, __VA_ARGS__); break; \
+        default: hipLaunchKernelGGL((KERN<T, 64>), GRID, dim3(kRegPlaneThreads), LDS, STREAM, __VA_ARGS__); break; \
+      }                                                                                        \
+    }                                                                                          \
+  } while (0)
+
 template <typename T> static size_t plane_lds(const Grid3& g) {
   const int n = ct_size(g);
   switch (n) {
@@ -647,8 +685,8 @@ template <typename T>
 void LaunchFft<T>::zfft_fwd(const Grid3& g, const void* sticks, const void* x, int64_t xs, void* y,
                             const int* map, const void* kin, const double* eps, int nb, int nbnd,
                             int npwx, const LzDevState* st, hipStream_t s) {
-  dim3 grid((g.S + kStickTile - 1) / kStickTile, nb);
   const T scale = T(1.0 / ((double)g.n1 * g.n2 * g.n3));
+  dim3 grid((g.S + kStickTile - 1) / kStickTile, nb);
   LZ_STICK_LAUNCH(k_zfft_fwd, T, g, grid, stick_lds<T>(g), s, (const cplx<T>*)sticks,
                   (const cplx<T>*)x, xs, (cplx<T>*)y, map, (const T*)kin, eps, g.S, g.n3, nbnd,
                   npwx, scale, g.p3, (const cplx<T>*)g.tw3, st);
@@ -657,6 +695,13 @@ void LaunchFft<T>::zfft_fwd(const Grid3& g, const void* sticks, const void* x, i
 template <typename T>
 void LaunchFft<T>::plane_local(const Grid3& g, const void* sin, void* sout, const void* vloc,
                                int nb, const LzDevState* st, hipStream_t s) {
+  if (const int n = reg_plane_size<T>(g)) {
+    const int npb = kRegPlaneThreads / n, nplanes = nb * n;
+    const size_t lds = (size_t)npb * n * (n + 1) * sizeof(cplx<T>);
+    LZ_REG_LAUNCH(k_rl_local, T, n, dim3((nplanes + npb - 1) / npb), lds, s, (const cplx<T>*)sin,
+                  (cplx<T>*)sout, (const T*)vloc, reg_args(g), nplanes, st);
+    return;
+  }
   LZ_PLANE_LAUNCH(k_plane_local, T, g, dim3(g.n3, nb), plane_lds<T>(g), s, (const cplx<T>*)sin,
                   (cplx<T>*)sout, (const T*)vloc, plane_args(g), (const cplx<T>*)g.tw1,
                   (const cplx<T>*)g.tw2, st);
@@ -668,6 +713,14 @@ void LaunchFft<T>::plane_local_density(const Grid3& g, const void* sin, void* so
                                        void* dpart, int nb, int gsize, const LzDevState* st,
                                        hipStream_t s) {
   const int ng = (nb + gsize - 1) / gsize;
+  if (const int n = reg_plane_size<T>(g)) {
+    const int npb = kRegPlaneThreads / n;
+    const size_t lds = (size_t)npb * n * (n + 1) * sizeof(cplx<T>);
+    LZ_REG_LAUNCH(k_rl_density, T, n, dim3(g.n3, ng), lds, s, (const cplx<T>*)sin,
+                  (cplx<T>*)sout, (const T*)vloc, (const cplx<T>*)ur, bandw, (cplx<T>*)dpart, nb,
+                  gsize, reg_args(g), st);
+    return;
+  }
   LZ_PLANE_LAUNCH(k_plane_local_density, T, g, dim3(g.n3, ng), plane_lds<T>(g), s,
                   (const cplx<T>*)sin, (cplx<T>*)sout, (const T*)vloc, (const cplx<T>*)ur, bandw,
                   (cplx<T>*)dpart, nb, gsize, plane_args(g), (const cplx<T>*)g.tw1,
@@ -684,6 +737,13 @@ void LaunchFft<T>::plane_to_real(const Grid3& g, const void* sin, void* rout, in
 template <typename T>
 void LaunchFft<T>::plane_vu(const Grid3& g, const void* ur, const void* vp, void* sout, int nb,
                             const LzDevState* st, hipStream_t s) {
+  if (const int n = reg_plane_size<T>(g)) {
+    const int npb = kRegPlaneThreads / n, nplanes = nb * n;
+    const size_t lds = (size_t)npb * n * (n + 1) * sizeof(cplx<T>);
+    LZ_REG_LAUNCH(k_rl_vu, T, n, dim3((nplanes + npb - 1) / npb), lds, s, (const cplx<T>*)ur,
+                  (const cplx<T>*)vp, (cplx<T>*)sout, reg_args(g), nplanes, st);
+    return;
+  }
   LZ_PLANE_LAUNCH(k_plane_vu, T, g, dim3(g.n3, nb), plane_lds<T>(g), s, (const cplx<T>*)ur,
                   (const cplx<T>*)vp, (cplx<T>*)sout, plane_args(g), (const cplx<T>*)g.tw1,
                   (const cplx<T>*)g.tw2, st);
@@ -735,6 +795,19 @@ hipError_t enable_large_lds_fft() {
   LZ_LDS_ATTR(k_hxc_planes_fwd)
   LZ_LDS_ATTR(k_hxc_planes_inv)
 #undef LZ_LDS_ATTR
+#define LZ_REG_ATTR(KERN)                                                                     \
+  if constexpr (reg_plane_ok<T, 48>()) {                                                      \
+    const void* fns[] = {(const void*)KERN<T, 24>, (const void*)KERN<T, 32>,                  \
+                         (const void*)KERN<T, 48>, (const void*)KERN<T, 64>};                 \
+    for (const void* f : fns) {                                                               \
+      hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, big); \
+      if (e != hipSuccess) return e;                                                          \
+    }                                                                                         \
+  }
+  LZ_REG_ATTR(k_rl_local)
+  LZ_REG_ATTR(k_rl_density)
+  LZ_REG_ATTR(k_rl_vu)
+#undef LZ_REG_ATTR
   return hipSuccess;
 }
 

@@ -8,6 +8,14 @@
 
 namespace lz {
 
+// Row tables of the register-line plane kernels (lz_plane_reg.h).
+struct RegPlaneArgs {
+  int S, nact;
+  const int* soff;        // [S] LDS offset of each stick in a plane (row pitch n + 1)
+  const int* act;         // [nact] grid row i1 of each stored row
+  signed char slot[64];   // index of grid row i1 in act, -1 when it holds no stick
+};
+
 // Geometry of the FFT work shared by the kernels of one instance.
 struct Grid3 {
   int n1, n2, n3;
@@ -21,6 +29,9 @@ struct Grid3 {
   const void* tw1;  // twiddles of each plan (cplx<T>)
   const void* tw2;
   const void* tw3;
+  // register-line plane kernels (cubic grids, see reg_plane_size)
+  const int* soff_f;       // [S] LDS offset si1 (n+1) + si2 of each stick
+  signed char slot[64];    // index of each grid row i1 in act, or -1
 };
 
 template <typename T> struct LaunchFft {
@@ -66,7 +77,7 @@ template <typename T> struct LaunchLin {
   static void proj_update(void* Y, const void* A, int P, int a_rows, const void* C, int c_rows,
                           int nbnd, int npwx, int nks, const void* X, const void* y,
                           const double* wk, double* lzpart, const LzDevState* st, hipStream_t s);
-  static int update_blocks(int nbnd, int npwx, int nks);
+  static int update_blocks(int P, int nbnd, int npwx, int nks);
   // Lanczos: w <- a*LW + b*w
   static void lz_update(void* w, const void* lw, int64_t n, const LzDevState* st, hipStream_t s);
   // user order <-> internal order
@@ -78,6 +89,8 @@ template <typename T> struct LaunchLin {
 };
 
 template <typename T> hipError_t enable_large_lds_fft();
+// grid size N served by the register-line plane kernels (0: the LDS-pass kernels)
+template <typename T> int reg_plane_size(const Grid3& g);
 
 void launch_lz_finalize(const double* partial, int nblk, LzDevState* st, double* beta, double* z,
                         int max_steps, double tol, double yscale, hipStream_t s);

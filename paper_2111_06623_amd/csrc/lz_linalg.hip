@@ -224,30 +224,40 @@ __global__ __launch_bounds__(256) void k_coef_out(const cplx<T>* __restrict__ Ro
 // Y[k][n][G] += sum_{p<P} A[k][p][G] C[k][p][n]; with DOTS the block also
 // accumulates the Lanczos sums of its elements,
 //   s0 = sum w_k Re(conj(X) Y_new),  s1 + i s2 = sum w_k conj(y) X,
-// into lzpart[block] (fixed order inside the block).
+// into lzpart[block] (fixed order inside the block).  A block covers 256/qn
+// plane waves and qn x NBT bands (qn = 4 when the coefficients fit in LDS):
+// its qn groups of threads read the same rows of A (cache hits after the
+// first), so A is fetched once per qn NBT bands.
+
 template <typename T, int NBT, bool DOTS>
 __global__ __launch_bounds__(256) void k_proj_update(
     cplx<T>* __restrict__ Y, const cplx<T>* __restrict__ A, int P, int a_rows,
     const cplx<T>* __restrict__ C, int c_rows, int nbnd, int npwx,
     const cplx<T>* __restrict__ X, const cplx<T>* __restrict__ yv, const double* __restrict__ wk,
-    double* __restrict__ lzpart, const LzDevState* st) {
+    double* __restrict__ lzpart, int qn, const LzDevState* st) {
   if (st && st->status) return;
+  const int NB = qn * NBT;
+  const int npt = 256 / qn;  // plane waves per block
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  cplx<T>* Cs = reinterpret_cast<cplx<T>*>(smem_raw);  // [P][NBT]
+  cplx<T>* Cs = reinterpret_cast<cplx<T>*>(smem_raw);  // [P][NB]
   __shared__ double red[3][256];
   const int k = blockIdx.z;
-  const int n0 = blockIdx.y * NBT;
-  const int nbt = min(NBT, nbnd - n0);
+  const int nb0 = blockIdx.y * NB;
+  const int nbb = min(NB, nbnd - nb0);
   const cplx<T>* Ck = C + (int64_t)k * c_rows * nbnd;
-  for (int t = threadIdx.x; t < P * NBT; t += 256) {
-    const int p = t / NBT, j = t - p * NBT;
-    Cs[t] = j < nbt ? Ck[p * nbnd + n0 + j] : czero<T>();
+  for (int t = threadIdx.x; t < P * NB; t += 256) {
+    const int p = t / NB, j = t - p * NB;
+    Cs[t] = j < nbb ? Ck[p * nbnd + nb0 + j] : czero<T>();
   }
   __syncthreads();
-  const int g = blockIdx.x * 256 + threadIdx.x;
+  const int q = threadIdx.x / npt;
+  const int g = blockIdx.x * npt + (threadIdx.x % npt);
+  const int n0 = nb0 + q * NBT;
+  const int nbt = min(NBT, nbnd - n0);
   double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-  if (g < npwx) {
+  if (g < npwx && nbt > 0) {
     const cplx<T>* Ak = A + (int64_t)k * a_rows * npwx;
+    const cplx<T>* Cq = Cs + q * NBT;
     cplx<T> acc[NBT];
 #pragma unroll
     for (int j = 0; j < NBT; ++j) acc[j] = czero<T>();
@@ -255,7 +265,7 @@ __global__ __launch_bounds__(256) void k_proj_update(
     for (int p = 0; p < P; ++p) {
       const cplx<T> a = Ak[(int64_t)p * npwx + g];
 #pragma unroll
-      for (int j = 0; j < NBT; ++j) acc[j] = cadd<T>(acc[j], cmul<T>(a, Cs[p * NBT + j]));
+      for (int j = 0; j < NBT; ++j) acc[j] = cadd<T>(acc[j], cmul<T>(a, Cq[p * NB + j]));
     }
     const int64_t kb = (int64_t)k * nbnd * npwx;
     const double w = DOTS ? wk[k] : 0.0;
@@ -514,13 +524,19 @@ void LaunchLin<T>::coef_out(const void* Rout, const void* Cin, const void* M, in
                      (cplx<T>*)C, st);
 }
 
-// bands per block of the update: few, so that a launch has many blocks
-static int upd_bands(int nbnd) { return nbnd <= 4 ? 4 : nbnd <= 32 ? 4 : 8; }
+// bands per thread of the update, and thread groups sharing a block
+static int upd_bands(int nbnd) { return nbnd <= 16 ? 4 : 8; }
+template <typename T>
+static int upd_groups(int P, int nbt) {
+  return (size_t)P * 4 * nbt * sizeof(cplx<T>) <= 65536 ? 4 : 1;
+}
 
 template <typename T>
-int LaunchLin<T>::update_blocks(int nbnd, int npwx, int nks) {
+int LaunchLin<T>::update_blocks(int P, int nbnd, int npwx, int nks) {
   const int nbt = upd_bands(nbnd);
-  return ((npwx + 255) / 256) * ((nbnd + nbt - 1) / nbt) * nks;
+  const int qn = upd_groups<T>(P, nbt);
+  const int npt = 256 / qn;
+  return ((npwx + npt - 1) / npt) * ((nbnd + qn * nbt - 1) / (qn * nbt)) * nks;
 }
 
 template <typename T>
@@ -529,13 +545,15 @@ void LaunchLin<T>::proj_update(void* Y, const void* A, int P, int a_rows, const 
                                const void* y, const double* wk, double* lzpart,
                                const LzDevState* st, hipStream_t s) {
   const int nbt = upd_bands(nbnd);
-  dim3 grid((npwx + 255) / 256, (nbnd + nbt - 1) / nbt, nks);
-  const size_t lds = (size_t)P * nbt * sizeof(cplx<T>);
+  const int qn = upd_groups<T>(P, nbt);
+  const int npt = 256 / qn;
+  dim3 grid((npwx + npt - 1) / npt, (nbnd + qn * nbt - 1) / (qn * nbt), nks);
+  const size_t lds = (size_t)P * qn * nbt * sizeof(cplx<T>);
   const bool dots = lzpart != nullptr;
 #define LZ_UPD(NBT, DOTS)                                                                        \
   hipLaunchKernelGGL((k_proj_update<T, NBT, DOTS>), grid, dim3(256), lds, s, (cplx<T>*)Y,        \
                      (const cplx<T>*)A, P, a_rows, (const cplx<T>*)C, c_rows, nbnd, npwx,        \
-                     (const cplx<T>*)X, (const cplx<T>*)y, wk, lzpart, st);
+                     (const cplx<T>*)X, (const cplx<T>*)y, wk, lzpart, qn, st);
   if (nbt == 4) { if (dots) { LZ_UPD(4, true) } else { LZ_UPD(4, false) } }
   else { if (dots) { LZ_UPD(8, true) } else { LZ_UPD(8, false) } }
 #undef LZ_UPD

@@ -1,0 +1,228 @@
+// Plane passes of the Liouvillian application with register-resident line
+// transforms, for cubic grids N^3 with N in {24, 32, 48, 64}, single
+// precision (in double precision a line of 48 no longer fits the register
+// file with room to spare, and the LDS-pass kernels are faster).  The 2-D transform of a z-plane of one band (Sec. 2.4: the
+// local potential applied in real space to every response orbital) runs as
+//   rows along i2 (only the rows that hold a stick), one line per thread;
+//   columns along i1, one line per thread, where the pointwise work happens
+//   between the inverse and the forward transform without leaving registers;
+//   rows again, forward.
+// A block of 192 threads holds 192/N planes in LDS (row pitch N + 1), so that
+// every access of a column thread has a compile-time offset.  Row tasks of
+// all the planes of a block are packed onto the first threads, so waves
+// without a row idle instead of issuing masked transforms.
+#pragma once
+#include "lz_fft_reg.h"
+#include "lz_kernels.h"
+
+namespace lz {
+
+constexpr int kRegPlaneThreads = 192;
+
+template <int N> struct RegPlane {
+  static constexpr int NPB = kRegPlaneThreads / N;  // planes per block
+  static constexpr int P = N + 1;                   // LDS row pitch
+  static constexpr int R = (N + NPB - 1) / NPB;     // density rows per thread
+};
+
+template <typename T, int N>
+__host__ __device__ constexpr bool reg_plane_ok() {
+  return sizeof(T) == 4 && (N == 24 || N == 32 || N == 48 || N == 64);
+}
+
+// Row transforms of the planes of a block: task t < NPB * nact is row a of
+// plane pp (row index row(a) in the plane's storage).
+template <typename T, int N, int DIR, typename RowOf>
+__device__ __forceinline__ void reg_rows(cplx<T>* planes, int pstride, int nact, int tid,
+                                         RowOf row) {
+  constexpr int NPB = RegPlane<N>::NPB, P = RegPlane<N>::P;
+  if (tid < NPB * nact) {
+    const int pp = tid / nact, a = tid - pp * nact;
+    cplx<T>* r = planes + pp * pstride + row(a) * P;
+    cplx<T> x[N];
+#pragma unroll
+    for (int j = 0; j < N; ++j) x[j] = r[j];
+    reg_fft<T, N, DIR>(x);
+#pragma unroll
+    for (int j = 0; j < N; ++j) r[j] = x[j];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// D step: sticks -> IFFT2 -> V x -> FFT2 -> sticks, for nplanes planes
+// (band-major, z fastest).
+// ---------------------------------------------------------------------------
+template <typename T, int N>
+__global__ __launch_bounds__(kRegPlaneThreads) void k_rl_local(const cplx<T>* __restrict__ sin,
+                                                               cplx<T>* __restrict__ sout,
+                                                               const T* __restrict__ vloc,
+                                                               RegPlaneArgs a, int nplanes,
+                                                               const LzDevState* st) {
+  if (st && st->status) return;
+  constexpr int NPB = RegPlane<N>::NPB, P = RegPlane<N>::P;
+  constexpr int pstride = N * P;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cplx<T>* planes = reinterpret_cast<cplx<T>*>(smem_raw);
+  const int tid = threadIdx.x, pp = tid / N, l = tid - pp * N;
+  const int pidx = blockIdx.x * NPB + pp;
+  const bool live = pidx < nplanes;
+  const int z = pidx % N;
+  const int64_t so = (int64_t)pidx * a.S;
+  cplx<T>* pl = planes + pp * pstride;
+#pragma unroll
+  for (int i = 0; i < N; ++i) pl[i * P + l] = mk<T>(T(0), T(0));
+  __syncthreads();
+  if (live)
+    for (int s = l; s < a.S; s += N) pl[a.soff[s]] = sin[so + s];
+  __syncthreads();
+  reg_rows<T, N, +1>(planes, pstride, a.nact, tid, [&](int r) { return a.act[r]; });
+  __syncthreads();
+  {
+    cplx<T> x[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) x[i] = pl[i * P + l];
+    reg_fft<T, N, +1>(x);
+    const T* vz = vloc + (int64_t)z * N * N + l;
+#pragma unroll
+    for (int i = 0; i < N; ++i) x[i] = cscale<T>(x[i], vz[i * N]);
+    reg_fft<T, N, -1>(x);
+#pragma unroll
+    for (int i = 0; i < N; ++i) pl[i * P + l] = x[i];
+  }
+  __syncthreads();
+  reg_rows<T, N, -1>(planes, pstride, a.nact, tid, [&](int r) { return a.act[r]; });
+  __syncthreads();
+  if (live)
+    for (int s = l; s < a.S; s += N) sout[so + s] = pl[a.soff[s]];
+}
+
+// ---------------------------------------------------------------------------
+// D+K step: as k_rl_local for the bands of a group at one z, NPB bands at a
+// time, also accumulating the response density
+//   n'(r) += bandw_b conj(u_b(r)) x_b(r)
+// per group into dpart[g][z].  The column threads write their density
+// products into their own plane, and after a barrier thread (pp, l) adds rows
+// [pp R, pp R + R) of column l over the NPB planes in plane order into
+// registers.  Rows without a stick are not cleared between bands; the column
+// threads read them as zero.
+// ---------------------------------------------------------------------------
+template <typename T, int N>
+__global__ __launch_bounds__(kRegPlaneThreads) void k_rl_density(
+    const cplx<T>* __restrict__ sin, cplx<T>* __restrict__ sout, const T* __restrict__ vloc,
+    const cplx<T>* __restrict__ ur, const double* __restrict__ bandw, cplx<T>* __restrict__ dpart,
+    int nb, int gsize, RegPlaneArgs a, const LzDevState* st) {
+  if (st && st->status) return;
+  constexpr int NPB = RegPlane<N>::NPB, P = RegPlane<N>::P, R = RegPlane<N>::R;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cplx<T>* planes = reinterpret_cast<cplx<T>*>(smem_raw);
+  constexpr int pstride = N * P;
+  const int nact = a.nact;
+  const int tid = threadIdx.x, pp = tid / N, l = tid - pp * N;
+  const int z = blockIdx.x, g = blockIdx.y;
+  const int b0 = g * gsize, b1 = min(nb, b0 + gsize);
+  cplx<T>* pl = planes + pp * pstride;
+  cplx<T> acc[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) acc[r] = mk<T>(T(0), T(0));
+  const T* vz = vloc + (int64_t)z * N * N + l;
+  for (int cb = b0; cb < b1; cb += NPB) {
+    const int b = cb + pp;
+    const bool live = b < b1;
+    // clear the active rows, then scatter this band's sticks
+    for (int t = l; t < nact * P; t += N) {
+      const int ar = t / P, c = t - ar * P;
+      pl[a.act[ar] * P + c] = mk<T>(T(0), T(0));
+    }
+    __syncthreads();
+    const int64_t so = ((int64_t)(live ? b : b0) * N + z) * a.S;
+    if (live)
+      for (int s = l; s < a.S; s += N) pl[a.soff[s]] = sin[so + s];
+    __syncthreads();
+    reg_rows<T, N, +1>(planes, pstride, nact, tid, [&](int r) { return a.act[r]; });
+    __syncthreads();
+    cplx<T> x[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      const cplx<T> v = pl[i * P + l];
+      x[i] = a.slot[i] >= 0 ? v : mk<T>(T(0), T(0));
+    }
+    reg_fft<T, N, +1>(x);
+    {
+      const cplx<T>* ub = ur + ((int64_t)(live ? b : b0) * N + z) * N * N + l;
+      const T wb = live ? T(bandw[b]) : T(0);
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+        const cplx<T> d = cmulc<T>(ub[i * N], x[i]);
+        pl[i * P + l] = mk<T>(wb * d.x, wb * d.y);
+        x[i] = cscale<T>(x[i], vz[i * N]);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int i = pp * R + r;
+      if (i < N) {
+        cplx<T> sum = planes[i * P + l];
+#pragma unroll
+        for (int q = 1; q < NPB; ++q) sum = cadd<T>(sum, planes[q * pstride + i * P + l]);
+        acc[r] = cadd<T>(acc[r], sum);
+      }
+    }
+    __syncthreads();
+    reg_fft<T, N, -1>(x);
+#pragma unroll
+    for (int i = 0; i < N; ++i) pl[i * P + l] = x[i];
+    __syncthreads();
+    reg_rows<T, N, -1>(planes, pstride, nact, tid, [&](int r) { return a.act[r]; });
+    __syncthreads();
+    if (live)
+      for (int s = l; s < a.S; s += N) sout[so + s] = pl[a.soff[s]];
+    __syncthreads();
+  }
+  cplx<T>* dp = dpart + ((int64_t)g * N + z) * N * N + l;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int i = pp * R + r;
+    if (i < N) dp[i * N] = acc[r];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// v'(r) u_b(r) -> FFT2 -> added to the sticks of the same band
+// ---------------------------------------------------------------------------
+template <typename T, int N>
+__global__ __launch_bounds__(kRegPlaneThreads) void k_rl_vu(const cplx<T>* __restrict__ ur,
+                                                            const cplx<T>* __restrict__ vp,
+                                                            cplx<T>* __restrict__ sout,
+                                                            RegPlaneArgs a, int nplanes,
+                                                            const LzDevState* st) {
+  if (st && st->status) return;
+  constexpr int NPB = RegPlane<N>::NPB, P = RegPlane<N>::P;
+  constexpr int pstride = N * P;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cplx<T>* planes = reinterpret_cast<cplx<T>*>(smem_raw);
+  const int tid = threadIdx.x, pp = tid / N, l = tid - pp * N;
+  const int pidx = blockIdx.x * NPB + pp;
+  const bool live = pidx < nplanes;
+  const int z = pidx % N;
+  cplx<T>* pl = planes + pp * pstride;
+  {
+    const cplx<T>* ub = ur + (int64_t)(live ? pidx : 0) * N * N + l;
+    const cplx<T>* vz = vp + (int64_t)z * N * N + l;
+    cplx<T> x[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) x[i] = cmul<T>(ub[i * N], vz[i * N]);
+    reg_fft<T, N, -1>(x);
+#pragma unroll
+    for (int i = 0; i < N; ++i) pl[i * P + l] = x[i];
+  }
+  __syncthreads();
+  reg_rows<T, N, -1>(planes, pstride, a.nact, tid, [&](int r) { return a.act[r]; });
+  __syncthreads();
+  if (live) {
+    const int64_t so = (int64_t)pidx * a.S;
+    for (int s = l; s < a.S; s += N) sout[so + s] = cadd<T>(sout[so + s], pl[a.soff[s]]);
+  }
+}
+
+}  // namespace lz

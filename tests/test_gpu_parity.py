@@ -176,20 +176,49 @@ def test_argument_errors_are_reported(cfg1):
     ctx.free()
 
 
-@pytest.mark.slow
-def test_cfg2_first_50_steps_full_size():
-    """The benchmark workload at its full size (48^3, 16 bands, 8 k)."""
-    lz = _lz()
+@pytest.fixture(scope="module")
+def cfg2_oracle_50():
+    """The oracle's first 50 steps on the benchmark workload (48^3, 16 bands, 8 k)."""
     s = config_system("cfg2")
-    print("[cfg2] init", flush=True)
-    ctx = lz.lz_init(s, prec="fp64", max_steps=64)
+    print("[cfg2] oracle", flush=True)
+    return s, lanczos.run(Liouvillian(s), 50)
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32", 2e-5)])
+def test_cfg2_first_50_steps_full_size(cfg2_oracle_50, prec, tol):
+    """The benchmark workload at its full size, in both precisions: FP64 to
+    the parity bar, the mixed path (FP32 bulk, FP64 scalars) to 2e-5."""
+    lz = _lz()
+    s, ref = cfg2_oracle_50
+    print(f"[cfg2] {prec}", flush=True)
+    ctx = lz.lz_init(s, prec=prec, max_steps=64)
     done, st = ctx.step(50)
     assert done == 50
-    print("[cfg2] oracle", flush=True)
-    ref = lanczos.run(Liouvillian(s), 50)
     beta, _, z = ctx.coefficients()
-    assert np.max(np.abs(beta - ref.beta) / ref.beta) < 1e-10
-    assert np.abs(z - ref.z).max() < 1e-10 * np.abs(ref.z).max()
+    assert np.max(np.abs(beta - ref.beta) / ref.beta) < tol
+    assert np.abs(z - ref.z).max() < tol * np.abs(ref.z).max()
+    ctx.free()
+
+
+@pytest.mark.parametrize("name", ["cfg1", "cfg2lo", "cfg2"])
+def test_apply_liouvillian_fp32_matches_oracle(name):
+    """Single-precision applications (the kernels of the mixed path, at the
+    benchmark grid for cfg2) against the FP64 oracle: 2e-5 of the largest
+    output element."""
+    lz = _lz()
+    s = config_system(name)
+    print(f"[apply32] {name}", flush=True)
+    ctx = lz.lz_init(s, prec="fp32", max_steps=8)
+    L = Liouvillian(s)
+    p = random_batch(s, 21)
+    q = random_batch(s, 22)
+    qo = torch.zeros(p.shape, dtype=torch.complex64, device="cuda")
+    po = torch.zeros_like(qo)
+    ctx.apply_liouvillian(_to_dev(q, torch.complex64), _to_dev(p, torch.complex64), qo, po)
+    torch.cuda.synchronize()
+    assert _rel(qo.cpu().numpy(), L.apply_D(p)) < 2e-5
+    assert _rel(po.cpu().numpy(), L.apply_DK(q)) < 2e-5
     ctx.free()
 
 
