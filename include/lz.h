@@ -42,8 +42,8 @@ typedef enum {
   LZ_FP64 = 0,            /* every array and every FFT in double precision */
   LZ_FP32 = 1,            /* vectors, FFTs, pointwise work and projector products in
                              single precision; Lanczos scalars and the spectrum in double */
-  LZ_FP32_SPLITBF16 = 2   /* as LZ_FP32, projector products as three bf16 MFMA products
-                             of (hi, lo) bf16 splits with fp32 accumulation */
+  LZ_FP32_SPLITBF16 = 2   /* reserved for projector products as three bf16 MFMA products of
+                             (hi, lo) splits; not available: lz_init returns LZ_ERR_ARG */
 } lz_precision;
 
 typedef enum {   /* levels of theory of Sec. 3.2 */

@@ -778,8 +778,9 @@ lz_status lz_init(const lz_system* sys, int32_t n_inst, const lz_options* opt, i
     if (!sys || !opt || !out) fail(LZ_ERR_ARG, "null argument");
     if (n_inst < 1) fail(LZ_ERR_ARG, "n_inst must be >= 1");
     if (opt->max_steps < 1) fail(LZ_ERR_ARG, "max_steps must be >= 1");
-    if (opt->prec != LZ_FP64 && opt->prec != LZ_FP32 && opt->prec != LZ_FP32_SPLITBF16)
-      fail(LZ_ERR_ARG, "unknown precision");
+    if (opt->prec == LZ_FP32_SPLITBF16)
+      fail(LZ_ERR_ARG, "LZ_FP32_SPLITBF16 (split-bf16 projector products) is not available");
+    if (opt->prec != LZ_FP64 && opt->prec != LZ_FP32) fail(LZ_ERR_ARG, "unknown precision");
     if (opt->approx != LZ_TDDFT && opt->approx != LZ_RPA && opt->approx != LZ_IPA)
       fail(LZ_ERR_ARG, "unknown approximation");
     int ndev = 0;

@@ -8,6 +8,14 @@
         (32 in total), 16 bands, 8 k on a 2x2x2 mesh with a seeded shift,
         q = 0.2 (2pi/a) along [100], Perdew-Zunger ALDA, 1000 Lanczos steps.
   cfg3  cfg2 run in mixed precision (3000 steps).
+  cfg5r the large cell (64 wells = the 2x2x2 supercell of cfg2's sites, a=20.5
+        bohr, 96^3 grid at ecut 25 Ha, 256 projectors, 128 bands, 4 k on a
+        2x2x1 mesh, q = (0.2, 0.1, 0) 2pi/a) with seeded random orthonormal
+        orbitals in place of eigenstates: operator-level parity and
+        throughput at the full size.
+  uneven members of the batched workload (seeded grids in {32, 40, 48, 64,
+        72} with a = 10.26 N/48 bohr, ecut 25 Ha, wells with 4 projectors
+        each, random orthonormal orbitals); `uneven_sizes` trims bands and k.
   micro small cells for brute-force diagonalisation of the explicit Liouvillian.
   free  free electrons (V=0): one closed shell of 7 bands, Gamma only,
         q = (0.1,0,0) b, G0 = (1,0,0).
@@ -93,6 +101,43 @@ def _spec(name: str, **kw) -> dict:
                     depth=4.0, width=1.2, nbnd=16, kpts=mp_kpoints(at, (2, 2, 2), shift)[:nk],
                     q=[0.2 * 2 * np.pi / a, 0.0, 0.0], xc="pz",
                     kb=dict(radii=radii, dkb=dkb))
+    if name == "cfg5r":
+        a = 20.5
+        at = np.eye(3) * a
+        sites = np.array([(DIAMOND_SITES[i] + np.array(o)) / 2.0
+                          for o in [(0, 0, 0), (0, 0, 1), (0, 1, 0), (0, 1, 1),
+                                    (1, 0, 0), (1, 0, 1), (1, 1, 0), (1, 1, 1)]
+                          for i in range(8)])
+        rng = np.random.default_rng(5)
+        radii = rng.uniform(0.8, 1.2, (64, 2))
+        dkb = np.stack([rng.uniform(3.0, 8.0, 64), rng.uniform(0.1, 0.5, 64)], axis=1)
+        shift = rng.random(3)
+        shift[2] = 0.0
+        nbnd = kw.get("nbnd", 128)
+        nk = kw.get("nk", 4)
+        return dict(at=at, nr=(96, 96, 96), ecut=25.0, tau_frac=sites, depth=4.0, width=1.2,
+                    nbnd=nbnd, kpts=mp_kpoints(at, (2, 2, 1), shift)[:nk],
+                    q=[0.2 * 2 * np.pi / a, 0.1 * 2 * np.pi / a, 0.0], xc="pz",
+                    kb=dict(radii=radii, dkb=dkb), orbitals="random", seed=5, extra_bands=0)
+    if name == "uneven":
+        i = kw.get("index", 0)
+        rng = np.random.default_rng(4000 + i)
+        n = int(kw.get("grid", rng.choice([32, 40, 48, 64, 72])))
+        a = 10.26 * n / 48
+        at = np.eye(3) * a
+        nbnd = int(kw.get("nbnd", rng.choice(np.arange(8, 49, 8))))
+        nat = max(1, nbnd // 2)
+        tau = rng.random((nat, 3))
+        radii = rng.uniform(0.8, 1.2, (nat, 2))
+        dkb = np.stack([rng.uniform(3.0, 8.0, nat), rng.uniform(0.1, 0.5, nat)], axis=1)
+        nkmax = int(kw.get("nk", rng.integers(1, 17)))
+        ks = mp_kpoints(at, (4, 2, 2), rng.random(3))[:nkmax]
+        d = rng.standard_normal(3)
+        d /= np.linalg.norm(d)
+        qn = rng.uniform(0.05, 0.5) * 2 * np.pi / a
+        return dict(at=at, nr=(n, n, n), ecut=25.0, tau_frac=tau, depth=4.0, width=1.2,
+                    nbnd=nbnd, kpts=ks, q=list(qn * d), xc="pz", kb=dict(radii=radii, dkb=dkb),
+                    orbitals="random", seed=4000 + i, extra_bands=0)
     if name == "micro":
         # a tiny gapped cell: two wells, s+p projectors, two bands, two k
         a = 6.0

@@ -320,6 +320,25 @@ def _solve_sphere(args):
     return mill, v, w, vkb
 
 
+def _random_sphere(args):
+    """Sphere and projectors of one k or k+q point with random orthonormal
+    orbitals instead of eigenstates (operator-level tests of large cells,
+    where diagonalisation is out of reach).  The orbital energies are placed
+    below a lower bound of the Hamiltonian on the sphere, so that D stays
+    positive definite on the conduction manifold."""
+    at, nr, vloc, kv, kbase, ecut, tau, radii, dkb, nev, tol, union_g0, seed = args
+    mill = sphere_miller(at, nr, kv, ecut)
+    vkb = kb_projectors(at, mill, kv, tau, radii) if radii is not None else None
+    rng = np.random.default_rng(seed)
+    x = rng.standard_normal((len(mill), nev)) + 1j * rng.standard_normal((len(mill), nev))
+    v, _ = np.linalg.qr(x)
+    lower = float(vloc.min())
+    if vkb is not None:
+        lower += float(np.sum(np.minimum(dkb, 0.0) * np.sum(np.abs(vkb) ** 2, axis=1)))
+    w = lower - 0.5 - 0.05 * np.arange(nev)[::-1]
+    return mill, v, w, vkb
+
+
 def _pool_init():
     global _WORKERS, _LIMITER
     _WORKERS = 1
@@ -329,6 +348,8 @@ def _pool_init():
 
 def _run_jobs(jobs):
     """Solve the spheres, in worker processes when there are several large ones."""
+    if len(jobs[0]) == 13:
+        return [_random_sphere(j) for j in jobs]
     big = sum(1 for j in jobs if sphere_miller(j[0], j[1], j[3], j[5]).shape[0] > 2600)
     ncpu = min(len(os.sched_getaffinity(0)), 16)
     if big < 2 or ncpu < 2:
@@ -400,12 +421,14 @@ class SystemArrays:
 
 def build_system(*, at, nr, ecut, tau_frac, depth, width, nbnd, kpts, q, g0=(0, 0, 0),
                  kb=None, xc="pz", wk=None, kq_basis="sphere", extra_bands=2,
-                 tol=1e-10) -> SystemArrays:
+                 tol=1e-10, orbitals="eigen", seed=0) -> SystemArrays:
     """Assemble one synthetic instance.
 
     kb: None or dict(radii=[nat,2], dkb=[nat,2]) for s/p projectors.
     kq_basis: "sphere" (the k+q sphere) or "union" (the k+q sphere together
-    with the k sphere shifted by G0, used where an exact f-sum is required)."""
+    with the k sphere shifted by G0, used where an exact f-sum is required).
+    orbitals: "eigen" (lowest eigenpairs) or "random" (seeded orthonormal
+    orbitals, for operator tests of cells too large to diagonalise)."""
     at = np.asarray(at, dtype=np.float64)
     nr = np.asarray(nr, dtype=np.int32)
     tau_frac = np.asarray(tau_frac, dtype=np.float64)
@@ -425,10 +448,14 @@ def build_system(*, at, nr, ecut, tau_frac, depth, width, nbnd, kpts, q, g0=(0, 
         dkb = np.zeros(0)
     nev = nbnd + extra_bands
     jobs = []
-    for k in kpts:
+    for i, k in enumerate(kpts):
         jobs.append((at, nr, vloc, k, k, ecut, tau, radii, dkb, nev, tol, None))
         jobs.append((at, nr, vloc, k + q, k, ecut, tau, radii, dkb, nev, tol,
                      g0 if kq_basis == "union" else None))
+    if orbitals == "random":
+        jobs = [j + (seed * 1000 + t,) for t, j in enumerate(jobs)]
+    elif orbitals != "eigen":
+        raise ValueError(orbitals)
     res = _run_jobs(jobs)
     mk, mkq, uk, ukq, ek, ekq, bkq = [], [], [], [], [], [], []
     for i in range(nks):

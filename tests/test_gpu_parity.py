@@ -281,3 +281,93 @@ def test_graph_replay_equals_eager(name, prec):
         print(f"[graph] {name} {prec} replay {rep}", flush=True)
         assert np.array_equal(got[0], ref[0]) and np.array_equal(got[2], ref[2])
     g.free()
+
+
+@pytest.fixture(scope="module")
+def cfg5r_ref():
+    """The large cell (96^3, 128 bands, 4 k, 256 projectors; random
+    orthonormal orbitals) and the oracle's D p and (D+K) q on it."""
+    import oracle.pw as opw
+    opw.FFT_WORKERS = min(len(__import__("os").sched_getaffinity(0)), 16)
+    s = config_system("cfg5r")
+    print("[cfg5r] oracle", flush=True)
+    L = Liouvillian(s)
+    p = random_batch(s, 31)
+    q = random_batch(s, 32)
+    return s, p, q, L.apply_D(p), L.apply_DK(q)
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 2e-5)])
+def test_large_cell_apply_full_size(cfg5r_ref, prec, tol):
+    """Every kernel at the large-cell size (general 96^3 transforms, projector
+    products spanning several tiles) against the oracle."""
+    lz = _lz()
+    s, p, q, d_ref, dk_ref = cfg5r_ref
+    print(f"[cfg5r] {prec}", flush=True)
+    dt = torch.complex128 if prec == "fp64" else torch.complex64
+    ctx = lz.lz_init(s, prec=prec, max_steps=4)
+    qo = torch.zeros(p.shape, dtype=dt, device="cuda")
+    po = torch.zeros_like(qo)
+    ctx.apply_liouvillian(_to_dev(q, dt), _to_dev(p, dt), qo, po)
+    torch.cuda.synchronize()
+    assert _rel(qo.cpu().numpy(), d_ref) < tol
+    assert _rel(po.cpu().numpy(), dk_ref) < tol
+    ctx.free()
+
+
+@pytest.mark.parametrize("grid,nbnd,nk", [(40, 8, 2), (72, 8, 1), (64, 16, 1)])
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 2e-5)])
+def test_uneven_grid_apply(grid, nbnd, nk, prec, tol):
+    """Members of the batched workload: runtime-plan grids (40 = 8 x 5,
+    72 = 8 x 9) and the compile-time 64^3 grid."""
+    lz = _lz()
+    s = config_system("uneven", index=grid, grid=grid, nbnd=nbnd, nk=nk)
+    print(f"[uneven] {grid} {prec}", flush=True)
+    dt = torch.complex128 if prec == "fp64" else torch.complex64
+    L = Liouvillian(s)
+    p = random_batch(s, 41)
+    q = random_batch(s, 42)
+    ctx = lz.lz_init(s, prec=prec, max_steps=4)
+    qo = torch.zeros(p.shape, dtype=dt, device="cuda")
+    po = torch.zeros_like(qo)
+    ctx.apply_liouvillian(_to_dev(q, dt), _to_dev(p, dt), qo, po)
+    torch.cuda.synchronize()
+    assert _rel(qo.cpu().numpy(), L.apply_D(p)) < tol
+    assert _rel(po.cpu().numpy(), L.apply_DK(q)) < tol
+    ctx.free()
+
+
+def test_instances_in_one_context_match_single_contexts():
+    """Three instances of different grids (24^3, 12^3, 32^3) in one context:
+    every instance's recursion is bit for bit the one of a context of its
+    own, and applications on the concatenated layout are the instances'."""
+    lz = _lz()
+    names = ["cfg1", "micro", "cfg2lo"]
+    systems = [config_system(n) for n in names]
+    single = []
+    for s in systems:
+        c = lz.lz_init(s, prec="fp64", max_steps=40)
+        c.step(30)
+        single.append(c.coefficients())
+        c.free()
+    ctx = lz.lz_init(systems, prec="fp64", max_steps=40)
+    done, st = ctx.step(30)
+    assert done == 30
+    for i in range(3):
+        beta, _, z = ctx.coefficients(inst=i)
+        assert np.array_equal(beta, single[i][0]) and np.array_equal(z, single[i][2])
+    ps = [random_batch(s, 51) for s in systems]
+    flat = np.concatenate([x.ravel() for x in ps])
+    qo = torch.zeros(flat.shape, dtype=torch.complex128, device="cuda")
+    po = torch.zeros_like(qo)
+    ctx.apply_liouvillian(_to_dev(flat), _to_dev(flat), qo, po)
+    torch.cuda.synchronize()
+    off = 0
+    for s, x in zip(systems, ps):
+        L = Liouvillian(s)
+        n = x.size
+        assert _rel(qo.cpu().numpy()[off:off + n].reshape(x.shape), L.apply_D(x)) < 1e-12
+        assert _rel(po.cpu().numpy()[off:off + n].reshape(x.shape), L.apply_DK(x)) < 1e-12
+        off += n
+    ctx.free()
