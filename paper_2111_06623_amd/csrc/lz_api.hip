@@ -189,7 +189,7 @@ struct Instance {
   DBuf tw1, tw2, tw3;
   DBuf kin, eps, wk, bandw, vloc, fxc, khart;
   DBuf U, vkb, dkb;
-  DBuf Aio, Mkb, Rin, Cin, Rout, Cout;
+  DBuf Aio, Mkb, Cin, Cout;
   DBuf ur, y;
   DBuf X0, X1, LW;
   DBuf sa, sb;
@@ -255,9 +255,9 @@ void input_side(Instance& I, void* x, const void* lw, bool project, const LzDevS
     STAGE(I, ST_LANCZOS, s, LaunchLin<T>::lz_update(x, lw, I.nvec, st, s));
   STAGE(I, ST_PROJ, s,
         LaunchLin<T>::proj_dot(I.Aio.p, I.ptot, I.ptot, x, fuse ? lw : nullptr, I.nbnd, I.npwx,
-                               I.nks, I.chunk, I.nchunk, I.dpartial.p, I.Rin.p, st, s);
-        LaunchLin<T>::coef_in(I.Rin.p, I.Mkb.p, I.dkb.as<double>(), I.nbnd, I.nproj, I.nks,
-                              !project, I.Cin.p, st, s));
+                               I.nks, I.chunk, I.nchunk, I.dpartial.p, st, s);
+        LaunchLin<T>::reduce_coef_in(I.dpartial.p, I.nchunk, I.Mkb.p, I.dkb.as<double>(),
+                                     I.nbnd, I.nproj, I.nks, !project, I.Cin.p, st, s));
   if (project)
     STAGE(I, ST_PROJ, s,
           LaunchLin<T>::proj_update(x, I.Aio.p, I.nbnd, I.ptot, I.Cin.p, I.ptot, I.nbnd, I.npwx,
@@ -272,8 +272,9 @@ void output_side(Instance& I, void* out, const void* x, double* lzpart, const Lz
                  hipStream_t s) {
   STAGE(I, ST_PROJ, s,
         LaunchLin<T>::proj_dot(I.Aio.p, I.nbnd, I.ptot, out, nullptr, I.nbnd, I.npwx, I.nks,
-                               I.chunk, I.nchunk, I.dpartial.p, I.Rout.p, st, s);
-        LaunchLin<T>::coef_out(I.Rout.p, I.Cin.p, I.Mkb.p, I.nbnd, I.nproj, I.nks, I.Cout.p, st, s);
+                               I.chunk, I.nchunk, I.dpartial.p, st, s);
+        LaunchLin<T>::reduce_coef_out(I.dpartial.p, I.nchunk, I.Cin.p, I.Mkb.p, I.nbnd, I.nproj,
+                                      I.nks, I.Cout.p, st, s);
         LaunchLin<T>::proj_update(out, I.Aio.p, I.ptot, I.ptot, I.Cout.p, I.ptot, I.nbnd, I.npwx,
                                   I.nks, x, I.y.p, I.wk.as<double>(), lzpart, st, s));
 }
@@ -315,9 +316,9 @@ void apply_half(Instance& I, void* in, void* out, bool upper, hipStream_t s) {
 template <typename T>
 void project_c(Instance& I, void* x, hipStream_t s) {
   LaunchLin<T>::proj_dot(I.Aio.p, I.nbnd, I.ptot, x, nullptr, I.nbnd, I.npwx, I.nks, I.chunk,
-                         I.nchunk, I.dpartial.p, I.Rin.p, nullptr, s);
-  LaunchLin<T>::coef_in(I.Rin.p, I.Mkb.p, I.dkb.as<double>(), I.nbnd, 0, I.nks, false, I.Cin.p,
-                        nullptr, s);
+                         I.nchunk, I.dpartial.p, nullptr, s);
+  LaunchLin<T>::reduce_coef_in(I.dpartial.p, I.nchunk, I.Mkb.p, I.dkb.as<double>(), I.nbnd, 0,
+                               I.nks, false, I.Cin.p, nullptr, s);
   LaunchLin<T>::proj_update(x, I.Aio.p, I.nbnd, I.ptot, I.Cin.p, I.nbnd, I.nbnd, I.npwx, I.nks,
                             nullptr, nullptr, nullptr, nullptr, nullptr, s);
 }
@@ -374,7 +375,8 @@ void build_device_tables(Instance& I, hipStream_t s, const std::vector<double>& 
   if (I.nproj > 0) {
     const void* beta = (const char*)I.Aio.p + (size_t)I.nbnd * I.npwx * I.csz;
     LaunchLin<T>::proj_dot(beta, I.nproj, I.ptot, I.U.p, nullptr, I.nbnd, I.npwx, I.nks, I.chunk,
-                           I.nchunk, I.dpartial.p, I.Mkb.p, nullptr, s);
+                           I.nchunk, I.dpartial.p, nullptr, s);
+    LaunchLin<T>::reduce(I.dpartial.p, I.nchunk, I.nproj, I.nbnd, I.nks, I.Mkb.p, s);
   }
   // y = P_c (shifted u)
   project_c<T>(I, I.y.p, s);
@@ -681,9 +683,7 @@ std::unique_ptr<Instance> build_instance(const lz_system& sys, const lz_options&
   I.chunk = kProjChunk;
   I.nchunk = (I.npwx + I.chunk - 1) / I.chunk;
   I.dpartial.alloc((size_t)I.nks * I.nchunk * I.ptot * I.nbnd * I.csz);
-  I.Rin.alloc((size_t)I.nks * I.ptot * I.nbnd * I.csz);
   I.Cin.alloc((size_t)I.nks * I.ptot * I.nbnd * I.csz);
-  I.Rout.alloc((size_t)I.nks * I.nbnd * I.nbnd * I.csz);
   I.Cout.alloc((size_t)I.nks * I.ptot * I.nbnd * I.csz);
   I.Mkb.alloc((size_t)I.nks * std::max(1, I.nproj) * I.nbnd * I.csz);
   I.nlzblk = I.fp64 ? LaunchLin<double>::update_blocks(I.ptot, I.nbnd, I.npwx, I.nks)

@@ -61,17 +61,23 @@ template <typename T> struct LaunchFft {
 };
 
 template <typename T> struct LaunchLin {
-  // R[k][p][n] = sum_G conj(A[k][p][G]) X[k][n][G], rows p < P of A (a_rows per k);
-  // with LW != null the dot first forms X <- a*LW + b*X (state coefficients)
+  // chunk partials of R[k][p][n] = sum_G conj(A[k][p][G]) X[k][n][G], rows p < P
+  // of A (a_rows per k), laid out [k][chunk][n][p]; with LW != null the dot
+  // first forms X <- a*LW + b*X (state coefficients)
   static void proj_dot(const void* A, int P, int a_rows, void* X, const void* LW, int nbnd,
-                       int npwx, int nks, int chunk, int nchunk, void* partial, void* R,
+                       int npwx, int nks, int chunk, int nchunk, void* partial,
                        const LzDevState* st, hipStream_t s);
   static bool dot_single_tile(int P, int nbnd);
-  // update coefficients from the reduced overlaps (see lz_linalg.hip)
-  static void coef_in(const void* R, const void* M, const double* dkb, int nbnd, int nproj,
-                      int nks, bool skip_pc, void* C, const LzDevState* st, hipStream_t s);
-  static void coef_out(const void* Rout, const void* Cin, const void* M, int nbnd, int nproj,
-                       int nks, void* C, const LzDevState* st, hipStream_t s);
+  // R[k][p][n] from the partials
+  static void reduce(const void* partial, int nchunk, int P, int nbnd, int nks, void* R,
+                     hipStream_t s);
+  // reduction of the partials and the update coefficients (see lz_linalg.hip)
+  static void reduce_coef_in(const void* partial, int nchunk, const void* M, const double* dkb,
+                             int nbnd, int nproj, int nks, bool skip_pc, void* C,
+                             const LzDevState* st, hipStream_t s);
+  static void reduce_coef_out(const void* partial, int nchunk, const void* Cin, const void* M,
+                              int nbnd, int nproj, int nks, void* C, const LzDevState* st,
+                              hipStream_t s);
   // Y[k][n][G] += sum_{p<P} A[k][p][G] C[k][p][n]; with lzpart the Lanczos
   // sums of (X, Y, y) per block (update_blocks of them)
   static void proj_update(void* Y, const void* A, int P, int a_rows, const void* C, int c_rows,

@@ -22,9 +22,10 @@ __device__ __forceinline__ cplx<T> czero() { return mk<T>(T(0), T(0)); }
 // (nbnd rows, P_c = 1 - U U^H) followed by the separable projectors beta
 // (nproj rows, V_NL = beta D beta^H), all on the k+q sphere.
 //
-//   dot     R[k][p][n]  = sum_G conj(A[k][p][G]) X[k][n][G]   (split over G,
-//                         partials summed in a fixed order by k_proj_reduce)
-//   coef    small per-k matrices turning R into update coefficients
+//   dot     R[k][p][n]  = sum_G conj(A[k][p][G]) X[k][n][G]   (split over G
+//                         into chunk partials)
+//   coef    the partials of one column n of R summed in a fixed order, and
+//           the small per-k matrices turning it into update coefficients
 //   update  Y[k][n][G] += sum_p A[k][p][G] C[k][p][n]
 //
 // With S = U^H w, B' = beta^H w and M = beta^H U (fixed), the projector of
@@ -112,113 +113,134 @@ __global__ __launch_bounds__(256) void k_proj_dot(const cplx<T>* __restrict__ A,
 #pragma unroll
     for (int j = 0; j < TNJ; ++j) {
       const int p = p0 + ty + 16 * i, n = n0 + tx + 16 * j;
-      if (p < P && n < nbnd) out[p * nbnd + n] = acc[i][j];
+      if (p < P && n < nbnd) out[n * P + p] = acc[i][j];
     }
 }
 
-// R[k][i] = sum over chunks, accumulated in double in a fixed order: block
-// (16 outputs) x (16 lanes); lane l sums chunks l, l+16, ..., then the 16
-// lane sums are added in lane order.
+// Column n of R[k] (P rows) from the chunk partials [k][chunk][n][p], summed in
+// double in a fixed order: 16 rows at a time, lane l of a row sums chunks
+// l, l+16, ..., then the 16 lane sums are added in lane order.  The result,
+// rounded to T, is left in Rc[0..P).
 template <typename T>
-__global__ __launch_bounds__(256) void k_proj_reduce(const cplx<T>* __restrict__ partial,
-                                                     int nchunk, int PN, cplx<T>* __restrict__ R,
-                                                     const LzDevState* st) {
-  if (st && st->status) return;
+__device__ __forceinline__ void reduce_column(const cplx<T>* __restrict__ partial, int nchunk,
+                                              int P, int nbnd, int n, int k, cplx<T>* Rc) {
   __shared__ double rx[16][17], ry[16][17];
-  const int k = blockIdx.y;
   const int o = threadIdx.x % 16, lane = threadIdx.x / 16;
-  const int i = blockIdx.x * 16 + o;
-  const cplx<T>* pk = partial + (int64_t)k * nchunk * PN;
-  double sx = 0.0, sy = 0.0;
-  if (i < PN) {
+  const int64_t cs = (int64_t)P * nbnd;
+  const cplx<T>* pk = partial + (int64_t)k * nchunk * cs + (int64_t)n * P;
+  for (int p0 = 0; p0 < P; p0 += 16) {
+    const int p = p0 + o;
+    double sx = 0.0, sy = 0.0;
+    if (p < P) {
 #pragma unroll 4
-    for (int c = lane; c < nchunk; c += 16) {
-      const cplx<T> v = pk[(int64_t)c * PN + i];
-      sx += double(v.x);
-      sy += double(v.y);
+      for (int c = lane; c < nchunk; c += 16) {
+        const cplx<T> v = pk[(int64_t)c * cs + p];
+        sx += double(v.x);
+        sy += double(v.y);
+      }
     }
-  }
-  rx[o][lane] = sx;
-  ry[o][lane] = sy;
-  __syncthreads();
-  if (lane == 0 && i < PN) {
-    double ax = 0.0, ay = 0.0;
-    for (int l = 0; l < 16; ++l) {
-      ax += rx[o][l];
-      ay += ry[o][l];
+    rx[o][lane] = sx;
+    ry[o][lane] = sy;
+    __syncthreads();
+    if (lane == 0 && p < P) {
+      double ax = 0.0, ay = 0.0;
+      for (int l = 0; l < 16; ++l) {
+        ax += rx[o][l];
+        ay += ry[o][l];
+      }
+      Rc[p] = mk<T>(T(ax), T(ay));
     }
-    R[(int64_t)k * PN + i] = mk<T>(T(ax), T(ay));
+    __syncthreads();
   }
 }
 
-// input side: R = [S; B'] (rows nbnd + nproj).  C_in = [-S; D (B' - M S)];
+// Block (n, k): R[k][p][n] = column n of the reduced partials (set-up).
+template <typename T>
+__global__ __launch_bounds__(256) void k_reduce_plain(const cplx<T>* __restrict__ partial,
+                                                      int nchunk, int P, int nbnd,
+                                                      cplx<T>* __restrict__ R) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cplx<T>* Rc = reinterpret_cast<cplx<T>*>(smem_raw);  // [P]
+  const int n = blockIdx.x, k = blockIdx.y;
+  reduce_column<T>(partial, nchunk, P, nbnd, n, k, Rc);
+  for (int p = threadIdx.x; p < P; p += 256) R[((int64_t)k * P + p) * nbnd + n] = Rc[p];
+}
+
+// Input side, block (n, k): R[:, n] = [S; B'][:, n] reduced, then
+//   C_in[:, n] = [-S; D (B' - M S)][:, n];
 // with skip_pc (the start vector, or an operator application on a vector the
 // caller did not project) S is not applied: C_in = [0; D B'].
 template <typename T>
-__global__ __launch_bounds__(256) void k_coef_in(const cplx<T>* __restrict__ R,
-                                                 const cplx<T>* __restrict__ M,
-                                                 const double* __restrict__ dkb, int nbnd,
-                                                 int nproj, int skip_pc, cplx<T>* __restrict__ C,
-                                                 const LzDevState* st) {
+__global__ __launch_bounds__(256) void k_reduce_coef_in(const cplx<T>* __restrict__ partial,
+                                                        int nchunk, const cplx<T>* __restrict__ M,
+                                                        const double* __restrict__ dkb, int nbnd,
+                                                        int nproj, int skip_pc,
+                                                        cplx<T>* __restrict__ C,
+                                                        const LzDevState* st) {
   if (st && st->status) return;
-  const int k = blockIdx.y;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cplx<T>* Rc = reinterpret_cast<cplx<T>*>(smem_raw);  // [P]
+  const int n = blockIdx.x, k = blockIdx.y;
   const int P = nbnd + nproj;
-  const int i = blockIdx.x * 256 + threadIdx.x;
-  if (i >= P * nbnd) return;
-  const int p = i / nbnd, n = i - p * nbnd;
-  const cplx<T>* Rk = R + (int64_t)k * P * nbnd;
-  cplx<T> out;
-  if (p < nbnd) {
-    out = skip_pc ? czero<T>() : mk<T>(-Rk[i].x, -Rk[i].y);
-  } else {
-    const int q = p - nbnd;
-    double ax = double(Rk[i].x), ay = double(Rk[i].y);
-    if (!skip_pc) {
-      const cplx<T>* Mq = M + ((int64_t)k * nproj + q) * nbnd;
+  reduce_column<T>(partial, nchunk, P, nbnd, n, k, Rc);
+  cplx<T>* Ck = C + (int64_t)k * P * nbnd;
+  for (int p = threadIdx.x; p < P; p += 256) {
+    cplx<T> out;
+    if (p < nbnd) {
+      out = skip_pc ? czero<T>() : mk<T>(-Rc[p].x, -Rc[p].y);
+    } else {
+      const int q = p - nbnd;
+      double ax = double(Rc[p].x), ay = double(Rc[p].y);
+      if (!skip_pc) {
+        const cplx<T>* Mq = M + ((int64_t)k * nproj + q) * nbnd;
 #pragma unroll 4
-      for (int m = 0; m < nbnd; ++m) {
-        const cplx<T> mm = Mq[m], s = Rk[m * nbnd + n];
-        ax -= double(mm.x) * double(s.x) - double(mm.y) * double(s.y);
-        ay -= double(mm.x) * double(s.y) + double(mm.y) * double(s.x);
+        for (int m = 0; m < nbnd; ++m) {
+          const cplx<T> mm = Mq[m], sv = Rc[m];
+          ax -= double(mm.x) * double(sv.x) - double(mm.y) * double(sv.y);
+          ay -= double(mm.x) * double(sv.y) + double(mm.y) * double(sv.x);
+        }
       }
+      const double d = dkb[q];
+      out = mk<T>(T(d * ax), T(d * ay));
     }
-    const double d = dkb[q];
-    out = mk<T>(T(d * ax), T(d * ay));
+    Ck[p * nbnd + n] = out;
   }
-  C[(int64_t)k * P * nbnd + i] = out;
 }
 
-// output side: Rout = U^H Y (nbnd x nbnd), DB = rows nbnd.. of C_in.
-//   C_out = [-(Rout + M^H DB); DB]
+// Output side, block (n, k): Rout[:, n] = (U^H Y)[:, n] reduced, DB = rows
+// nbnd.. of C_in:  C_out[:, n] = [-(Rout + M^H DB); DB][:, n].
 template <typename T>
-__global__ __launch_bounds__(256) void k_coef_out(const cplx<T>* __restrict__ Rout,
-                                                  const cplx<T>* __restrict__ Cin,
-                                                  const cplx<T>* __restrict__ M, int nbnd,
-                                                  int nproj, cplx<T>* __restrict__ C,
-                                                  const LzDevState* st) {
+__global__ __launch_bounds__(256) void k_reduce_coef_out(const cplx<T>* __restrict__ partial,
+                                                         int nchunk,
+                                                         const cplx<T>* __restrict__ Cin,
+                                                         const cplx<T>* __restrict__ M, int nbnd,
+                                                         int nproj, cplx<T>* __restrict__ C,
+                                                         const LzDevState* st) {
   if (st && st->status) return;
-  const int k = blockIdx.y;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cplx<T>* Rc = reinterpret_cast<cplx<T>*>(smem_raw);  // [nbnd]
+  const int n = blockIdx.x, k = blockIdx.y;
   const int P = nbnd + nproj;
-  const int i = blockIdx.x * 256 + threadIdx.x;
-  if (i >= P * nbnd) return;
-  const int p = i / nbnd, n = i - p * nbnd;
+  reduce_column<T>(partial, nchunk, nbnd, nbnd, n, k, Rc);
   const cplx<T>* Ck = Cin + (int64_t)k * P * nbnd;
-  cplx<T> out;
-  if (p < nbnd) {
-    const cplx<T> r = Rout[((int64_t)k * nbnd + p) * nbnd + n];
-    double ax = double(r.x), ay = double(r.y);
+  cplx<T>* Co = C + (int64_t)k * P * nbnd;
+  for (int p = threadIdx.x; p < P; p += 256) {
+    cplx<T> out;
+    if (p < nbnd) {
+      double ax = double(Rc[p].x), ay = double(Rc[p].y);
 #pragma unroll 4
-    for (int q = 0; q < nproj; ++q) {
-      const cplx<T> mm = M[((int64_t)k * nproj + q) * nbnd + p];   // conj taken below
-      const cplx<T> db = Ck[(nbnd + q) * nbnd + n];
-      ax += double(mm.x) * double(db.x) + double(mm.y) * double(db.y);
-      ay += double(mm.x) * double(db.y) - double(mm.y) * double(db.x);
+      for (int q = 0; q < nproj; ++q) {
+        const cplx<T> mm = M[((int64_t)k * nproj + q) * nbnd + p];  // conj taken below
+        const cplx<T> db = Ck[(nbnd + q) * nbnd + n];
+        ax += double(mm.x) * double(db.x) + double(mm.y) * double(db.y);
+        ay += double(mm.x) * double(db.y) - double(mm.y) * double(db.x);
+      }
+      out = mk<T>(T(-ax), T(-ay));
+    } else {
+      out = Ck[p * nbnd + n];
     }
-    out = mk<T>(T(-ax), T(-ay));
-  } else {
-    out = Ck[i];
+    Co[p * nbnd + n] = out;
   }
-  C[(int64_t)k * P * nbnd + i] = out;
 }
 
 // Y[k][n][G] += sum_{p<P} A[k][p][G] C[k][p][n]; with DOTS the block also
@@ -472,7 +494,7 @@ __global__ __launch_bounds__(256) void k_spectrum(const double* __restrict__ bet
 // ---------------------------------------------------------------------------
 template <typename T>
 void LaunchLin<T>::proj_dot(const void* A, int P, int a_rows, void* X, const void* LW, int nbnd,
-                            int npwx, int nks, int chunk, int nchunk, void* partial, void* R,
+                            int npwx, int nks, int chunk, int nchunk, void* partial,
                             const LzDevState* st, hipStream_t s) {
   const int tpi = P <= 16 ? 1 : P <= 32 ? 2 : P <= 48 ? 3 : 4;
   const int tnj = nbnd <= 16 ? 1 : 2;
@@ -494,9 +516,6 @@ void LaunchLin<T>::proj_dot(const void* A, int P, int a_rows, void* X, const voi
     if (tpi == 1) { LZ_DOT(1, 2) } else if (tpi == 2) { LZ_DOT(2, 2) } else if (tpi == 3) { LZ_DOT(3, 2) } else { LZ_DOT(4, 2) }
   }
 #undef LZ_DOT
-  const int pn = P * nbnd;
-  hipLaunchKernelGGL(k_proj_reduce<T>, dim3((pn + 15) / 16, nks), dim3(256), 0, s,
-                     (const cplx<T>*)partial, nchunk, pn, (cplx<T>*)R, st);
 }
 
 template <typename T>
@@ -507,21 +526,30 @@ bool LaunchLin<T>::dot_single_tile(int P, int nbnd) {
 }
 
 template <typename T>
-void LaunchLin<T>::coef_in(const void* R, const void* M, const double* dkb, int nbnd, int nproj,
-                           int nks, bool skip_pc, void* C, const LzDevState* st, hipStream_t s) {
-  const int pn = (nbnd + nproj) * nbnd;
-  hipLaunchKernelGGL(k_coef_in<T>, dim3((pn + 255) / 256, nks), dim3(256), 0, s,
-                     (const cplx<T>*)R, (const cplx<T>*)M, dkb, nbnd, nproj, skip_pc ? 1 : 0,
-                     (cplx<T>*)C, st);
+void LaunchLin<T>::reduce(const void* partial, int nchunk, int P, int nbnd, int nks, void* R,
+                          hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce_plain<T>, dim3(nbnd, nks), dim3(256), (size_t)P * sizeof(cplx<T>),
+                     s, (const cplx<T>*)partial, nchunk, P, nbnd, (cplx<T>*)R);
 }
 
 template <typename T>
-void LaunchLin<T>::coef_out(const void* Rout, const void* Cin, const void* M, int nbnd, int nproj,
-                            int nks, void* C, const LzDevState* st, hipStream_t s) {
-  const int pn = (nbnd + nproj) * nbnd;
-  hipLaunchKernelGGL(k_coef_out<T>, dim3((pn + 255) / 256, nks), dim3(256), 0, s,
-                     (const cplx<T>*)Rout, (const cplx<T>*)Cin, (const cplx<T>*)M, nbnd, nproj,
-                     (cplx<T>*)C, st);
+void LaunchLin<T>::reduce_coef_in(const void* partial, int nchunk, const void* M,
+                                  const double* dkb, int nbnd, int nproj, int nks, bool skip_pc,
+                                  void* C, const LzDevState* st, hipStream_t s) {
+  const size_t lds = (size_t)(nbnd + nproj) * sizeof(cplx<T>);
+  hipLaunchKernelGGL(k_reduce_coef_in<T>, dim3(nbnd, nks), dim3(256), lds, s,
+                     (const cplx<T>*)partial, nchunk, (const cplx<T>*)M, dkb, nbnd, nproj,
+                     skip_pc ? 1 : 0, (cplx<T>*)C, st);
+}
+
+template <typename T>
+void LaunchLin<T>::reduce_coef_out(const void* partial, int nchunk, const void* Cin,
+                                   const void* M, int nbnd, int nproj, int nks, void* C,
+                                   const LzDevState* st, hipStream_t s) {
+  const size_t lds = (size_t)nbnd * sizeof(cplx<T>);
+  hipLaunchKernelGGL(k_reduce_coef_out<T>, dim3(nbnd, nks), dim3(256), lds, s,
+                     (const cplx<T>*)partial, nchunk, (const cplx<T>*)Cin, (const cplx<T>*)M,
+                     nbnd, nproj, (cplx<T>*)C, st);
 }
 
 // bands per thread of the update, and thread groups sharing a block

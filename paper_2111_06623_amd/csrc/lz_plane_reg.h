@@ -1,8 +1,9 @@
 // Plane passes of the Liouvillian application with register-resident line
 // transforms, for cubic grids N^3 with N in {24, 32, 48, 64}, single
 // precision (in double precision a line of 48 no longer fits the register
-// file with room to spare, and the LDS-pass kernels are faster).  The 2-D transform of a z-plane of one band (Sec. 2.4: the
-// local potential applied in real space to every response orbital) runs as
+// file with room to spare, and the LDS-pass kernels are faster).  The 2-D
+// transform of a z-plane of one band (Sec. 2.4: the local potential applied
+// in real space to every response orbital) runs as
 //   rows along i2 (only the rows that hold a stick), one line per thread;
 //   columns along i1, one line per thread, where the pointwise work happens
 //   between the inverse and the forward transform without leaving registers;
