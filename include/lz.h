@@ -178,6 +178,27 @@ lz_status lz_spectrum(lz_ctx *ctx, int32_t inst, int32_t m, const double *omega,
                       int32_t n_omega, double eta, double *chi, double *eps_inv,
                       double *loss);
 
+/* Extrapolation of the Lanczos coefficients for the spectrum (Sec. 3.3, the
+ * itermax0 / itermax / extrapolation inputs of the spectrum program). */
+typedef enum {
+  LZ_EXTRAP_NONE = 0,      /* the m0 computed coefficients only */
+  LZ_EXTRAP_CONSTANT = 1,  /* beta_i for i > m0: mean of the last half of beta_2..beta_m0 */
+  LZ_EXTRAP_OSC = 2        /* bi-constant: the mean over the same window of the beta_i
+                              with the parity of i */
+} lz_extrapolation;
+
+/*
+ * As lz_spectrum from the first m0 computed coefficients, the tridiagonal
+ * matrix extended to dimension m >= m0 by `extrapolation` (z_j = 0 beyond
+ * m0).  The extension costs O(m) per frequency, so m may be taken far larger
+ * than the number of steps run.  m is ignored with LZ_EXTRAP_NONE.  Errors:
+ * LZ_ERR_ARG for an unknown scheme, m < m0, or m > m0 with m0 < 4;
+ * LZ_ERR_STATE when m0 exceeds the completed steps.
+ */
+lz_status lz_spectrum_ext(lz_ctx *ctx, int32_t inst, int32_t m0, int32_t m,
+                          int32_t extrapolation, const double *omega, int32_t n_omega,
+                          double eta, double *chi, double *eps_inv, double *loss);
+
 /* Copy the right-hand side y of instance inst to a device array in the
  * caller's layout and precision (as lz_apply_liouvillian). */
 lz_status lz_get_rhs(lz_ctx *ctx, int32_t inst, void *y_out);

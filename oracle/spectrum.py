@@ -20,6 +20,14 @@ first-moment (f-sum) closed form.
 
 Each frequency is solved by LU with partial pivoting on the band matrix
 (LAPACK gbsv through scipy.linalg.solve_banded).
+
+Extrapolation (Sec. 3.3, the itermax0 / itermax / extrapolation inputs of
+the spectrum program; the paper defers the scheme to its references): the
+computed coefficients are extended to a larger tridiagonal matrix.  Reading
+used here: beyond the m0 computed coefficients every beta takes the mean of
+the last half of the computed beta_2..beta_m0 ('constant'), or the mean of the
+members of that window with the same index parity ('osc', bi-constant), and
+z_j = 0.
 """
 from __future__ import annotations
 
@@ -48,6 +56,28 @@ def chi_from_coefficients(beta, z, omega, eta, volume, m=None):
     return (4.0 / volume) * beta[0] * out
 
 
+def extrapolate(beta, z, m0, m, scheme):
+    """The first m0 coefficients extended to m by `scheme` ('no', 'constant'
+    or 'osc').  Returns (beta[0..m), z[0..m)); beta[i-1] is beta_i."""
+    beta = np.asarray(beta, dtype=np.float64)[:m0]
+    z = np.asarray(z, dtype=np.complex128)[:m0]
+    if scheme == "no" or m <= m0:
+        return beta, z
+    if m0 < 4:
+        raise ValueError("extrapolation needs at least 4 computed coefficients")
+    lo = max(2, m0 // 2 + 1)                       # window beta_lo..beta_m0 (1-based)
+    idx = np.arange(lo, m0 + 1)
+    win = beta[idx - 1]
+    if scheme == "constant":
+        tail = {0: win.mean(), 1: win.mean()}
+    elif scheme == "osc":
+        tail = {par: win[idx % 2 == par].mean() for par in (0, 1)}
+    else:
+        raise ValueError(scheme)
+    ext = np.array([tail[i % 2] for i in range(m0 + 1, m + 1)])
+    return np.concatenate([beta, ext]), np.concatenate([z, np.zeros(m - m0, dtype=np.complex128)])
+
+
 def dielectric(chi, qcart):
     """eps^-1, loss = -Im eps^-1 and eps = 1/eps^-1 (a scalar inverse)."""
     q2 = float(np.dot(qcart, qcart))
@@ -55,7 +85,13 @@ def dielectric(chi, qcart):
     return eps_inv, -eps_inv.imag, 1.0 / eps_inv
 
 
-def spectrum(beta, z, omega, eta, volume, qcart, m=None):
+def spectrum(beta, z, omega, eta, volume, qcart, m=None, m_total=None, scheme="no"):
+    """With m_total > m and scheme 'constant' or 'osc', the coefficients are
+    extrapolated from the first m to m_total before the solve."""
+    if m_total is not None and scheme != "no":
+        m0 = len(beta) if m is None else int(m)
+        beta, z = extrapolate(beta, z, m0, int(m_total), scheme)
+        m = len(beta)
     chi = chi_from_coefficients(beta, z, omega, eta, volume, m)
     eps_inv, loss, eps = dielectric(chi, qcart)
     return chi, eps_inv, loss, eps

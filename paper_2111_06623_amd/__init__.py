@@ -21,6 +21,8 @@ LZ_FP64, LZ_FP32, LZ_FP32_SPLITBF16 = 0, 1, 2
 LZ_TDDFT, LZ_RPA, LZ_IPA = 0, 1, 2
 APPROX = {"tddft": LZ_TDDFT, "rpa": LZ_RPA, "ipa": LZ_IPA}
 PREC = {"fp64": LZ_FP64, "fp32": LZ_FP32, "splitbf16": LZ_FP32_SPLITBF16}
+LZ_EXTRAP_NONE, LZ_EXTRAP_CONSTANT, LZ_EXTRAP_OSC = 0, 1, 2
+EXTRAPOLATION = {"no": LZ_EXTRAP_NONE, "constant": LZ_EXTRAP_CONSTANT, "osc": LZ_EXTRAP_OSC}
 STATUS_NAMES = {0: "ok", 1: "arg", 2: "hip", 3: "oom", 4: "not_pd", 5: "state", 6: "breakdown"}
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "liblz.so")
@@ -74,6 +76,8 @@ def load(path: str = LIB_PATH):
     lib.lz_get_state.argtypes = [vp, ctypes.c_int32, _ip, _ip]
     lib.lz_spectrum.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, _dp, ctypes.c_int32,
                                 ctypes.c_double, _dp, _dp, _dp]
+    lib.lz_spectrum_ext.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                    _dp, ctypes.c_int32, ctypes.c_double, _dp, _dp, _dp]
     lib.lz_get_rhs.argtypes = [vp, ctypes.c_int32, vp]
     lib.lz_reset.argtypes = [vp]
     lib.lz_stage_timer.argtypes = [vp, ctypes.c_int32]
@@ -81,7 +85,7 @@ def load(path: str = LIB_PATH):
     lib.lz_free.argtypes = [vp]
     lib.lz_last_error.restype = ctypes.c_char_p
     for f in ("lz_init", "lz_apply_liouvillian", "lz_step", "lz_get_coefficients", "lz_get_state",
-              "lz_spectrum", "lz_get_rhs", "lz_reset", "lz_stage_timer", "lz_stage_times", "lz_free"):
+              "lz_spectrum", "lz_spectrum_ext", "lz_get_rhs", "lz_reset", "lz_stage_timer", "lz_stage_times", "lz_free"):
         getattr(lib, f).restype = ctypes.c_int
     if path == LIB_PATH:
         _lib = lib
@@ -217,16 +221,22 @@ class Context:
                                        _ptr(beta, _dp), _ptr(gamma, _dp), _ptr(z, _dp)))
         return beta, gamma, z.view(np.complex128)
 
-    def spectrum(self, omega, eta, m=None, inst=0):
+    def spectrum(self, omega, eta, m=None, inst=0, m_total=None, extrapolation="no"):
+        """chi, eps^-1 and the loss function from the first m coefficients
+        (default: all computed), with extrapolation 'constant' or 'osc' of the
+        tridiagonal matrix to dimension m_total (lz_spectrum_ext)."""
         lib = load()
         omega = _f64(omega)
         if m is None:
             m = self.state(inst)[0]
+        scheme = EXTRAPOLATION[extrapolation] if isinstance(extrapolation, str) else int(extrapolation)
+        mt = int(m if m_total is None else m_total)
         chi = np.zeros(2 * len(omega))
         einv = np.zeros(2 * len(omega))
         loss = np.zeros(len(omega))
-        _check(lib.lz_spectrum(self.handle, int(inst), int(m), _ptr(omega, _dp), len(omega),
-                               float(eta), _ptr(chi, _dp), _ptr(einv, _dp), _ptr(loss, _dp)))
+        _check(lib.lz_spectrum_ext(self.handle, int(inst), int(m), mt, scheme, _ptr(omega, _dp),
+                                   len(omega), float(eta), _ptr(chi, _dp), _ptr(einv, _dp),
+                                   _ptr(loss, _dp)))
         return chi.view(np.complex128), einv.view(np.complex128), loss
 
     def rhs(self, inst=0):

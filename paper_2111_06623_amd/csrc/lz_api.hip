@@ -934,31 +934,64 @@ lz_status lz_get_coefficients(lz_ctx* c, int32_t inst, int32_t first, int32_t co
   });
 }
 
-lz_status lz_spectrum(lz_ctx* c, int32_t inst, int32_t m, const double* omega, int32_t n_omega,
-                      double eta, double* chi, double* eps_inv, double* loss) {
+lz_status lz_spectrum_ext(lz_ctx* c, int32_t inst, int32_t m0, int32_t m,
+                          int32_t extrapolation, const double* omega, int32_t n_omega, double eta,
+                          double* chi, double* eps_inv, double* loss) {
   return guarded([&] {
     if (!c || inst < 0 || inst >= (int)c->inst.size()) fail(LZ_ERR_ARG, "bad context or instance");
     if (n_omega < 0 || (n_omega > 0 && !omega)) fail(LZ_ERR_ARG, "bad frequency grid");
     if (!(eta > 0)) fail(LZ_ERR_ARG, "eta must be > 0");
+    if (extrapolation != LZ_EXTRAP_NONE && extrapolation != LZ_EXTRAP_CONSTANT &&
+        extrapolation != LZ_EXTRAP_OSC)
+      fail(LZ_ERR_ARG, "unknown extrapolation scheme");
+    if (extrapolation == LZ_EXTRAP_NONE) m = m0;
+    if (m < m0) fail(LZ_ERR_ARG, "m must be >= m0");
+    if (m > m0 && m0 < 4) fail(LZ_ERR_ARG, "extrapolation needs at least 4 computed coefficients");
     HIPC(hipSetDevice(c->device));
     read_state(c);
     Instance& I = *c->inst[inst];
-    if (m < 0 || m > I.steps_host) fail(LZ_ERR_STATE, "m exceeds the completed steps");
+    if (m0 < 0 || m0 > I.steps_host) fail(LZ_ERR_STATE, "m0 exceeds the completed steps");
     if (n_omega == 0) return;
+    // tail of the extended matrix: means over the last half of beta_2..beta_m0
+    double tail[2] = {0.0, 0.0};
+    if (m > m0) {
+      std::vector<double> b(m0);
+      HIPC(hipMemcpy(b.data(), I.beta.p, m0 * sizeof(double), hipMemcpyDeviceToHost));
+      const int lo = std::max(2, m0 / 2 + 1);
+      double sum[2] = {0.0, 0.0}, all = 0.0;
+      int cnt[2] = {0, 0};
+      for (int k = lo; k <= m0; ++k) {
+        sum[k & 1] += b[k - 1];
+        cnt[k & 1] += 1;
+        all += b[k - 1];
+      }
+      if (extrapolation == LZ_EXTRAP_OSC) {
+        tail[0] = sum[0] / cnt[0];
+        tail[1] = sum[1] / cnt[1];
+      } else {
+        tail[0] = tail[1] = all / (cnt[0] + cnt[1]);
+      }
+    }
     DBuf dw, dchi, dei, dl;
     dw.alloc(n_omega * sizeof(double));
     dchi.alloc(2 * n_omega * sizeof(double));
     dei.alloc(2 * n_omega * sizeof(double));
     dl.alloc(n_omega * sizeof(double));
     HIPC(hipMemcpyAsync(dw.p, omega, n_omega * sizeof(double), hipMemcpyHostToDevice, c->stream));
-    launch_spectrum(I.beta.as<double>(), I.z.as<double>(), m, dw.as<double>(), n_omega, eta, I.pref,
-                    I.fq, dchi.as<double>(), dei.as<double>(), dl.as<double>(), c->stream);
+    launch_spectrum(I.beta.as<double>(), I.z.as<double>(), m0, m, tail[0], tail[1],
+                    dw.as<double>(), n_omega, eta, I.pref, I.fq, dchi.as<double>(),
+                    dei.as<double>(), dl.as<double>(), c->stream);
     HIPC(hipGetLastError());
     HIPC(hipStreamSynchronize(c->stream));
     if (chi) HIPC(hipMemcpy(chi, dchi.p, 2 * n_omega * sizeof(double), hipMemcpyDeviceToHost));
     if (eps_inv) HIPC(hipMemcpy(eps_inv, dei.p, 2 * n_omega * sizeof(double), hipMemcpyDeviceToHost));
     if (loss) HIPC(hipMemcpy(loss, dl.p, n_omega * sizeof(double), hipMemcpyDeviceToHost));
   });
+}
+
+lz_status lz_spectrum(lz_ctx* c, int32_t inst, int32_t m, const double* omega, int32_t n_omega,
+                      double eta, double* chi, double* eps_inv, double* loss) {
+  return lz_spectrum_ext(c, inst, m, m, LZ_EXTRAP_NONE, omega, n_omega, eta, chi, eps_inv, loss);
 }
 
 lz_status lz_get_rhs(lz_ctx* c, int32_t inst, void* y_out) {

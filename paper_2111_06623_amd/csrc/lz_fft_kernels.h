@@ -102,23 +102,27 @@ __device__ __forceinline__ void plane_zero_scatter(const PlaneShm<T, N>& sh, con
 // ---------------------------------------------------------------------------
 // z pass, inverse: sphere -> sticks
 // ---------------------------------------------------------------------------
-template <typename T, int N>
+// sticks per block of the z passes (measured: 64-stick tiles on the
+// compile-time grids are slower; the passes want many small blocks)
+__host__ __device__ constexpr int zpass_tile(int) { return kStickTile; }
+
+template <typename T, int N, int ST = kStickTile>
 __device__ __forceinline__ void stick_fft(cplx<T>* lds, int pitch, const FftPlan& pz, int nst,
                                           const cplx<T>* tw, int tid, int dir) {
   if constexpr (N > 0) {
-    if (dir > 0) ct_fft<T, N, +1, kStickTile>(lds, LayRowsAll<N + 1>{}, nst, tw, tid);
-    else ct_fft<T, N, -1, kStickTile>(lds, LayRowsAll<N + 1>{}, nst, tw, tid);
+    if (dir > 0) ct_fft<T, N, +1, ST>(lds, LayRowsAll<N + 1>{}, nst, tw, tid);
+    else ct_fft<T, N, -1, ST>(lds, LayRowsAll<N + 1>{}, nst, tw, tid);
   } else {
     if (dir > 0) fft_lds<T, kStickMaxPt, +1>(lds, Lay{1, pitch, nullptr}, pz, nst, tw, tid, 256);
     else fft_lds<T, kStickMaxPt, -1>(lds, Lay{1, pitch, nullptr}, pz, nst, tw, tid, 256);
   }
 }
 
-// twiddles of the z plan: LDS copy behind the stick tile (compile-time form)
-template <typename T, int N>
+// twiddles of the z plan: LDS copy behind the tile of ST lines (compile-time form)
+template <typename T, int N, int ST = kStickTile>
 __device__ __forceinline__ const cplx<T>* stick_tw(cplx<T>* lds, const cplx<T>* twg, int tid) {
   if constexpr (N > 0) {
-    cplx<T>* t = lds + kStickTile * (N + 1);
+    cplx<T>* t = lds + ST * (N + 1);
     for (int i = tid; i < ct_twsize(N); i += 256) t[i] = twg[i];
     return t;
   } else {
@@ -139,11 +143,12 @@ __global__ __launch_bounds__(256) void k_zfft_inv(const cplx<T>* __restrict__ x,
   const int n3 = N > 0 ? N : n3_rt;
   const int b = blockIdx.y;
   const int k = b / nbnd;
-  const int s0 = blockIdx.x * kStickTile;
-  const int nst = min(kStickTile, S - s0);
+  constexpr int ST = zpass_tile(N);
+  const int s0 = blockIdx.x * ST;
+  const int nst = min(ST, S - s0);
   const int pitch = n3 + 1;
   const int tid = threadIdx.x;
-  const cplx<T>* tw = stick_tw<T, N>(lds, twg, tid);
+  const cplx<T>* tw = stick_tw<T, N, ST>(lds, twg, tid);
   const cplx<T>* xb = x + b * xs;
   const int* mp = map + ((int64_t)k * S + s0) * n3;
   for (int t = tid; t < nst * n3; t += 256) {
@@ -152,7 +157,7 @@ __global__ __launch_bounds__(256) void k_zfft_inv(const cplx<T>* __restrict__ x,
     lds[ls * pitch + z] = idx >= 0 ? xb[idx] : czero<T>();
   }
   __syncthreads();
-  stick_fft<T, N>(lds, pitch, pz, nst, tw, tid, +1);
+  stick_fft<T, N, ST>(lds, pitch, pz, nst, tw, tid, +1);
   cplx<T>* ob = out + (int64_t)b * n3 * S + s0;
   for (int t = tid; t < nst * n3; t += 256) {
     const int z = t / nst, ls = t - z * nst;
@@ -179,18 +184,19 @@ __global__ __launch_bounds__(256) void k_zfft_fwd(const cplx<T>* __restrict__ st
   const int n3 = N > 0 ? N : n3_rt;
   const int b = blockIdx.y;
   const int k = b / nbnd;
-  const int s0 = blockIdx.x * kStickTile;
-  const int nst = min(kStickTile, S - s0);
+  constexpr int ST = zpass_tile(N);
+  const int s0 = blockIdx.x * ST;
+  const int nst = min(ST, S - s0);
   const int pitch = n3 + 1;
   const int tid = threadIdx.x;
-  const cplx<T>* tw = stick_tw<T, N>(lds, twg, tid);
+  const cplx<T>* tw = stick_tw<T, N, ST>(lds, twg, tid);
   const cplx<T>* sb = sticks + (int64_t)b * n3 * S + s0;
   for (int t = tid; t < nst * n3; t += 256) {
     const int z = t / nst, ls = t - z * nst;
     lds[ls * pitch + z] = sb[(int64_t)z * S + ls];
   }
   __syncthreads();
-  stick_fft<T, N>(lds, pitch, pz, nst, tw, tid, -1);
+  stick_fft<T, N, ST>(lds, pitch, pz, nst, tw, tid, -1);
   const int* mp = map + ((int64_t)k * S + s0) * n3;
   const cplx<T>* xb = x + b * xs;
   cplx<T>* yb = y + b * xs;
@@ -642,7 +648,7 @@ template <typename T> static size_t plane_lds(const Grid3& g) {
 }
 template <typename T> static size_t stick_lds(const Grid3& g) {
   const int n = ct_size(g);
-  return (size_t)(kStickTile * (g.n3 + 1) + (n ? ct_twsize(n) : 0)) * sizeof(cplx<T>);
+  return (size_t)(zpass_tile(n) * (g.n3 + 1) + (n ? ct_twsize(n) : 0)) * sizeof(cplx<T>);
 }
 
 // dispatch a plane kernel on (N, MP)
@@ -676,7 +682,8 @@ template <typename T> static size_t stick_lds(const Grid3& g) {
 template <typename T>
 void LaunchFft<T>::zfft_inv(const Grid3& g, const void* x, int64_t xs, void* sticks,
                             const int* map, int nb, int nbnd, const LzDevState* st, hipStream_t s) {
-  dim3 grid((g.S + kStickTile - 1) / kStickTile, nb);
+  const int tile = zpass_tile(ct_size(g));
+  dim3 grid((g.S + tile - 1) / tile, nb);
   LZ_STICK_LAUNCH(k_zfft_inv, T, g, grid, stick_lds<T>(g), s, (const cplx<T>*)x, xs,
                   (cplx<T>*)sticks, map, g.S, g.n3, nbnd, g.p3, (const cplx<T>*)g.tw3, st);
 }
@@ -686,7 +693,8 @@ void LaunchFft<T>::zfft_fwd(const Grid3& g, const void* sticks, const void* x, i
                             const int* map, const void* kin, const double* eps, int nb, int nbnd,
                             int npwx, const LzDevState* st, hipStream_t s) {
   const T scale = T(1.0 / ((double)g.n1 * g.n2 * g.n3));
-  dim3 grid((g.S + kStickTile - 1) / kStickTile, nb);
+  const int tile = zpass_tile(ct_size(g));
+  dim3 grid((g.S + tile - 1) / tile, nb);
   LZ_STICK_LAUNCH(k_zfft_fwd, T, g, grid, stick_lds<T>(g), s, (const cplx<T>*)sticks,
                   (const cplx<T>*)x, xs, (cplx<T>*)y, map, (const T*)kin, eps, g.S, g.n3, nbnd,
                   npwx, scale, g.p3, (const cplx<T>*)g.tw3, st);
@@ -803,6 +811,16 @@ hipError_t enable_large_lds_fft() {
       hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, big); \
       if (e != hipSuccess) return e;                                                          \
     }                                                                                         \
+  }
+  {
+    const void* fns[] = {(const void*)k_zfft_inv<T, 24>, (const void*)k_zfft_inv<T, 32>,
+                         (const void*)k_zfft_inv<T, 48>, (const void*)k_zfft_inv<T, 64>,
+                         (const void*)k_zfft_fwd<T, 24>, (const void*)k_zfft_fwd<T, 32>,
+                         (const void*)k_zfft_fwd<T, 48>, (const void*)k_zfft_fwd<T, 64>};
+    for (const void* f : fns) {
+      hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, big);
+      if (e != hipSuccess) return e;
+    }
   }
   LZ_REG_ATTR(k_rl_local)
   LZ_REG_ATTR(k_rl_density)

@@ -100,9 +100,10 @@ template <typename T> int reg_plane_size(const Grid3& g);
 
 void launch_lz_finalize(const double* partial, int nblk, LzDevState* st, double* beta, double* z,
                         int max_steps, double tol, double yscale, hipStream_t s);
-void launch_spectrum(const double* beta, const double* z, int m, const double* omega, int nw,
-                     double eta, double pref, double fq, double* chi, double* einv, double* loss,
-                     hipStream_t s);
+// m coefficients, the first m0 computed, beta_i = tail_even / tail_odd beyond
+void launch_spectrum(const double* beta, const double* z, int m0, int m, double tail_even,
+                     double tail_odd, const double* omega, int nw, double eta, double pref,
+                     double fq, double* chi, double* einv, double* loss, hipStream_t s);
 void launch_set_state(LzDevState* st, hipStream_t s);
 
 constexpr int kStickTile = 16;    // sticks per block in the z passes

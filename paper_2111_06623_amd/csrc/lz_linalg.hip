@@ -283,11 +283,32 @@ __global__ __launch_bounds__(256) void k_proj_update(
     cplx<T> acc[NBT];
 #pragma unroll
     for (int j = 0; j < NBT; ++j) acc[j] = czero<T>();
-#pragma unroll 4
-    for (int p = 0; p < P; ++p) {
-      const cplx<T> a = Ak[(int64_t)p * npwx + g];
+    if constexpr (sizeof(T) == 8) {
+      // rows of A in batches of 16 whose loads are issued before they are
+      // used (faster in double precision; single precision measured faster
+      // with the plain loop below)
+      constexpr int kB = 16;
+      for (int p0 = 0; p0 < P; p0 += kB) {
+        cplx<T> a[kB];
 #pragma unroll
-      for (int j = 0; j < NBT; ++j) acc[j] = cadd<T>(acc[j], cmul<T>(a, Cq[p * NB + j]));
+        for (int i = 0; i < kB; ++i)
+          a[i] = p0 + i < P ? Ak[(int64_t)(p0 + i) * npwx + g] : czero<T>();
+#pragma unroll
+        for (int i = 0; i < kB; ++i) {
+          if (p0 + i < P) {
+#pragma unroll
+            for (int j = 0; j < NBT; ++j)
+              acc[j] = cadd<T>(acc[j], cmul<T>(a[i], Cq[(p0 + i) * NB + j]));
+          }
+        }
+      }
+    } else {
+#pragma unroll 4
+      for (int p = 0; p < P; ++p) {
+        const cplx<T> a = Ak[(int64_t)p * npwx + g];
+#pragma unroll
+        for (int j = 0; j < NBT; ++j) acc[j] = cadd<T>(acc[j], cmul<T>(a, Cq[p * NB + j]));
+      }
     }
     const int64_t kb = (int64_t)k * nbnd * npwx;
     const double w = DOTS ? wk[k] : 0.0;
@@ -464,21 +485,32 @@ __device__ __forceinline__ double2 zdiv(double2 a, double2 b) {
   return make_double2((a.x * b.x + a.y * b.y) / d, (a.y * b.x - a.x * b.y) / d);
 }
 
-__global__ __launch_bounds__(256) void k_spectrum(const double* __restrict__ beta, const double* __restrict__ z, int m,
-                           const double* __restrict__ omega, int nw, double eta, double pref,
-                           double fq, double* __restrict__ chi, double* __restrict__ einv,
-                           double* __restrict__ loss) {
+// Backward sweep of the transposed system, one frequency per thread, over the
+// m coefficients of an extended tridiagonal matrix: beta_i for i <= m0 from
+// the recursion, tail[i % 2] beyond (extrapolation), z_j = 0 for j > m0.
+__global__ __launch_bounds__(256) void k_spectrum(const double* __restrict__ beta,
+                                                  const double* __restrict__ z, int m0, int m,
+                                                  double tail_even, double tail_odd,
+                                                  const double* __restrict__ omega, int nw,
+                                                  double eta, double pref, double fq,
+                                                  double* __restrict__ chi,
+                                                  double* __restrict__ einv,
+                                                  double* __restrict__ loss) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nw) return;
+  auto bet = [&](int k) {  // beta_k, 1-based
+    return k <= m0 ? beta[k - 1] : ((k & 1) ? tail_odd : tail_even);
+  };
   const double2 wt = make_double2(omega[i], eta);
   double2 c = make_double2(0.0, 0.0), d = make_double2(0.0, 0.0);
   for (int j = m; j >= 1; --j) {
-    const double bnext = j < m ? beta[j] : 0.0;  // beta_{j+1}
+    const double bnext = j < m ? bet(j + 1) : 0.0;  // beta_{j+1}
     const double2 den = make_double2(wt.x - bnext * c.x, wt.y - bnext * c.y);
     // z_j is real in exact arithmetic; its rounding-level imaginary part is dropped
-    const double2 num = make_double2(z[2 * (j - 1)] + bnext * d.x, bnext * d.y);
+    const double zj = j <= m0 ? z[2 * (j - 1)] : 0.0;
+    const double2 num = make_double2(zj + bnext * d.x, bnext * d.y);
     d = zdiv(num, den);
-    c = zdiv(make_double2(beta[j - 1], 0.0), den);
+    c = zdiv(make_double2(bet(j), 0.0), den);
   }
   double2 ch = make_double2(0.0, 0.0);
   if (m > 0) ch = make_double2(pref * beta[0] * d.x, pref * beta[0] * d.y);
@@ -618,11 +650,11 @@ void launch_lz_finalize(const double* partial, int nblk, LzDevState* st, double*
                      max_steps, tol, yscale);
 }
 
-void launch_spectrum(const double* beta, const double* z, int m, const double* omega, int nw,
-                     double eta, double pref, double fq, double* chi, double* einv, double* loss,
-                     hipStream_t s) {
-  hipLaunchKernelGGL(k_spectrum, dim3((nw + 63) / 64), dim3(64), 0, s, beta, z, m, omega, nw, eta,
-                     pref, fq, chi, einv, loss);
+void launch_spectrum(const double* beta, const double* z, int m0, int m, double tail_even,
+                     double tail_odd, const double* omega, int nw, double eta, double pref,
+                     double fq, double* chi, double* einv, double* loss, hipStream_t s) {
+  hipLaunchKernelGGL(k_spectrum, dim3((nw + 63) / 64), dim3(64), 0, s, beta, z, m0, m, tail_even,
+                     tail_odd, omega, nw, eta, pref, fq, chi, einv, loss);
 }
 
 void launch_set_state(LzDevState* st, hipStream_t s) {

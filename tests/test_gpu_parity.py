@@ -371,3 +371,31 @@ def test_instances_in_one_context_match_single_contexts():
         assert _rel(po.cpu().numpy()[off:off + n].reshape(x.shape), L.apply_DK(x)) < 1e-12
         off += n
     ctx.free()
+
+
+@pytest.mark.parametrize("scheme", ["constant", "osc"])
+def test_extrapolated_spectrum_matches_oracle(scheme):
+    """cfg1, 200 computed steps extended to 20000 (the paper's use of the
+    extrapolation): the device sweep against the oracle's banded solve on the
+    same coefficients, and against the oracle's own recursion."""
+    lz = _lz()
+    s = config_system("cfg1")
+    ctx = lz.lz_init(s, prec="fp64", max_steps=200)
+    ctx.step(200)
+    om = np.linspace(0.0, 2.0, 400)
+    chi, _, loss = ctx.spectrum(om, 0.01, m=200, m_total=20000, extrapolation=scheme)
+    L = Liouvillian(s)
+    beta, _, z = ctx.coefficients()
+    same = spectrum.spectrum(beta, z, om, 0.01, L.cell.omega, L.Q, m=200, m_total=20000,
+                             scheme=scheme)
+    assert _rel(chi, same[0]) < 1e-10
+    ref = lanczos.run(L, 200)
+    chi_r, _, loss_r, _ = spectrum.spectrum(ref.beta, ref.z, om, 0.01, L.cell.omega, L.Q, m=200,
+                                            m_total=20000, scheme=scheme)
+    assert _loss_err(loss, loss_r) < 1e-6
+    plain, _, _ = ctx.spectrum(om, 0.01, m=200)
+    assert _rel(chi, plain) > 1e-8  # the tail changes the spectrum
+    with pytest.raises(lz.LzError) as e:
+        ctx.spectrum(om, 0.01, m=200, m_total=100, extrapolation=scheme)
+    assert e.value.status == lz.LZ_ERR_ARG
+    ctx.free()

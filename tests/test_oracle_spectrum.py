@@ -79,3 +79,65 @@ def test_high_frequency_tail_is_first_moment(approx):
     chi = spectrum.chi_from_coefficients(r.beta, r.z, w, 0.0, L.cell.omega)
     ref = 4.0 / L.cell.omega * closed_forms.first_moment(s)
     assert np.allclose((chi * w ** 2).real, ref, rtol=1e-6)
+
+
+def _tail_green(w, b_in, b_out):
+    """Green's function at the first site of a semi-infinite chain with zero
+    diagonal whose couplings alternate: b_out from the first site to the
+    second, b_in from the second to the third, and so on.  Closed form of the
+    periodic continued fraction g = 1/(w - b_out^2/(w - b_in^2 g)), i.e. the
+    root of w b_in^2 g^2 - (w^2 - b_out^2 + b_in^2) g + w = 0 with Im g < 0."""
+    a, bb, c = w * b_in ** 2, -(w * w - b_out ** 2 + b_in ** 2), w
+    disc = np.sqrt(bb * bb - 4 * a * c + 0j)
+    roots = [(-bb + disc) / (2 * a), (-bb - disc) / (2 * a)]
+    good = [r for r in roots if r.imag < 0]
+    assert len(good) == 1
+    return good[0]
+
+
+@pytest.mark.parametrize("scheme", ["constant", "osc"])
+def test_extrapolated_spectrum_equals_infinite_tail_closed_form(scheme):
+    """The extrapolated tridiagonal matrix, taken long enough, equals the
+    finite matrix closed by the self-energy of its infinite periodic tail."""
+    rng = np.random.default_rng(7)
+    m0 = 40
+    beta = rng.uniform(0.5, 1.5, m0)
+    beta[1::2] += 0.3  # an odd/even alternation, as the pseudo-Hermitian recursion gives
+    z = np.zeros(m0, dtype=np.complex128)
+    z[1::2] = rng.standard_normal(m0 // 2)
+    eta, vol = 0.05, 50.0
+    om = np.linspace(-0.5, 3.5, 41)
+    chi = spectrum.spectrum(beta, z, om, eta, vol, np.array([0.3, 0, 0]), m=m0, m_total=6000,
+                            scheme=scheme)[0]
+    lo = m0 // 2 + 1
+    idx = np.arange(lo, m0 + 1)
+    win = beta[idx - 1]
+    if scheme == "constant":
+        t = {0: win.mean(), 1: win.mean()}
+    else:
+        t = {p: win[idx % 2 == p].mean() for p in (0, 1)}
+    tm = np.diag(beta[1:m0], 1) + np.diag(beta[1:m0], -1)
+    ref = []
+    for w in om:
+        wt = w + 1j * eta
+        # site m0+1 couples to m0 through beta_{m0+1}, to m0+2 through beta_{m0+2}
+        g = _tail_green(wt, t[(m0 + 3) % 2], t[(m0 + 2) % 2])
+        sigma = t[(m0 + 1) % 2] ** 2 * g
+        a = wt * np.eye(m0) - tm
+        a[m0 - 1, m0 - 1] -= sigma
+        x = np.linalg.solve(a, np.eye(m0)[:, 0])
+        ref.append((4 / vol) * beta[0] * np.sum(z.real * x))
+    ref = np.array(ref)
+    assert np.abs(chi - ref).max() < 1e-10 * np.abs(ref).max()
+
+
+def test_extrapolation_keeps_the_computed_coefficients():
+    beta, z = _random_coefficients(30, 3)
+    b2, z2 = spectrum.extrapolate(beta, z, 30, 100, "osc")
+    assert np.array_equal(b2[:30], beta) and np.all(z2[30:] == 0)
+    assert np.all(b2[30::2] == b2[30]) and np.all(b2[31::2] == b2[31])
+    om = np.linspace(0, 2, 11)
+    plain = spectrum.chi_from_coefficients(beta, z, om, 0.05, 10.0)
+    same = spectrum.spectrum(beta, z, om, 0.05, 10.0, np.array([1.0, 0, 0]), m=30, m_total=30,
+                             scheme="osc")[0]
+    assert np.array_equal(plain, same)
