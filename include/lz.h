@@ -217,6 +217,21 @@ lz_status lz_get_rhs(lz_ctx *ctx, int32_t inst, void *y_out);
 lz_status lz_stage_timer(lz_ctx *ctx, int32_t mask);
 lz_status lz_stage_times(lz_ctx *ctx, int32_t inst, double *total_ms, int32_t *count);
 
+/*
+ * Checkpoint and restart of the recursion of one instance (Sec. 3.2 and the
+ * restart / restart_step inputs of App. A: more steps added to an existing
+ * run): the step count and scalar state, the coefficients
+ * computed so far and the three Lanczos vectors, in a host buffer the caller
+ * owns (lz_checkpoint_size bytes; about 3 vectors of the instance).  Loading
+ * into a context of the same system and precision, with max_steps at least
+ * the saved step count, continues the recursion bit for bit.  Errors:
+ * LZ_ERR_ARG for a small buffer, another system or precision, or a corrupt
+ * header.  All three synchronise the context's stream.
+ */
+lz_status lz_checkpoint_size(lz_ctx *ctx, int32_t inst, uint64_t *bytes);
+lz_status lz_checkpoint_save(lz_ctx *ctx, int32_t inst, void *buf, uint64_t bytes);
+lz_status lz_checkpoint_load(lz_ctx *ctx, int32_t inst, const void *buf, uint64_t bytes);
+
 /* Release every resource of the context (NULL is accepted). */
 lz_status lz_free(lz_ctx *ctx);
 

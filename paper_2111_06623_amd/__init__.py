@@ -78,6 +78,9 @@ def load(path: str = LIB_PATH):
                                 ctypes.c_double, _dp, _dp, _dp]
     lib.lz_spectrum_ext.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                     _dp, ctypes.c_int32, ctypes.c_double, _dp, _dp, _dp]
+    lib.lz_checkpoint_size.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_uint64)]
+    lib.lz_checkpoint_save.argtypes = [vp, ctypes.c_int32, vp, ctypes.c_uint64]
+    lib.lz_checkpoint_load.argtypes = [vp, ctypes.c_int32, vp, ctypes.c_uint64]
     lib.lz_get_rhs.argtypes = [vp, ctypes.c_int32, vp]
     lib.lz_reset.argtypes = [vp]
     lib.lz_stage_timer.argtypes = [vp, ctypes.c_int32]
@@ -85,7 +88,8 @@ def load(path: str = LIB_PATH):
     lib.lz_free.argtypes = [vp]
     lib.lz_last_error.restype = ctypes.c_char_p
     for f in ("lz_init", "lz_apply_liouvillian", "lz_step", "lz_get_coefficients", "lz_get_state",
-              "lz_spectrum", "lz_spectrum_ext", "lz_get_rhs", "lz_reset", "lz_stage_timer", "lz_stage_times", "lz_free"):
+              "lz_spectrum", "lz_spectrum_ext", "lz_checkpoint_size", "lz_checkpoint_save",
+              "lz_checkpoint_load", "lz_get_rhs", "lz_reset", "lz_stage_timer", "lz_stage_times", "lz_free"):
         getattr(lib, f).restype = ctypes.c_int
     if path == LIB_PATH:
         _lib = lib
@@ -238,6 +242,21 @@ class Context:
                                    len(omega), float(eta), _ptr(chi, _dp), _ptr(einv, _dp),
                                    _ptr(loss, _dp)))
         return chi.view(np.complex128), einv.view(np.complex128), loss
+
+    def checkpoint(self, inst=0):
+        """The recursion state of one instance as bytes (lz_checkpoint_save)."""
+        lib = load()
+        n = ctypes.c_uint64()
+        _check(lib.lz_checkpoint_size(self.handle, int(inst), ctypes.byref(n)))
+        buf = ctypes.create_string_buffer(n.value)
+        _check(lib.lz_checkpoint_save(self.handle, int(inst), buf, n.value))
+        return buf.raw
+
+    def restore(self, blob, inst=0):
+        """Continue from a checkpoint of the same system (lz_checkpoint_load)."""
+        lib = load()
+        buf = ctypes.create_string_buffer(bytes(blob), len(blob))
+        _check(lib.lz_checkpoint_load(self.handle, int(inst), buf, len(blob)))
 
     def rhs(self, inst=0):
         import torch

@@ -1033,6 +1033,96 @@ lz_status lz_stage_times(lz_ctx* c, int32_t inst, double* total_ms, int32_t* cou
   });
 }
 
+// ---- checkpoint / restart of the recursion state of one instance ----------
+namespace {
+constexpr uint64_t kCkptMagic = 0x4C5A434B50543031ull;  // "LZCKPT01"
+struct CkptHeader {
+  uint64_t magic;
+  int32_t prec, nks, nbnd, nproj, npwx, n1, n2, n3;
+  int32_t step, pad;
+  int64_t nvec;
+  LzDevState st;
+};
+uint64_t ckpt_bytes(const Instance& I, int step) {
+  return sizeof(CkptHeader) + (uint64_t)step * 3 * sizeof(double) + 3ull * I.nvec * I.csz;
+}
+}  // namespace
+
+lz_status lz_checkpoint_size(lz_ctx* c, int32_t inst, uint64_t* bytes) {
+  return guarded([&] {
+    if (!c || inst < 0 || inst >= (int)c->inst.size() || !bytes) fail(LZ_ERR_ARG, "bad argument");
+    HIPC(hipSetDevice(c->device));
+    read_state(c);
+    const Instance& I = *c->inst[inst];
+    *bytes = ckpt_bytes(I, I.steps_host);
+  });
+}
+
+lz_status lz_checkpoint_save(lz_ctx* c, int32_t inst, void* buf, uint64_t bytes) {
+  return guarded([&] {
+    if (!c || inst < 0 || inst >= (int)c->inst.size() || !buf) fail(LZ_ERR_ARG, "bad argument");
+    HIPC(hipSetDevice(c->device));
+    read_state(c);
+    Instance& I = *c->inst[inst];
+    const int step = I.steps_host;
+    if (bytes < ckpt_bytes(I, step)) fail(LZ_ERR_ARG, "checkpoint buffer too small");
+    CkptHeader h{};
+    h.magic = kCkptMagic;
+    h.prec = I.prec; h.nks = I.nks; h.nbnd = I.nbnd; h.nproj = I.nproj; h.npwx = I.npwx;
+    h.n1 = I.n1; h.n2 = I.n2; h.n3 = I.n3; h.step = step; h.nvec = I.nvec;
+    HIPC(hipMemcpy(&h.st, I.st.p, sizeof(LzDevState), hipMemcpyDeviceToHost));
+    char* o = static_cast<char*>(buf);
+    std::memcpy(o, &h, sizeof(h));
+    o += sizeof(h);
+    if (step > 0) {
+      HIPC(hipMemcpy(o, I.beta.p, step * sizeof(double), hipMemcpyDeviceToHost));
+      o += step * sizeof(double);
+      HIPC(hipMemcpy(o, I.z.p, 2 * step * sizeof(double), hipMemcpyDeviceToHost));
+      o += 2 * step * sizeof(double);
+    }
+    const size_t vb = (size_t)I.nvec * I.csz;
+    for (DBuf* d : {&I.X0, &I.X1, &I.LW}) {
+      HIPC(hipMemcpy(o, d->p, vb, hipMemcpyDeviceToHost));
+      o += vb;
+    }
+  });
+}
+
+lz_status lz_checkpoint_load(lz_ctx* c, int32_t inst, const void* buf, uint64_t bytes) {
+  return guarded([&] {
+    if (!c || inst < 0 || inst >= (int)c->inst.size() || !buf) fail(LZ_ERR_ARG, "bad argument");
+    if (bytes < sizeof(CkptHeader)) fail(LZ_ERR_ARG, "checkpoint truncated");
+    HIPC(hipSetDevice(c->device));
+    read_state(c);
+    Instance& I = *c->inst[inst];
+    CkptHeader h;
+    std::memcpy(&h, buf, sizeof(h));
+    if (h.magic != kCkptMagic) fail(LZ_ERR_ARG, "not a checkpoint of this library");
+    if (h.prec != I.prec || h.nks != I.nks || h.nbnd != I.nbnd || h.nproj != I.nproj ||
+        h.npwx != I.npwx || h.n1 != I.n1 || h.n2 != I.n2 || h.n3 != I.n3 || h.nvec != I.nvec)
+      fail(LZ_ERR_ARG, "checkpoint of a different system or precision");
+    if (h.step < 0 || h.step > I.max_steps) fail(LZ_ERR_ARG, "checkpoint exceeds max_steps");
+    if (bytes < ckpt_bytes(I, h.step)) fail(LZ_ERR_ARG, "checkpoint truncated");
+    const char* o = static_cast<const char*>(buf) + sizeof(h);
+    HIPC(hipMemcpy(I.st.p, &h.st, sizeof(LzDevState), hipMemcpyHostToDevice));
+    if (h.step > 0) {
+      HIPC(hipMemcpy(I.beta.p, o, h.step * sizeof(double), hipMemcpyHostToDevice));
+      o += h.step * sizeof(double);
+      HIPC(hipMemcpy(I.z.p, o, 2 * h.step * sizeof(double), hipMemcpyHostToDevice));
+      o += 2 * h.step * sizeof(double);
+    }
+    const size_t vb = (size_t)I.nvec * I.csz;
+    for (DBuf* d : {&I.X0, &I.X1, &I.LW}) {
+      HIPC(hipMemcpy(d->p, o, vb, hipMemcpyHostToDevice));
+      o += vb;
+    }
+    HIPC(hipDeviceSynchronize());
+    I.steps_host = h.step;
+    I.status_host = h.st.status;
+    c->started = true;
+  });
+}
+
 lz_status lz_free(lz_ctx* c) {
   return guarded([&] {
     if (!c) return;

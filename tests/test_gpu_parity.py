@@ -399,3 +399,31 @@ def test_extrapolated_spectrum_matches_oracle(scheme):
         ctx.spectrum(om, 0.01, m=200, m_total=100, extrapolation=scheme)
     assert e.value.status == lz.LZ_ERR_ARG
     ctx.free()
+
+
+@pytest.mark.parametrize("name,prec", [("cfg1", "fp64"), ("cfg2lo", "fp32")])
+def test_checkpoint_restart_continues_bit_for_bit(name, prec):
+    """30 steps, checkpoint, 20 more in the same context; a fresh context
+    loaded from the checkpoint runs the same 20 steps to the same bits."""
+    lz = _lz()
+    s = config_system(name)
+    a = lz.lz_init(s, prec=prec, max_steps=64)
+    a.step(31)
+    blob = a.checkpoint()
+    a.step(20)
+    ref = a.coefficients()
+    b = lz.lz_init(s, prec=prec, max_steps=64)
+    b.restore(blob)
+    assert b.state()[0] == 31
+    b.step(20)
+    got = b.coefficients()
+    assert np.array_equal(got[0], ref[0]) and np.array_equal(got[2], ref[2])
+    # a checkpoint of another system is refused
+    other = lz.lz_init(config_system("micro"), prec=prec, max_steps=64)
+    with pytest.raises(lz.LzError) as e:
+        other.restore(blob)
+    assert e.value.status == lz.LZ_ERR_ARG
+    with pytest.raises(lz.LzError):
+        b.restore(blob[:100])
+    for c in (a, b, other):
+        c.free()
