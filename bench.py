@@ -255,6 +255,9 @@ def main():
     dom = r["dom"]
     ngroups = max(1, min(s.nks * s.nbnd, -(-1024 // int(s.nr[2]))))
     gsize = -(-(s.nks * s.nbnd) // ngroups)
+    n = int(s.nr[0])
+    if head == "fp32" and n in (24, 32, 48, 64) and all(int(v) == n for v in s.nr):
+        gsize = 192 // n  # the register-line density pass: one chunk of bands per block
     ngroups = -(-(s.nks * s.nbnd) // gsize)
     nbytes, _ = stage_bytes(s, head, ngroups)
     gbs = {k: round(nbytes[k] / (per_launch[k] * 1e-3) / 1e9, 1) for k in nbytes if per_launch.get(k, 0) > 0}

@@ -668,12 +668,11 @@ std::unique_ptr<Instance> build_instance(const lz_system& sys, const lz_options&
   I.ngroups = std::max(1, std::min(I.nb, (1024 + I.n3 - 1) / I.n3));
   I.gsize = (I.nb + I.ngroups - 1) / I.ngroups;
   {
-    // the register-line kernel takes the bands of a group kRegPlaneThreads/N at a time
+    // the register-line kernel takes the bands of a group 192/N at a time
     const int rn = I.fp64 ? reg_plane_size<double>(I.grid) : reg_plane_size<float>(I.grid);
-    if (rn) {
-      const int npb = 192 / rn;
-      I.gsize = (I.gsize + npb - 1) / npb * npb;
-    }
+    // one chunk of 192/N bands per block: the block count is then a multiple of
+    // what the compute units hold at once, with no partly filled last round
+    if (rn) I.gsize = 192 / rn;
   }
   I.ngroups = (I.nb + I.gsize - 1) / I.gsize;
   I.dpart.alloc((size_t)I.ngroups * I.N * I.csz);
