@@ -382,6 +382,7 @@ __global__ __launch_bounds__(256) void k_hxc_planes_fwd(const cplx<T>* __restric
   const int64_t plane = (int64_t)n3 * np;
   for (int p = tid; p < np; p += 256) {
     cplx<T> s = czero<T>();
+#pragma unroll 8
     for (int g = 0; g < ngroups; ++g) s = cadd<T>(s, dpart[g * plane + (int64_t)z * np + p]);
     nr[(int64_t)z * np + p] = s;
     const int i1 = p / n2, i2 = p - i1 * n2;
@@ -493,6 +494,7 @@ __global__ __launch_bounds__(256) void k_hxc_l2_fwd(const cplx<T>* __restrict__ 
     const int ll = t / N, i = t - ll * N;
     const int64_t idx = (l0 + ll) * N + i;
     cplx<T> v = czero<T>();
+#pragma unroll 8
     for (int g = 0; g < ngroups; ++g) v = cadd<T>(v, dpart[g * NG + idx]);
     nr[idx] = v;
     lds[ll * P + i] = v;
