@@ -118,9 +118,76 @@ def pseudo_hermitian_lanczos(apply_D, apply_DK, inner, y, nsteps: int, project=N
     return LanczosResult(beta[:done].copy(), beta[:done].copy(), z[:done].copy(), status, done)
 
 
-def run(liouvillian, nsteps: int, reorth: bool = False) -> LanczosResult:
-    """Lanczos on an oracle Liouvillian from its own right-hand side y."""
+def nonhermitian_lanczos(apply_D, apply_DK, inner, y, nsteps: int, project=None,
+                         reorth: bool = False, tol: float = BREAKDOWN_TOL,
+                         y_scale: float = 1.0) -> LanczosResult:
+    """The non-Hermitian Lanczos biorthogonalisation of Sec. 2.5: two chains,
+    v_j driven by L and u_j by L^dagger = [[0, D+K], [D, 0]], both started
+    from u_1 = v_1 = (0, y) / ||y||, with (u_i, v_j) = delta_ij and
+    T_ij = (u_i, L v_j).  Reading of the coefficients (the paper names the
+    algorithm and its beta, gamma): with s = (u^_{j+1}, v^_{j+1}),
+        v^_{j+1} = L v_j - gamma_j v_{j-1},   u^_{j+1} = L^dagger u_j - beta_j u_{j-1},
+        beta_{j+1} = sqrt|s|,  gamma_{j+1} = s / beta_{j+1}  (complex in general),
+        v_{j+1} = v^_{j+1} / beta_{j+1},  u_{j+1} = u^_{j+1} / conj(gamma_{j+1}),
+    so T has sub-diagonal beta and super-diagonal gamma (zero diagonal: the
+    chains alternate between the components as in the pseudo-Hermitian
+    form).  z_j = ((y, 0), v_j).  Each step applies L once and L^dagger once:
+    one D and one D+K application, twice the pseudo-Hermitian cost.  beta_1 =
+    ||y||; a step with |s| <= (tol b)^2 (b the largest beta_2..beta_j) is a
+    breakdown; P_c is applied to both new vectors as in the other form."""
+    beta = np.zeros(nsteps)
+    gamma = np.zeros(nsteps, dtype=np.complex128)
+    z = np.zeros(nsteps, dtype=np.complex128)
+    ny2 = inner(y, y).real
+    if ny2 <= (tol ** 2) * y_scale:
+        return LanczosResult(beta[:0], gamma[:0], z[:0], "breakdown", 0)
+    beta[0] = math.sqrt(ny2)
+    gamma[0] = beta[0]
+    v = y / beta[0]
+    u = v.copy()
+    v_prev = np.zeros_like(y)
+    u_prev = np.zeros_like(y)
+    upper = False
+    basis = [(v, u, upper)] if reorth else None
+    status, done, bmax = "ok", 1, 0.0
+    for j in range(1, nsteps):
+        if upper:        # v = (q, 0): L v = (0, (D+K) q);  L^dagger u = (0, D q_u)
+            Lv, Lu = apply_DK(v), apply_D(u)
+        else:            # v = (0, p): L v = (D p, 0);      L^dagger u = ((D+K) p_u, 0)
+            Lv, Lu = apply_D(v), apply_DK(u)
+        vh = Lv - gamma[j - 1] * v_prev
+        uh = Lu - beta[j - 1] * u_prev
+        if project is not None:
+            vh, uh = project(vh), project(uh)
+        new_upper = not upper
+        if reorth:
+            for _ in range(2):
+                for (bv, bu, bup) in basis:
+                    if bup == new_upper:
+                        vh = vh - inner(bu, vh) * bv
+                        uh = uh - inner(bv, uh) * bu
+        sv = inner(uh, vh)
+        if abs(sv) <= (tol * bmax) ** 2:
+            status = "breakdown"
+            break
+        bj = math.sqrt(abs(sv))
+        gj = sv / bj
+        beta[j], gamma[j] = bj, gj
+        bmax = max(bmax, bj)
+        v_prev, v = v, vh / bj
+        u_prev, u = u, uh / np.conj(gj)
+        upper = new_upper
+        z[j] = inner(y, v) if upper else 0.0
+        done = j + 1
+        if reorth:
+            basis.append((v, u, upper))
+    return LanczosResult(beta[:done].copy(), gamma[:done].copy(), z[:done].copy(), status, done)
+
+
+def run(liouvillian, nsteps: int, reorth: bool = False, variant: str = "ph") -> LanczosResult:
+    """Lanczos on an oracle Liouvillian from its own right-hand side y:
+    variant "ph" (pseudo-Hermitian) or "nh" (non-Hermitian biorthogonal)."""
     y = liouvillian.rhs()
-    return pseudo_hermitian_lanczos(liouvillian.apply_D, liouvillian.apply_DK,
-                                    liouvillian.inner, y, nsteps, project=liouvillian.project_c,
-                                    reorth=reorth, y_scale=float(liouvillian.nbnd))
+    fn = pseudo_hermitian_lanczos if variant == "ph" else nonhermitian_lanczos
+    return fn(liouvillian.apply_D, liouvillian.apply_DK, liouvillian.inner, y, nsteps,
+              project=liouvillian.project_c, reorth=reorth, y_scale=float(liouvillian.nbnd))

@@ -19,7 +19,9 @@ orbitals.  It is pinned by the independent-particle sum over states and by the
 first-moment (f-sum) closed form.
 
 Each frequency is solved by LU with partial pivoting on the band matrix
-(LAPACK gbsv through scipy.linalg.solve_banded).
+(LAPACK gbsv through scipy.linalg.solve_banded).  The non-Hermitian form
+(gamma given) has a non-symmetric T with sub-diagonal beta and super-diagonal
+gamma, and its z_j are used as they are.
 
 Extrapolation (Sec. 3.3, the itermax0 / itermax / extrapolation inputs of
 the spectrum program; the paper defers the scheme to its references): the
@@ -35,20 +37,26 @@ import numpy as np
 import scipy.linalg as sla
 
 
-def chi_from_coefficients(beta, z, omega, eta, volume, m=None):
+def chi_from_coefficients(beta, z, omega, eta, volume, m=None, gamma=None):
+    """gamma None: the pseudo-Hermitian T (symmetric, real z reading);
+    otherwise T has sub-diagonal beta and super-diagonal gamma (the
+    non-Hermitian form) and z is kept complex."""
     beta = np.asarray(beta, dtype=np.float64)
-    z = np.asarray(z, dtype=np.complex128).real
+    z = np.asarray(z, dtype=np.complex128)
+    if gamma is None:
+        z = z.real
     m = len(beta) if m is None else int(m)
     if m == 0:
         # no Lanczos vector: the right-hand side vanished, chi = 0
         return np.zeros(len(omega), dtype=np.complex128)
-    off = beta[1:m]
+    sub = beta[1:m]
+    sup = sub if gamma is None else np.asarray(gamma, dtype=np.complex128)[1:m]
     out = np.empty(len(omega), dtype=np.complex128)
     rhs = np.zeros(m, dtype=np.complex128)
     rhs[0] = 1.0
     ab = np.zeros((3, m), dtype=np.complex128)
-    ab[0, 1:] = -off
-    ab[2, :-1] = -off
+    ab[0, 1:] = -sup
+    ab[2, :-1] = -sub
     for i, w in enumerate(np.asarray(omega, dtype=np.float64)):
         ab[1, :] = w + 1j * eta
         x = sla.solve_banded((1, 1), ab, rhs)
@@ -85,13 +93,16 @@ def dielectric(chi, qcart):
     return eps_inv, -eps_inv.imag, 1.0 / eps_inv
 
 
-def spectrum(beta, z, omega, eta, volume, qcart, m=None, m_total=None, scheme="no"):
+def spectrum(beta, z, omega, eta, volume, qcart, m=None, m_total=None, scheme="no", gamma=None):
     """With m_total > m and scheme 'constant' or 'osc', the coefficients are
-    extrapolated from the first m to m_total before the solve."""
+    extrapolated from the first m to m_total before the solve (pseudo-Hermitian
+    form only); gamma selects the non-Hermitian form."""
     if m_total is not None and scheme != "no":
+        if gamma is not None:
+            raise ValueError("extrapolation of the non-Hermitian coefficients is not defined here")
         m0 = len(beta) if m is None else int(m)
         beta, z = extrapolate(beta, z, m0, int(m_total), scheme)
         m = len(beta)
-    chi = chi_from_coefficients(beta, z, omega, eta, volume, m)
+    chi = chi_from_coefficients(beta, z, omega, eta, volume, m, gamma=gamma)
     eps_inv, loss, eps = dielectric(chi, qcart)
     return chi, eps_inv, loss, eps

@@ -139,3 +139,38 @@ def test_tridiagonal_eigenvalues_come_in_pairs_and_z_is_real(cfg1):
     assert np.abs(r.z.imag).max() < 1e-12 * np.abs(r.z).max()
     assert np.all(r.z[0::2] == 0)
     assert m == 60
+
+
+@pytest.mark.parametrize("approx", ["tddft", "rpa", "ipa"])
+def test_nonhermitian_exhaustive_equals_direct_resolvent(micro, approx):
+    """The biorthogonal recursion with two-sided re-biorthogonalisation
+    exhausts the Krylov space at the same dimension and reproduces the
+    direct resolvent of the explicit L."""
+    L = Liouvillian(micro, approx)
+    b = Brute(micro, approx).matrices()
+    nt = len(b.dE)
+    r = lanczos.run(L, 2 * nt + 5, reorth=True, variant="nh")
+    assert r.status == "breakdown" and r.steps == 2 * nt
+    chi = spectrum.chi_from_coefficients(r.beta, r.z, OMEGA, 0.05, L.cell.omega, gamma=r.gamma)
+    ref = b.chi_direct(OMEGA, 0.05)
+    assert np.abs(chi - ref).max() < 1e-10 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("approx", ["ipa", "rpa", "tddft"])
+def test_nonhermitian_free_electron_dyson_and_breakdown(free, approx):
+    L = Liouvillian(free, approx)
+    r = lanczos.run(L, 60, variant="nh")
+    d = closed_forms.free_electron_transitions(free.at, free.ecut, free.q, free.g0)
+    assert r.status == "breakdown"
+    assert r.steps == 2 * len(np.unique(np.round(d, 9)))
+    chi = spectrum.chi_from_coefficients(r.beta, r.z, OMEGA, 0.02, L.cell.omega, gamma=r.gamma)
+    fxc = float(free.fxc_r[0])
+    ref = closed_forms.free_electron_chi(free.at, free.ecut, free.q, free.g0, OMEGA, 0.02, approx, fxc)
+    assert np.abs(chi - ref).max() < 1e-12 * np.abs(ref).max()
+
+
+def test_nonhermitian_reduces_to_symmetric_chain_without_kernel(micro):
+    """IPA (K = 0): L^dagger = L, so u_j = v_j, gamma = beta and the chain is
+    the Hermitian Lanczos of L in the plain product."""
+    r = lanczos.run(Liouvillian(micro, "ipa"), 40, variant="nh")
+    assert np.abs(r.gamma - r.beta).max() < 1e-12 * r.beta.max()
