@@ -45,6 +45,8 @@ def _args():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a plain device copy of this size (counter calibration)")
+    ap.add_argument("--nh-steps", type=int, default=60,
+                    help="steps of the per-step comparison with the non-Hermitian recursion (0: skip)")
     ap.add_argument("--graph", action="store_true",
                     help="replay pairs of steps as captured graphs (measured no faster than eager)")
     return ap.parse_args()
@@ -109,6 +111,31 @@ def run_gpu(s, prec, applies, warmup, M, graph):
     ctx.free()
     return dict(elapsed=elapsed, applies=applies, loss=loss, t_spec=t_spec, stage_ms=ms,
                 stage_cnt=cnt, dom=dom, dom_ms=dms[di] / max(dcnt[di], 1), dom_launches=int(dcnt[di]))
+
+
+def nh_vs_ph(s, prec, steps):
+    """Wall time per Lanczos step of the pseudo-Hermitian and the non-Hermitian
+    recursions on the same system and precision (steps after a few warmup
+    steps, device synchronised on both sides; outside the timed region of the
+    headline metric)."""
+    import torch
+
+    import paper_2111_06623_amd as lz
+    out = {"precision": prec, "steps": steps}
+    for alg in ("ph", "nh"):
+        ctx = lz.lz_init(s, prec=prec, max_steps=steps + 8, algorithm=alg)
+        ctx.step(4)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        done, _ = ctx.step(steps)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        if done != steps + 4:
+            raise RuntimeError(f"{alg} recursion stopped at {done} steps")
+        out[f"{alg}_ms_per_step"] = round(1e3 * dt / steps, 4)
+        ctx.free()
+    out["nh_over_ph"] = round(out["nh_ms_per_step"] / out["ph_ms_per_step"], 3)
+    return out
 
 
 def kernel_sources_sha():
@@ -289,6 +316,10 @@ def main():
         out["mixed_vs_fp64"] = {"fp64_applies_per_s": round(rate["fp64"], 2),
                                 "fp32_applies_per_s": round(rate["fp32"], 2),
                                 "speedup": round(rate["fp32"] / rate["fp64"], 3), "gate": gate}
+    if a.nh_steps > 0:
+        _log(f"[bench] per-step cost: pseudo-Hermitian vs non-Hermitian, {a.nh_steps} steps ({head})")
+        out["nh_vs_ph"] = nh_vs_ph(s, head, a.nh_steps)
+        _log(f"[bench] {out['nh_vs_ph']}")
     if not a.no_cpu_baseline:
         _log("[bench] cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(s, a.cpu_seconds)

@@ -7,7 +7,9 @@
  * batch representation (Sec. 2.4, eqs. Liouvillian_SBR, D_super-operator_2,
  * K_super-operator_2) to a batch of response orbitals over bands and
  * k-points at fixed q, runs the pseudo-Hermitian Lanczos recursion (Sec. 2.5)
- * and evaluates chi, eps^-1 and the loss function from the tridiagonal matrix
+ * -- or, for comparison, the non-Hermitian biorthogonal one the paper
+ * contrasts it with -- and evaluates chi, eps^-1 and the loss function from
+ * the tridiagonal matrix
  * (eqs. post_processing, resolvent_Liouvillian_Lanczos_2_for_chi,
  * def_inv_microscopic_diel_tensor).
  *
@@ -97,6 +99,13 @@ typedef struct {
   const double *vkb_kq, *dkb;
 } lz_system;
 
+typedef enum {             /* Lanczos recursions of Sec. 2.5 */
+  LZ_PSEUDO_HERMITIAN = 0, /* one Liouvillian half-application per step (the production method) */
+  LZ_NON_HERMITIAN = 1     /* biorthogonal chains v (driven by L) and u (by L^dagger, with
+                              L^dagger = [[0, D+K], [D, 0]]): one D and one D+K application per
+                              step; complex gamma and z */
+} lz_algorithm;
+
 typedef struct {
   lz_precision prec;
   lz_approx approx;
@@ -105,6 +114,7 @@ typedef struct {
                          captured hipGraph (built on first use; not while the stage timer is
                          on); results are bitwise identical to the eager launches */
   int32_t autotune;   /* reserved, must be 0 or 1 (1 = time launch shapes at init) */
+  lz_algorithm algorithm;
 } lz_options;
 
 /*
@@ -136,10 +146,17 @@ lz_status lz_apply_liouvillian(lz_ctx *ctx, const void *q_in, const void *p_in,
                                void *q_out, void *p_out);
 
 /*
- * Advance the pseudo-Hermitian Lanczos recursion of every instance by n_steps
- * steps (one Liouvillian half-application each); the first call starts from
- * the vector (0, y).  Step j gives beta_{j+1}, gamma_{j+1} = beta_{j+1} and
- * z_{j+1}.  Coefficients stay on the device.  On return *steps_done is the
+ * Advance the Lanczos recursion of every instance by n_steps steps; the first
+ * call starts from the vector (0, y).  Step j gives beta_{j+1}, gamma_{j+1}
+ * and z_{j+1}.
+ * Pseudo-Hermitian: one Liouvillian half-application per step, gamma = beta.
+ * Non-Hermitian: u_1 = v_1 = (0, y)/||y||; step 0 takes only the norm
+ * (beta_1 = gamma_1 = ||y||), every later step applies L to v_j and L^dagger
+ * to u_j (one D and one D+K application) and sets, with
+ * s = (L^dagger u_j - beta_j u_{j-1}, L v_j - gamma_j v_{j-1}),
+ * beta_{j+1} = sqrt|s|, gamma_{j+1} = s / beta_{j+1} (complex) and
+ * z_{j+1} = ((y, 0), v_{j+1}); breakdown when |s| <= (1e-7 max beta)^2.
+ * Coefficients stay on the device.  On return *steps_done is the
  * total number of completed steps of instance 0.  Synchronises the stream once
  * at the end to read the status flags.
  * Returns LZ_BREAKDOWN when an instance exhausted its Krylov space (its
@@ -156,9 +173,17 @@ lz_status lz_reset(lz_ctx *ctx);
 
 /* Copy coefficients first..first+count-1 (0-based: index j holds beta_{j+1})
  * of instance inst to host arrays beta[count], gamma[count], z[count][2].
- * Any of the three may be NULL.  LZ_ERR_STATE if they are not computed yet. */
+ * Any of the three may be NULL.  LZ_ERR_STATE if they are not computed yet;
+ * LZ_ERR_ARG for a non-NULL gamma of a non-Hermitian instance (complex: see
+ * lz_get_gamma). */
 lz_status lz_get_coefficients(lz_ctx *ctx, int32_t inst, int32_t first, int32_t count,
                               double *beta, double *gamma, double *z);
+
+/* gamma_{first+1}..gamma_{first+count} of instance inst as complex numbers,
+ * host array gamma[count][2] (the super-diagonal of T; equal to beta with a
+ * zero imaginary part for the pseudo-Hermitian recursion).  LZ_ERR_STATE if
+ * not computed yet. */
+lz_status lz_get_gamma(lz_ctx *ctx, int32_t inst, int32_t first, int32_t count, double *gamma);
 
 /* Number of completed steps and recursion status (0 running, LZ_BREAKDOWN,
  * LZ_ERR_NOT_PD) of one instance.  Synchronises the stream. */
@@ -169,6 +194,8 @@ lz_status lz_get_state(lz_ctx *ctx, int32_t inst, int32_t *steps_done, int32_t *
  * computed on the device in double precision:
  *   (omega + i eta - T_m) x = e_1,   chi = (4/Omega) beta_1 sum_j Re(z_j) x_j,
  * (z_j is real in exact arithmetic; its rounding-level imaginary part is dropped),
+ * T_m with sub-diagonal beta and super-diagonal gamma.  For a non-Hermitian
+ * instance gamma and z are complex and sum_j z_j x_j is used as it is.
  *   eps^-1 = 1 + 4 pi chi / |Q|^2,   loss = -Im eps^-1.
  * omega: host [n_omega] (Ha); eta > 0 (Ha).  Outputs are host arrays:
  * chi[n_omega][2], eps_inv[n_omega][2], loss[n_omega]; any may be NULL.
@@ -192,7 +219,8 @@ typedef enum {
  * matrix extended to dimension m >= m0 by `extrapolation` (z_j = 0 beyond
  * m0).  The extension costs O(m) per frequency, so m may be taken far larger
  * than the number of steps run.  m is ignored with LZ_EXTRAP_NONE.  Errors:
- * LZ_ERR_ARG for an unknown scheme, m < m0, or m > m0 with m0 < 4;
+ * LZ_ERR_ARG for an unknown scheme, m < m0, m > m0 with m0 < 4, or m > m0 for
+ * a non-Hermitian instance;
  * LZ_ERR_STATE when m0 exceeds the completed steps.
  */
 lz_status lz_spectrum_ext(lz_ctx *ctx, int32_t inst, int32_t m0, int32_t m,
@@ -221,12 +249,12 @@ lz_status lz_stage_times(lz_ctx *ctx, int32_t inst, double *total_ms, int32_t *c
  * Checkpoint and restart of the recursion of one instance (Sec. 3.2 and the
  * restart / restart_step inputs of App. A: more steps added to an existing
  * run): the step count and scalar state, the coefficients
- * computed so far and the three Lanczos vectors, in a host buffer the caller
- * owns (lz_checkpoint_size bytes; about 3 vectors of the instance).  Loading
- * into a context of the same system and precision, with max_steps at least
- * the saved step count, continues the recursion bit for bit.  Errors:
- * LZ_ERR_ARG for a small buffer, another system or precision, or a corrupt
- * header.  All three synchronise the context's stream.
+ * computed so far and the Lanczos vectors, in a host buffer the caller
+ * owns (lz_checkpoint_size bytes; about 3 vectors of the instance, 4 for the
+ * non-Hermitian recursion).  Loading into a context of the same system,
+ * precision and algorithm, with max_steps at least the saved step count,
+ * continues the recursion bit for bit.  Errors: LZ_ERR_ARG for a small
+ * buffer, another system, precision or algorithm, or a corrupt header.  All three synchronise the context's stream.
  */
 lz_status lz_checkpoint_size(lz_ctx *ctx, int32_t inst, uint64_t *bytes);
 lz_status lz_checkpoint_save(lz_ctx *ctx, int32_t inst, void *buf, uint64_t bytes);

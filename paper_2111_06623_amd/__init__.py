@@ -23,6 +23,8 @@ APPROX = {"tddft": LZ_TDDFT, "rpa": LZ_RPA, "ipa": LZ_IPA}
 PREC = {"fp64": LZ_FP64, "fp32": LZ_FP32, "splitbf16": LZ_FP32_SPLITBF16}
 LZ_EXTRAP_NONE, LZ_EXTRAP_CONSTANT, LZ_EXTRAP_OSC = 0, 1, 2
 EXTRAPOLATION = {"no": LZ_EXTRAP_NONE, "constant": LZ_EXTRAP_CONSTANT, "osc": LZ_EXTRAP_OSC}
+LZ_PSEUDO_HERMITIAN, LZ_NON_HERMITIAN = 0, 1
+ALGORITHM = {"ph": LZ_PSEUDO_HERMITIAN, "nh": LZ_NON_HERMITIAN}
 STATUS_NAMES = {0: "ok", 1: "arg", 2: "hip", 3: "oom", 4: "not_pd", 5: "state", 6: "breakdown"}
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "liblz.so")
@@ -46,7 +48,8 @@ class LzSystem(ctypes.Structure):
 
 class LzOptions(ctypes.Structure):
     _fields_ = [("prec", ctypes.c_int), ("approx", ctypes.c_int), ("max_steps", ctypes.c_int32),
-                ("use_graph", ctypes.c_int32), ("autotune", ctypes.c_int32)]
+                ("use_graph", ctypes.c_int32), ("autotune", ctypes.c_int32),
+                ("algorithm", ctypes.c_int)]
 
 
 class LzError(RuntimeError):
@@ -74,6 +77,7 @@ def load(path: str = LIB_PATH):
     lib.lz_step.argtypes = [vp, ctypes.c_int32, _ip]
     lib.lz_get_coefficients.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _dp, _dp, _dp]
     lib.lz_get_state.argtypes = [vp, ctypes.c_int32, _ip, _ip]
+    lib.lz_get_gamma.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _dp]
     lib.lz_spectrum.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, _dp, ctypes.c_int32,
                                 ctypes.c_double, _dp, _dp, _dp]
     lib.lz_spectrum_ext.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
@@ -87,7 +91,8 @@ def load(path: str = LIB_PATH):
     lib.lz_stage_times.argtypes = [vp, ctypes.c_int32, _dp, _ip]
     lib.lz_free.argtypes = [vp]
     lib.lz_last_error.restype = ctypes.c_char_p
-    for f in ("lz_init", "lz_apply_liouvillian", "lz_step", "lz_get_coefficients", "lz_get_state",
+    for f in ("lz_init", "lz_apply_liouvillian", "lz_step", "lz_get_coefficients", "lz_get_gamma",
+              "lz_get_state",
               "lz_spectrum", "lz_spectrum_ext", "lz_checkpoint_size", "lz_checkpoint_save",
               "lz_checkpoint_load", "lz_get_rhs", "lz_reset", "lz_stage_timer", "lz_stage_times", "lz_free"):
         getattr(lib, f).restype = ctypes.c_int
@@ -152,8 +157,9 @@ def _stream_handle(device):
 
 
 def lz_init(systems, prec="fp64", approx="tddft", max_steps=1000, use_graph=False, autotune=False,
-            device=0, stream=None):
-    """Create a context for one system or a list of systems; returns a handle."""
+            device=0, stream=None, algorithm="ph"):
+    """Create a context for one system or a list of systems; returns a handle.
+    algorithm: "ph" (pseudo-Hermitian) or "nh" (non-Hermitian biorthogonal)."""
     lib = load()
     systems = systems if isinstance(systems, (list, tuple)) else [systems]
     arr = (LzSystem * len(systems))()
@@ -163,7 +169,8 @@ def lz_init(systems, prec="fp64", approx="tddft", max_steps=1000, use_graph=Fals
         keep.append(k)
     opt = LzOptions(PREC[prec] if isinstance(prec, str) else int(prec),
                     APPROX[approx] if isinstance(approx, str) else int(approx),
-                    int(max_steps), int(bool(use_graph)), int(bool(autotune)))
+                    int(max_steps), int(bool(use_graph)), int(bool(autotune)),
+                    ALGORITHM[algorithm] if isinstance(algorithm, str) else int(algorithm))
     out = ctypes.c_void_p()
     hs = _stream_handle(device) if stream is None else ctypes.c_void_p(stream)
     _check(lib.lz_init(arr, len(systems), ctypes.byref(opt), int(device), hs, ctypes.byref(out)))
@@ -176,6 +183,7 @@ class Context:
     def __init__(self, handle, systems, opt):
         self.handle = handle
         self.prec = opt.prec
+        self.algorithm = opt.algorithm
         self.nvec = [int(np.asarray(s.xk).shape[0]) * int(np.asarray(s.et_k).shape[1]) *
                      int(np.asarray(s.nl_kq).shape[1]) for s in systems]
         self.shapes = [(int(np.asarray(s.xk).shape[0]), int(np.asarray(s.et_k).shape[1]),
@@ -219,10 +227,14 @@ class Context:
         if count is None:
             count = self.state(inst)[0] - first
         beta = np.zeros(count)
-        gamma = np.zeros(count)
+        gamma = np.zeros(2 * count)
         z = np.zeros(2 * count)
         _check(lib.lz_get_coefficients(self.handle, int(inst), int(first), int(count),
-                                       _ptr(beta, _dp), _ptr(gamma, _dp), _ptr(z, _dp)))
+                                       _ptr(beta, _dp), None, _ptr(z, _dp)))
+        _check(lib.lz_get_gamma(self.handle, int(inst), int(first), int(count), _ptr(gamma, _dp)))
+        gamma = gamma.view(np.complex128)
+        if self.algorithm == LZ_PSEUDO_HERMITIAN:
+            gamma = gamma.real.copy()
         return beta, gamma, z.view(np.complex128)
 
     def spectrum(self, omega, eta, m=None, inst=0, m_total=None, extrapolation="no"):

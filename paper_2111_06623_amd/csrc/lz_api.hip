@@ -170,6 +170,7 @@ struct StageTimer {
 struct Instance {
   lz_precision prec;
   lz_approx approx;
+  bool nh = false;  // non-Hermitian biorthogonal recursion
   bool fp64;
   size_t csz;  // bytes per complex element
   int n1, n2, n3, N;
@@ -192,6 +193,7 @@ struct Instance {
   DBuf Aio, Mkb, Cin, Cout;
   DBuf ur, y;
   DBuf X0, X1, LW;
+  DBuf Y0, Y1, LU, gam;  // non-Hermitian recursion: the u chain and complex gamma
   DBuf sa, sb;
   DBuf dpart, nr, work, vp;
   DBuf dpartial;
@@ -337,6 +339,59 @@ void lanczos_step(Instance& I, int j, hipStream_t s) {
                            I.z.as<double>(), I.max_steps, kBreakdownTol, (double)I.nbnd, s));
 }
 
+// Non-Hermitian step j (Sec. 2.5).  Step 0 only takes ||y||.  Step j >= 1
+// applies L^dagger to u^_{j-1} and L to v^_{j-1} (X/Y of parity (j-1) & 1, a
+// lower vector for even j-1: L applies D to it and L^dagger D+K), and forms
+// u^_j and v^_j in place of u^_{j-2}, v^_{j-2} on the output sides; the v
+// formation also sums (u^_j, v^_j) and (y, v^_j) for the scalar decisions.
+template <typename T>
+void nh_step(Instance& I, int j, hipStream_t s) {
+  LzDevState* st = I.st.as<LzDevState>();
+  double* part = I.lzpart.as<double>();
+  if (j == 0) {
+    STAGE(I, ST_LANCZOS, s,
+          launch_nh_norm<T>(I.y.p, I.wk.as<double>(), (int64_t)I.nbnd * I.npwx, I.nks, part, s);
+          launch_nh_finalize(part, kNhNormBlocks, st, I.beta.as<double>(), I.gam.as<double>(),
+                             I.z.as<double>(), I.max_steps, kBreakdownTol, (double)I.nbnd, s));
+    return;
+  }
+  const int c = (j - 1) & 1;
+  void* V = c ? I.X1.p : I.X0.p;
+  void* Vn = c ? I.X0.p : I.X1.p;
+  void* U = c ? I.Y1.p : I.Y0.p;
+  void* Un = c ? I.Y0.p : I.Y1.p;
+  const bool v_upper = c != 0;
+  // u chain: L^dagger u^_{j-1}, then u^_j
+  input_side<T>(I, U, nullptr, true, st, s);
+  apply_core<T>(I, U, I.LU.p, !v_upper, st, s);
+  STAGE(I, ST_PROJ, s,
+        LaunchLin<T>::proj_dot(I.Aio.p, I.nbnd, I.ptot, I.LU.p, nullptr, I.nbnd, I.npwx, I.nks,
+                               I.chunk, I.nchunk, I.dpartial.p, st, s);
+        LaunchLin<T>::reduce_coef_out(I.dpartial.p, I.nchunk, I.Cin.p, I.Mkb.p, I.nbnd, I.nproj,
+                                      I.nks, I.Cout.p, st, s);
+        LaunchLin<T>::nh_form(false, I.LU.p, I.Aio.p, I.ptot, I.Cout.p, I.nbnd, I.npwx, I.nks, Un,
+                              nullptr, nullptr, nullptr, nullptr, st, s));
+  // v chain: L v^_{j-1}, then v^_j with the sums
+  input_side<T>(I, V, nullptr, true, st, s);
+  apply_core<T>(I, V, I.LW.p, v_upper, st, s);
+  STAGE(I, ST_PROJ, s,
+        LaunchLin<T>::proj_dot(I.Aio.p, I.nbnd, I.ptot, I.LW.p, nullptr, I.nbnd, I.npwx, I.nks,
+                               I.chunk, I.nchunk, I.dpartial.p, st, s);
+        LaunchLin<T>::reduce_coef_out(I.dpartial.p, I.nchunk, I.Cin.p, I.Mkb.p, I.nbnd, I.nproj,
+                                      I.nks, I.Cout.p, st, s);
+        LaunchLin<T>::nh_form(true, I.LW.p, I.Aio.p, I.ptot, I.Cout.p, I.nbnd, I.npwx, I.nks, Vn,
+                              I.y.p, Un, I.wk.as<double>(), part, st, s));
+  STAGE(I, ST_LANCZOS, s,
+        launch_nh_finalize(part, I.nlzblk, st, I.beta.as<double>(), I.gam.as<double>(),
+                           I.z.as<double>(), I.max_steps, kBreakdownTol, (double)I.nbnd, s));
+}
+
+template <typename T>
+void any_step(Instance& I, int j, hipStream_t s) {
+  if (I.nh) nh_step<T>(I, j, s);
+  else lanczos_step<T>(I, j, s);
+}
+
 // Capture one odd step (D+K on the upper vector) and the following even step
 // (D on the lower vector) as a graph.  Every step after the first has one of
 // these two forms: the kernels read the step number and the update
@@ -345,11 +400,11 @@ void build_pair_graph(Instance& I, hipStream_t s) {
   hipGraph_t g = nullptr;
   HIPC(hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed));
   if (I.fp64) {
-    lanczos_step<double>(I, 1, s);
-    lanczos_step<double>(I, 2, s);
+    any_step<double>(I, 1, s);
+    any_step<double>(I, 2, s);
   } else {
-    lanczos_step<float>(I, 1, s);
-    lanczos_step<float>(I, 2, s);
+    any_step<float>(I, 1, s);
+    any_step<float>(I, 2, s);
   }
   const hipError_t e = hipStreamEndCapture(s, &g);
   if (e != hipSuccess || g == nullptr) fail(LZ_ERR_HIP, std::string("graph capture: ") + hipGetErrorString(e));
@@ -389,6 +444,7 @@ std::unique_ptr<Instance> build_instance(const lz_system& sys, const lz_options&
   Instance& I = *Ip;
   I.prec = opt.prec;
   I.approx = opt.approx;
+  I.nh = opt.algorithm == LZ_NON_HERMITIAN;
   I.fp64 = opt.prec == LZ_FP64;
   I.csz = I.fp64 ? 16 : 8;
   I.max_steps = opt.max_steps;
@@ -687,10 +743,14 @@ std::unique_ptr<Instance> build_instance(const lz_system& sys, const lz_options&
   I.Mkb.alloc((size_t)I.nks * std::max(1, I.nproj) * I.nbnd * I.csz);
   I.nlzblk = I.fp64 ? LaunchLin<double>::update_blocks(I.ptot, I.nbnd, I.npwx, I.nks)
                     : LaunchLin<float>::update_blocks(I.ptot, I.nbnd, I.npwx, I.nks);
-  I.lzpart.alloc((size_t)I.nlzblk * 3 * sizeof(double));
+  I.lzpart.alloc((size_t)std::max(I.nlzblk, kNhNormBlocks) * 4 * sizeof(double));
   I.st.alloc(sizeof(LzDevState));
   I.beta.alloc((size_t)I.max_steps * sizeof(double));
   I.z.alloc((size_t)I.max_steps * 2 * sizeof(double));
+  if (I.nh) {
+    I.Y0.alloc(vb); I.Y1.alloc(vb); I.LU.alloc(vb);
+    I.gam.alloc((size_t)I.max_steps * 2 * sizeof(double));
+  }
   if (I.fp64) build_device_tables<double>(I, s, EK);
   else build_device_tables<float>(I, s, EK);
   return Ip;
@@ -749,6 +809,10 @@ void start_recursion(lz_ctx* c) {
     launch_set_state(I.st.as<LzDevState>(), c->stream);
     HIPC(hipMemcpyAsync(I.X0.p, I.y.p, (size_t)I.nvec * I.csz, hipMemcpyDeviceToDevice, c->stream));
     HIPC(hipMemsetAsync(I.X1.p, 0, (size_t)I.nvec * I.csz, c->stream));
+    if (I.nh) {
+      HIPC(hipMemcpyAsync(I.Y0.p, I.y.p, (size_t)I.nvec * I.csz, hipMemcpyDeviceToDevice, c->stream));
+      HIPC(hipMemsetAsync(I.Y1.p, 0, (size_t)I.nvec * I.csz, c->stream));
+    }
     I.steps_host = 0;
     I.status_host = 0;
   }
@@ -782,6 +846,8 @@ lz_status lz_init(const lz_system* sys, int32_t n_inst, const lz_options* opt, i
     if (opt->prec != LZ_FP64 && opt->prec != LZ_FP32) fail(LZ_ERR_ARG, "unknown precision");
     if (opt->approx != LZ_TDDFT && opt->approx != LZ_RPA && opt->approx != LZ_IPA)
       fail(LZ_ERR_ARG, "unknown approximation");
+    if (opt->algorithm != LZ_PSEUDO_HERMITIAN && opt->algorithm != LZ_NON_HERMITIAN)
+      fail(LZ_ERR_ARG, "unknown Lanczos algorithm");
     int ndev = 0;
     HIPC(hipGetDeviceCount(&ndev));
     if (device < 0 || device >= ndev) fail(LZ_ERR_ARG, "no such device");
@@ -885,8 +951,8 @@ lz_status lz_step(lz_ctx* c, int32_t n_steps, int32_t* steps_done) {
           HIPC(hipGraphLaunch(I.gpair, c->stream));
           j += 2;
         } else {
-          if (I.fp64) lanczos_step<double>(I, j, c->stream);
-          else lanczos_step<float>(I, j, c->stream);
+          if (I.fp64) any_step<double>(I, j, c->stream);
+          else any_step<float>(I, j, c->stream);
           ++j;
         }
       }
@@ -926,10 +992,31 @@ lz_status lz_get_coefficients(lz_ctx* c, int32_t inst, int32_t first, int32_t co
     read_state(c);
     Instance& I = *c->inst[inst];
     if (first + count > I.steps_host) fail(LZ_ERR_STATE, "coefficients not computed yet");
+    if (gamma && I.nh) fail(LZ_ERR_ARG, "gamma is complex in the non-Hermitian recursion: use lz_get_gamma");
     if (count == 0) return;
     if (beta) HIPC(hipMemcpy(beta, I.beta.as<double>() + first, count * sizeof(double), hipMemcpyDeviceToHost));
     if (gamma) HIPC(hipMemcpy(gamma, I.beta.as<double>() + first, count * sizeof(double), hipMemcpyDeviceToHost));
     if (z) HIPC(hipMemcpy(z, I.z.as<double>() + 2 * first, 2 * count * sizeof(double), hipMemcpyDeviceToHost));
+  });
+}
+
+lz_status lz_get_gamma(lz_ctx* c, int32_t inst, int32_t first, int32_t count, double* gamma) {
+  return guarded([&] {
+    if (!c || inst < 0 || inst >= (int)c->inst.size()) fail(LZ_ERR_ARG, "bad context or instance");
+    if (first < 0 || count < 0) fail(LZ_ERR_ARG, "negative range");
+    if (count > 0 && !gamma) fail(LZ_ERR_ARG, "null gamma");
+    HIPC(hipSetDevice(c->device));
+    read_state(c);
+    Instance& I = *c->inst[inst];
+    if (first + count > I.steps_host) fail(LZ_ERR_STATE, "coefficients not computed yet");
+    if (count == 0) return;
+    if (I.nh) {
+      HIPC(hipMemcpy(gamma, I.gam.as<double>() + 2 * first, 2 * count * sizeof(double), hipMemcpyDeviceToHost));
+    } else {
+      std::vector<double> b(count);
+      HIPC(hipMemcpy(b.data(), I.beta.as<double>() + first, count * sizeof(double), hipMemcpyDeviceToHost));
+      for (int i = 0; i < count; ++i) { gamma[2 * i] = b[i]; gamma[2 * i + 1] = 0.0; }
+    }
   });
 }
 
@@ -950,6 +1037,7 @@ lz_status lz_spectrum_ext(lz_ctx* c, int32_t inst, int32_t m0, int32_t m,
     read_state(c);
     Instance& I = *c->inst[inst];
     if (m0 < 0 || m0 > I.steps_host) fail(LZ_ERR_STATE, "m0 exceeds the completed steps");
+    if (I.nh && m > m0) fail(LZ_ERR_ARG, "extrapolation is defined for the pseudo-Hermitian recursion only");
     if (n_omega == 0) return;
     // tail of the extended matrix: means over the last half of beta_2..beta_m0
     double tail[2] = {0.0, 0.0};
@@ -977,7 +1065,8 @@ lz_status lz_spectrum_ext(lz_ctx* c, int32_t inst, int32_t m0, int32_t m,
     dei.alloc(2 * n_omega * sizeof(double));
     dl.alloc(n_omega * sizeof(double));
     HIPC(hipMemcpyAsync(dw.p, omega, n_omega * sizeof(double), hipMemcpyHostToDevice, c->stream));
-    launch_spectrum(I.beta.as<double>(), I.z.as<double>(), m0, m, tail[0], tail[1],
+    launch_spectrum(I.beta.as<double>(), I.nh ? I.gam.as<double>() : nullptr, I.z.as<double>(),
+                    m0, m, tail[0], tail[1],
                     dw.as<double>(), n_omega, eta, I.pref, I.fq, dchi.as<double>(),
                     dei.as<double>(), dl.as<double>(), c->stream);
     HIPC(hipGetLastError());
@@ -1034,16 +1123,29 @@ lz_status lz_stage_times(lz_ctx* c, int32_t inst, double* total_ms, int32_t* cou
 
 // ---- checkpoint / restart of the recursion state of one instance ----------
 namespace {
-constexpr uint64_t kCkptMagic = 0x4C5A434B50543031ull;  // "LZCKPT01"
+constexpr uint64_t kCkptMagic = 0x4C5A434B50543032ull;  // "LZCKPT02"
 struct CkptHeader {
   uint64_t magic;
   int32_t prec, nks, nbnd, nproj, npwx, n1, n2, n3;
-  int32_t step, pad;
+  int32_t step, alg;
   int64_t nvec;
   LzDevState st;
 };
+// pseudo-Hermitian: beta, z and the vectors X0, X1, LW; non-Hermitian: beta,
+// gamma, z and the two chains X0, X1, Y0, Y1
 uint64_t ckpt_bytes(const Instance& I, int step) {
-  return sizeof(CkptHeader) + (uint64_t)step * 3 * sizeof(double) + 3ull * I.nvec * I.csz;
+  const uint64_t coef = I.nh ? 5 : 3, vecs = I.nh ? 4 : 3;
+  return sizeof(CkptHeader) + (uint64_t)step * coef * sizeof(double) + vecs * I.nvec * I.csz;
+}
+struct CkptVectors {
+  DBuf* v[4];
+  int n;
+  DBuf** begin() { return v; }
+  DBuf** end() { return v + n; }
+};
+CkptVectors ckpt_vectors(Instance& I) {
+  if (I.nh) return {{&I.X0, &I.X1, &I.Y0, &I.Y1}, 4};
+  return {{&I.X0, &I.X1, &I.LW, nullptr}, 3};
 }
 }  // namespace
 
@@ -1069,6 +1171,7 @@ lz_status lz_checkpoint_save(lz_ctx* c, int32_t inst, void* buf, uint64_t bytes)
     h.magic = kCkptMagic;
     h.prec = I.prec; h.nks = I.nks; h.nbnd = I.nbnd; h.nproj = I.nproj; h.npwx = I.npwx;
     h.n1 = I.n1; h.n2 = I.n2; h.n3 = I.n3; h.step = step; h.nvec = I.nvec;
+    h.alg = I.nh ? LZ_NON_HERMITIAN : LZ_PSEUDO_HERMITIAN;
     HIPC(hipMemcpy(&h.st, I.st.p, sizeof(LzDevState), hipMemcpyDeviceToHost));
     char* o = static_cast<char*>(buf);
     std::memcpy(o, &h, sizeof(h));
@@ -1076,11 +1179,15 @@ lz_status lz_checkpoint_save(lz_ctx* c, int32_t inst, void* buf, uint64_t bytes)
     if (step > 0) {
       HIPC(hipMemcpy(o, I.beta.p, step * sizeof(double), hipMemcpyDeviceToHost));
       o += step * sizeof(double);
+      if (I.nh) {
+        HIPC(hipMemcpy(o, I.gam.p, 2 * step * sizeof(double), hipMemcpyDeviceToHost));
+        o += 2 * step * sizeof(double);
+      }
       HIPC(hipMemcpy(o, I.z.p, 2 * step * sizeof(double), hipMemcpyDeviceToHost));
       o += 2 * step * sizeof(double);
     }
     const size_t vb = (size_t)I.nvec * I.csz;
-    for (DBuf* d : {&I.X0, &I.X1, &I.LW}) {
+    for (DBuf* d : ckpt_vectors(I)) {
       HIPC(hipMemcpy(o, d->p, vb, hipMemcpyDeviceToHost));
       o += vb;
     }
@@ -1100,6 +1207,8 @@ lz_status lz_checkpoint_load(lz_ctx* c, int32_t inst, const void* buf, uint64_t 
     if (h.prec != I.prec || h.nks != I.nks || h.nbnd != I.nbnd || h.nproj != I.nproj ||
         h.npwx != I.npwx || h.n1 != I.n1 || h.n2 != I.n2 || h.n3 != I.n3 || h.nvec != I.nvec)
       fail(LZ_ERR_ARG, "checkpoint of a different system or precision");
+    if (h.alg != (I.nh ? LZ_NON_HERMITIAN : LZ_PSEUDO_HERMITIAN))
+      fail(LZ_ERR_ARG, "checkpoint of the other Lanczos algorithm");
     if (h.step < 0 || h.step > I.max_steps) fail(LZ_ERR_ARG, "checkpoint exceeds max_steps");
     if (bytes < ckpt_bytes(I, h.step)) fail(LZ_ERR_ARG, "checkpoint truncated");
     const char* o = static_cast<const char*>(buf) + sizeof(h);
@@ -1107,11 +1216,15 @@ lz_status lz_checkpoint_load(lz_ctx* c, int32_t inst, const void* buf, uint64_t 
     if (h.step > 0) {
       HIPC(hipMemcpy(I.beta.p, o, h.step * sizeof(double), hipMemcpyHostToDevice));
       o += h.step * sizeof(double);
+      if (I.nh) {
+        HIPC(hipMemcpy(I.gam.p, o, 2 * h.step * sizeof(double), hipMemcpyHostToDevice));
+        o += 2 * h.step * sizeof(double);
+      }
       HIPC(hipMemcpy(I.z.p, o, 2 * h.step * sizeof(double), hipMemcpyHostToDevice));
       o += 2 * h.step * sizeof(double);
     }
     const size_t vb = (size_t)I.nvec * I.csz;
-    for (DBuf* d : {&I.X0, &I.X1, &I.LW}) {
+    for (DBuf* d : ckpt_vectors(I)) {
       HIPC(hipMemcpy(d->p, o, vb, hipMemcpyHostToDevice));
       o += vb;
     }

@@ -198,6 +198,11 @@ struct LzDevState {
   double bmax;       // largest beta_2..beta_j so far
   double a, b;       // next update: w <- a*LW + b*w_old
   double beta_prev;  // beta of the last completed step
+  // non-Hermitian recursion: complex coefficients (re, im) of the next
+  // formation v^ <- cv1 L v^ + cv2 v^_old, u^ <- cu1 L^dagger u^ + cu2 u^_old,
+  // and gamma of the last completed step
+  double cv1[2], cv2[2], cu1[2], cu2[2];
+  double gamma_prev[2];
 };
 
 }  // namespace lz

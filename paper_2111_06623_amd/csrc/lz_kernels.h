@@ -84,6 +84,13 @@ template <typename T> struct LaunchLin {
                           int nbnd, int npwx, int nks, const void* X, const void* y,
                           const double* wk, double* lzpart, const LzDevState* st, hipStream_t s);
   static int update_blocks(int P, int nbnd, int npwx, int nks);
+  // non-Hermitian formation on the output side (P = a_rows = c_rows): as
+  // proj_update, then H <- c1 LY' + c2 H with the state coefficients of the
+  // u chain (v_chain false) or of the v chain, which also sums (U2, H) and
+  // (y, H) into lzpart (4 per block, update_blocks of them)
+  static void nh_form(bool v_chain, void* LY, const void* A, int P, const void* C, int nbnd,
+                      int npwx, int nks, void* H, const void* y, const void* U2, const double* wk,
+                      double* lzpart, const LzDevState* st, hipStream_t s);
   // Lanczos: w <- a*LW + b*w
   static void lz_update(void* w, const void* lw, int64_t n, const LzDevState* st, hipStream_t s);
   // user order <-> internal order
@@ -100,10 +107,20 @@ template <typename T> int reg_plane_size(const Grid3& g);
 
 void launch_lz_finalize(const double* partial, int nblk, LzDevState* st, double* beta, double* z,
                         int max_steps, double tol, double yscale, hipStream_t s);
-// m coefficients, the first m0 computed, beta_i = tail_even / tail_odd beyond
-void launch_spectrum(const double* beta, const double* z, int m0, int m, double tail_even,
-                     double tail_odd, const double* omega, int nw, double eta, double pref,
-                     double fq, double* chi, double* einv, double* loss, hipStream_t s);
+// m coefficients, the first m0 computed, beta_i = tail_even / tail_odd beyond;
+// gam (complex) non-null for the non-Hermitian recursion
+void launch_spectrum(const double* beta, const double* gam, const double* z, int m0, int m,
+                     double tail_even, double tail_odd, const double* omega, int nw, double eta,
+                     double pref, double fq, double* chi, double* einv, double* loss,
+                     hipStream_t s);
+// non-Hermitian recursion: ||y||^2 partials (kNhNormBlocks x 4) and the
+// scalar decisions of one step
+constexpr int kNhNormBlocks = 256;
+template <typename T>
+void launch_nh_norm(const void* y, const double* wk, int64_t per_k, int nks, double* partial,
+                    hipStream_t s);
+void launch_nh_finalize(const double* partial, int nblk, LzDevState* st, double* beta, double* gam,
+                        double* z, int max_steps, double tol, double yscale, hipStream_t s);
 void launch_set_state(LzDevState* st, hipStream_t s);
 
 constexpr int kStickTile = 16;    // sticks per block in the z passes

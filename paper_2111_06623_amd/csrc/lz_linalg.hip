@@ -243,26 +243,37 @@ __global__ __launch_bounds__(256) void k_reduce_coef_out(const cplx<T>* __restri
   }
 }
 
-// Y[k][n][G] += sum_{p<P} A[k][p][G] C[k][p][n]; with DOTS the block also
-// accumulates the Lanczos sums of its elements,
-//   s0 = sum w_k Re(conj(X) Y_new),  s1 + i s2 = sum w_k conj(y) X,
-// into lzpart[block] (fixed order inside the block).  A block covers 256/qn
-// plane waves and qn x NBT bands (qn = 4 when the coefficients fit in LDS):
-// its qn groups of threads read the same rows of A (cache hits after the
-// first), so A is fetched once per qn NBT bands.
+// Y[k][n][G] += sum_{p<P} A[k][p][G] C[k][p][n], and what the recursion does
+// with the updated element Y' (MODE):
+//   kUpdPlain  Y <- Y'
+//   kUpdDots   Y <- Y', and the pseudo-Hermitian sums of the block
+//              s0 = sum w_k Re(conj(X) Y'),  s1 + i s2 = sum w_k conj(y) X
+//   kUpdNhU    X <- cu1 Y' + cu2 X   (u^ of the non-Hermitian recursion formed
+//              in place of the vector two steps back; Y is left as it was)
+//   kUpdNhV    X <- v^ = cv1 Y' + cv2 X, and the non-Hermitian sums
+//              s + i t = sum w_k conj(U2) v^,  zr + i zi = sum w_k conj(y) v^
+//              (U2 = u^ of the same step, formed by a kUpdNhU launch before)
+// The sums go to lzpart[block] (fixed order inside the block; 3 per block, 4
+// for kUpdNhV).  A block covers 256/qn plane waves and qn x NBT bands (qn = 4
+// when the coefficients fit in LDS): its qn groups of threads read the same
+// rows of A (cache hits after the first), so A is fetched once per qn NBT
+// bands.
+constexpr int kUpdPlain = 0, kUpdDots = 1, kUpdNhU = 2, kUpdNhV = 3;
 
-template <typename T, int NBT, bool DOTS>
+template <typename T, int NBT, int MODE>
 __global__ __launch_bounds__(256) void k_proj_update(
     cplx<T>* __restrict__ Y, const cplx<T>* __restrict__ A, int P, int a_rows,
-    const cplx<T>* __restrict__ C, int c_rows, int nbnd, int npwx,
-    const cplx<T>* __restrict__ X, const cplx<T>* __restrict__ yv, const double* __restrict__ wk,
-    double* __restrict__ lzpart, int qn, const LzDevState* st) {
+    const cplx<T>* __restrict__ C, int c_rows, int nbnd, int npwx, cplx<T>* __restrict__ X,
+    const cplx<T>* __restrict__ yv, const cplx<T>* __restrict__ U2,
+    const double* __restrict__ wk, double* __restrict__ lzpart, int qn, const LzDevState* st) {
+  constexpr bool DOTS = MODE == kUpdDots || MODE == kUpdNhV;
+  constexpr int NR = MODE == kUpdNhV ? 4 : 3;
   if (st && st->status) return;
   const int NB = qn * NBT;
   const int npt = 256 / qn;  // plane waves per block
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cplx<T>* Cs = reinterpret_cast<cplx<T>*>(smem_raw);  // [P][NB]
-  __shared__ double red[3][256];
+  __shared__ double red[NR][256];
   const int k = blockIdx.z;
   const int nb0 = blockIdx.y * NB;
   const int nbb = min(NB, nbnd - nb0);
@@ -276,7 +287,7 @@ __global__ __launch_bounds__(256) void k_proj_update(
   const int g = blockIdx.x * npt + (threadIdx.x % npt);
   const int n0 = nb0 + q * NBT;
   const int nbt = min(NBT, nbnd - n0);
-  double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
   if (g < npwx && nbt > 0) {
     const cplx<T>* Ak = A + (int64_t)k * a_rows * npwx;
     const cplx<T>* Cq = Cs + q * NBT;
@@ -312,39 +323,56 @@ __global__ __launch_bounds__(256) void k_proj_update(
     }
     const int64_t kb = (int64_t)k * nbnd * npwx;
     const double w = DOTS ? wk[k] : 0.0;
+    cplx<T> c1 = czero<T>(), c2 = czero<T>();
+    if constexpr (MODE == kUpdNhU) {
+      c1 = mk<T>(T(st->cu1[0]), T(st->cu1[1]));
+      c2 = mk<T>(T(st->cu2[0]), T(st->cu2[1]));
+    } else if constexpr (MODE == kUpdNhV) {
+      c1 = mk<T>(T(st->cv1[0]), T(st->cv1[1]));
+      c2 = mk<T>(T(st->cv2[0]), T(st->cv2[1]));
+    }
 #pragma unroll
     for (int j = 0; j < NBT; ++j) {
       if (j < nbt) {
         const int64_t o = kb + (int64_t)(n0 + j) * npwx + g;
         cplx<T> yv_new = cadd<T>(Y[o], acc[j]);
-        Y[o] = yv_new;
-        if constexpr (DOTS) {
+        if constexpr (MODE == kUpdPlain || MODE == kUpdDots) Y[o] = yv_new;
+        if constexpr (MODE == kUpdDots) {
           const cplx<T> xv = X[o], rv = yv[o];
           s0 += w * (double(xv.x) * double(yv_new.x) + double(xv.y) * double(yv_new.y));
           s1 += w * (double(rv.x) * double(xv.x) + double(rv.y) * double(xv.y));
           s2 += w * (double(rv.x) * double(xv.y) - double(rv.y) * double(xv.x));
         }
+        if constexpr (MODE == kUpdNhU || MODE == kUpdNhV) {
+          const cplx<T> h = cadd<T>(cmul<T>(c1, yv_new), cmul<T>(c2, X[o]));
+          X[o] = h;
+          if constexpr (MODE == kUpdNhV) {
+            const cplx<T> uv = U2[o], rv = yv[o];
+            s0 += w * (double(uv.x) * double(h.x) + double(uv.y) * double(h.y));
+            s1 += w * (double(uv.x) * double(h.y) - double(uv.y) * double(h.x));
+            s2 += w * (double(rv.x) * double(h.x) + double(rv.y) * double(h.y));
+            s3 += w * (double(rv.x) * double(h.y) - double(rv.y) * double(h.x));
+          }
+        }
       }
     }
   }
   if constexpr (DOTS) {
-    red[0][threadIdx.x] = s0;
-    red[1][threadIdx.x] = s1;
-    red[2][threadIdx.x] = s2;
+    const double sv[4] = {s0, s1, s2, s3};
+#pragma unroll
+    for (int r = 0; r < NR; ++r) red[r][threadIdx.x] = sv[r];
     __syncthreads();
     for (int h = 128; h > 0; h >>= 1) {
       if (threadIdx.x < h) {
-        red[0][threadIdx.x] += red[0][threadIdx.x + h];
-        red[1][threadIdx.x] += red[1][threadIdx.x + h];
-        red[2][threadIdx.x] += red[2][threadIdx.x + h];
+#pragma unroll
+        for (int r = 0; r < NR; ++r) red[r][threadIdx.x] += red[r][threadIdx.x + h];
       }
       __syncthreads();
     }
     if (threadIdx.x == 0) {
       const int blk = (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
-      lzpart[3 * blk + 0] = red[0][0];
-      lzpart[3 * blk + 1] = red[1][0];
-      lzpart[3 * blk + 2] = red[2][0];
+#pragma unroll
+      for (int r = 0; r < NR; ++r) lzpart[NR * blk + r] = red[r][0];
     }
   }
 }
@@ -430,6 +458,127 @@ __global__ __launch_bounds__(256) void k_lz_finalize(const double* __restrict__ 
   st->step = j + 1;
 }
 
+// ---------------------------------------------------------------------------
+// Non-Hermitian biorthogonal recursion (Sec. 2.5).  The two chains are kept
+// unnormalised, v^_j = beta_j v_j and u^_j = conj(gamma_j) u_j, so that the
+// scalings fold into the formation of the next pair:
+//   v^_{j+1} = L v^_j / beta_j - (gamma_j / beta_{j-1}) v^_{j-1}
+//   u^_{j+1} = L^dagger u^_j / conj(gamma_j) - (beta_j / conj(gamma_{j-1})) u^_{j-1}
+//   s = (u^_{j+1}, v^_{j+1}),  beta_{j+1} = sqrt|s|,  gamma_{j+1} = s / beta_{j+1},
+//   z_{j+1} = (y, v^_{j+1}) / beta_{j+1} for an upper vector, else 0.
+// ---------------------------------------------------------------------------
+
+
+// Block partial sums of w_k |y|^2 over the internal layout [k][n][G]
+// (4 entries per block, the last three zero).
+template <typename T>
+__global__ __launch_bounds__(256) void k_nh_norm(const cplx<T>* __restrict__ y,
+                                                 const double* __restrict__ wk, int64_t per_k,
+                                                 int nks, double* __restrict__ partial) {
+  __shared__ double red[256];
+  const int64_t n = per_k * nks;
+  double acc = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const cplx<T> v = y[i];
+    acc += wk[i / per_k] * (double(v.x) * double(v.x) + double(v.y) * double(v.y));
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    partial[4 * blockIdx.x + 0] = red[0];
+    partial[4 * blockIdx.x + 1] = 0.0;
+    partial[4 * blockIdx.x + 2] = 0.0;
+    partial[4 * blockIdx.x + 3] = 0.0;
+  }
+}
+
+// Sum the partials (4 per block) and take the scalar decisions of one
+// non-Hermitian step.  j = st->step.  j == 0: the partials hold ||y||^2;
+// beta_1 = gamma_1 = ||y|| (breakdown when y vanished).  j >= 1: the
+// partials hold (s, (y, v^_{j+1})); breakdown when |s| <= (tol bmax)^2 with
+// bmax the largest beta_2..beta_j.  gamma and z are complex (re, im).
+__global__ __launch_bounds__(256) void k_nh_finalize(const double* __restrict__ partial, int nblk,
+                                                     LzDevState* __restrict__ st,
+                                                     double* __restrict__ beta,
+                                                     double* __restrict__ gam,
+                                                     double* __restrict__ z, int max_steps,
+                                                     double tol, double yscale) {
+  __shared__ double red[4][kDotThreads];
+  if (st->status) return;
+  double a[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int i = threadIdx.x; i < nblk; i += kDotThreads)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) a[r] += partial[i * 4 + r];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) red[r][threadIdx.x] = a[r];
+  __syncthreads();
+  for (int h = kDotThreads / 2; h > 0; h >>= 1) {
+    if (threadIdx.x < h) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) red[r][threadIdx.x] += red[r][threadIdx.x + h];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x != 0) return;
+  const double sr = red[0][0], si = red[1][0], zr = red[2][0], zi = red[3][0];
+  const int j = st->step;
+  if (j >= max_steps) { st->status = 5; return; }
+  if (!isfinite(sr) || !isfinite(si) || !isfinite(zr) || !isfinite(zi)) { st->status = 7; return; }
+  if (j == 0) {
+    if (sr <= tol * tol * yscale) { st->status = 6; return; }  // y = 0: chi vanishes
+    const double bt = sqrt(sr);
+    beta[0] = bt;
+    gam[0] = bt;
+    gam[1] = 0.0;
+    z[0] = 0.0;
+    z[1] = 0.0;
+    st->cv1[0] = 1.0 / bt; st->cv1[1] = 0.0;
+    st->cu1[0] = 1.0 / bt; st->cu1[1] = 0.0;
+    st->cv2[0] = st->cv2[1] = 0.0;  // no vector before the first
+    st->cu2[0] = st->cu2[1] = 0.0;
+    st->beta_prev = bt;
+    st->gamma_prev[0] = bt;
+    st->gamma_prev[1] = 0.0;
+    st->bmax = 0.0;
+    st->step = 1;
+    return;
+  }
+  const double as = hypot(sr, si);
+  const double bm = st->bmax;
+  if (as <= (tol * bm) * (tol * bm)) { st->status = 6; return; }
+  const double bt = sqrt(as);
+  const double gr = sr / bt, gi = si / bt;
+  beta[j] = bt;
+  gam[2 * j] = gr;
+  gam[2 * j + 1] = gi;
+  if (j & 1) {
+    z[2 * j] = zr / bt;
+    z[2 * j + 1] = zi / bt;
+  } else {
+    z[2 * j] = 0.0;
+    z[2 * j + 1] = 0.0;
+  }
+  // next formation: cv1 = 1/beta_{j+1}, cv2 = -gamma_{j+1}/beta_j,
+  // cu1 = 1/conj(gamma_{j+1}), cu2 = -beta_{j+1}/conj(gamma_j)
+  const double g2 = gr * gr + gi * gi;
+  const double pr = st->gamma_prev[0], pi = st->gamma_prev[1];
+  const double p2 = pr * pr + pi * pi;
+  st->cv1[0] = 1.0 / bt; st->cv1[1] = 0.0;
+  st->cv2[0] = -gr / st->beta_prev; st->cv2[1] = -gi / st->beta_prev;
+  st->cu1[0] = gr / g2; st->cu1[1] = gi / g2;          // 1/conj(g) = g/|g|^2
+  st->cu2[0] = -bt * pr / p2; st->cu2[1] = -bt * pi / p2;
+  st->bmax = bm > bt ? bm : bt;
+  st->beta_prev = bt;
+  st->gamma_prev[0] = gr;
+  st->gamma_prev[1] = gi;
+  st->step = j + 1;
+}
+
 __global__ __launch_bounds__(256) void k_set_state(LzDevState* st) {
   st->step = 0;
   st->status = 0;
@@ -437,6 +586,10 @@ __global__ __launch_bounds__(256) void k_set_state(LzDevState* st) {
   st->a = 0.0;
   st->b = 0.0;
   st->beta_prev = 0.0;
+  for (int r = 0; r < 2; ++r) {
+    st->cv1[r] = st->cv2[r] = st->cu1[r] = st->cu2[r] = 0.0;
+    st->gamma_prev[r] = 0.0;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -488,7 +641,11 @@ __device__ __forceinline__ double2 zdiv(double2 a, double2 b) {
 // Backward sweep of the transposed system, one frequency per thread, over the
 // m coefficients of an extended tridiagonal matrix: beta_i for i <= m0 from
 // the recursion, tail[i % 2] beyond (extrapolation), z_j = 0 for j > m0.
+// With gam (complex, non-Hermitian recursion) T has super-diagonal gamma:
+// the transposed system then has c_j = gamma_j / den_j, and z_j is taken
+// complex.  No pivoting: |Im den_j| >= eta holds only for symmetric T.
 __global__ __launch_bounds__(256) void k_spectrum(const double* __restrict__ beta,
+                                                  const double* __restrict__ gam,
                                                   const double* __restrict__ z, int m0, int m,
                                                   double tail_even, double tail_odd,
                                                   const double* __restrict__ omega, int nw,
@@ -506,11 +663,14 @@ __global__ __launch_bounds__(256) void k_spectrum(const double* __restrict__ bet
   for (int j = m; j >= 1; --j) {
     const double bnext = j < m ? bet(j + 1) : 0.0;  // beta_{j+1}
     const double2 den = make_double2(wt.x - bnext * c.x, wt.y - bnext * c.y);
-    // z_j is real in exact arithmetic; its rounding-level imaginary part is dropped
+    // pseudo-Hermitian: z_j is real in exact arithmetic; its rounding-level
+    // imaginary part is dropped
     const double zj = j <= m0 ? z[2 * (j - 1)] : 0.0;
-    const double2 num = make_double2(zj + bnext * d.x, bnext * d.y);
+    const double zij = (gam && j <= m0) ? z[2 * (j - 1) + 1] : 0.0;
+    const double2 num = make_double2(zj + bnext * d.x, zij + bnext * d.y);
     d = zdiv(num, den);
-    c = zdiv(make_double2(bet(j), 0.0), den);
+    c = zdiv(gam ? make_double2(gam[2 * (j - 1)], gam[2 * (j - 1) + 1]) : make_double2(bet(j), 0.0),
+             den);
   }
   double2 ch = make_double2(0.0, 0.0);
   if (m > 0) ch = make_double2(pref * beta[0] * d.x, pref * beta[0] * d.y);
@@ -600,23 +760,47 @@ int LaunchLin<T>::update_blocks(int P, int nbnd, int npwx, int nks) {
 }
 
 template <typename T>
-void LaunchLin<T>::proj_update(void* Y, const void* A, int P, int a_rows, const void* C,
-                               int c_rows, int nbnd, int npwx, int nks, const void* X,
-                               const void* y, const double* wk, double* lzpart,
-                               const LzDevState* st, hipStream_t s) {
+static void launch_update(int mode, void* Y, const void* A, int P, int a_rows, const void* C,
+                          int c_rows, int nbnd, int npwx, int nks, void* X, const void* y,
+                          const void* U2, const double* wk, double* lzpart, const LzDevState* st,
+                          hipStream_t s) {
   const int nbt = upd_bands(nbnd);
   const int qn = upd_groups<T>(P, nbt);
   const int npt = 256 / qn;
   dim3 grid((npwx + npt - 1) / npt, (nbnd + qn * nbt - 1) / (qn * nbt), nks);
   const size_t lds = (size_t)P * qn * nbt * sizeof(cplx<T>);
-  const bool dots = lzpart != nullptr;
-#define LZ_UPD(NBT, DOTS)                                                                        \
-  hipLaunchKernelGGL((k_proj_update<T, NBT, DOTS>), grid, dim3(256), lds, s, (cplx<T>*)Y,        \
+#define LZ_UPD(NBT, MODE)                                                                        \
+  hipLaunchKernelGGL((k_proj_update<T, NBT, MODE>), grid, dim3(256), lds, s, (cplx<T>*)Y,        \
                      (const cplx<T>*)A, P, a_rows, (const cplx<T>*)C, c_rows, nbnd, npwx,        \
-                     (const cplx<T>*)X, (const cplx<T>*)y, wk, lzpart, qn, st);
-  if (nbt == 4) { if (dots) { LZ_UPD(4, true) } else { LZ_UPD(4, false) } }
-  else { if (dots) { LZ_UPD(8, true) } else { LZ_UPD(8, false) } }
+                     (cplx<T>*)X, (const cplx<T>*)y, (const cplx<T>*)U2, wk, lzpart, qn, st);
+#define LZ_UPD_MODES(NBT)                                          \
+  switch (mode) {                                                  \
+    case kUpdDots: LZ_UPD(NBT, kUpdDots) break;                    \
+    case kUpdNhU: LZ_UPD(NBT, kUpdNhU) break;                      \
+    case kUpdNhV: LZ_UPD(NBT, kUpdNhV) break;                      \
+    default: LZ_UPD(NBT, kUpdPlain) break;                         \
+  }
+  if (nbt == 4) { LZ_UPD_MODES(4) } else { LZ_UPD_MODES(8) }
+#undef LZ_UPD_MODES
 #undef LZ_UPD
+}
+
+template <typename T>
+void LaunchLin<T>::proj_update(void* Y, const void* A, int P, int a_rows, const void* C,
+                               int c_rows, int nbnd, int npwx, int nks, const void* X,
+                               const void* y, const double* wk, double* lzpart,
+                               const LzDevState* st, hipStream_t s) {
+  launch_update<T>(lzpart != nullptr ? kUpdDots : kUpdPlain, Y, A, P, a_rows, C, c_rows, nbnd,
+                   npwx, nks, const_cast<void*>(X), y, nullptr, wk, lzpart, st, s);
+}
+
+template <typename T>
+void LaunchLin<T>::nh_form(bool v_chain, void* LY, const void* A, int P, const void* C, int nbnd,
+                           int npwx, int nks, void* H, const void* y, const void* U2,
+                           const double* wk, double* lzpart, const LzDevState* st,
+                           hipStream_t s) {
+  launch_update<T>(v_chain ? kUpdNhV : kUpdNhU, LY, A, P, P, C, P, nbnd, npwx, nks, H, y, U2, wk,
+                   v_chain ? lzpart : nullptr, st, s);
 }
 
 template <typename T>
@@ -650,11 +834,27 @@ void launch_lz_finalize(const double* partial, int nblk, LzDevState* st, double*
                      max_steps, tol, yscale);
 }
 
-void launch_spectrum(const double* beta, const double* z, int m0, int m, double tail_even,
-                     double tail_odd, const double* omega, int nw, double eta, double pref,
-                     double fq, double* chi, double* einv, double* loss, hipStream_t s) {
-  hipLaunchKernelGGL(k_spectrum, dim3((nw + 63) / 64), dim3(64), 0, s, beta, z, m0, m, tail_even,
-                     tail_odd, omega, nw, eta, pref, fq, chi, einv, loss);
+void launch_spectrum(const double* beta, const double* gam, const double* z, int m0, int m,
+                     double tail_even, double tail_odd, const double* omega, int nw, double eta,
+                     double pref, double fq, double* chi, double* einv, double* loss,
+                     hipStream_t s) {
+  hipLaunchKernelGGL(k_spectrum, dim3((nw + 63) / 64), dim3(64), 0, s, beta, gam, z, m0, m,
+                     tail_even, tail_odd, omega, nw, eta, pref, fq, chi, einv, loss);
+}
+
+template <typename T>
+void launch_nh_norm(const void* y, const double* wk, int64_t per_k, int nks, double* partial,
+                    hipStream_t s) {
+  hipLaunchKernelGGL(k_nh_norm<T>, dim3(kNhNormBlocks), dim3(256), 0, s, (const cplx<T>*)y, wk,
+                     per_k, nks, partial);
+}
+template void launch_nh_norm<float>(const void*, const double*, int64_t, int, double*, hipStream_t);
+template void launch_nh_norm<double>(const void*, const double*, int64_t, int, double*, hipStream_t);
+
+void launch_nh_finalize(const double* partial, int nblk, LzDevState* st, double* beta, double* gam,
+                        double* z, int max_steps, double tol, double yscale, hipStream_t s) {
+  hipLaunchKernelGGL(k_nh_finalize, dim3(1), dim3(kDotThreads), 0, s, partial, nblk, st, beta, gam,
+                     z, max_steps, tol, yscale);
 }
 
 void launch_set_state(LzDevState* st, hipStream_t s) {
