@@ -47,6 +47,8 @@ def _args():
                     help="only run a plain device copy of this size (counter calibration)")
     ap.add_argument("--nh-steps", type=int, default=60,
                     help="steps of the per-step comparison with the non-Hermitian recursion (0: skip)")
+    ap.add_argument("--sweep-steps", type=int, default=200,
+                    help="steps of the q-sweep throughput comparison (0: skip)")
     ap.add_argument("--graph", action="store_true",
                     help="replay pairs of steps as captured graphs (measured no faster than eager)")
     return ap.parse_args()
@@ -135,6 +137,39 @@ def nh_vs_ph(s, prec, steps):
         out[f"{alg}_ms_per_step"] = round(1e3 * dt / steps, 4)
         ctx.free()
     out["nh_over_ph"] = round(out["nh_ms_per_step"] / out["ph_ms_per_step"], 3)
+    return out
+
+
+def q_sweep_rate(prec, steps):
+    """Instance-applies/s of a q-dispersion sweep (the 32^3 crystal at eight
+    q along [100], one instance per q, in one context): the instances one
+    after another on one stream against side by side on the library's
+    default streams, each with and without graph replay.  Outside the timed
+    region of the headline metric."""
+    import torch
+
+    import paper_2111_06623_amd as lz
+    from synth import q_sweep
+    systems = q_sweep("cfg2lo")
+    out = {"workload": "q sweep: 32^3 cell (cfg2 crystal at ecut 8 Ha, 16 bands, 2 k) at "
+                       "q = (0.05..0.6) 2pi/a [100], 8 instances", "precision": prec,
+           "instances": len(systems), "steps": steps}
+    for streams, tag in ((1, "one_stream"), (0, "side_by_side")):
+        for graph in (False, True):
+            ctx = lz.lz_init(systems, prec=prec, max_steps=steps + 8, use_graph=graph,
+                             streams=streams)
+            ctx.step(4)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            done, _ = ctx.step(steps)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            if done != steps + 4:
+                raise RuntimeError(f"sweep stopped at {done} steps")
+            key = f"{tag}{'_graph' if graph else ''}"
+            out[key] = round(len(systems) * steps / 2 / dt, 1)
+            ctx.free()
+    out["unit"] = "instance-applies/s"
     return out
 
 
@@ -320,6 +355,10 @@ def main():
         _log(f"[bench] per-step cost: pseudo-Hermitian vs non-Hermitian, {a.nh_steps} steps ({head})")
         out["nh_vs_ph"] = nh_vs_ph(s, head, a.nh_steps)
         _log(f"[bench] {out['nh_vs_ph']}")
+    if a.sweep_steps > 0:
+        _log(f"[bench] q sweep, {a.sweep_steps} steps ({head})")
+        out["q_sweep"] = q_sweep_rate(head, a.sweep_steps)
+        _log(f"[bench] {out['q_sweep']}")
     if not a.no_cpu_baseline:
         _log("[bench] cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(s, a.cpu_seconds)

@@ -115,6 +115,10 @@ typedef struct {
                          on); results are bitwise identical to the eager launches */
   int32_t autotune;   /* reserved, must be 0 or 1 (1 = time launch shapes at init) */
   lz_algorithm algorithm;
+  int32_t streams;    /* instances of one context that lz_step advances side by side, each
+                         on its own HIP stream (instance i on stream i mod streams):
+                         0 = min(n_inst, 4), 1 = one instance after another; at most 64.
+                         Results do not depend on it (bitwise). */
 } lz_options;
 
 /*

@@ -49,7 +49,7 @@ class LzSystem(ctypes.Structure):
 class LzOptions(ctypes.Structure):
     _fields_ = [("prec", ctypes.c_int), ("approx", ctypes.c_int), ("max_steps", ctypes.c_int32),
                 ("use_graph", ctypes.c_int32), ("autotune", ctypes.c_int32),
-                ("algorithm", ctypes.c_int)]
+                ("algorithm", ctypes.c_int), ("streams", ctypes.c_int32)]
 
 
 class LzError(RuntimeError):
@@ -157,9 +157,10 @@ def _stream_handle(device):
 
 
 def lz_init(systems, prec="fp64", approx="tddft", max_steps=1000, use_graph=False, autotune=False,
-            device=0, stream=None, algorithm="ph"):
+            device=0, stream=None, algorithm="ph", streams=0):
     """Create a context for one system or a list of systems; returns a handle.
-    algorithm: "ph" (pseudo-Hermitian) or "nh" (non-Hermitian biorthogonal)."""
+    algorithm: "ph" (pseudo-Hermitian) or "nh" (non-Hermitian biorthogonal);
+    streams: instances stepped side by side (0: the library default)."""
     lib = load()
     systems = systems if isinstance(systems, (list, tuple)) else [systems]
     arr = (LzSystem * len(systems))()
@@ -170,7 +171,8 @@ def lz_init(systems, prec="fp64", approx="tddft", max_steps=1000, use_graph=Fals
     opt = LzOptions(PREC[prec] if isinstance(prec, str) else int(prec),
                     APPROX[approx] if isinstance(approx, str) else int(approx),
                     int(max_steps), int(bool(use_graph)), int(bool(autotune)),
-                    ALGORITHM[algorithm] if isinstance(algorithm, str) else int(algorithm))
+                    ALGORITHM[algorithm] if isinstance(algorithm, str) else int(algorithm),
+                    int(streams))
     out = ctypes.c_void_p()
     hs = _stream_handle(device) if stream is None else ctypes.c_void_p(stream)
     _check(lib.lz_init(arr, len(systems), ctypes.byref(opt), int(device), hs, ctypes.byref(out)))

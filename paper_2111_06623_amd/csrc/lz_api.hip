@@ -40,6 +40,9 @@ struct LzError {
 
 constexpr double kTwoPi = 6.283185307179586476925286766559;
 constexpr double kBreakdownTol = 1e-7;
+// default number of streams for the instances of one context (the hardware
+// queues a process gets by default)
+constexpr int kInstStreams = 4;
 
 // device buffer with RAII
 struct DBuf {
@@ -763,11 +766,19 @@ struct lz_ctx {
   hipStream_t user = nullptr;
   hipStream_t stream = nullptr;
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  // streams on which lz_step runs the instances side by side (empty: every
+  // instance on `stream`, one after another); instance i uses qs[i % size]
+  std::vector<hipStream_t> qs;
+  std::vector<hipEvent_t> qdone;
+  hipEvent_t ev_fork = nullptr;
   lz_options opt{};
   std::vector<std::unique_ptr<Instance>> inst;
   bool started = false;
   ~lz_ctx() {
     inst.clear();
+    for (auto e : qdone) (void)hipEventDestroy(e);
+    for (auto q : qs) (void)hipStreamDestroy(q);
+    if (ev_fork) (void)hipEventDestroy(ev_fork);
     if (ev_in) (void)hipEventDestroy(ev_in);
     if (ev_out) (void)hipEventDestroy(ev_out);
     if (stream) (void)hipStreamDestroy(stream);
@@ -848,6 +859,7 @@ lz_status lz_init(const lz_system* sys, int32_t n_inst, const lz_options* opt, i
       fail(LZ_ERR_ARG, "unknown approximation");
     if (opt->algorithm != LZ_PSEUDO_HERMITIAN && opt->algorithm != LZ_NON_HERMITIAN)
       fail(LZ_ERR_ARG, "unknown Lanczos algorithm");
+    if (opt->streams < 0 || opt->streams > 64) fail(LZ_ERR_ARG, "streams must lie in [0, 64]");
     int ndev = 0;
     HIPC(hipGetDeviceCount(&ndev));
     if (device < 0 || device >= ndev) fail(LZ_ERR_ARG, "no such device");
@@ -859,6 +871,20 @@ lz_status lz_init(const lz_system* sys, int32_t n_inst, const lz_options* opt, i
     HIPC(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
     HIPC(hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming));
     HIPC(hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming));
+    {
+      const int nq = std::min(n_inst, opt->streams > 0 ? (int)opt->streams : kInstStreams);
+      if (nq > 1) {
+        HIPC(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
+        for (int i = 0; i < nq; ++i) {
+          hipStream_t q = nullptr;
+          hipEvent_t e = nullptr;
+          HIPC(hipStreamCreateWithFlags(&q, hipStreamNonBlocking));
+          c->qs.push_back(q);
+          HIPC(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+          c->qdone.push_back(e);
+        }
+      }
+    }
     HIPC(enable_large_lds_fft<double>());
     HIPC(enable_large_lds_fft<float>());
     c->enter();
@@ -939,23 +965,51 @@ lz_status lz_step(lz_ctx* c, int32_t n_steps, int32_t* steps_done) {
       if (ip->status_host == 0 && ip->steps_host + n_steps > ip->max_steps)
         fail(LZ_ERR_STATE, "max_steps would be exceeded");
     c->enter();
-    for (auto& ip : c->inst) {
-      Instance& I = *ip;
-      if (I.status_host != 0) continue;
+    // With several streams the instances advance side by side: their steps
+    // are issued round-robin, one unit (a step or a replayed pair) per
+    // instance per round, each instance on its own stream, so the small
+    // kernels of one instance overlap with the work of the others.
+    const int ni = (int)c->inst.size();
+    const bool fork = !c->qs.empty();
+    if (fork) {
+      HIPC(hipEventRecord(c->ev_fork, c->stream));
+      for (auto q : c->qs) HIPC(hipStreamWaitEvent(q, c->ev_fork, 0));
+    }
+    std::vector<int> jj(ni), end(ni);
+    for (int i = 0; i < ni; ++i) {
+      jj[i] = c->inst[i]->steps_host;
+      end[i] = c->inst[i]->status_host == 0 ? jj[i] + n_steps : jj[i];
+    }
+    // one unit of instance i on stream s; returns false when it has none left
+    auto issue = [&](int i, hipStream_t s) {
+      Instance& I = *c->inst[i];
+      int& j = jj[i];
+      if (j >= end[i]) return false;
       const bool graphs = c->opt.use_graph != 0 && !I.timer.on;
-      const int end = I.steps_host + n_steps;
-      int j = I.steps_host;
-      while (j < end) {
-        if (graphs && (j & 1) && j + 1 < end) {
-          if (!I.gpair) build_pair_graph(I, c->stream);
-          HIPC(hipGraphLaunch(I.gpair, c->stream));
-          j += 2;
-        } else {
-          if (I.fp64) any_step<double>(I, j, c->stream);
-          else any_step<float>(I, j, c->stream);
-          ++j;
-        }
+      if (graphs && (j & 1) && j + 1 < end[i]) {
+        if (!I.gpair) build_pair_graph(I, s);
+        HIPC(hipGraphLaunch(I.gpair, s));
+        j += 2;
+      } else {
+        if (I.fp64) any_step<double>(I, j, s);
+        else any_step<float>(I, j, s);
+        ++j;
       }
+      return true;
+    };
+    if (fork) {
+      for (bool more = true; more;) {
+        more = false;
+        for (int i = 0; i < ni; ++i) more |= issue(i, c->qs[i % c->qs.size()]);
+      }
+      for (size_t q = 0; q < c->qs.size(); ++q) {
+        HIPC(hipEventRecord(c->qdone[q], c->qs[q]));
+        HIPC(hipStreamWaitEvent(c->stream, c->qdone[q], 0));
+      }
+    } else {
+      for (int i = 0; i < ni; ++i)
+        while (issue(i, c->stream)) {
+        }
     }
     HIPC(hipGetLastError());
     c->leave();

@@ -16,6 +16,8 @@
   uneven members of the batched workload (seeded grids in {32, 40, 48, 64,
         72} with a = 10.26 N/48 bohr, ecut 25 Ha, wells with 4 projectors
         each, random orthonormal orbitals); `uneven_sizes` trims bands and k.
+  qsweep the same crystal at several transferred momenta q = f (2pi/a) [100]
+        (q_sweep): a loss-function dispersion, one instance per q.
   micro small cells for brute-force diagonalisation of the explicit Liouvillian.
   free  free electrons (V=0): one closed shell of 7 bands, Gamma only,
         q = (0.1,0,0) b, G0 = (1,0,0).
@@ -97,9 +99,10 @@ def _spec(name: str, **kw) -> dict:
         dkb = np.stack([rng.uniform(3.0, 8.0, 8), rng.uniform(0.1, 0.5, 8)], axis=1)
         shift = rng.random(3)
         nk = kw.get("nk", 2)
+        qf = kw.get("qfrac", 0.2)
         return dict(at=at, nr=(32, 32, 32), ecut=8.0, tau_frac=DIAMOND_SITES,
                     depth=4.0, width=1.2, nbnd=16, kpts=mp_kpoints(at, (2, 2, 2), shift)[:nk],
-                    q=[0.2 * 2 * np.pi / a, 0.0, 0.0], xc="pz",
+                    q=[qf * 2 * np.pi / a, 0.0, 0.0], xc="pz",
                     kb=dict(radii=radii, dkb=dkb))
     if name == "cfg5r":
         a = 20.5
@@ -192,3 +195,12 @@ def config_system(name: str, use_cache: bool = True, **kw) -> SystemArrays:
                  info=json.dumps(s.info, default=lambda o: o.tolist() if hasattr(o, "tolist") else str(o)))
         os.replace(tmp, path)
     return s
+
+
+QSWEEP_FRACS = (0.05, 0.1, 0.15, 0.2, 0.3, 0.4, 0.5, 0.6)
+
+
+def q_sweep(name: str = "cfg2lo", fracs=QSWEEP_FRACS, **kw):
+    """One system per q = f (2 pi / a) along [100] of the crystal `name`
+    (cfg2 or cfg2lo): the instances of a dispersion run."""
+    return [config_system(name, qfrac=float(f), **kw) for f in fracs]
