@@ -15,10 +15,16 @@ namespace lz {
 __host__ __device__ constexpr int ct_radix(int n, int p) {
   return n == 24   ? (p == 0 ? 8 : p == 1 ? 3 : 0)
          : n == 32 ? (p == 0 ? 8 : p == 1 ? 4 : 0)
+         : n == 40 ? (p == 0 ? 8 : p == 1 ? 5 : 0)
          : n == 48 ? (p == 0 ? 16 : p == 1 ? 3 : 0)
          : n == 64 ? (p == 0 ? 16 : p == 1 ? 4 : 0)
+         : n == 72 ? (p == 0 ? 8 : p == 1 ? 3 : p == 2 ? 3 : 0)
+         : n == 96 ? (p == 0 ? 8 : p == 1 ? 4 : p == 2 ? 3 : 0)
                    : 0;
 }
+
+// every length with a compile-time plan, for the kernel dispatch switches
+#define LZ_CT_SIZES(X) X(24) X(32) X(40) X(48) X(64) X(72) X(96)
 __host__ __device__ constexpr int ct_npass(int n) {
   int c = 0;
   while (c < 8 && ct_radix(n, c) != 0) ++c;

@@ -641,10 +641,9 @@ static inline RegPlaneArgs reg_args(const Grid3& g) {
 template <typename T> static size_t plane_lds(const Grid3& g) {
   const int n = ct_size(g);
   switch (n) {
-    case 24: return plane_shm_bytes_ct<T, 24>();
-    case 32: return plane_shm_bytes_ct<T, 32>();
-    case 48: return plane_shm_bytes_ct<T, 48>();
-    case 64: return plane_shm_bytes_ct<T, 64>();
+#define LZ_CASE(N) case N: return plane_shm_bytes_ct<T, N>();
+    LZ_CT_SIZES(LZ_CASE)
+#undef LZ_CASE
     default: return (size_t)g.n1 * g.pitch2 * sizeof(cplx<T>);
   }
 }
@@ -659,8 +658,11 @@ template <typename T> static size_t stick_lds(const Grid3& g) {
     switch (ct_size(G)) {                                                                       \
       case 24: hipLaunchKernelGGL((KERN<T, 24, 0>), GRID, dim3(256), LDS, STREAM, __VA_ARGS__); break; \
       case 32: hipLaunchKernelGGL((KERN<T, 32, 0>), GRID, dim3(256), LDS, STREAM, __VA_ARGS__); break; \
+      case 40: hipLaunchKernelGGL((KERN<T, 40, 0>), GRID, dim3(256), LDS, STREAM, __VA_ARGS__); break; \
       case 48: hipLaunchKernelGGL((KERN<T, 48, 0>), GRID, dim3(256), LDS, STREAM, __VA_ARGS__); break; \
       case 64: hipLaunchKernelGGL((KERN<T, 64, 0>), GRID, dim3(256), LDS, STREAM, __VA_ARGS__); break; \
+      case 72: hipLaunchKernelGGL((KERN<T, 72, 0>), GRID, dim3(256), LDS, STREAM, __VA_ARGS__); break; \
+      case 96: hipLaunchKernelGGL((KERN<T, 96, 0>), GRID, dim3(256), LDS, STREAM, __VA_ARGS__); break; \
       default:                                                                                  \
         switch (plane_mp((G).n1, (G).n2)) {                                                     \
           case 12: hipLaunchKernelGGL((KERN<T, 0, 12>), GRID, dim3(256), LDS, STREAM, __VA_ARGS__); break; \
@@ -675,8 +677,11 @@ template <typename T> static size_t stick_lds(const Grid3& g) {
     switch (ct_size(G)) {                                                                     \
       case 24: hipLaunchKernelGGL((KERN<T, 24>), GRID, dim3(256), LDS, STREAM, __VA_ARGS__); break; \
       case 32: hipLaunchKernelGGL((KERN<T, 32>), GRID, dim3(256), LDS, STREAM, __VA_ARGS__); break; \
+      case 40: hipLaunchKernelGGL((KERN<T, 40>), GRID, dim3(256), LDS, STREAM, __VA_ARGS__); break; \
       case 48: hipLaunchKernelGGL((KERN<T, 48>), GRID, dim3(256), LDS, STREAM, __VA_ARGS__); break; \
       case 64: hipLaunchKernelGGL((KERN<T, 64>), GRID, dim3(256), LDS, STREAM, __VA_ARGS__); break; \
+      case 72: hipLaunchKernelGGL((KERN<T, 72>), GRID, dim3(256), LDS, STREAM, __VA_ARGS__); break; \
+      case 96: hipLaunchKernelGGL((KERN<T, 96>), GRID, dim3(256), LDS, STREAM, __VA_ARGS__); break; \
       default: hipLaunchKernelGGL((KERN<T, 0>), GRID, dim3(256), LDS, STREAM, __VA_ARGS__); break; \
     }                                                                                         \
   } while (0)
@@ -768,6 +773,9 @@ void LaunchFft<T>::hxc(const Grid3& g, const void* dpart, int ngroups, void* nr,
     case 32: return hxc_lines<T, 32>(g, dpart, ngroups, nr, work, khart, fxc, with_fxc, vp, st, s);
     case 48: return hxc_lines<T, 48>(g, dpart, ngroups, nr, work, khart, fxc, with_fxc, vp, st, s);
     case 64: return hxc_lines<T, 64>(g, dpart, ngroups, nr, work, khart, fxc, with_fxc, vp, st, s);
+    case 40: return hxc_lines<T, 40>(g, dpart, ngroups, nr, work, khart, fxc, with_fxc, vp, st, s);
+    case 72: return hxc_lines<T, 72>(g, dpart, ngroups, nr, work, khart, fxc, with_fxc, vp, st, s);
+    case 96: return hxc_lines<T, 96>(g, dpart, ngroups, nr, work, khart, fxc, with_fxc, vp, st, s);
     default: break;
   }
   const int np = g.n1 * g.n2;
@@ -791,8 +799,9 @@ hipError_t enable_large_lds_fft() {
   {                                                                                           \
     const void* fns[] = {(const void*)KERN<T, 0, 12>, (const void*)KERN<T, 0, 24>,            \
                          (const void*)KERN<T, 0, 36>, (const void*)KERN<T, 24, 0>,            \
-                         (const void*)KERN<T, 32, 0>, (const void*)KERN<T, 48, 0>,            \
-                         (const void*)KERN<T, 64, 0>};                                        \
+                         (const void*)KERN<T, 32, 0>, (const void*)KERN<T, 40, 0>,            \
+                         (const void*)KERN<T, 48, 0>, (const void*)KERN<T, 64, 0>,            \
+                         (const void*)KERN<T, 72, 0>, (const void*)KERN<T, 96, 0>};           \
     for (const void* f : fns) {                                                               \
       hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, big); \
       if (e != hipSuccess) return e;                                                          \
@@ -816,9 +825,13 @@ hipError_t enable_large_lds_fft() {
   }
   {
     const void* fns[] = {(const void*)k_zfft_inv<T, 24>, (const void*)k_zfft_inv<T, 32>,
-                         (const void*)k_zfft_inv<T, 48>, (const void*)k_zfft_inv<T, 64>,
+                         (const void*)k_zfft_inv<T, 40>, (const void*)k_zfft_inv<T, 48>,
+                         (const void*)k_zfft_inv<T, 64>, (const void*)k_zfft_inv<T, 72>,
+                         (const void*)k_zfft_inv<T, 96>,
                          (const void*)k_zfft_fwd<T, 24>, (const void*)k_zfft_fwd<T, 32>,
-                         (const void*)k_zfft_fwd<T, 48>, (const void*)k_zfft_fwd<T, 64>};
+                         (const void*)k_zfft_fwd<T, 40>, (const void*)k_zfft_fwd<T, 48>,
+                         (const void*)k_zfft_fwd<T, 64>, (const void*)k_zfft_fwd<T, 72>,
+                         (const void*)k_zfft_fwd<T, 96>};
     for (const void* f : fns) {
       hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, big);
       if (e != hipSuccess) return e;
