@@ -106,6 +106,12 @@ typedef enum {             /* Lanczos recursions of Sec. 2.5 */
                               step; complex gamma and z */
 } lz_algorithm;
 
+typedef enum {        /* where the projector products (P_c and separable projectors) run */
+  LZ_GEMM_AUTO = 0,   /* matrix cores when nbnd >= 32 and nbnd + nproj >= 64, else vector ALU */
+  LZ_GEMM_VALU = 1,   /* vector ALU kernels (tuned for few bands) */
+  LZ_GEMM_MFMA = 2    /* matrix cores (MFMA), any size */
+} lz_projector_gemm;
+
 typedef struct {
   lz_precision prec;
   lz_approx approx;
@@ -119,6 +125,7 @@ typedef struct {
                          on its own HIP stream (instance i on stream i mod streams):
                          0 = min(n_inst, 4), 1 = one instance after another; at most 64.
                          Results do not depend on it (bitwise). */
+  lz_projector_gemm projector_gemm;  /* results agree to rounding across the choices */
 } lz_options;
 
 /*

@@ -25,6 +25,8 @@ LZ_EXTRAP_NONE, LZ_EXTRAP_CONSTANT, LZ_EXTRAP_OSC = 0, 1, 2
 EXTRAPOLATION = {"no": LZ_EXTRAP_NONE, "constant": LZ_EXTRAP_CONSTANT, "osc": LZ_EXTRAP_OSC}
 LZ_PSEUDO_HERMITIAN, LZ_NON_HERMITIAN = 0, 1
 ALGORITHM = {"ph": LZ_PSEUDO_HERMITIAN, "nh": LZ_NON_HERMITIAN}
+LZ_GEMM_AUTO, LZ_GEMM_VALU, LZ_GEMM_MFMA = 0, 1, 2
+GEMM = {"auto": LZ_GEMM_AUTO, "valu": LZ_GEMM_VALU, "mfma": LZ_GEMM_MFMA}
 STATUS_NAMES = {0: "ok", 1: "arg", 2: "hip", 3: "oom", 4: "not_pd", 5: "state", 6: "breakdown"}
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "liblz.so")
@@ -49,7 +51,8 @@ class LzSystem(ctypes.Structure):
 class LzOptions(ctypes.Structure):
     _fields_ = [("prec", ctypes.c_int), ("approx", ctypes.c_int), ("max_steps", ctypes.c_int32),
                 ("use_graph", ctypes.c_int32), ("autotune", ctypes.c_int32),
-                ("algorithm", ctypes.c_int), ("streams", ctypes.c_int32)]
+                ("algorithm", ctypes.c_int), ("streams", ctypes.c_int32),
+                ("projector_gemm", ctypes.c_int)]
 
 
 class LzError(RuntimeError):
@@ -157,10 +160,11 @@ def _stream_handle(device):
 
 
 def lz_init(systems, prec="fp64", approx="tddft", max_steps=1000, use_graph=False, autotune=False,
-            device=0, stream=None, algorithm="ph", streams=0):
+            device=0, stream=None, algorithm="ph", streams=0, projector_gemm="auto"):
     """Create a context for one system or a list of systems; returns a handle.
     algorithm: "ph" (pseudo-Hermitian) or "nh" (non-Hermitian biorthogonal);
-    streams: instances stepped side by side (0: the library default)."""
+    streams: instances stepped side by side (0: the library default);
+    projector_gemm: "auto", "valu" or "mfma" (where the projector products run)."""
     lib = load()
     systems = systems if isinstance(systems, (list, tuple)) else [systems]
     arr = (LzSystem * len(systems))()
@@ -172,7 +176,8 @@ def lz_init(systems, prec="fp64", approx="tddft", max_steps=1000, use_graph=Fals
                     APPROX[approx] if isinstance(approx, str) else int(approx),
                     int(max_steps), int(bool(use_graph)), int(bool(autotune)),
                     ALGORITHM[algorithm] if isinstance(algorithm, str) else int(algorithm),
-                    int(streams))
+                    int(streams),
+                    GEMM[projector_gemm] if isinstance(projector_gemm, str) else int(projector_gemm))
     out = ctypes.c_void_p()
     hs = _stream_handle(device) if stream is None else ctypes.c_void_p(stream)
     _check(lib.lz_init(arr, len(systems), ctypes.byref(opt), int(device), hs, ctypes.byref(out)))

@@ -1,0 +1,245 @@
+// Projector products on the matrix cores (MFMA) for instances with many
+// bands and projectors (Sec. 2.3 P_c and the separable projectors; the
+// products are complex GEMMs over plane waves).  Same contracts as the
+// vector-ALU kernels k_proj_dot / k_proj_update in lz_linalg.hip:
+//
+//   dot     partial[k][chunk][n][p] = sum_{G in chunk} conj(A[k][p][G]) X[k][n][G]
+//   update  Y[k][n][G] += sum_p A[k][p][G] C[k][p][n], then the epilogue of
+//           the recursion (plain, Lanczos sums, non-Hermitian formation)
+//
+// A complex product is four real MFMA products into separate real and
+// imaginary accumulators.  A wave owns a 32 x 32 complex output tile:
+//   float   one v_mfma_f32_32x32x2f32 per real product, k step 2; lane l
+//           supplies left[l % 32][l / 32] and right[l / 32][l % 32], and
+//           holds outputs (8 (v / 4) + 4 (l / 32) + v % 4, l % 32), v < 16;
+//   double  2 x 2 tiles of v_mfma_f64_16x16x4f64, k step 4; lane l supplies
+//           left[l % 16][l / 16] and right[l / 16][l % 16] per tile and
+//           holds outputs (l / 16 + 4 w, l % 16), w < 4, per tile.
+// (Lane layouts checked on the device against a host product.)  A block is
+// 2 x 2 waves over a 64 x 64 output tile; both operands of a k chunk are
+// staged in LDS.  Every sum has a fixed order: results do not depend on
+// scheduling.
+#pragma once
+#include "lz_kernels.h"
+
+namespace lz {
+
+typedef float mfma_f32x16 __attribute__((ext_vector_type(16)));
+typedef double mfma_f64x4 __attribute__((ext_vector_type(4)));
+
+template <typename T> struct WaveTile;
+
+template <> struct WaveTile<float> {
+  static constexpr int KS = 2;   // k per step
+  static constexpr int NV = 16;  // outputs per lane
+  mfma_f32x16 re, im;
+  __device__ __forceinline__ void zero() {
+#pragma unroll
+    for (int v = 0; v < 16; ++v) { re[v] = 0.f; im[v] = 0.f; }
+  }
+  // one k step; left(row, kq) and right(kq, col) return the operands.
+  // CONJ: accumulate conj(left) * right, else left * right.
+  template <bool CONJ, typename FL, typename FR>
+  __device__ __forceinline__ void step(int l, FL left, FR right) {
+    const float2 a = left(l % 32, l / 32);
+    const float2 b = right(l / 32, l % 32);
+    const float ai = CONJ ? a.y : -a.y;  // re += ar br + (conj ? +ai bi : -ai bi)
+    re = __builtin_amdgcn_mfma_f32_32x32x2f32(a.x, b.x, re, 0, 0, 0);
+    re = __builtin_amdgcn_mfma_f32_32x32x2f32(ai, b.y, re, 0, 0, 0);
+    im = __builtin_amdgcn_mfma_f32_32x32x2f32(a.x, b.y, im, 0, 0, 0);
+    im = __builtin_amdgcn_mfma_f32_32x32x2f32(-ai, b.x, im, 0, 0, 0);
+  }
+  __device__ __forceinline__ static int row(int v, int l) { return 8 * (v / 4) + 4 * (l / 32) + (v % 4); }
+  __device__ __forceinline__ static int col(int v, int l) { return l % 32; }
+  __device__ __forceinline__ float2 at(int v) const { return make_float2(re[v], im[v]); }
+};
+
+template <> struct WaveTile<double> {
+  static constexpr int KS = 4;
+  static constexpr int NV = 16;
+  mfma_f64x4 re[2][2], im[2][2];
+  __device__ __forceinline__ void zero() {
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+      for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int w = 0; w < 4; ++w) { re[r][c][w] = 0.0; im[r][c][w] = 0.0; }
+  }
+  template <bool CONJ, typename FL, typename FR>
+  __device__ __forceinline__ void step(int l, FL left, FR right) {
+    double2 a[2], b[2];
+#pragma unroll
+    for (int r = 0; r < 2; ++r) a[r] = left(16 * r + l % 16, l / 16);
+#pragma unroll
+    for (int c = 0; c < 2; ++c) b[c] = right(l / 16, 16 * c + l % 16);
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      const double ai = CONJ ? a[r].y : -a[r].y;
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        re[r][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[r].x, b[c].x, re[r][c], 0, 0, 0);
+        re[r][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, b[c].y, re[r][c], 0, 0, 0);
+        im[r][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[r].x, b[c].y, im[r][c], 0, 0, 0);
+        im[r][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai, b[c].x, im[r][c], 0, 0, 0);
+      }
+    }
+  }
+  // v = 8 r + 4 c + w
+  __device__ __forceinline__ static int row(int v, int l) { return 16 * (v / 8) + l / 16 + 4 * (v % 4); }
+  __device__ __forceinline__ static int col(int v, int l) { return 16 * ((v / 4) % 2) + l % 16; }
+  __device__ __forceinline__ double2 at(int v) const {
+    return make_double2(re[v / 8][(v / 4) % 2][v % 4], im[v / 8][(v / 4) % 2][v % 4]);
+  }
+};
+
+// k chunk staged per LDS round (multiple of the MFMA k step)
+template <typename T> constexpr int mfma_kc() { return sizeof(T) == 4 ? 32 : 16; }
+constexpr int kMfmaTile = 64;  // block output tile (both dimensions)
+
+// ---------------------------------------------------------------------------
+// dot: block = (p tile, n tile) x G chunk x k
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_proj_dot_mfma(const cplx<T>* __restrict__ A, int P,
+                                                       int a_rows, const cplx<T>* __restrict__ X,
+                                                       int nbnd, int npwx, int chunk, int nchunk,
+                                                       cplx<T>* __restrict__ partial,
+                                                       const LzDevState* st) {
+  if (st && st->status) return;
+  constexpr int BT = kMfmaTile, KC = mfma_kc<T>(), PITCH = KC + 1;
+  __shared__ cplx<T> As[BT * PITCH], Xs[BT * PITCH];
+  const int tilesN = (nbnd + BT - 1) / BT;
+  const int p0 = (blockIdx.x / tilesN) * BT, n0 = (blockIdx.x % tilesN) * BT;
+  const int ci = blockIdx.y, k = blockIdx.z;
+  const int tid = threadIdx.x, l = tid % 64, wave = tid / 64;
+  const int wp = (wave / 2) * 32, wn = (wave % 2) * 32;
+  const cplx<T>* Ak = A + (int64_t)k * a_rows * npwx;
+  const cplx<T>* Xk = X + (int64_t)k * nbnd * npwx;
+  const int g_begin = ci * chunk, g_end = min(npwx, g_begin + chunk);
+  const cplx<T> zero = mk<T>(T(0), T(0));
+  WaveTile<T> acc;
+  acc.zero();
+  for (int g0 = g_begin; g0 < g_end; g0 += KC) {
+    for (int t = tid; t < BT * KC; t += 256) {
+      const int r = t / KC, c = t - r * KC;
+      const int g = g0 + c;
+      const int p = p0 + r, n = n0 + r;
+      As[r * PITCH + c] = (p < P && g < g_end) ? Ak[(int64_t)p * npwx + g] : zero;
+      Xs[r * PITCH + c] = (n < nbnd && g < g_end) ? Xk[(int64_t)n * npwx + g] : zero;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < KC; kk += WaveTile<T>::KS) {
+      acc.template step<true>(
+          l, [&](int row, int kq) { return As[(wp + row) * PITCH + kk + kq]; },
+          [&](int kq, int col) { return Xs[(wn + col) * PITCH + kk + kq]; });
+    }
+    __syncthreads();
+  }
+  cplx<T>* out = partial + ((int64_t)k * nchunk + ci) * P * nbnd;
+#pragma unroll
+  for (int v = 0; v < WaveTile<T>::NV; ++v) {
+    const int p = p0 + wp + WaveTile<T>::row(v, l), n = n0 + wn + WaveTile<T>::col(v, l);
+    if (p < P && n < nbnd) out[(int64_t)n * P + p] = acc.at(v);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// update: block = (G tile, band tile, k); epilogue MODE as k_proj_update
+// ---------------------------------------------------------------------------
+template <typename T, int MODE>
+__global__ __launch_bounds__(256) void k_proj_update_mfma(
+    cplx<T>* __restrict__ Y, const cplx<T>* __restrict__ A, int P, int a_rows,
+    const cplx<T>* __restrict__ C, int c_rows, int nbnd, int npwx, cplx<T>* __restrict__ X,
+    const cplx<T>* __restrict__ yv, const cplx<T>* __restrict__ U2,
+    const double* __restrict__ wk, double* __restrict__ lzpart, const LzDevState* st) {
+  constexpr bool DOTS = MODE == kUpdDots || MODE == kUpdNhV;
+  constexpr int NR = MODE == kUpdNhV ? 4 : 3;
+  if (st && st->status) return;
+  constexpr int BT = kMfmaTile, KC = mfma_kc<T>(), PITCH = BT + 1;
+  __shared__ cplx<T> Cs[KC * PITCH], As[KC * PITCH];
+  __shared__ double red[NR][256];
+  const int g0 = blockIdx.x * BT, b0 = blockIdx.y * BT, k = blockIdx.z;
+  const int tid = threadIdx.x, l = tid % 64, wave = tid / 64;
+  const int wb = (wave / 2) * 32, wg = (wave % 2) * 32;
+  const cplx<T>* Ak = A + (int64_t)k * a_rows * npwx;
+  const cplx<T>* Ck = C + (int64_t)k * c_rows * nbnd;
+  const cplx<T> zero = mk<T>(T(0), T(0));
+  WaveTile<T> acc;
+  acc.zero();
+  for (int pc = 0; pc < P; pc += KC) {
+    for (int t = tid; t < KC * BT; t += 256) {
+      const int kk = t / BT, j = t - kk * BT;
+      const int p = pc + kk;
+      const int b = b0 + j, g = g0 + j;
+      Cs[kk * PITCH + j] = (p < P && b < nbnd) ? Ck[(int64_t)p * nbnd + b] : zero;
+      As[kk * PITCH + j] = (p < P && g < npwx) ? Ak[(int64_t)p * npwx + g] : zero;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < KC; kk += WaveTile<T>::KS) {
+      acc.template step<false>(
+          l, [&](int row, int kq) { return Cs[(kk + kq) * PITCH + wb + row]; },
+          [&](int kq, int col) { return As[(kk + kq) * PITCH + wg + col]; });
+    }
+    __syncthreads();
+  }
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  const int64_t kb = (int64_t)k * nbnd * npwx;
+  const double w = DOTS ? wk[k] : 0.0;
+  cplx<T> c1 = zero, c2 = zero;
+  if constexpr (MODE == kUpdNhU) {
+    c1 = mk<T>(T(st->cu1[0]), T(st->cu1[1]));
+    c2 = mk<T>(T(st->cu2[0]), T(st->cu2[1]));
+  } else if constexpr (MODE == kUpdNhV) {
+    c1 = mk<T>(T(st->cv1[0]), T(st->cv1[1]));
+    c2 = mk<T>(T(st->cv2[0]), T(st->cv2[1]));
+  }
+#pragma unroll
+  for (int v = 0; v < WaveTile<T>::NV; ++v) {
+    const int b = b0 + wb + WaveTile<T>::row(v, l), g = g0 + wg + WaveTile<T>::col(v, l);
+    if (b < nbnd && g < npwx) {
+      const int64_t o = kb + (int64_t)b * npwx + g;
+      const cplx<T> yn = cadd<T>(Y[o], acc.at(v));
+      if constexpr (MODE == kUpdPlain || MODE == kUpdDots) Y[o] = yn;
+      if constexpr (MODE == kUpdDots) {
+        const cplx<T> xv = X[o], rv = yv[o];
+        s0 += w * (double(xv.x) * double(yn.x) + double(xv.y) * double(yn.y));
+        s1 += w * (double(rv.x) * double(xv.x) + double(rv.y) * double(xv.y));
+        s2 += w * (double(rv.x) * double(xv.y) - double(rv.y) * double(xv.x));
+      }
+      if constexpr (MODE == kUpdNhU || MODE == kUpdNhV) {
+        const cplx<T> h = cadd<T>(cmul<T>(c1, yn), cmul<T>(c2, X[o]));
+        X[o] = h;
+        if constexpr (MODE == kUpdNhV) {
+          const cplx<T> uv = U2[o], rv = yv[o];
+          s0 += w * (double(uv.x) * double(h.x) + double(uv.y) * double(h.y));
+          s1 += w * (double(uv.x) * double(h.y) - double(uv.y) * double(h.x));
+          s2 += w * (double(rv.x) * double(h.x) + double(rv.y) * double(h.y));
+          s3 += w * (double(rv.x) * double(h.y) - double(rv.y) * double(h.x));
+        }
+      }
+    }
+  }
+  if constexpr (DOTS) {
+    const double sv[4] = {s0, s1, s2, s3};
+#pragma unroll
+    for (int r = 0; r < NR; ++r) red[r][tid] = sv[r];
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+      if (tid < h) {
+#pragma unroll
+        for (int r = 0; r < NR; ++r) red[r][tid] += red[r][tid + h];
+      }
+      __syncthreads();
+    }
+    if (tid == 0) {
+      const int blk = (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+#pragma unroll
+      for (int r = 0; r < NR; ++r) lzpart[NR * blk + r] = red[r][0];
+    }
+  }
+}
+
+}  // namespace lz

@@ -64,10 +64,13 @@ template <typename T> struct LaunchLin {
   // chunk partials of R[k][p][n] = sum_G conj(A[k][p][G]) X[k][n][G], rows p < P
   // of A (a_rows per k), laid out [k][chunk][n][p]; with LW != null the dot
   // first forms X <- a*LW + b*X (state coefficients)
+  // (mfma: on the matrix cores, lz_gemm_mfma.h; LW must then be null)
   static void proj_dot(const void* A, int P, int a_rows, void* X, const void* LW, int nbnd,
                        int npwx, int nks, int chunk, int nchunk, void* partial,
-                       const LzDevState* st, hipStream_t s);
-  static bool dot_single_tile(int P, int nbnd);
+                       const LzDevState* st, hipStream_t s, bool mfma = false);
+  static bool dot_single_tile(int P, int nbnd, bool mfma = false);
+  // G per chunk of the matrix-core dot for P rows (about 1024 blocks in all)
+  static int mfma_chunk(int P, int nbnd, int npwx, int nks);
   // R[k][p][n] from the partials
   static void reduce(const void* partial, int nchunk, int P, int nbnd, int nks, void* R,
                      hipStream_t s);
@@ -82,15 +85,16 @@ template <typename T> struct LaunchLin {
   // sums of (X, Y, y) per block (update_blocks of them)
   static void proj_update(void* Y, const void* A, int P, int a_rows, const void* C, int c_rows,
                           int nbnd, int npwx, int nks, const void* X, const void* y,
-                          const double* wk, double* lzpart, const LzDevState* st, hipStream_t s);
-  static int update_blocks(int P, int nbnd, int npwx, int nks);
+                          const double* wk, double* lzpart, const LzDevState* st, hipStream_t s,
+                          bool mfma = false);
+  static int update_blocks(int P, int nbnd, int npwx, int nks, bool mfma = false);
   // non-Hermitian formation on the output side (P = a_rows = c_rows): as
   // proj_update, then H <- c1 LY' + c2 H with the state coefficients of the
   // u chain (v_chain false) or of the v chain, which also sums (U2, H) and
   // (y, H) into lzpart (4 per block, update_blocks of them)
   static void nh_form(bool v_chain, void* LY, const void* A, int P, const void* C, int nbnd,
                       int npwx, int nks, void* H, const void* y, const void* U2, const double* wk,
-                      double* lzpart, const LzDevState* st, hipStream_t s);
+                      double* lzpart, const LzDevState* st, hipStream_t s, bool mfma = false);
   // Lanczos: w <- a*LW + b*w
   static void lz_update(void* w, const void* lw, int64_t n, const LzDevState* st, hipStream_t s);
   // user order <-> internal order

@@ -2,6 +2,8 @@
 // pseudo-Hermitian Lanczos recursion (Secs. 2.3-2.5 of the turboEELS paper):
 // projector products (P_c and separable projectors), Lanczos vector updates
 // and deterministic reductions, the spectrum solve, and layout permutations.
+#include <algorithm>
+
 #include "lz_kernels.h"
 
 namespace lz {
@@ -377,6 +379,10 @@ __global__ __launch_bounds__(256) void k_proj_update(
   }
 }
 
+}  // namespace lz
+#include "lz_gemm_mfma.h"
+namespace lz {
+
 // ---------------------------------------------------------------------------
 // Lanczos vectors and scalars
 // ---------------------------------------------------------------------------
@@ -687,7 +693,14 @@ __global__ __launch_bounds__(256) void k_spectrum(const double* __restrict__ bet
 template <typename T>
 void LaunchLin<T>::proj_dot(const void* A, int P, int a_rows, void* X, const void* LW, int nbnd,
                             int npwx, int nks, int chunk, int nchunk, void* partial,
-                            const LzDevState* st, hipStream_t s) {
+                            const LzDevState* st, hipStream_t s, bool mfma) {
+  if (mfma) {
+    const int tiles = ((P + kMfmaTile - 1) / kMfmaTile) * ((nbnd + kMfmaTile - 1) / kMfmaTile);
+    hipLaunchKernelGGL(k_proj_dot_mfma<T>, dim3(tiles, nchunk, nks), dim3(256), 0, s,
+                       (const cplx<T>*)A, P, a_rows, (const cplx<T>*)X, nbnd, npwx, chunk, nchunk,
+                       (cplx<T>*)partial, st);
+    return;
+  }
   const int tpi = P <= 16 ? 1 : P <= 32 ? 2 : P <= 48 ? 3 : 4;
   const int tnj = nbnd <= 16 ? 1 : 2;
   const int tiles = ((P + 16 * tpi - 1) / (16 * tpi)) * ((nbnd + 16 * tnj - 1) / (16 * tnj));
@@ -711,7 +724,18 @@ void LaunchLin<T>::proj_dot(const void* A, int P, int a_rows, void* X, const voi
 }
 
 template <typename T>
-bool LaunchLin<T>::dot_single_tile(int P, int nbnd) {
+int LaunchLin<T>::mfma_chunk(int P, int nbnd, int npwx, int nks) {
+  const int tiles = ((P + kMfmaTile - 1) / kMfmaTile) * ((nbnd + kMfmaTile - 1) / kMfmaTile) * nks;
+  const int target = std::max(1, 1024 / tiles);
+  const int kc = mfma_kc<T>();
+  int chunk = (npwx + target - 1) / target;
+  chunk = std::max(kc, (chunk + kc - 1) / kc * kc);
+  return chunk;
+}
+
+template <typename T>
+bool LaunchLin<T>::dot_single_tile(int P, int nbnd, bool mfma) {
+  if (mfma) return false;
   const int tpi = P <= 16 ? 1 : P <= 32 ? 2 : P <= 48 ? 3 : 4;
   const int tnj = nbnd <= 16 ? 1 : 2;
   return P <= 16 * tpi && nbnd <= 16 * tnj;
@@ -752,7 +776,9 @@ static int upd_groups(int P, int nbt) {
 }
 
 template <typename T>
-int LaunchLin<T>::update_blocks(int P, int nbnd, int npwx, int nks) {
+int LaunchLin<T>::update_blocks(int P, int nbnd, int npwx, int nks, bool mfma) {
+  if (mfma)
+    return ((npwx + kMfmaTile - 1) / kMfmaTile) * ((nbnd + kMfmaTile - 1) / kMfmaTile) * nks;
   const int nbt = upd_bands(nbnd);
   const int qn = upd_groups<T>(P, nbt);
   const int npt = 256 / qn;
@@ -763,7 +789,22 @@ template <typename T>
 static void launch_update(int mode, void* Y, const void* A, int P, int a_rows, const void* C,
                           int c_rows, int nbnd, int npwx, int nks, void* X, const void* y,
                           const void* U2, const double* wk, double* lzpart, const LzDevState* st,
-                          hipStream_t s) {
+                          hipStream_t s, bool mfma) {
+  if (mfma) {
+    dim3 grid((npwx + kMfmaTile - 1) / kMfmaTile, (nbnd + kMfmaTile - 1) / kMfmaTile, nks);
+#define LZ_UPDM(MODE)                                                                            \
+  hipLaunchKernelGGL((k_proj_update_mfma<T, MODE>), grid, dim3(256), 0, s, (cplx<T>*)Y,          \
+                     (const cplx<T>*)A, P, a_rows, (const cplx<T>*)C, c_rows, nbnd, npwx,        \
+                     (cplx<T>*)X, (const cplx<T>*)y, (const cplx<T>*)U2, wk, lzpart, st);
+    switch (mode) {
+      case kUpdDots: LZ_UPDM(kUpdDots) break;
+      case kUpdNhU: LZ_UPDM(kUpdNhU) break;
+      case kUpdNhV: LZ_UPDM(kUpdNhV) break;
+      default: LZ_UPDM(kUpdPlain) break;
+    }
+#undef LZ_UPDM
+    return;
+  }
   const int nbt = upd_bands(nbnd);
   const int qn = upd_groups<T>(P, nbt);
   const int npt = 256 / qn;
@@ -789,18 +830,18 @@ template <typename T>
 void LaunchLin<T>::proj_update(void* Y, const void* A, int P, int a_rows, const void* C,
                                int c_rows, int nbnd, int npwx, int nks, const void* X,
                                const void* y, const double* wk, double* lzpart,
-                               const LzDevState* st, hipStream_t s) {
+                               const LzDevState* st, hipStream_t s, bool mfma) {
   launch_update<T>(lzpart != nullptr ? kUpdDots : kUpdPlain, Y, A, P, a_rows, C, c_rows, nbnd,
-                   npwx, nks, const_cast<void*>(X), y, nullptr, wk, lzpart, st, s);
+                   npwx, nks, const_cast<void*>(X), y, nullptr, wk, lzpart, st, s, mfma);
 }
 
 template <typename T>
 void LaunchLin<T>::nh_form(bool v_chain, void* LY, const void* A, int P, const void* C, int nbnd,
                            int npwx, int nks, void* H, const void* y, const void* U2,
                            const double* wk, double* lzpart, const LzDevState* st,
-                           hipStream_t s) {
+                           hipStream_t s, bool mfma) {
   launch_update<T>(v_chain ? kUpdNhV : kUpdNhU, LY, A, P, P, C, P, nbnd, npwx, nks, H, y, U2, wk,
-                   v_chain ? lzpart : nullptr, st, s);
+                   v_chain ? lzpart : nullptr, st, s, mfma);
 }
 
 template <typename T>
