@@ -264,10 +264,17 @@ __global__ __launch_bounds__(256) void k_plane_local_density(
   PlaneShm<T, N> sh(smem_raw, a, tw1, tid);
   const int n1 = N > 0 ? N : a.n1, n2 = N > 0 ? N : a.n2, n3 = N > 0 ? N : a.n3;
   const int pitch = N > 0 ? N + 1 : a.pitch;
-  constexpr int ACC = N > 0 ? (N * N + 255) / 256 : MP;
+  // large double-precision planes (72^2, 96^2) keep the running sums in
+  // dpart itself (the block's own slice, read and written by the same thread
+  // in band order: the same sums, bitwise, as register accumulators, which
+  // would spill; in single precision the registers measured faster)
+  constexpr bool GACC = sizeof(T) == 8 && N >= 72;
+  constexpr int NIT = N > 0 ? (N * N + 255) / 256 : MP;
+  constexpr int ACC = GACC ? 1 : NIT;
   const int z = blockIdx.x, g = blockIdx.y;
   const int np = n1 * n2;
   const T* vz = vloc + (int64_t)z * np;
+  cplx<T>* dp = dpart + ((int64_t)g * n3 + z) * np;
   cplx<T> acc[ACC];
 #pragma unroll
   for (int i = 0; i < ACC; ++i) acc[i] = czero<T>();
@@ -279,15 +286,22 @@ __global__ __launch_bounds__(256) void k_plane_local_density(
     plane_cols<T, N, MP, +1>(sh, a, tw1, tid);
     const cplx<T>* ub = ur + ((int64_t)b * n3 + z) * np;
     const T wb = T(bandw[b]);
-#pragma unroll
-    for (int i = 0; i < ACC; ++i) {
+#pragma unroll(GACC ? 4 : NIT)
+    for (int i = 0; i < NIT; ++i) {
       const int p = tid + i * 256;
       if (p < np) {
         const int i1 = p / n2, i2 = p - i1 * n2;
         cplx<T>& c = sh.plane[i1 * pitch + i2];
         const cplx<T> d = cmulc<T>(ub[p], c);
-        acc[i].x += wb * d.x;
-        acc[i].y += wb * d.y;
+        if constexpr (GACC) {
+          cplx<T> s = b == b0 ? czero<T>() : dp[p];
+          s.x += wb * d.x;
+          s.y += wb * d.y;
+          dp[p] = s;
+        } else {
+          acc[i].x += wb * d.x;
+          acc[i].y += wb * d.y;
+        }
         c = cscale<T>(c, vz[p]);
       }
     }
@@ -297,11 +311,12 @@ __global__ __launch_bounds__(256) void k_plane_local_density(
     for (int s = tid; s < a.S; s += 256) sout[so + s] = sh.plane[a.si1[s] * pitch + a.si2[s]];
     __syncthreads();
   }
-  cplx<T>* dp = dpart + ((int64_t)g * n3 + z) * np;
+  if constexpr (!GACC) {
 #pragma unroll
-  for (int i = 0; i < ACC; ++i) {
-    const int p = tid + i * 256;
-    if (p < np) dp[p] = acc[i];
+    for (int i = 0; i < ACC; ++i) {
+      const int p = tid + i * 256;
+      if (p < np) dp[p] = acc[i];
+    }
   }
 }
 
