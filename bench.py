@@ -39,6 +39,8 @@ def _args():
     ap.add_argument("--warmup", type=int, default=10, help="untimed Liouvillian applications")
     ap.add_argument("--config", default="cfg2")
     ap.add_argument("--prec", default="both", choices=["fp64", "fp32", "both"])
+    ap.add_argument("--splitbf16", action="store_true",
+                    help="also time the split-bf16 projector products against the same FP64 gate")
     ap.add_argument("--lanczos-steps", type=int, default=300,
                     help="steps of one recursion (the mixed path tracks FP64 to 1e-4 up to ~350)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the oracle sample")
@@ -298,6 +300,9 @@ def main():
              f"recursions of {a.lanczos_steps} steps")
         res[p] = run_gpu(s, p, a.steps, a.warmup, a.lanczos_steps, a.graph)
         _log(f"[bench] gpu {p}: {res[p]['applies'] / res[p]['elapsed']:.1f} applies/s")
+    if a.splitbf16:
+        _log("[bench] gpu splitbf16")
+        res_b3 = run_gpu(s, "splitbf16", a.steps, a.warmup, a.lanczos_steps, a.graph)
     rate = {p: res[p]["applies"] / res[p]["elapsed"] for p in res}
     gate = None
     head = precs[-1]
@@ -359,6 +364,12 @@ def main():
         _log(f"[bench] q sweep, {a.sweep_steps} steps ({head})")
         out["q_sweep"] = q_sweep_rate(head, a.sweep_steps)
         _log(f"[bench] {out['q_sweep']}")
+    if a.splitbf16 and "fp64" in res:
+        f64, b3 = res["fp64"]["loss"], res_b3["loss"]
+        floor = 1e-6 * np.abs(f64).max()
+        err = float(np.max(np.abs(b3 - f64) / np.maximum(np.abs(f64), floor)))
+        out["splitbf16_vs_fp64"] = {"applies_per_s": round(res_b3["applies"] / res_b3["elapsed"], 2),
+                                    "max_rel_err": err, "pass": err <= GATE}
     if not a.no_cpu_baseline:
         _log("[bench] cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(s, a.cpu_seconds)

@@ -44,8 +44,10 @@ typedef enum {
   LZ_FP64 = 0,            /* every array and every FFT in double precision */
   LZ_FP32 = 1,            /* vectors, FFTs, pointwise work and projector products in
                              single precision; Lanczos scalars and the spectrum in double */
-  LZ_FP32_SPLITBF16 = 2   /* reserved for projector products as three bf16 MFMA products of
-                             (hi, lo) splits; not available: lz_init returns LZ_ERR_ARG */
+  LZ_FP32_SPLITBF16 = 2   /* as LZ_FP32, with the projector products on the matrix cores as
+                             three bf16 products of (hi, lo) splits of every FP32 operand
+                             (x ~ bf16(x) + bf16(x - bf16(x)); the lo*lo term is dropped,
+                             about 2^-16 relative per product), FP32 accumulation */
 } lz_precision;
 
 typedef enum {   /* levels of theory of Sec. 3.2 */

@@ -185,7 +185,7 @@ struct Instance {
   int ngroups = 1, gsize = 1;
   int ptot = 0;                // rows of the stacked projector array [U; beta]
   int chunk = 32, nchunk = 1;  // split of the projector products over G
-  bool mfma = false;           // projector products on the matrix cores
+  int gemm = kGemmValu;        // where the projector products run
   int nlzblk = 1;              // blocks of the output update (Lanczos partial sums)
   int64_t nvec;  // complex elements of one batch
   Grid3 grid;
@@ -256,18 +256,18 @@ bool valid_len(int n) {
 template <typename T>
 void input_side(Instance& I, void* x, const void* lw, bool project, const LzDevState* st,
                 hipStream_t s) {
-  const bool fuse = lw != nullptr && LaunchLin<T>::dot_single_tile(I.ptot, I.nbnd, I.mfma);
+  const bool fuse = lw != nullptr && LaunchLin<T>::dot_single_tile(I.ptot, I.nbnd, I.gemm);
   if (lw != nullptr && !fuse)
     STAGE(I, ST_LANCZOS, s, LaunchLin<T>::lz_update(x, lw, I.nvec, st, s));
   STAGE(I, ST_PROJ, s,
         LaunchLin<T>::proj_dot(I.Aio.p, I.ptot, I.ptot, x, fuse ? lw : nullptr, I.nbnd, I.npwx,
-                               I.nks, I.chunk, I.nchunk, I.dpartial.p, st, s, I.mfma);
+                               I.nks, I.chunk, I.nchunk, I.dpartial.p, st, s, I.gemm);
         LaunchLin<T>::reduce_coef_in(I.dpartial.p, I.nchunk, I.Mkb.p, I.dkb.as<double>(),
                                      I.nbnd, I.nproj, I.nks, !project, I.Cin.p, st, s));
   if (project)
     STAGE(I, ST_PROJ, s,
           LaunchLin<T>::proj_update(x, I.Aio.p, I.nbnd, I.ptot, I.Cin.p, I.ptot, I.nbnd, I.npwx,
-                                    I.nks, nullptr, nullptr, nullptr, nullptr, st, s, I.mfma));
+                                    I.nks, nullptr, nullptr, nullptr, nullptr, st, s, I.gemm));
 }
 
 // Output side: out <- P_c (out + beta D B), as out + [U; beta] C_out with
@@ -278,11 +278,11 @@ void output_side(Instance& I, void* out, const void* x, double* lzpart, const Lz
                  hipStream_t s) {
   STAGE(I, ST_PROJ, s,
         LaunchLin<T>::proj_dot(I.Aio.p, I.nbnd, I.ptot, out, nullptr, I.nbnd, I.npwx, I.nks,
-                               I.chunk, I.nchunk, I.dpartial.p, st, s, I.mfma);
+                               I.chunk, I.nchunk, I.dpartial.p, st, s, I.gemm);
         LaunchLin<T>::reduce_coef_out(I.dpartial.p, I.nchunk, I.Cin.p, I.Mkb.p, I.nbnd, I.nproj,
                                       I.nks, I.Cout.p, st, s);
         LaunchLin<T>::proj_update(out, I.Aio.p, I.ptot, I.ptot, I.Cout.p, I.ptot, I.nbnd, I.npwx,
-                                  I.nks, x, I.y.p, I.wk.as<double>(), lzpart, st, s, I.mfma));
+                                  I.nks, x, I.y.p, I.wk.as<double>(), lzpart, st, s, I.gemm));
 }
 
 // FFT part of one half-application: out = (H_loc - eps) in (+ v'u for an
@@ -322,11 +322,11 @@ void apply_half(Instance& I, void* in, void* out, bool upper, hipStream_t s) {
 template <typename T>
 void project_c(Instance& I, void* x, hipStream_t s) {
   LaunchLin<T>::proj_dot(I.Aio.p, I.nbnd, I.ptot, x, nullptr, I.nbnd, I.npwx, I.nks, I.chunk,
-                         I.nchunk, I.dpartial.p, nullptr, s, I.mfma);
+                         I.nchunk, I.dpartial.p, nullptr, s, I.gemm);
   LaunchLin<T>::reduce_coef_in(I.dpartial.p, I.nchunk, I.Mkb.p, I.dkb.as<double>(), I.nbnd, 0,
                                I.nks, false, I.Cin.p, nullptr, s);
   LaunchLin<T>::proj_update(x, I.Aio.p, I.nbnd, I.ptot, I.Cin.p, I.nbnd, I.nbnd, I.npwx, I.nks,
-                            nullptr, nullptr, nullptr, nullptr, nullptr, s, I.mfma);
+                            nullptr, nullptr, nullptr, nullptr, nullptr, s, I.gemm);
 }
 
 // Lanczos step j: w_j = a LW + b w_{j-2} (j > 0), w_j <- P_c w_j, LW = L w_j,
@@ -370,21 +370,21 @@ void nh_step(Instance& I, int j, hipStream_t s) {
   apply_core<T>(I, U, I.LU.p, !v_upper, st, s);
   STAGE(I, ST_PROJ, s,
         LaunchLin<T>::proj_dot(I.Aio.p, I.nbnd, I.ptot, I.LU.p, nullptr, I.nbnd, I.npwx, I.nks,
-                               I.chunk, I.nchunk, I.dpartial.p, st, s, I.mfma);
+                               I.chunk, I.nchunk, I.dpartial.p, st, s, I.gemm);
         LaunchLin<T>::reduce_coef_out(I.dpartial.p, I.nchunk, I.Cin.p, I.Mkb.p, I.nbnd, I.nproj,
                                       I.nks, I.Cout.p, st, s);
         LaunchLin<T>::nh_form(false, I.LU.p, I.Aio.p, I.ptot, I.Cout.p, I.nbnd, I.npwx, I.nks, Un,
-                              nullptr, nullptr, nullptr, nullptr, st, s, I.mfma));
+                              nullptr, nullptr, nullptr, nullptr, st, s, I.gemm));
   // v chain: L v^_{j-1}, then v^_j with the sums
   input_side<T>(I, V, nullptr, true, st, s);
   apply_core<T>(I, V, I.LW.p, v_upper, st, s);
   STAGE(I, ST_PROJ, s,
         LaunchLin<T>::proj_dot(I.Aio.p, I.nbnd, I.ptot, I.LW.p, nullptr, I.nbnd, I.npwx, I.nks,
-                               I.chunk, I.nchunk, I.dpartial.p, st, s, I.mfma);
+                               I.chunk, I.nchunk, I.dpartial.p, st, s, I.gemm);
         LaunchLin<T>::reduce_coef_out(I.dpartial.p, I.nchunk, I.Cin.p, I.Mkb.p, I.nbnd, I.nproj,
                                       I.nks, I.Cout.p, st, s);
         LaunchLin<T>::nh_form(true, I.LW.p, I.Aio.p, I.ptot, I.Cout.p, I.nbnd, I.npwx, I.nks, Vn,
-                              I.y.p, Un, I.wk.as<double>(), part, st, s, I.mfma));
+                              I.y.p, Un, I.wk.as<double>(), part, st, s, I.gemm));
   STAGE(I, ST_LANCZOS, s,
         launch_nh_finalize(part, I.nlzblk, st, I.beta.as<double>(), I.gam.as<double>(),
                            I.z.as<double>(), I.max_steps, kBreakdownTol, (double)I.nbnd, s));
@@ -434,7 +434,7 @@ void build_device_tables(Instance& I, hipStream_t s, const std::vector<double>& 
   if (I.nproj > 0) {
     const void* beta = (const char*)I.Aio.p + (size_t)I.nbnd * I.npwx * I.csz;
     LaunchLin<T>::proj_dot(beta, I.nproj, I.ptot, I.U.p, nullptr, I.nbnd, I.npwx, I.nks, I.chunk,
-                           I.nchunk, I.dpartial.p, nullptr, s, I.mfma);
+                           I.nchunk, I.dpartial.p, nullptr, s, I.gemm);
     LaunchLin<T>::reduce(I.dpartial.p, I.nchunk, I.nproj, I.nbnd, I.nks, I.Mkb.p, s);
   }
   // y = P_c (shifted u)
@@ -739,10 +739,12 @@ std::unique_ptr<Instance> build_instance(const lz_system& sys, const lz_options&
   I.nr.alloc((size_t)I.N * I.csz);
   I.work.alloc((size_t)I.N * I.csz);
   I.vp.alloc((size_t)I.N * I.csz);
-  // projector products: matrix cores for many bands and rows (or as asked)
-  I.mfma = opt.projector_gemm == LZ_GEMM_MFMA ||
-           (opt.projector_gemm == LZ_GEMM_AUTO && I.nbnd >= 32 && I.ptot >= 64);
-  if (I.mfma)
+  // projector products: matrix cores for many bands and rows (or as asked);
+  // the split-bf16 precision always takes the matrix cores
+  const bool mc = opt.projector_gemm == LZ_GEMM_MFMA ||
+                  (opt.projector_gemm == LZ_GEMM_AUTO && I.nbnd >= 32 && I.ptot >= 64);
+  I.gemm = I.prec == LZ_FP32_SPLITBF16 ? kGemmBf16x3 : mc ? kGemmMfma : kGemmValu;
+  if (I.gemm != kGemmValu)
     I.chunk = I.fp64 ? LaunchLin<double>::mfma_chunk(I.ptot, I.nbnd, I.npwx, I.nks)
                      : LaunchLin<float>::mfma_chunk(I.ptot, I.nbnd, I.npwx, I.nks);
   else
@@ -752,8 +754,8 @@ std::unique_ptr<Instance> build_instance(const lz_system& sys, const lz_options&
   I.Cin.alloc((size_t)I.nks * I.ptot * I.nbnd * I.csz);
   I.Cout.alloc((size_t)I.nks * I.ptot * I.nbnd * I.csz);
   I.Mkb.alloc((size_t)I.nks * std::max(1, I.nproj) * I.nbnd * I.csz);
-  I.nlzblk = I.fp64 ? LaunchLin<double>::update_blocks(I.ptot, I.nbnd, I.npwx, I.nks, I.mfma)
-                    : LaunchLin<float>::update_blocks(I.ptot, I.nbnd, I.npwx, I.nks, I.mfma);
+  I.nlzblk = I.fp64 ? LaunchLin<double>::update_blocks(I.ptot, I.nbnd, I.npwx, I.nks, I.gemm)
+                    : LaunchLin<float>::update_blocks(I.ptot, I.nbnd, I.npwx, I.nks, I.gemm);
   I.lzpart.alloc((size_t)std::max(I.nlzblk, kNhNormBlocks) * 4 * sizeof(double));
   I.st.alloc(sizeof(LzDevState));
   I.beta.alloc((size_t)I.max_steps * sizeof(double));
@@ -860,9 +862,8 @@ lz_status lz_init(const lz_system* sys, int32_t n_inst, const lz_options* opt, i
     if (!sys || !opt || !out) fail(LZ_ERR_ARG, "null argument");
     if (n_inst < 1) fail(LZ_ERR_ARG, "n_inst must be >= 1");
     if (opt->max_steps < 1) fail(LZ_ERR_ARG, "max_steps must be >= 1");
-    if (opt->prec == LZ_FP32_SPLITBF16)
-      fail(LZ_ERR_ARG, "LZ_FP32_SPLITBF16 (split-bf16 projector products) is not available");
-    if (opt->prec != LZ_FP64 && opt->prec != LZ_FP32) fail(LZ_ERR_ARG, "unknown precision");
+    if (opt->prec != LZ_FP64 && opt->prec != LZ_FP32 && opt->prec != LZ_FP32_SPLITBF16)
+      fail(LZ_ERR_ARG, "unknown precision");
     if (opt->approx != LZ_TDDFT && opt->approx != LZ_RPA && opt->approx != LZ_IPA)
       fail(LZ_ERR_ARG, "unknown approximation");
     if (opt->algorithm != LZ_PSEUDO_HERMITIAN && opt->algorithm != LZ_NON_HERMITIAN)

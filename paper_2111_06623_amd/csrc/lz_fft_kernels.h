@@ -271,6 +271,7 @@ __global__ __launch_bounds__(256) void k_plane_local_density(
   constexpr bool GACC = sizeof(T) == 8 && N >= 72;
   constexpr int NIT = N > 0 ? (N * N + 255) / 256 : MP;
   constexpr int ACC = GACC ? 1 : NIT;
+  constexpr int UNR = GACC ? 4 : NIT;
   const int z = blockIdx.x, g = blockIdx.y;
   const int np = n1 * n2;
   const T* vz = vloc + (int64_t)z * np;
@@ -286,7 +287,7 @@ __global__ __launch_bounds__(256) void k_plane_local_density(
     plane_cols<T, N, MP, +1>(sh, a, tw1, tid);
     const cplx<T>* ub = ur + ((int64_t)b * n3 + z) * np;
     const T wb = T(bandw[b]);
-#pragma unroll(GACC ? 4 : NIT)
+#pragma unroll UNR
     for (int i = 0; i < NIT; ++i) {
       const int p = tid + i * 256;
       if (p < np) {

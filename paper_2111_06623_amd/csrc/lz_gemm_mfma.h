@@ -145,46 +145,22 @@ __global__ __launch_bounds__(256) void k_proj_dot_mfma(const cplx<T>* __restrict
   }
 }
 
-// ---------------------------------------------------------------------------
-// update: block = (G tile, band tile, k); epilogue MODE as k_proj_update
-// ---------------------------------------------------------------------------
-template <typename T, int MODE>
-__global__ __launch_bounds__(256) void k_proj_update_mfma(
-    cplx<T>* __restrict__ Y, const cplx<T>* __restrict__ A, int P, int a_rows,
-    const cplx<T>* __restrict__ C, int c_rows, int nbnd, int npwx, cplx<T>* __restrict__ X,
-    const cplx<T>* __restrict__ yv, const cplx<T>* __restrict__ U2,
-    const double* __restrict__ wk, double* __restrict__ lzpart, const LzDevState* st) {
+// Epilogue of an update tile (MODE as k_proj_update): the wave's outputs
+// at band bw + row, plane wave gw + col; block sums into lzpart.
+template <typename T, int MODE, typename TILE>
+__device__ __forceinline__ void update_epilogue(const TILE& acc, cplx<T>* __restrict__ Y,
+                                                int nbnd, int npwx,
+                                                cplx<T>* __restrict__ X,
+                                                const cplx<T>* __restrict__ yv,
+                                                const cplx<T>* __restrict__ U2,
+                                                const double* __restrict__ wk,
+                                                double* __restrict__ lzpart, const LzDevState* st,
+                                                int bw, int gw, int k, int l,
+                                                double (*red)[256]) {
   constexpr bool DOTS = MODE == kUpdDots || MODE == kUpdNhV;
   constexpr int NR = MODE == kUpdNhV ? 4 : 3;
-  if (st && st->status) return;
-  constexpr int BT = kMfmaTile, KC = mfma_kc<T>(), PITCH = BT + 1;
-  __shared__ cplx<T> Cs[KC * PITCH], As[KC * PITCH];
-  __shared__ double red[NR][256];
-  const int g0 = blockIdx.x * BT, b0 = blockIdx.y * BT, k = blockIdx.z;
-  const int tid = threadIdx.x, l = tid % 64, wave = tid / 64;
-  const int wb = (wave / 2) * 32, wg = (wave % 2) * 32;
-  const cplx<T>* Ak = A + (int64_t)k * a_rows * npwx;
-  const cplx<T>* Ck = C + (int64_t)k * c_rows * nbnd;
+  const int tid = threadIdx.x;
   const cplx<T> zero = mk<T>(T(0), T(0));
-  WaveTile<T> acc;
-  acc.zero();
-  for (int pc = 0; pc < P; pc += KC) {
-    for (int t = tid; t < KC * BT; t += 256) {
-      const int kk = t / BT, j = t - kk * BT;
-      const int p = pc + kk;
-      const int b = b0 + j, g = g0 + j;
-      Cs[kk * PITCH + j] = (p < P && b < nbnd) ? Ck[(int64_t)p * nbnd + b] : zero;
-      As[kk * PITCH + j] = (p < P && g < npwx) ? Ak[(int64_t)p * npwx + g] : zero;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int kk = 0; kk < KC; kk += WaveTile<T>::KS) {
-      acc.template step<false>(
-          l, [&](int row, int kq) { return Cs[(kk + kq) * PITCH + wb + row]; },
-          [&](int kq, int col) { return As[(kk + kq) * PITCH + wg + col]; });
-    }
-    __syncthreads();
-  }
   double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
   const int64_t kb = (int64_t)k * nbnd * npwx;
   const double w = DOTS ? wk[k] : 0.0;
@@ -197,8 +173,8 @@ __global__ __launch_bounds__(256) void k_proj_update_mfma(
     c2 = mk<T>(T(st->cv2[0]), T(st->cv2[1]));
   }
 #pragma unroll
-  for (int v = 0; v < WaveTile<T>::NV; ++v) {
-    const int b = b0 + wb + WaveTile<T>::row(v, l), g = g0 + wg + WaveTile<T>::col(v, l);
+  for (int v = 0; v < TILE::NV; ++v) {
+    const int b = bw + TILE::row(v, l), g = gw + TILE::col(v, l);
     if (b < nbnd && g < npwx) {
       const int64_t o = kb + (int64_t)b * npwx + g;
       const cplx<T> yn = cadd<T>(Y[o], acc.at(v));
@@ -240,6 +216,220 @@ __global__ __launch_bounds__(256) void k_proj_update_mfma(
       for (int r = 0; r < NR; ++r) lzpart[NR * blk + r] = red[r][0];
     }
   }
+}
+
+// ---------------------------------------------------------------------------
+// update: block = (G tile, band tile, k); epilogue MODE as k_proj_update
+// ---------------------------------------------------------------------------
+template <typename T, int MODE>
+__global__ __launch_bounds__(256) void k_proj_update_mfma(
+    cplx<T>* __restrict__ Y, const cplx<T>* __restrict__ A, int P, int a_rows,
+    const cplx<T>* __restrict__ C, int c_rows, int nbnd, int npwx, cplx<T>* __restrict__ X,
+    const cplx<T>* __restrict__ yv, const cplx<T>* __restrict__ U2,
+    const double* __restrict__ wk, double* __restrict__ lzpart, const LzDevState* st) {
+  constexpr int NR = MODE == kUpdNhV ? 4 : 3;
+  if (st && st->status) return;
+  constexpr int BT = kMfmaTile, KC = mfma_kc<T>(), PITCH = BT + 1;
+  __shared__ cplx<T> Cs[KC * PITCH], As[KC * PITCH];
+  __shared__ double red[NR][256];
+  const int g0 = blockIdx.x * BT, b0 = blockIdx.y * BT, k = blockIdx.z;
+  const int tid = threadIdx.x, l = tid % 64, wave = tid / 64;
+  const int wb = (wave / 2) * 32, wg = (wave % 2) * 32;
+  const cplx<T>* Ak = A + (int64_t)k * a_rows * npwx;
+  const cplx<T>* Ck = C + (int64_t)k * c_rows * nbnd;
+  const cplx<T> zero = mk<T>(T(0), T(0));
+  WaveTile<T> acc;
+  acc.zero();
+  for (int pc = 0; pc < P; pc += KC) {
+    for (int t = tid; t < KC * BT; t += 256) {
+      const int kk = t / BT, j = t - kk * BT;
+      const int p = pc + kk;
+      const int b = b0 + j, g = g0 + j;
+      Cs[kk * PITCH + j] = (p < P && b < nbnd) ? Ck[(int64_t)p * nbnd + b] : zero;
+      As[kk * PITCH + j] = (p < P && g < npwx) ? Ak[(int64_t)p * npwx + g] : zero;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < KC; kk += WaveTile<T>::KS) {
+      acc.template step<false>(
+          l, [&](int row, int kq) { return Cs[(kk + kq) * PITCH + wb + row]; },
+          [&](int kq, int col) { return As[(kk + kq) * PITCH + wg + col]; });
+    }
+    __syncthreads();
+  }
+  update_epilogue<T, MODE, WaveTile<T>>(acc, Y, nbnd, npwx, X, yv, U2, wk, lzpart, st, b0 + wb,
+                                        g0 + wg, k, l, red);
+}
+
+
+// ---------------------------------------------------------------------------
+// Split-bf16 products (precision LZ_FP32_SPLITBF16): every FP32 operand
+// value x is held as x ~ hi + lo with hi = bf16(x) and lo = bf16(x - hi)
+// (round to nearest even; x - hi is exact in FP32), and a real product
+// x y as hi_x hi_y + hi_x lo_y + lo_x hi_y, three v_mfma_f32_32x32x16_bf16
+// with FP32 accumulation (the dropped lo_x lo_y is 2^-16 relative).  Lane l
+// supplies left[l % 32][8 (l / 32) + t] and right[8 (l / 32) + t][l % 32],
+// t < 8, and holds the outputs of the f32 32x32 tile above.  Operands sit in
+// LDS as four bf16 planes (re hi, re lo, im hi, im lo), k contiguous.
+// ---------------------------------------------------------------------------
+typedef __bf16 mfma_bf16x8 __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ unsigned short bf16_rne(float x) {
+  unsigned u = __float_as_uint(x);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (unsigned short)(u >> 16);
+}
+__device__ __forceinline__ float bf16_value(unsigned short h) {
+  return __uint_as_float((unsigned)h << 16);
+}
+
+constexpr int kB3Kc = 32;           // k per LDS round
+constexpr int kB3Pitch = kB3Kc + 8; // bf16 per LDS row (16-byte aligned rows)
+
+// four planes [4][64 rows][kB3Pitch] of bf16
+struct B3Planes {
+  unsigned short* base;
+  __device__ __forceinline__ unsigned short* plane(int q) const { return base + q * 64 * kB3Pitch; }
+  // store complex value v at (row, k): split both parts
+  __device__ __forceinline__ void put(int row, int k, float2 v) const {
+    const int o = row * kB3Pitch + k;
+    const unsigned short rh = bf16_rne(v.x), ih = bf16_rne(v.y);
+    plane(0)[o] = rh;
+    plane(1)[o] = bf16_rne(v.x - bf16_value(rh));
+    plane(2)[o] = ih;
+    plane(3)[o] = bf16_rne(v.y - bf16_value(ih));
+  }
+  // eight consecutive k of one row of plane q (16 bytes)
+  __device__ __forceinline__ uint4 get8(int q, int row, int k) const {
+    return *reinterpret_cast<const uint4*>(plane(q) + row * kB3Pitch + k);
+  }
+};
+
+__device__ __forceinline__ mfma_bf16x8 as_bf16x8(uint4 v) { return __builtin_bit_cast(mfma_bf16x8, v); }
+__device__ __forceinline__ uint4 neg8(uint4 v) {
+  return make_uint4(v.x ^ 0x80008000u, v.y ^ 0x80008000u, v.z ^ 0x80008000u, v.w ^ 0x80008000u);
+}
+
+struct WaveTileB3 {
+  static constexpr int KS = 16;
+  static constexpr int NV = 16;
+  mfma_f32x16 re, im;
+  __device__ __forceinline__ void zero() {
+#pragma unroll
+    for (int v = 0; v < 16; ++v) { re[v] = 0.f; im[v] = 0.f; }
+  }
+  // acc += x y over 16 k, x and y as (hi, lo) pairs
+  __device__ __forceinline__ static mfma_f32x16 prod(mfma_f32x16 acc, uint4 xh, uint4 xl, uint4 yh,
+                                                     uint4 yl) {
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf16x8(xh), as_bf16x8(yh), acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf16x8(xh), as_bf16x8(yl), acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf16x8(xl), as_bf16x8(yh), acc, 0, 0, 0);
+    return acc;
+  }
+  // one k step of 16 at k0: left rows lr + l % 32 of L, right rows rr + l % 32
+  // of R (R stored [col][k]); CONJ: conj(left) * right
+  template <bool CONJ>
+  __device__ __forceinline__ void step(int l, const B3Planes& L, int lr, const B3Planes& R, int rr,
+                                       int k0) {
+    const int kq = k0 + 8 * (l / 32);
+    const int li = lr + l % 32, rj = rr + l % 32;
+    const uint4 arh = L.get8(0, li, kq), arl = L.get8(1, li, kq);
+    uint4 aih = L.get8(2, li, kq), ail = L.get8(3, li, kq);
+    const uint4 brh = R.get8(0, rj, kq), brl = R.get8(1, rj, kq);
+    const uint4 bih = R.get8(2, rj, kq), bil = R.get8(3, rj, kq);
+    // conj: re += ar br + ai bi, im += ar bi - ai br
+    // else: re += ar br - ai bi, im += ar bi + ai br
+    const uint4 pih = CONJ ? aih : neg8(aih), pil = CONJ ? ail : neg8(ail);  // sign into re
+    const uint4 qih = CONJ ? neg8(aih) : aih, qil = CONJ ? neg8(ail) : ail;  // sign into im
+    re = prod(re, arh, arl, brh, brl);
+    re = prod(re, pih, pil, bih, bil);
+    im = prod(im, arh, arl, bih, bil);
+    im = prod(im, qih, qil, brh, brl);
+  }
+  __device__ __forceinline__ static int row(int v, int l) { return 8 * (v / 4) + 4 * (l / 32) + (v % 4); }
+  __device__ __forceinline__ static int col(int v, int l) { return l % 32; }
+  __device__ __forceinline__ float2 at(int v) const { return make_float2(re[v], im[v]); }
+};
+
+// dot with split-bf16 products (contract of k_proj_dot_mfma, FP32)
+__global__ __launch_bounds__(256) void k_proj_dot_b3(const float2* __restrict__ A, int P,
+                                                     int a_rows, const float2* __restrict__ X,
+                                                     int nbnd, int npwx, int chunk, int nchunk,
+                                                     float2* __restrict__ partial,
+                                                     const LzDevState* st) {
+  if (st && st->status) return;
+  constexpr int BT = kMfmaTile, KC = kB3Kc;
+  __shared__ __align__(16) unsigned short lds[2 * 4 * 64 * kB3Pitch];
+  const B3Planes As{lds}, Xs{lds + 4 * 64 * kB3Pitch};
+  const int tilesN = (nbnd + BT - 1) / BT;
+  const int p0 = (blockIdx.x / tilesN) * BT, n0 = (blockIdx.x % tilesN) * BT;
+  const int ci = blockIdx.y, k = blockIdx.z;
+  const int tid = threadIdx.x, l = tid % 64, wave = tid / 64;
+  const int wp = (wave / 2) * 32, wn = (wave % 2) * 32;
+  const float2* Ak = A + (int64_t)k * a_rows * npwx;
+  const float2* Xk = X + (int64_t)k * nbnd * npwx;
+  const int g_begin = ci * chunk, g_end = min(npwx, g_begin + chunk);
+  const float2 zero = make_float2(0.f, 0.f);
+  WaveTileB3 acc;
+  acc.zero();
+  for (int g0 = g_begin; g0 < g_end; g0 += KC) {
+    for (int t = tid; t < BT * KC; t += 256) {
+      const int r = t / KC, c = t - r * KC;
+      const int g = g0 + c;
+      const int p = p0 + r, n = n0 + r;
+      As.put(r, c, (p < P && g < g_end) ? Ak[(int64_t)p * npwx + g] : zero);
+      Xs.put(r, c, (n < nbnd && g < g_end) ? Xk[(int64_t)n * npwx + g] : zero);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < KC; kk += WaveTileB3::KS) acc.step<true>(l, As, wp, Xs, wn, kk);
+    __syncthreads();
+  }
+  float2* out = partial + ((int64_t)k * nchunk + ci) * P * nbnd;
+#pragma unroll
+  for (int v = 0; v < WaveTileB3::NV; ++v) {
+    const int p = p0 + wp + WaveTileB3::row(v, l), n = n0 + wn + WaveTileB3::col(v, l);
+    if (p < P && n < nbnd) out[(int64_t)n * P + p] = acc.at(v);
+  }
+}
+
+// update with split-bf16 products (contract of k_proj_update_mfma, FP32):
+// C^T rows (bands) and A^T rows (plane waves) staged with p contiguous
+template <int MODE>
+__global__ __launch_bounds__(256) void k_proj_update_b3(
+    float2* __restrict__ Y, const float2* __restrict__ A, int P, int a_rows,
+    const float2* __restrict__ C, int c_rows, int nbnd, int npwx, float2* __restrict__ X,
+    const float2* __restrict__ yv, const float2* __restrict__ U2, const double* __restrict__ wk,
+    double* __restrict__ lzpart, const LzDevState* st) {
+  constexpr int NR = MODE == kUpdNhV ? 4 : 3;
+  if (st && st->status) return;
+  constexpr int BT = kMfmaTile, KC = kB3Kc;
+  __shared__ __align__(16) unsigned short lds[2 * 4 * 64 * kB3Pitch];
+  __shared__ double red[NR][256];
+  const B3Planes Cs{lds}, As{lds + 4 * 64 * kB3Pitch};
+  const int g0 = blockIdx.x * BT, b0 = blockIdx.y * BT, k = blockIdx.z;
+  const int tid = threadIdx.x, l = tid % 64, wave = tid / 64;
+  const int wb = (wave / 2) * 32, wg = (wave % 2) * 32;
+  const float2* Ak = A + (int64_t)k * a_rows * npwx;
+  const float2* Ck = C + (int64_t)k * c_rows * nbnd;
+  const float2 zero = make_float2(0.f, 0.f);
+  WaveTileB3 acc;
+  acc.zero();
+  for (int pc = 0; pc < P; pc += KC) {
+    for (int t = tid; t < KC * BT; t += 256) {
+      const int kk = t / BT, j = t - kk * BT;
+      const int p = pc + kk;
+      const int b = b0 + j, g = g0 + j;
+      Cs.put(j, kk, (p < P && b < nbnd) ? Ck[(int64_t)p * nbnd + b] : zero);
+      As.put(j, kk, (p < P && g < npwx) ? Ak[(int64_t)p * npwx + g] : zero);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < KC; kk += WaveTileB3::KS) acc.step<false>(l, Cs, wb, As, wg, kk);
+    __syncthreads();
+  }
+  update_epilogue<float, MODE, WaveTileB3>(acc, Y, nbnd, npwx, X, yv, U2, wk, lzpart, st,
+                                           b0 + wb, g0 + wg, k, l, red);
 }
 
 }  // namespace lz

@@ -64,11 +64,13 @@ template <typename T> struct LaunchLin {
   // chunk partials of R[k][p][n] = sum_G conj(A[k][p][G]) X[k][n][G], rows p < P
   // of A (a_rows per k), laid out [k][chunk][n][p]; with LW != null the dot
   // first forms X <- a*LW + b*X (state coefficients)
-  // (mfma: on the matrix cores, lz_gemm_mfma.h; LW must then be null)
+  // (gemm: kGemmValu vector ALU, kGemmMfma matrix cores, kGemmBf16x3 matrix
+  // cores with split-bf16 products (FP32 only), lz_gemm_mfma.h; with the
+  // matrix cores LW must be null)
   static void proj_dot(const void* A, int P, int a_rows, void* X, const void* LW, int nbnd,
                        int npwx, int nks, int chunk, int nchunk, void* partial,
-                       const LzDevState* st, hipStream_t s, bool mfma = false);
-  static bool dot_single_tile(int P, int nbnd, bool mfma = false);
+                       const LzDevState* st, hipStream_t s, int gemm = 0);
+  static bool dot_single_tile(int P, int nbnd, int gemm = 0);
   // G per chunk of the matrix-core dot for P rows (about 1024 blocks in all)
   static int mfma_chunk(int P, int nbnd, int npwx, int nks);
   // R[k][p][n] from the partials
@@ -86,15 +88,15 @@ template <typename T> struct LaunchLin {
   static void proj_update(void* Y, const void* A, int P, int a_rows, const void* C, int c_rows,
                           int nbnd, int npwx, int nks, const void* X, const void* y,
                           const double* wk, double* lzpart, const LzDevState* st, hipStream_t s,
-                          bool mfma = false);
-  static int update_blocks(int P, int nbnd, int npwx, int nks, bool mfma = false);
+                          int gemm = 0);
+  static int update_blocks(int P, int nbnd, int npwx, int nks, int gemm = 0);
   // non-Hermitian formation on the output side (P = a_rows = c_rows): as
   // proj_update, then H <- c1 LY' + c2 H with the state coefficients of the
   // u chain (v_chain false) or of the v chain, which also sums (U2, H) and
   // (y, H) into lzpart (4 per block, update_blocks of them)
   static void nh_form(bool v_chain, void* LY, const void* A, int P, const void* C, int nbnd,
                       int npwx, int nks, void* H, const void* y, const void* U2, const double* wk,
-                      double* lzpart, const LzDevState* st, hipStream_t s, bool mfma = false);
+                      double* lzpart, const LzDevState* st, hipStream_t s, int gemm = 0);
   // Lanczos: w <- a*LW + b*w
   static void lz_update(void* w, const void* lw, int64_t n, const LzDevState* st, hipStream_t s);
   // user order <-> internal order
@@ -132,5 +134,6 @@ constexpr int kStickMaxPt = 8;
 constexpr int kColTile = 16;      // grid columns per block in the Hartree z pass
 int plane_mp(int n1, int n2);
 constexpr int kProjChunk = 64;  // plane waves per block of a projector product
+constexpr int kGemmValu = 0, kGemmMfma = 1, kGemmBf16x3 = 2;
 
 }  // namespace lz

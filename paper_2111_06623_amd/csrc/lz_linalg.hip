@@ -693,9 +693,17 @@ __global__ __launch_bounds__(256) void k_spectrum(const double* __restrict__ bet
 template <typename T>
 void LaunchLin<T>::proj_dot(const void* A, int P, int a_rows, void* X, const void* LW, int nbnd,
                             int npwx, int nks, int chunk, int nchunk, void* partial,
-                            const LzDevState* st, hipStream_t s, bool mfma) {
-  if (mfma) {
+                            const LzDevState* st, hipStream_t s, int gemm) {
+  if (gemm != kGemmValu) {
     const int tiles = ((P + kMfmaTile - 1) / kMfmaTile) * ((nbnd + kMfmaTile - 1) / kMfmaTile);
+    if constexpr (sizeof(T) == 4) {
+      if (gemm == kGemmBf16x3) {
+        hipLaunchKernelGGL(k_proj_dot_b3, dim3(tiles, nchunk, nks), dim3(256), 0, s,
+                           (const float2*)A, P, a_rows, (const float2*)X, nbnd, npwx, chunk,
+                           nchunk, (float2*)partial, st);
+        return;
+      }
+    }
     hipLaunchKernelGGL(k_proj_dot_mfma<T>, dim3(tiles, nchunk, nks), dim3(256), 0, s,
                        (const cplx<T>*)A, P, a_rows, (const cplx<T>*)X, nbnd, npwx, chunk, nchunk,
                        (cplx<T>*)partial, st);
@@ -734,8 +742,8 @@ int LaunchLin<T>::mfma_chunk(int P, int nbnd, int npwx, int nks) {
 }
 
 template <typename T>
-bool LaunchLin<T>::dot_single_tile(int P, int nbnd, bool mfma) {
-  if (mfma) return false;
+bool LaunchLin<T>::dot_single_tile(int P, int nbnd, int gemm) {
+  if (gemm != kGemmValu) return false;
   const int tpi = P <= 16 ? 1 : P <= 32 ? 2 : P <= 48 ? 3 : 4;
   const int tnj = nbnd <= 16 ? 1 : 2;
   return P <= 16 * tpi && nbnd <= 16 * tnj;
@@ -776,8 +784,8 @@ static int upd_groups(int P, int nbt) {
 }
 
 template <typename T>
-int LaunchLin<T>::update_blocks(int P, int nbnd, int npwx, int nks, bool mfma) {
-  if (mfma)
+int LaunchLin<T>::update_blocks(int P, int nbnd, int npwx, int nks, int gemm) {
+  if (gemm != kGemmValu)
     return ((npwx + kMfmaTile - 1) / kMfmaTile) * ((nbnd + kMfmaTile - 1) / kMfmaTile) * nks;
   const int nbt = upd_bands(nbnd);
   const int qn = upd_groups<T>(P, nbt);
@@ -789,9 +797,25 @@ template <typename T>
 static void launch_update(int mode, void* Y, const void* A, int P, int a_rows, const void* C,
                           int c_rows, int nbnd, int npwx, int nks, void* X, const void* y,
                           const void* U2, const double* wk, double* lzpart, const LzDevState* st,
-                          hipStream_t s, bool mfma) {
-  if (mfma) {
+                          hipStream_t s, int gemm) {
+  if (gemm != kGemmValu) {
     dim3 grid((npwx + kMfmaTile - 1) / kMfmaTile, (nbnd + kMfmaTile - 1) / kMfmaTile, nks);
+    if constexpr (sizeof(T) == 4) {
+      if (gemm == kGemmBf16x3) {
+#define LZ_UPDB(MODE)                                                                            \
+  hipLaunchKernelGGL((k_proj_update_b3<MODE>), grid, dim3(256), 0, s, (float2*)Y,                \
+                     (const float2*)A, P, a_rows, (const float2*)C, c_rows, nbnd, npwx,          \
+                     (float2*)X, (const float2*)y, (const float2*)U2, wk, lzpart, st);
+        switch (mode) {
+          case kUpdDots: LZ_UPDB(kUpdDots) break;
+          case kUpdNhU: LZ_UPDB(kUpdNhU) break;
+          case kUpdNhV: LZ_UPDB(kUpdNhV) break;
+          default: LZ_UPDB(kUpdPlain) break;
+        }
+#undef LZ_UPDB
+        return;
+      }
+    }
 #define LZ_UPDM(MODE)                                                                            \
   hipLaunchKernelGGL((k_proj_update_mfma<T, MODE>), grid, dim3(256), 0, s, (cplx<T>*)Y,          \
                      (const cplx<T>*)A, P, a_rows, (const cplx<T>*)C, c_rows, nbnd, npwx,        \
@@ -830,18 +854,18 @@ template <typename T>
 void LaunchLin<T>::proj_update(void* Y, const void* A, int P, int a_rows, const void* C,
                                int c_rows, int nbnd, int npwx, int nks, const void* X,
                                const void* y, const double* wk, double* lzpart,
-                               const LzDevState* st, hipStream_t s, bool mfma) {
+                               const LzDevState* st, hipStream_t s, int gemm) {
   launch_update<T>(lzpart != nullptr ? kUpdDots : kUpdPlain, Y, A, P, a_rows, C, c_rows, nbnd,
-                   npwx, nks, const_cast<void*>(X), y, nullptr, wk, lzpart, st, s, mfma);
+                   npwx, nks, const_cast<void*>(X), y, nullptr, wk, lzpart, st, s, gemm);
 }
 
 template <typename T>
 void LaunchLin<T>::nh_form(bool v_chain, void* LY, const void* A, int P, const void* C, int nbnd,
                            int npwx, int nks, void* H, const void* y, const void* U2,
                            const double* wk, double* lzpart, const LzDevState* st,
-                           hipStream_t s, bool mfma) {
+                           hipStream_t s, int gemm) {
   launch_update<T>(v_chain ? kUpdNhV : kUpdNhU, LY, A, P, P, C, P, nbnd, npwx, nks, H, y, U2, wk,
-                   v_chain ? lzpart : nullptr, st, s, mfma);
+                   v_chain ? lzpart : nullptr, st, s, gemm);
 }
 
 template <typename T>

@@ -43,16 +43,16 @@ def test_null_arguments_rejected_before_device_work():
 
 
 @pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
-def test_unavailable_precision_rejected_before_device_work():
+def test_unknown_precision_rejected_before_device_work():
     import paper_2111_06623_amd as lz
     from synth import config_system
     lib = lz.load()
     sysarr, keep = lz.make_system(config_system("micro"))
-    opt = lz.LzOptions(lz.LZ_FP32_SPLITBF16, 0, 8, 0, 0)
+    opt = lz.LzOptions(3, 0, 8, 0, 0)
     out = ctypes.c_void_p()
     assert lib.lz_init(ctypes.byref(sysarr), 1, ctypes.byref(opt), 0, None,
                        ctypes.byref(out)) == lz.LZ_ERR_ARG
-    assert "not available" in lz.lz_last_error()
+    assert "precision" in lz.lz_last_error()
 
 
 def test_binding_fails_loudly_without_library(tmp_path):
