@@ -45,6 +45,8 @@ def _args():
                     help="steps of one recursion (the mixed path tracks FP64 to 1e-4 up to ~350)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--apply-stages", default=None, metavar="CONFIG",
+                    help="only time the stages of operator applications on CONFIG (e.g. cfg5r)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a plain device copy of this size (counter calibration)")
     ap.add_argument("--nh-steps", type=int, default=60,
@@ -175,6 +177,57 @@ def q_sweep_rate(prec, steps):
     return out
 
 
+def apply_stages(config, precs, reps=5):
+    """Per-stage cost of lz_apply_liouvillian (both halves: a D and a D+K
+    application) on one workload, for the large cells that do not run the
+    recursion here (cfg5r has random orbitals).  Stage times come from HIP
+    events on the library's stream; the projector products are also given
+    in TFLOP/s against the precision's dense matrix-core peak."""
+    import numpy as np
+    import torch
+
+    import paper_2111_06623_amd as lz
+    from synth import config_system
+    s = config_system(config)
+    peak = {"fp64": 78.6, "fp32": 157.3, "splitbf16": 2500.0 / 3.0}
+    out = {"workload": config, "nr": [int(v) for v in s.nr], "nks": int(s.nks),
+           "nbnd": int(s.nbnd), "nproj": int(s.nproj), "npwx": int(s.nl_kq.shape[1])}
+    npw = int(np.sum(s.npw_kq))
+    # complex multiply-adds of the four projector products of both halves:
+    # per half the input dot (nbnd + nproj rows), input P_c update (nbnd),
+    # output dot (nbnd) and output update (nbnd + nproj), each 8 flops
+    ptot = s.nbnd + s.nproj
+    flops = 2 * 8.0 * npw * s.nbnd * (ptot + s.nbnd + s.nbnd + ptot)
+    for prec in precs:
+        ctx = lz.lz_init(s, prec=prec, max_steps=4)
+        dt = torch.complex128 if prec == "fp64" else torch.complex64
+        x = torch.randn(sum(ctx.nvec), dtype=dt, device="cuda")
+        qo, po = torch.empty_like(x), torch.empty_like(x)
+        for _ in range(2):
+            ctx.apply_liouvillian(x, x, qo, po)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            ctx.apply_liouvillian(x, x, qo, po)
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) / reps
+        ctx.stage_timer(True)
+        for _ in range(reps):
+            ctx.apply_liouvillian(x, x, qo, po)
+        torch.cuda.synchronize()
+        ms, cnt = ctx.stage_times()
+        ctx.stage_timer(False)
+        st = {n: round(float(m) / reps, 4) for n, m in zip(lz.STAGES, ms) if cnt[lz.STAGES.index(n)]}
+        pr = st.get("projectors", 0.0)
+        out[prec] = {"ms_per_apply": round(1e3 * wall, 3), "stage_ms_per_apply": st,
+                     "projector_tflops": round(flops / (pr * 1e-3) / 1e12, 1) if pr else None,
+                     "projector_frac_of_matrix_peak":
+                         round(flops / (pr * 1e-3) / 1e12 / peak[prec], 3) if pr else None}
+        _log(f"[bench] {config} {prec}: {out[prec]}")
+        ctx.free()
+    print(json.dumps(out), flush=True)
+
+
 def kernel_sources_sha():
     """sha256 over the kernel sources; a change invalidates counter data."""
     import hashlib
@@ -280,6 +333,12 @@ def main():
         sys.exit(2)
     if a.copy_probe_mib:
         copy_probe(a.copy_probe_mib, 8)
+        return
+    if a.apply_stages:
+        import paper_2111_06623_amd as lz
+        lz.load()
+        precs = ["fp64", "fp32", "splitbf16"] if a.prec == "both" else [a.prec]
+        apply_stages(a.apply_stages, precs)
         return
     import numpy as np
     import torch
