@@ -72,6 +72,14 @@ def load(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise ImportError(f"{path} is missing: build it with python -m paper_2111_06623_amd.build")
+    # torch first: it carries its own HIP runtime under the same soname, and
+    # the library must bind to the runtime that owns torch's streams and
+    # memory (loaded the other way round, the process holds two runtimes and
+    # device discovery fails)
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(path)
     vp = ctypes.c_void_p
     lib.lz_init.argtypes = [ctypes.POINTER(LzSystem), ctypes.c_int32, ctypes.POINTER(LzOptions),
