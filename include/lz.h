@@ -121,7 +121,12 @@ typedef struct {
   int32_t use_graph;  /* nonzero: lz_step replays every pair of steps after the first as one
                          captured hipGraph (built on first use; not while the stage timer is
                          on); results are bitwise identical to the eager launches */
-  int32_t autotune;   /* reserved, must be 0 or 1 (1 = time launch shapes at init) */
+  int32_t autotune;   /* 0: the built-in launch heuristics.  1: lz_init times, per instance,
+                         candidate launch configurations (projector products on the vector
+                         ALU or the matrix cores, unless projector_gemm asks for one; two
+                         sizes of the density band groups) on a few operator applications
+                         and keeps the fastest (lz_get_tuning reports it).  Candidates agree
+                         to rounding, so with 1 the bits of a run may depend on the timing. */
   lz_algorithm algorithm;
   int32_t streams;    /* instances of one context that lz_step advances side by side, each
                          on its own HIP stream (instance i on stream i mod streams):
@@ -239,6 +244,14 @@ typedef enum {
 lz_status lz_spectrum_ext(lz_ctx *ctx, int32_t inst, int32_t m0, int32_t m,
                           int32_t extrapolation, const double *omega, int32_t n_omega,
                           double eta, double *chi, double *eps_inv, double *loss);
+
+/* Launch configuration of instance inst (after autotuning, if asked for):
+ * where its projector products run (LZ_GEMM_VALU or LZ_GEMM_MFMA; the
+ * split-bf16 precision reports LZ_GEMM_MFMA), the bands per group of its
+ * density pass and the plane-wave chunks of its projector dots.  Any output
+ * may be NULL. */
+lz_status lz_get_tuning(lz_ctx *ctx, int32_t inst, int32_t *projector_gemm,
+                        int32_t *density_group_bands, int32_t *projector_chunks);
 
 /* Copy the right-hand side y of instance inst to a device array in the
  * caller's layout and precision (as lz_apply_liouvillian). */

@@ -89,6 +89,7 @@ def load(path: str = LIB_PATH):
     lib.lz_get_coefficients.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _dp, _dp, _dp]
     lib.lz_get_state.argtypes = [vp, ctypes.c_int32, _ip, _ip]
     lib.lz_get_gamma.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _dp]
+    lib.lz_get_tuning.argtypes = [vp, ctypes.c_int32, _ip, _ip, _ip]
     lib.lz_spectrum.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, _dp, ctypes.c_int32,
                                 ctypes.c_double, _dp, _dp, _dp]
     lib.lz_spectrum_ext.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
@@ -103,6 +104,7 @@ def load(path: str = LIB_PATH):
     lib.lz_free.argtypes = [vp]
     lib.lz_last_error.restype = ctypes.c_char_p
     for f in ("lz_init", "lz_apply_liouvillian", "lz_step", "lz_get_coefficients", "lz_get_gamma",
+              "lz_get_tuning",
               "lz_get_state",
               "lz_spectrum", "lz_spectrum_ext", "lz_checkpoint_size", "lz_checkpoint_save",
               "lz_checkpoint_load", "lz_get_rhs", "lz_reset", "lz_stage_timer", "lz_stage_times", "lz_free"):
@@ -269,6 +271,14 @@ class Context:
                                    len(omega), float(eta), _ptr(chi, _dp), _ptr(einv, _dp),
                                    _ptr(loss, _dp)))
         return chi.view(np.complex128), einv.view(np.complex128), loss
+
+    def tuning(self, inst=0):
+        """(projector path name, density band-group size, projector dot chunks)
+        of one instance (lz_get_tuning)."""
+        g, b, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check(load().lz_get_tuning(self.handle, int(inst), ctypes.byref(g), ctypes.byref(b),
+                                    ctypes.byref(c)))
+        return {LZ_GEMM_VALU: "valu", LZ_GEMM_MFMA: "mfma"}[g.value], int(b.value), int(c.value)
 
     def checkpoint(self, inst=0):
         """The recursion state of one instance as bytes (lz_checkpoint_save)."""

@@ -421,6 +421,111 @@ void build_pair_graph(Instance& I, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------------------
+// launch configurations and the autotuner
+// ---------------------------------------------------------------------------
+struct LaunchCfg {
+  int gemm;     // projector products: kGemmValu, kGemmMfma, kGemmBf16x3
+  int chunk;    // plane waves per partial of a projector dot
+  int nchunk;
+  int nlzblk;   // blocks of the output update (Lanczos partial sums)
+  int gsize;    // bands per group of the density pass
+  int ngroups;
+};
+
+void set_cfg(Instance& I, const LaunchCfg& c) {
+  I.gemm = c.gemm;
+  I.chunk = c.chunk;
+  I.nchunk = c.nchunk;
+  I.nlzblk = c.nlzblk;
+  I.gsize = c.gsize;
+  I.ngroups = c.ngroups;
+}
+
+LaunchCfg make_cfg(const Instance& I, int gemm, int gsize) {
+  LaunchCfg c;
+  c.gemm = gemm;
+  if (gemm != kGemmValu)
+    c.chunk = I.fp64 ? LaunchLin<double>::mfma_chunk(I.ptot, I.nbnd, I.npwx, I.nks)
+                     : LaunchLin<float>::mfma_chunk(I.ptot, I.nbnd, I.npwx, I.nks);
+  else
+    c.chunk = kProjChunk;
+  c.nchunk = (I.npwx + c.chunk - 1) / c.chunk;
+  c.nlzblk = I.fp64 ? LaunchLin<double>::update_blocks(I.ptot, I.nbnd, I.npwx, I.nks, gemm)
+                    : LaunchLin<float>::update_blocks(I.ptot, I.nbnd, I.npwx, I.nks, gemm);
+  c.gsize = std::max(1, std::min(gsize, I.nb));
+  c.ngroups = (I.nb + c.gsize - 1) / c.gsize;
+  return c;
+}
+
+// The heuristic configuration first:
+//  - projector products on the matrix cores for many bands and rows (or as
+//    asked; the split-bf16 precision always takes them);
+//  - density band groups of about four blocks per compute unit, or on the
+//    register-line kernels one chunk of 192/N bands per block (the block
+//    count is then a multiple of what the compute units hold at once);
+// then, for the autotuner, the other projector path (unless one was asked
+// for) and groups of twice the bands.
+std::vector<LaunchCfg> launch_candidates(const Instance& I, const lz_options& opt) {
+  const bool mc = opt.projector_gemm == LZ_GEMM_MFMA ||
+                  (opt.projector_gemm == LZ_GEMM_AUTO && I.nbnd >= 32 && I.ptot >= 64);
+  const int gemm0 = I.prec == LZ_FP32_SPLITBF16 ? kGemmBf16x3 : mc ? kGemmMfma : kGemmValu;
+  const int rn = I.fp64 ? reg_plane_size<double>(I.grid) : reg_plane_size<float>(I.grid);
+  int g0;
+  if (rn) {
+    g0 = 192 / rn;
+  } else {
+    const int ng = std::max(1, std::min(I.nb, (1024 + I.n3 - 1) / I.n3));
+    g0 = (I.nb + ng - 1) / ng;
+  }
+  std::vector<LaunchCfg> c{make_cfg(I, gemm0, g0)};
+  if (!opt.autotune) return c;
+  std::vector<int> gemms{gemm0};
+  if (opt.projector_gemm == LZ_GEMM_AUTO && I.prec != LZ_FP32_SPLITBF16)
+    gemms.push_back(gemm0 == kGemmValu ? kGemmMfma : kGemmValu);
+  for (int gm : gemms)
+    for (int gs : {g0, 2 * g0}) {
+      if (gm == gemm0 && gs == g0) continue;
+      if (gs > I.nb && gs != g0) continue;
+      c.push_back(make_cfg(I, gm, gs));
+    }
+  return c;
+}
+
+// Time every candidate on a D and a D+K application of the right-hand side
+// (one untimed pair, then three, between events on the stream) and keep the
+// fastest.
+template <typename T>
+void autotune(Instance& I, const std::vector<LaunchCfg>& cands, hipStream_t s) {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIPC(hipEventCreate(&e0));
+  HIPC(hipEventCreate(&e1));
+  const size_t vb = (size_t)I.nvec * I.csz;
+  float best = 0.f;
+  size_t bi = 0;
+  for (size_t i = 0; i < cands.size(); ++i) {
+    set_cfg(I, cands[i]);
+    for (int rep = 0; rep < 4; ++rep) {
+      if (rep == 1) HIPC(hipEventRecord(e0, s));
+      HIPC(hipMemcpyAsync(I.tin.p, I.y.p, vb, hipMemcpyDeviceToDevice, s));
+      HIPC(hipMemcpyAsync(I.tin2.p, I.y.p, vb, hipMemcpyDeviceToDevice, s));
+      apply_half<T>(I, I.tin.p, I.tout.p, false, s);
+      apply_half<T>(I, I.tin2.p, I.tout2.p, true, s);
+    }
+    HIPC(hipEventRecord(e1, s));
+    HIPC(hipEventSynchronize(e1));
+    float ms = 0.f;
+    HIPC(hipEventElapsedTime(&ms, e0, e1));
+    if (i == 0 || ms < best) {
+      best = ms;
+      bi = i;
+    }
+  }
+  set_cfg(I, cands[bi]);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+}
+
+// ---------------------------------------------------------------------------
 // construction of one instance
 // ---------------------------------------------------------------------------
 template <typename T>
@@ -724,39 +829,25 @@ std::unique_ptr<Instance> build_instance(const lz_system& sys, const lz_options&
   I.sa.alloc((size_t)I.nb * I.n3 * I.S * I.csz);
   I.sb.alloc((size_t)I.nb * I.n3 * I.S * I.csz);
   I.ur.alloc((size_t)I.nb * I.N * I.csz);
-  // band groups of the density pass: about four blocks per compute unit
-  I.ngroups = std::max(1, std::min(I.nb, (1024 + I.n3 - 1) / I.n3));
-  I.gsize = (I.nb + I.ngroups - 1) / I.ngroups;
-  {
-    // the register-line kernel takes the bands of a group 192/N at a time
-    const int rn = I.fp64 ? reg_plane_size<double>(I.grid) : reg_plane_size<float>(I.grid);
-    // one chunk of 192/N bands per block: the block count is then a multiple of
-    // what the compute units hold at once, with no partly filled last round
-    if (rn) I.gsize = 192 / rn;
+  // launch configurations: the heuristic default first, then (autotune)
+  // the alternatives; buffers are sized for every candidate
+  std::vector<LaunchCfg> cands = launch_candidates(I, opt);
+  int max_groups = 0, max_chunks = 0, max_blk = kNhNormBlocks;
+  for (const LaunchCfg& c : cands) {
+    max_groups = std::max(max_groups, c.ngroups);
+    max_chunks = std::max(max_chunks, c.nchunk);
+    max_blk = std::max(max_blk, c.nlzblk);
   }
-  I.ngroups = (I.nb + I.gsize - 1) / I.gsize;
-  I.dpart.alloc((size_t)I.ngroups * I.N * I.csz);
+  set_cfg(I, cands[0]);
+  I.dpart.alloc((size_t)max_groups * I.N * I.csz);
   I.nr.alloc((size_t)I.N * I.csz);
   I.work.alloc((size_t)I.N * I.csz);
   I.vp.alloc((size_t)I.N * I.csz);
-  // projector products: matrix cores for many bands and rows (or as asked);
-  // the split-bf16 precision always takes the matrix cores
-  const bool mc = opt.projector_gemm == LZ_GEMM_MFMA ||
-                  (opt.projector_gemm == LZ_GEMM_AUTO && I.nbnd >= 32 && I.ptot >= 64);
-  I.gemm = I.prec == LZ_FP32_SPLITBF16 ? kGemmBf16x3 : mc ? kGemmMfma : kGemmValu;
-  if (I.gemm != kGemmValu)
-    I.chunk = I.fp64 ? LaunchLin<double>::mfma_chunk(I.ptot, I.nbnd, I.npwx, I.nks)
-                     : LaunchLin<float>::mfma_chunk(I.ptot, I.nbnd, I.npwx, I.nks);
-  else
-    I.chunk = kProjChunk;
-  I.nchunk = (I.npwx + I.chunk - 1) / I.chunk;
-  I.dpartial.alloc((size_t)I.nks * I.nchunk * I.ptot * I.nbnd * I.csz);
+  I.dpartial.alloc((size_t)I.nks * max_chunks * I.ptot * I.nbnd * I.csz);
   I.Cin.alloc((size_t)I.nks * I.ptot * I.nbnd * I.csz);
   I.Cout.alloc((size_t)I.nks * I.ptot * I.nbnd * I.csz);
   I.Mkb.alloc((size_t)I.nks * std::max(1, I.nproj) * I.nbnd * I.csz);
-  I.nlzblk = I.fp64 ? LaunchLin<double>::update_blocks(I.ptot, I.nbnd, I.npwx, I.nks, I.gemm)
-                    : LaunchLin<float>::update_blocks(I.ptot, I.nbnd, I.npwx, I.nks, I.gemm);
-  I.lzpart.alloc((size_t)std::max(I.nlzblk, kNhNormBlocks) * 4 * sizeof(double));
+  I.lzpart.alloc((size_t)max_blk * 4 * sizeof(double));
   I.st.alloc(sizeof(LzDevState));
   I.beta.alloc((size_t)I.max_steps * sizeof(double));
   I.z.alloc((size_t)I.max_steps * 2 * sizeof(double));
@@ -766,6 +857,10 @@ std::unique_ptr<Instance> build_instance(const lz_system& sys, const lz_options&
   }
   if (I.fp64) build_device_tables<double>(I, s, EK);
   else build_device_tables<float>(I, s, EK);
+  if (opt.autotune && cands.size() > 1) {
+    if (I.fp64) autotune<double>(I, cands, s);
+    else autotune<float>(I, cands, s);
+  }
   return Ip;
 }
 
@@ -862,6 +957,7 @@ lz_status lz_init(const lz_system* sys, int32_t n_inst, const lz_options* opt, i
     if (!sys || !opt || !out) fail(LZ_ERR_ARG, "null argument");
     if (n_inst < 1) fail(LZ_ERR_ARG, "n_inst must be >= 1");
     if (opt->max_steps < 1) fail(LZ_ERR_ARG, "max_steps must be >= 1");
+    if (opt->autotune != 0 && opt->autotune != 1) fail(LZ_ERR_ARG, "autotune must be 0 or 1");
     if (opt->prec != LZ_FP64 && opt->prec != LZ_FP32 && opt->prec != LZ_FP32_SPLITBF16)
       fail(LZ_ERR_ARG, "unknown precision");
     if (opt->approx != LZ_TDDFT && opt->approx != LZ_RPA && opt->approx != LZ_IPA)
@@ -1063,6 +1159,17 @@ lz_status lz_get_coefficients(lz_ctx* c, int32_t inst, int32_t first, int32_t co
     if (beta) HIPC(hipMemcpy(beta, I.beta.as<double>() + first, count * sizeof(double), hipMemcpyDeviceToHost));
     if (gamma) HIPC(hipMemcpy(gamma, I.beta.as<double>() + first, count * sizeof(double), hipMemcpyDeviceToHost));
     if (z) HIPC(hipMemcpy(z, I.z.as<double>() + 2 * first, 2 * count * sizeof(double), hipMemcpyDeviceToHost));
+  });
+}
+
+lz_status lz_get_tuning(lz_ctx* c, int32_t inst, int32_t* projector_gemm,
+                        int32_t* density_group_bands, int32_t* projector_chunks) {
+  return guarded([&] {
+    if (!c || inst < 0 || inst >= (int)c->inst.size()) fail(LZ_ERR_ARG, "bad context or instance");
+    const Instance& I = *c->inst[inst];
+    if (projector_gemm) *projector_gemm = I.gemm == kGemmValu ? LZ_GEMM_VALU : LZ_GEMM_MFMA;
+    if (density_group_bands) *density_group_bands = I.gsize;
+    if (projector_chunks) *projector_chunks = I.nchunk;
   });
 }
 

@@ -85,3 +85,16 @@ def test_stream_count_checked_before_device_work():
     assert lib.lz_init(ctypes.byref(sysarr), 1, ctypes.byref(opt), 0, None,
                        ctypes.byref(out)) == lz.LZ_ERR_ARG
     assert "streams" in lz.lz_last_error()
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_autotune_flag_checked_before_device_work():
+    import paper_2111_06623_amd as lz
+    from synth import config_system
+    lib = lz.load()
+    sysarr, keep = lz.make_system(config_system("micro"))
+    opt = lz.LzOptions(lz.LZ_FP64, 0, 8, 0, 2)
+    out = ctypes.c_void_p()
+    assert lib.lz_init(ctypes.byref(sysarr), 1, ctypes.byref(opt), 0, None,
+                       ctypes.byref(out)) == lz.LZ_ERR_ARG
+    assert "autotune" in lz.lz_last_error()
