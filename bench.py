@@ -53,6 +53,8 @@ def _args():
                     help="steps of the per-step comparison with the non-Hermitian recursion (0: skip)")
     ap.add_argument("--sweep-steps", type=int, default=200,
                     help="steps of the q-sweep throughput comparison (0: skip)")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="the built-in launch heuristics instead of the autotuner at init")
     ap.add_argument("--graph", action="store_true",
                     help="replay pairs of steps as captured graphs (measured no faster than eager)")
     return ap.parse_args()
@@ -83,13 +85,13 @@ def run_jobs(ctx, nsteps, M, om):
 SINGLE_KERNEL = ("zfft_inv", "plane_local", "plane_density", "plane_vu", "zfft_fwd")
 
 
-def run_gpu(s, prec, applies, warmup, M, graph):
+def run_gpu(s, prec, applies, warmup, M, graph, autotune=True):
     import numpy as np
     import torch
 
     import paper_2111_06623_amd as lz
     om = np.linspace(*OMEGA)
-    ctx = lz.lz_init(s, prec=prec, max_steps=max(M, 32) + 2, use_graph=graph)
+    ctx = lz.lz_init(s, prec=prec, max_steps=max(M, 32) + 2, use_graph=graph, autotune=autotune)
     run_jobs(ctx, 2 * warmup, M, om)
     # per-stage breakdown on a short window, every stage bracketed by events
     ctx.reset()
@@ -114,8 +116,9 @@ def run_gpu(s, prec, applies, warmup, M, graph):
     ts = time.perf_counter()
     _, _, loss = ctx.spectrum(om, ETA, m=M)
     t_spec = time.perf_counter() - ts
+    tuning = ctx.tuning()
     ctx.free()
-    return dict(elapsed=elapsed, applies=applies, loss=loss, t_spec=t_spec, stage_ms=ms,
+    return dict(elapsed=elapsed, applies=applies, loss=loss, t_spec=t_spec, stage_ms=ms, tuning=tuning,
                 stage_cnt=cnt, dom=dom, dom_ms=dms[di] / max(dcnt[di], 1), dom_launches=int(dcnt[di]))
 
 
@@ -357,11 +360,12 @@ def main():
     for p in precs:
         _log(f"[bench] gpu {p}: warmup {a.warmup}, timed {a.steps} applies, "
              f"recursions of {a.lanczos_steps} steps")
-        res[p] = run_gpu(s, p, a.steps, a.warmup, a.lanczos_steps, a.graph)
+        res[p] = run_gpu(s, p, a.steps, a.warmup, a.lanczos_steps, a.graph, not a.no_autotune)
         _log(f"[bench] gpu {p}: {res[p]['applies'] / res[p]['elapsed']:.1f} applies/s")
     if a.splitbf16:
         _log("[bench] gpu splitbf16")
-        res_b3 = run_gpu(s, "splitbf16", a.steps, a.warmup, a.lanczos_steps, a.graph)
+        res_b3 = run_gpu(s, "splitbf16", a.steps, a.warmup, a.lanczos_steps, a.graph,
+                         not a.no_autotune)
     rate = {p: res[p]["applies"] / res[p]["elapsed"] for p in res}
     gate = None
     head = precs[-1]
@@ -379,11 +383,7 @@ def main():
     per_launch = {names[i]: (r["stage_ms"][i] / r["stage_cnt"][i] if r["stage_cnt"][i] else 0.0)
                   for i in range(8)}
     dom = r["dom"]
-    ngroups = max(1, min(s.nks * s.nbnd, -(-1024 // int(s.nr[2]))))
-    gsize = -(-(s.nks * s.nbnd) // ngroups)
-    n = int(s.nr[0])
-    if head == "fp32" and n in (24, 32, 48, 64) and all(int(v) == n for v in s.nr):
-        gsize = 192 // n  # the register-line density pass: one chunk of bands per block
+    gsize = r["tuning"][1]  # bands per density group, as the library chose
     ngroups = -(-(s.nks * s.nbnd) // gsize)
     nbytes, _ = stage_bytes(s, head, ngroups)
     gbs = {k: round(nbytes[k] / (per_launch[k] * 1e-3) / 1e9, 1) for k in nbytes if per_launch.get(k, 0) > 0}
@@ -404,7 +404,9 @@ def main():
         "config": {"workload": "cfg2: SC a=10.26 bohr, 48^3 grid, ecut 25 Ha, 8 wells + 32 s/p "
                                "projectors, 16 bands, 8 k-points, q=0.2(2pi/a)[100], PZ-ALDA",
                    "precision": head, "lanczos_steps_per_recursion": a.lanczos_steps,
-                   "graph": a.graph,
+                   "graph": a.graph, "autotune": not a.no_autotune,
+                   "tuning": {p: dict(zip(("projector_gemm", "density_group_bands", "projector_chunks"),
+                                          res[p]["tuning"])) for p in res},
                    "spectrum": "2000 frequencies in [0, 2] Ha, eta 0.01 Ha"},
         "roofline": roof,
         "stage_ms_per_launch": {k: round(v, 5) for k, v in per_launch.items()},

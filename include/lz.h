@@ -124,7 +124,8 @@ typedef struct {
   int32_t autotune;   /* 0: the built-in launch heuristics.  1: lz_init times, per instance,
                          candidate launch configurations (projector products on the vector
                          ALU or the matrix cores, unless projector_gemm asks for one; two
-                         sizes of the density band groups) on a few operator applications
+                         sizes of the density band groups; three plane-wave chunk lengths of
+                         the vector-ALU projector dot) on a few operator applications
                          and keeps the fastest (lz_get_tuning reports it).  Candidates agree
                          to rounding, so with 1 the bits of a run may depend on the timing. */
   lz_algorithm algorithm;

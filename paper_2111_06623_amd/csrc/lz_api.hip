@@ -441,14 +441,14 @@ void set_cfg(Instance& I, const LaunchCfg& c) {
   I.ngroups = c.ngroups;
 }
 
-LaunchCfg make_cfg(const Instance& I, int gemm, int gsize) {
+LaunchCfg make_cfg(const Instance& I, int gemm, int gsize, int chunk = kProjChunk) {
   LaunchCfg c;
   c.gemm = gemm;
   if (gemm != kGemmValu)
     c.chunk = I.fp64 ? LaunchLin<double>::mfma_chunk(I.ptot, I.nbnd, I.npwx, I.nks)
                      : LaunchLin<float>::mfma_chunk(I.ptot, I.nbnd, I.npwx, I.nks);
   else
-    c.chunk = kProjChunk;
+    c.chunk = chunk;
   c.nchunk = (I.npwx + c.chunk - 1) / c.chunk;
   c.nlzblk = I.fp64 ? LaunchLin<double>::update_blocks(I.ptot, I.nbnd, I.npwx, I.nks, gemm)
                     : LaunchLin<float>::update_blocks(I.ptot, I.nbnd, I.npwx, I.nks, gemm);
@@ -464,7 +464,8 @@ LaunchCfg make_cfg(const Instance& I, int gemm, int gsize) {
 //    register-line kernels one chunk of 192/N bands per block (the block
 //    count is then a multiple of what the compute units hold at once);
 // then, for the autotuner, the other projector path (unless one was asked
-// for) and groups of twice the bands.
+// for), groups of twice the bands and, on the vector ALU, dot chunks of 128
+// and 256 plane waves.
 std::vector<LaunchCfg> launch_candidates(const Instance& I, const lz_options& opt) {
   const bool mc = opt.projector_gemm == LZ_GEMM_MFMA ||
                   (opt.projector_gemm == LZ_GEMM_AUTO && I.nbnd >= 32 && I.ptot >= 64);
@@ -484,9 +485,12 @@ std::vector<LaunchCfg> launch_candidates(const Instance& I, const lz_options& op
     gemms.push_back(gemm0 == kGemmValu ? kGemmMfma : kGemmValu);
   for (int gm : gemms)
     for (int gs : {g0, 2 * g0}) {
-      if (gm == gemm0 && gs == g0) continue;
       if (gs > I.nb && gs != g0) continue;
-      c.push_back(make_cfg(I, gm, gs));
+      for (int ch : {kProjChunk, 2 * kProjChunk, 4 * kProjChunk}) {
+        if (gm != kGemmValu && ch != kProjChunk) continue;  // the matrix-core dot sizes its own
+        if (gm == gemm0 && gs == g0 && ch == kProjChunk) continue;
+        c.push_back(make_cfg(I, gm, gs, ch));
+      }
     }
   return c;
 }
