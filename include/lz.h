@@ -287,6 +287,27 @@ lz_status lz_checkpoint_size(lz_ctx *ctx, int32_t inst, uint64_t *bytes);
 lz_status lz_checkpoint_save(lz_ctx *ctx, int32_t inst, void *buf, uint64_t bytes);
 lz_status lz_checkpoint_load(lz_ctx *ctx, int32_t inst, const void *buf, uint64_t bytes);
 
+/*
+ * Ground-state preparation on the device (the step before the response run,
+ * Sec. 3.1): the lowest sys->nbnd eigenpairs of the Kohn-Sham Hamiltonian
+ * H_{k+q} = -1/2 nabla^2 + V_loc + sum_p |beta_p> D_p <beta_p| on every k+q
+ * sphere of sys (for the orbitals at k, pass a system with q = 0 and the k
+ * spheres as k+q spheres).  Block Davidson with n_extra guard vectors, the
+ * Teter-Payne-Allan kinetic preconditioner and Rayleigh-Ritz in the span of
+ * the block and its orthonormalised corrections, in double precision on
+ * device `device`, ordered after `hip_stream`; it stops when every wanted
+ * residual norm ||H u - eps u|| is below tol, or after max_iter iterations.
+ * The orbital and energy fields of sys (evc_k, evc_kq, et_k, fxc_r) are not
+ * read.  Outputs (host): evc_out [nks][nbnd][npwx] complex (caller order of
+ * nl_kq, orthonormal, phases arbitrary), et_out [nks][nbnd] ascending,
+ * *iterations and *max_residual (either may be NULL).  Synchronous.  Errors:
+ * LZ_ERR_ARG for 2 (nbnd + n_extra) > 256, a sphere smaller than nbnd +
+ * n_extra, or the lz_init rules on the remaining fields.
+ */
+lz_status lz_ground_state(const lz_system *sys, int32_t n_extra, double tol, int32_t max_iter,
+                          int32_t device, void *hip_stream, double *evc_out, double *et_out,
+                          int32_t *iterations, double *max_residual);
+
 /* Release every resource of the context (NULL is accepted). */
 lz_status lz_free(lz_ctx *ctx);
 

@@ -90,6 +90,8 @@ def load(path: str = LIB_PATH):
     lib.lz_get_state.argtypes = [vp, ctypes.c_int32, _ip, _ip]
     lib.lz_get_gamma.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _dp]
     lib.lz_get_tuning.argtypes = [vp, ctypes.c_int32, _ip, _ip, _ip]
+    lib.lz_ground_state.argtypes = [ctypes.POINTER(LzSystem), ctypes.c_int32, ctypes.c_double,
+                                    ctypes.c_int32, ctypes.c_int32, vp, _dp, _dp, _ip, _dp]
     lib.lz_spectrum.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, _dp, ctypes.c_int32,
                                 ctypes.c_double, _dp, _dp, _dp]
     lib.lz_spectrum_ext.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
@@ -104,7 +106,7 @@ def load(path: str = LIB_PATH):
     lib.lz_free.argtypes = [vp]
     lib.lz_last_error.restype = ctypes.c_char_p
     for f in ("lz_init", "lz_apply_liouvillian", "lz_step", "lz_get_coefficients", "lz_get_gamma",
-              "lz_get_tuning",
+              "lz_get_tuning", "lz_ground_state",
               "lz_get_state",
               "lz_spectrum", "lz_spectrum_ext", "lz_checkpoint_size", "lz_checkpoint_save",
               "lz_checkpoint_load", "lz_get_rhs", "lz_reset", "lz_stage_timer", "lz_stage_times", "lz_free"):
@@ -192,6 +194,35 @@ def lz_init(systems, prec="fp64", approx="tddft", max_steps=1000, use_graph=Fals
     hs = _stream_handle(device) if stream is None else ctypes.c_void_p(stream)
     _check(lib.lz_init(arr, len(systems), ctypes.byref(opt), int(device), hs, ctypes.byref(out)))
     return Context(out, systems, opt)
+
+
+def lz_ground_state(system, nbnd=None, n_extra=4, tol=1e-9, max_iter=300, device=0, stream=None):
+    """The lowest nbnd eigenpairs of H_{k+q} on every k+q sphere of `system`
+    (lz_ground_state).  Returns (evc [nks][nbnd][npwx] complex128 in the
+    order of nl_kq, eps [nks][nbnd], iterations, max residual norm)."""
+    import copy
+    lib = load()
+    s = copy.copy(system)
+    nb = int(np.asarray(s.et_k).shape[1]) if nbnd is None else int(nbnd)
+    nks = int(np.asarray(s.xk).shape[0])
+    npwx = int(np.asarray(s.nl_kq).shape[1])
+    # placeholders of the right shapes for the fields the solver does not read
+    s.evc_k = np.zeros((nks, nb, npwx), dtype=np.complex128)
+    s.evc_kq = s.evc_k
+    s.et_k = np.zeros((nks, nb))
+    if getattr(s, "fxc_r", None) is None:
+        s.fxc_r = np.zeros_like(np.asarray(s.vloc_r))
+    arr, keep = make_system(s)
+    evc = np.zeros(nks * nb * npwx * 2)
+    eps = np.zeros(nks * nb)
+    it = ctypes.c_int32()
+    res = ctypes.c_double()
+    hs = _stream_handle(device) if stream is None else ctypes.c_void_p(stream)
+    _check(lib.lz_ground_state(ctypes.byref(arr), int(n_extra), float(tol), int(max_iter),
+                               int(device), hs, _ptr(evc, _dp), _ptr(eps, _dp), ctypes.byref(it),
+                               ctypes.byref(res)))
+    return (evc.view(np.complex128).reshape(nks, nb, npwx), eps.reshape(nks, nb), int(it.value),
+            float(res.value))
 
 
 class Context:

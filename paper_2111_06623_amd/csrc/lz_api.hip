@@ -1412,6 +1412,234 @@ lz_status lz_checkpoint_load(lz_ctx* c, int32_t inst, const void* buf, uint64_t 
   });
 }
 
+}  // extern "C"
+
+namespace {
+
+// LOBPCG (Knyazev 2001) for the lowest m eigenpairs of H on the k+q spheres
+// of an internal instance with no valence manifold (P_c = 1) and zero band
+// energies, whose D applications are then H x.  Per iteration, with X the
+// Ritz block, P the previous search direction and theta the Ritz values:
+//   R = H X - X theta, W = precond(R)             (k_gs_residual)
+//   Z = [W, P], HZ = [H W, H P]                    (one application, H P kept)
+//   Z <- Z - X (X^H Z) twice, HZ likewise
+//   Z' = Z Q lam^{-1/2} over the directions Z spans (Jacobi on Z^H Z)
+//   V = [X, Z'], T = V^H H V, T Y = Y theta       (Jacobi)
+//   X = V Y[:, :m], P = Z' Y[m:, :m]
+// All in double precision on the device; the host reads only the residual
+// norms to stop.
+struct GsBuffers {
+  DBuf X, HX, R, W, HW, P, HP, Z, HZ, Zc, HZc, V, HV, part, G, Tm, Ym, Cm, wv, keep, theta;
+};
+
+void gs_gram(Instance& I, GsBuffers& b, const void* A, int P, const void* B, int nb, void* out,
+             hipStream_t s) {
+  LaunchLin<double>::proj_dot(A, P, P, const_cast<void*>(B), nullptr, nb, I.npwx, I.nks,
+                              kProjChunk, (I.npwx + kProjChunk - 1) / kProjChunk, b.part.p,
+                              nullptr, s);
+  LaunchLin<double>::reduce(b.part.p, (I.npwx + kProjChunk - 1) / kProjChunk, P, nb, I.nks, out,
+                            s);
+}
+
+// Y[k][nb] (+)= A[k][P]^T C[k][P][nb]
+void gs_comb(Instance& I, void* Y, const void* A, int P, const void* C, int nb, bool accumulate,
+             hipStream_t s) {
+  if (!accumulate)
+    HIPC(hipMemsetAsync(Y, 0, (size_t)I.nks * nb * I.npwx * sizeof(double2), s));
+  LaunchLin<double>::proj_update(Y, A, P, P, C, P, nb, I.npwx, I.nks, nullptr, nullptr, nullptr,
+                                 nullptr, nullptr, s);
+}
+
+// rows [0, ra) of V[k] = A[k], rows [ra, ra + rb) = B[k]
+void gs_stack(Instance& I, void* V, const void* A, int ra, const void* B, int rb, hipStream_t s) {
+  const size_t row = (size_t)I.npwx * sizeof(double2);
+  const size_t pitch = (size_t)(ra + rb) * row;
+  HIPC(hipMemcpy2DAsync(V, pitch, A, ra * row, ra * row, I.nks, hipMemcpyDeviceToDevice, s));
+  HIPC(hipMemcpy2DAsync((char*)V + ra * row, pitch, B, rb * row, rb * row, I.nks,
+                        hipMemcpyDeviceToDevice, s));
+}
+
+}  // namespace
+
+extern "C" {
+
+lz_status lz_ground_state(const lz_system* sys, int32_t n_extra, double tol, int32_t max_iter,
+                          int32_t device, void* hip_stream, double* evc_out, double* et_out,
+                          int32_t* iterations, double* max_residual) {
+  return guarded([&] {
+    if (!sys || !evc_out || !et_out) fail(LZ_ERR_ARG, "null argument");
+    if (n_extra < 0 || !(tol > 0) || max_iter < 1) fail(LZ_ERR_ARG, "bad solver parameters");
+    const int nb_out = sys->nbnd;
+    const int m = nb_out + n_extra;
+    if (nb_out < 1 || 3 * m > kSmallOrderMax) fail(LZ_ERR_ARG, "3 (nbnd + n_extra) must lie in [3, 256]");
+    if (!sys->vloc_r || !sys->wk || !sys->xk || !sys->npw_kq || !sys->nl_kq || !sys->npw_k ||
+        !sys->nl_k)
+      fail(LZ_ERR_ARG, "null array in the system");
+    int ndev = 0;
+    HIPC(hipGetDeviceCount(&ndev));
+    if (device < 0 || device >= ndev) fail(LZ_ERR_ARG, "no such device");
+    HIPC(hipSetDevice(device));
+    HIPC(enable_large_lds_fft<double>());
+    hipStream_t s = nullptr;
+    hipEvent_t ev = nullptr;
+    HIPC(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    struct Guard {
+      hipStream_t& s;
+      hipEvent_t& e;
+      ~Guard() {
+        if (s) { (void)hipStreamSynchronize(s); (void)hipStreamDestroy(s); }
+        if (e) (void)hipEventDestroy(e);
+      }
+    } guard{s, ev};
+    HIPC(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    HIPC(hipEventRecord(ev, (hipStream_t)hip_stream));
+    HIPC(hipStreamWaitEvent(s, ev, 0));
+    // the internal instance: m bands, no valence manifold, zero energies
+    const int nks = sys->nks, npwx = sys->npwx;
+    const int N = sys->nr[0] * sys->nr[1] * sys->nr[2];
+    std::vector<double> zevc((size_t)nks * m * npwx * 2, 0.0), zet((size_t)nks * m, 0.0),
+        zf((size_t)N, 0.0);
+    lz_system g = *sys;
+    g.nbnd = m;
+    // no right-hand side is formed here: any nonzero Q passes the checks
+    g.g0[0] = 1;
+    g.g0[1] = 0;
+    g.g0[2] = 0;
+    g.evc_k = zevc.data();
+    g.evc_kq = zevc.data();
+    g.et_k = zet.data();
+    g.fxc_r = zf.data();
+    lz_options o{};
+    o.prec = LZ_FP64;
+    o.approx = LZ_IPA;
+    o.max_steps = 1;
+    o.projector_gemm = LZ_GEMM_VALU;
+    std::unique_ptr<Instance> Ip = build_instance(g, o, s);
+    Instance& I = *Ip;
+    const size_t vb = (size_t)nks * m * npwx * sizeof(double2);
+    const int n2 = 2 * m, n3 = 3 * m;
+    GsBuffers b;
+    for (DBuf* d : {&b.X, &b.HX, &b.R, &b.W, &b.HW, &b.P, &b.HP}) d->alloc(vb);
+    for (DBuf* d : {&b.Z, &b.HZ, &b.Zc, &b.HZc}) d->alloc(2 * vb);
+    b.V.alloc(3 * vb);
+    b.HV.alloc(3 * vb);
+    const int nch = (npwx + kProjChunk - 1) / kProjChunk;
+    b.part.alloc((size_t)nks * nch * n3 * n3 * sizeof(double2));
+    for (DBuf* d : {&b.G, &b.Tm, &b.Ym, &b.Cm}) d->alloc((size_t)nks * n3 * n3 * sizeof(double2));
+    b.wv.alloc((size_t)nks * n3 * sizeof(double));
+    b.keep.alloc((size_t)nks * n2 * sizeof(int));
+    b.theta.alloc((size_t)nks * m * sizeof(double));
+    // start: the m plane waves of lowest kinetic energy on each sphere, with a
+    // small deterministic admixture of the others, orthonormalised
+    std::vector<double> kin((size_t)nks * npwx);
+    HIPC(hipMemcpyAsync(kin.data(), I.kin.p, kin.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPC(hipStreamSynchronize(s));
+    std::vector<double> x0((size_t)nks * m * npwx * 2, 0.0);
+    uint64_t lcg = 0x9E3779B97F4A7C15ull;
+    auto urand = [&] {
+      lcg = lcg * 6364136223846793005ull + 1442695040888963407ull;
+      return (double)(lcg >> 11) * (1.0 / 9007199254740992.0) - 0.5;
+    };
+    for (int k = 0; k < nks; ++k) {
+      const int np = sys->npw_kq[k];
+      if (np < n3) fail(LZ_ERR_ARG, "a sphere holds fewer plane waves than 3 (nbnd + n_extra)");
+      std::vector<int> ord(np);
+      for (int i = 0; i < np; ++i) ord[i] = i;
+      std::stable_sort(ord.begin(), ord.end(), [&](int a, int c) {
+        return kin[(size_t)k * npwx + a] < kin[(size_t)k * npwx + c];
+      });
+      for (int bnd = 0; bnd < m; ++bnd) {
+        double* row = x0.data() + ((size_t)k * m + bnd) * npwx * 2;
+        for (int i = 0; i < np; ++i) {
+          row[2 * i] = 1e-3 * urand() / (1.0 + kin[(size_t)k * npwx + i]);
+          row[2 * i + 1] = 1e-3 * urand() / (1.0 + kin[(size_t)k * npwx + i]);
+        }
+        row[2 * ord[bnd]] += 1.0;
+      }
+    }
+    HIPC(hipMemcpyAsync(b.W.p, x0.data(), vb, hipMemcpyHostToDevice, s));
+    // orthonormalise the start block: X = W Q lam^{-1/2}
+    gs_gram(I, b, b.W.p, m, b.W.p, m, b.G.p, s);
+    launch_heev(b.G.p, m, m, b.wv.as<double>(), b.Ym.p, nks, s);
+    launch_orth_coef(b.Ym.p, b.wv.as<double>(), m, 1e-12, b.Cm.p, b.keep.as<int>(), nks, s);
+    gs_comb(I, b.X.p, b.W.p, m, b.Cm.p, m, false, s);
+    // Rayleigh-Ritz in span(X)
+    apply_half<double>(I, b.X.p, b.HX.p, false, s);
+    gs_gram(I, b, b.X.p, m, b.HX.p, m, b.G.p, s);
+    launch_heev(b.G.p, m, m, b.theta.as<double>(), b.Ym.p, nks, s);
+    gs_comb(I, b.W.p, b.X.p, m, b.Ym.p, m, false, s);
+    gs_comb(I, b.HW.p, b.HX.p, m, b.Ym.p, m, false, s);
+    std::swap(b.X.p, b.W.p);
+    std::swap(b.HX.p, b.HW.p);
+    std::vector<double2> rr((size_t)nks * m * m);
+    int it = 0;
+    double worst = 0.0;
+    for (;; ++it) {
+      // residuals, their norms, the preconditioned corrections and H W
+      launch_gs_residual(b.X.p, b.HX.p, b.theta.as<double>(), I.kin.p, m, npwx, nks, 1.0, b.R.p,
+                         b.W.p, s);
+      gs_gram(I, b, b.R.p, m, b.R.p, m, b.G.p, s);
+      HIPC(hipMemcpyAsync(rr.data(), b.G.p, rr.size() * sizeof(double2), hipMemcpyDeviceToHost, s));
+      HIPC(hipStreamSynchronize(s));
+      worst = 0.0;
+      for (int k = 0; k < nks; ++k)
+        for (int n = 0; n < nb_out; ++n)
+          worst = std::max(worst, std::sqrt(std::max(0.0, rr[((size_t)k * m + n) * m + n].x)));
+      if (worst < tol || it >= max_iter) break;
+      apply_half<double>(I, b.W.p, b.HW.p, false, s);
+      // Z = [W, P] (P = 0 on the first iteration: its directions are dropped)
+      gs_stack(I, b.Z.p, b.W.p, m, b.P.p, m, s);
+      gs_stack(I, b.HZ.p, b.HW.p, m, b.HP.p, m, s);
+      for (int pass = 0; pass < 2; ++pass) {
+        gs_gram(I, b, b.X.p, m, b.Z.p, n2, b.G.p, s);
+        launch_small_take(b.Cm.p, b.G.p, m, n2, n2, 0, m * n2, -1.0, nks, s);
+        gs_comb(I, b.Z.p, b.X.p, m, b.Cm.p, n2, true, s);
+        gs_comb(I, b.HZ.p, b.HX.p, m, b.Cm.p, n2, true, s);
+      }
+      // orthonormal directions of Z
+      gs_gram(I, b, b.Z.p, n2, b.Z.p, n2, b.G.p, s);
+      launch_heev(b.G.p, n2, n2, b.wv.as<double>(), b.Ym.p, nks, s);
+      launch_orth_coef(b.Ym.p, b.wv.as<double>(), n2, 1e-10, b.Cm.p, b.keep.as<int>(), nks, s);
+      gs_comb(I, b.Zc.p, b.Z.p, n2, b.Cm.p, n2, false, s);
+      gs_comb(I, b.HZc.p, b.HZ.p, n2, b.Cm.p, n2, false, s);
+      // Rayleigh-Ritz in span(X, Z')
+      gs_stack(I, b.V.p, b.X.p, m, b.Zc.p, n2, s);
+      gs_stack(I, b.HV.p, b.HX.p, m, b.HZc.p, n2, s);
+      gs_gram(I, b, b.V.p, n3, b.HV.p, n3, b.Tm.p, s);
+      launch_mask_dropped(b.Tm.p, n3, m, n2, b.keep.as<int>(), nks, s);
+      launch_heev(b.Tm.p, n3, n3, b.wv.as<double>(), b.Ym.p, nks, s);
+      launch_small_take(b.Cm.p, b.Ym.p, n3, m, n3, 0, n3 * n3, 1.0, nks, s);
+      gs_comb(I, b.X.p, b.V.p, n3, b.Cm.p, m, false, s);
+      gs_comb(I, b.HX.p, b.HV.p, n3, b.Cm.p, m, false, s);
+      // P = Z' Y[m:, :m]
+      launch_small_take(b.Cm.p, (const double2*)b.Ym.p + (size_t)m * n3, n2, m, n3, 0, n3 * n3,
+                        1.0, nks, s);
+      gs_comb(I, b.P.p, b.Zc.p, n2, b.Cm.p, m, false, s);
+      gs_comb(I, b.HP.p, b.HZc.p, n2, b.Cm.p, m, false, s);
+      HIPC(hipMemcpy2DAsync(b.theta.p, m * sizeof(double), b.wv.p, n3 * sizeof(double),
+                            m * sizeof(double), nks, hipMemcpyDeviceToDevice, s));
+    }
+    // eigenpairs 0..nbnd-1 in the caller's plane-wave order
+    LaunchLin<double>::perm_out(b.X.p, b.W.p, I.perm.as<int>(), I.npw_kq.as<int>(), nks, m, npwx,
+                                s);
+    std::vector<double> xo((size_t)nks * m * npwx * 2), th((size_t)nks * m);
+    HIPC(hipMemcpyAsync(xo.data(), b.W.p, vb, hipMemcpyDeviceToHost, s));
+    HIPC(hipMemcpyAsync(th.data(), b.theta.p, th.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPC(hipStreamSynchronize(s));
+    for (int k = 0; k < nks; ++k) {
+      std::memcpy(evc_out + (size_t)k * nb_out * npwx * 2, xo.data() + (size_t)k * m * npwx * 2,
+                  (size_t)nb_out * npwx * 2 * sizeof(double));
+      std::memcpy(et_out + (size_t)k * nb_out, th.data() + (size_t)k * m, nb_out * sizeof(double));
+    }
+    if (iterations) *iterations = it;
+    if (max_residual) *max_residual = worst;
+  });
+}
+
+}  // extern "C"
+
+extern "C" {
+
 lz_status lz_free(lz_ctx* c) {
   return guarded([&] {
     if (!c) return;

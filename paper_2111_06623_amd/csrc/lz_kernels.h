@@ -129,6 +129,19 @@ void launch_nh_finalize(const double* partial, int nblk, LzDevState* st, double*
                         double* z, int max_steps, double tol, double yscale, hipStream_t s);
 void launch_set_state(LzDevState* st, hipStream_t s);
 
+// small dense kernels of the ground-state eigensolver (double precision,
+// one block per k; lz_small.h)
+constexpr int kSmallOrderMax = 256;
+void launch_heev(void* A, int n, int ld, double* w, void* V, int nks, hipStream_t s);
+void launch_small_take(void* dst, const void* src, int rows, int cols, int lds, int col0,
+                       int src_stride, double alpha, int nks, hipStream_t s);
+void launch_orth_coef(const void* Q, const double* lam, int m, double tol, void* C, int* keep,
+                      int nks, hipStream_t s);
+void launch_mask_dropped(void* T, int n2, int off, int cnt, const int* keep, int nks,
+                         hipStream_t s);
+void launch_gs_residual(const void* X, const void* HX, const double* theta, const void* kin, int m,
+                        int npwx, int nks, double e0, void* R, void* W, hipStream_t s);
+
 constexpr int kStickTile = 16;    // sticks per block in the z passes
 constexpr int kStickMaxPt = 8;
 constexpr int kColTile = 16;      // grid columns per block in the Hartree z pass

@@ -381,6 +381,7 @@ __global__ __launch_bounds__(256) void k_proj_update(
 
 }  // namespace lz
 #include "lz_gemm_mfma.h"
+#include "lz_small.h"
 namespace lz {
 
 // ---------------------------------------------------------------------------
@@ -924,6 +925,31 @@ void launch_nh_finalize(const double* partial, int nblk, LzDevState* st, double*
 
 void launch_set_state(LzDevState* st, hipStream_t s) {
   hipLaunchKernelGGL(k_set_state, dim3(1), dim3(1), 0, s, st);
+}
+
+void launch_heev(void* A, int n, int ld, double* w, void* V, int nks, hipStream_t s) {
+  hipLaunchKernelGGL(k_heev_jacobi, dim3(nks), dim3(256), 0, s, (double2*)A, n, ld, w, (double2*)V,
+                     30);
+}
+void launch_small_take(void* dst, const void* src, int rows, int cols, int lds, int col0,
+                       int src_stride, double alpha, int nks, hipStream_t s) {
+  hipLaunchKernelGGL(k_small_take, dim3(nks), dim3(256), 0, s, (double2*)dst, (const double2*)src,
+                     rows, cols, lds, col0, src_stride, alpha);
+}
+void launch_orth_coef(const void* Q, const double* lam, int m, double tol, void* C, int* keep,
+                      int nks, hipStream_t s) {
+  hipLaunchKernelGGL(k_orth_coef, dim3(nks), dim3(256), 0, s, (const double2*)Q, lam, m, tol,
+                     (double2*)C, keep);
+}
+void launch_mask_dropped(void* T, int n2, int off, int cnt, const int* keep, int nks,
+                         hipStream_t s) {
+  hipLaunchKernelGGL(k_mask_dropped, dim3(nks), dim3(256), 0, s, (double2*)T, n2, off, cnt, keep);
+}
+void launch_gs_residual(const void* X, const void* HX, const double* theta, const void* kin, int m,
+                        int npwx, int nks, double e0, void* R, void* W, hipStream_t s) {
+  hipLaunchKernelGGL(k_gs_residual, dim3(1024), dim3(256), 0, s, (const double2*)X,
+                     (const double2*)HX, theta, (const double*)kin, m, npwx, nks, e0, (double2*)R,
+                     (double2*)W);
 }
 
 template struct LaunchLin<double>;

@@ -98,3 +98,11 @@ def test_autotune_flag_checked_before_device_work():
     assert lib.lz_init(ctypes.byref(sysarr), 1, ctypes.byref(opt), 0, None,
                        ctypes.byref(out)) == lz.LZ_ERR_ARG
     assert "autotune" in lz.lz_last_error()
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_ground_state_arguments_checked_before_device_work():
+    import paper_2111_06623_amd as lz
+    lib = lz.load()
+    assert lib.lz_ground_state(None, 4, 1e-9, 10, 0, None, None, None, None, None) == lz.LZ_ERR_ARG
+    assert "null" in lz.lz_last_error()
