@@ -47,6 +47,8 @@ def _args():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--apply-stages", default=None, metavar="CONFIG",
                     help="only time the stages of operator applications on CONFIG (e.g. cfg5r)")
+    ap.add_argument("--ground-state", default=None, metavar="CONFIG",
+                    help="only time the device ground-state preparation on CONFIG")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a plain device copy of this size (counter calibration)")
     ap.add_argument("--nh-steps", type=int, default=60,
@@ -231,6 +233,28 @@ def apply_stages(config, precs, reps=5):
     print(json.dumps(out), flush=True)
 
 
+def ground_state_time(config):
+    """Wall time of the device ground-state preparation on the k+q spheres
+    of a workload (LOBPCG to residual 1e-9), with its eigenvalue error
+    against the dense diagonalisation that built the synthetic system."""
+    import numpy as np
+    import torch
+
+    import paper_2111_06623_amd as lz
+    from synth import config_system
+    s = config_system(config)
+    nb = s.evc_kq.shape[1]
+    lz.lz_ground_state(s, n_extra=4, tol=1e-6, max_iter=3)  # warm-up (kernel loading)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    evc, eps, it, res = lz.lz_ground_state(s, n_extra=4, tol=1e-9)
+    dt = time.perf_counter() - t0
+    out = {"workload": config, "nks": int(s.nks), "nbnd": int(nb), "npwx": int(s.nl_kq.shape[1]),
+           "iterations": it, "max_residual": res, "seconds": round(dt, 4),
+           "max_eig_err_Ha": float(np.abs(eps - s.et_kq[:, :nb]).max())}
+    print(json.dumps(out), flush=True)
+
+
 def kernel_sources_sha():
     """sha256 over the kernel sources; a change invalidates counter data."""
     import hashlib
@@ -336,6 +360,11 @@ def main():
         sys.exit(2)
     if a.copy_probe_mib:
         copy_probe(a.copy_probe_mib, 8)
+        return
+    if a.ground_state:
+        import paper_2111_06623_amd as lz
+        lz.load()
+        ground_state_time(a.ground_state)
         return
     if a.apply_stages:
         import paper_2111_06623_amd as lz

@@ -1421,11 +1421,12 @@ namespace {
 // energies, whose D applications are then H x.  Per iteration, with X the
 // Ritz block, P the previous search direction and theta the Ritz values:
 //   R = H X - X theta, W = precond(R)             (k_gs_residual)
-//   Z = [W, P], HZ = [H W, H P]                    (one application, H P kept)
-//   Z <- Z - X (X^H Z) twice, HZ likewise
-//   Z' = Z Q lam^{-1/2} over the directions Z spans (Jacobi on Z^H Z)
+//   Z = [W, P], Z <- Z - X (X^H Z) twice
+//   Z' = Z Q lam^{-1/2} over the directions Z spans (Jacobi on Z^H Z), twice
+//   H Z' applied explicitly (products of H by combinations of earlier
+//   blocks drift once the Gram matrices are ill-conditioned)
 //   V = [X, Z'], T = V^H H V, T Y = Y theta       (Jacobi)
-//   X = V Y[:, :m], P = Z' Y[m:, :m]
+//   X = V Y[:, :m], H X = H V Y[:, :m], P = Z' Y[m:, :m]
 // All in double precision on the device; the host reads only the residual
 // norms to stop.
 struct GsBuffers {
@@ -1586,22 +1587,36 @@ lz_status lz_ground_state(const lz_system* sys, int32_t n_extra, double tol, int
         for (int n = 0; n < nb_out; ++n)
           worst = std::max(worst, std::sqrt(std::max(0.0, rr[((size_t)k * m + n) * m + n].x)));
       if (worst < tol || it >= max_iter) break;
-      apply_half<double>(I, b.W.p, b.HW.p, false, s);
       // Z = [W, P] (P = 0 on the first iteration: its directions are dropped)
       gs_stack(I, b.Z.p, b.W.p, m, b.P.p, m, s);
-      gs_stack(I, b.HZ.p, b.HW.p, m, b.HP.p, m, s);
       for (int pass = 0; pass < 2; ++pass) {
         gs_gram(I, b, b.X.p, m, b.Z.p, n2, b.G.p, s);
         launch_small_take(b.Cm.p, b.G.p, m, n2, n2, 0, m * n2, -1.0, nks, s);
         gs_comb(I, b.Z.p, b.X.p, m, b.Cm.p, n2, true, s);
-        gs_comb(I, b.HZ.p, b.HX.p, m, b.Cm.p, n2, true, s);
       }
-      // orthonormal directions of Z
+      // orthonormal directions of Z (the second pass removes what the first
+      // leaves of non-orthogonality; its directions all survive)
       gs_gram(I, b, b.Z.p, n2, b.Z.p, n2, b.G.p, s);
       launch_heev(b.G.p, n2, n2, b.wv.as<double>(), b.Ym.p, nks, s);
-      launch_orth_coef(b.Ym.p, b.wv.as<double>(), n2, 1e-10, b.Cm.p, b.keep.as<int>(), nks, s);
+      launch_orth_coef(b.Ym.p, b.wv.as<double>(), n2, 1e-10, b.Cm.p, b.HW.as<int>(), nks, s);
       gs_comb(I, b.Zc.p, b.Z.p, n2, b.Cm.p, n2, false, s);
-      gs_comb(I, b.HZc.p, b.HZ.p, n2, b.Cm.p, n2, false, s);
+      // (the kept columns of the second pass, in its own order, mark T)
+      gs_gram(I, b, b.Zc.p, n2, b.Zc.p, n2, b.G.p, s);
+      launch_heev(b.G.p, n2, n2, b.wv.as<double>(), b.Ym.p, nks, s);
+      launch_orth_coef(b.Ym.p, b.wv.as<double>(), n2, 1e-3, b.Cm.p, b.keep.as<int>(), nks, s);
+      gs_comb(I, b.Z.p, b.Zc.p, n2, b.Cm.p, n2, false, s);
+      // H on the two halves of the orthonormal block
+      {
+        const size_t row = (size_t)npwx * sizeof(double2);
+        HIPC(hipMemcpy2DAsync(b.W.p, m * row, b.Z.p, n2 * row, m * row, nks,
+                              hipMemcpyDeviceToDevice, s));
+        HIPC(hipMemcpy2DAsync(b.R.p, m * row, (const char*)b.Z.p + m * row, n2 * row, m * row,
+                              nks, hipMemcpyDeviceToDevice, s));
+      }
+      apply_half<double>(I, b.W.p, b.HW.p, false, s);
+      apply_half<double>(I, b.R.p, b.HP.p, false, s);
+      std::swap(b.Zc.p, b.Z.p);
+      gs_stack(I, b.HZc.p, b.HW.p, m, b.HP.p, m, s);
       // Rayleigh-Ritz in span(X, Z')
       gs_stack(I, b.V.p, b.X.p, m, b.Zc.p, n2, s);
       gs_stack(I, b.HV.p, b.HX.p, m, b.HZc.p, n2, s);
@@ -1615,7 +1630,6 @@ lz_status lz_ground_state(const lz_system* sys, int32_t n_extra, double tol, int
       launch_small_take(b.Cm.p, (const double2*)b.Ym.p + (size_t)m * n3, n2, m, n3, 0, n3 * n3,
                         1.0, nks, s);
       gs_comb(I, b.P.p, b.Zc.p, n2, b.Cm.p, m, false, s);
-      gs_comb(I, b.HP.p, b.HZc.p, n2, b.Cm.p, m, false, s);
       HIPC(hipMemcpy2DAsync(b.theta.p, m * sizeof(double), b.wv.p, n3 * sizeof(double),
                             m * sizeof(double), nks, hipMemcpyDeviceToDevice, s));
     }

@@ -35,7 +35,7 @@ def _subspace_err(u_ref, u):
     return err
 
 
-@pytest.mark.parametrize("name", ["cfg1", "micro", "cfg2lo"])
+@pytest.mark.parametrize("name", ["cfg1", "micro", "cfg2lo", "cfg2"])
 def test_ground_state_matches_dense_diagonalisation(name):
     lz = _lz()
     s = config_system(name)
