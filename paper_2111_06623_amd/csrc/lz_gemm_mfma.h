@@ -17,7 +17,8 @@
 //           holds outputs (l / 16 + 4 w, l % 16), w < 4, per tile.
 // (Lane layouts checked on the device against a host product.)  A block is
 // 2 x 2 waves over a 64 x 64 output tile; both operands of a k chunk are
-// staged in LDS.  Every sum has a fixed order: results do not depend on
+// staged in LDS, and the next chunk is fetched into registers while the
+// matrix cores work on the current one.  Every sum has a fixed order: results do not depend on
 // scheduling.
 #pragma once
 #include "lz_kernels.h"
@@ -120,15 +121,42 @@ __global__ __launch_bounds__(256) void k_proj_dot_mfma(const cplx<T>* __restrict
   const cplx<T> zero = mk<T>(T(0), T(0));
   WaveTile<T> acc;
   acc.zero();
-  for (int g0 = g_begin; g0 < g_end; g0 += KC) {
-    for (int t = tid; t < BT * KC; t += 256) {
+  // the next chunk is fetched into registers while the current one computes
+  constexpr int NPT = BT * KC / 256;
+  T rar[NPT], rai[NPT], rxr[NPT], rxi[NPT];  // split parts: kept in registers
+  {
+#pragma unroll
+    for (int i = 0; i < NPT; ++i) {
+      const int t = tid + i * 256;
       const int r = t / KC, c = t - r * KC;
-      const int g = g0 + c;
+      const int g = (g_begin) + c;
       const int p = p0 + r, n = n0 + r;
-      As[r * PITCH + c] = (p < P && g < g_end) ? Ak[(int64_t)p * npwx + g] : zero;
-      Xs[r * PITCH + c] = (n < nbnd && g < g_end) ? Xk[(int64_t)n * npwx + g] : zero;
+      const cplx<T> av = (p < P && g < g_end) ? Ak[(int64_t)p * npwx + g] : zero;
+      const cplx<T> xv = (n < nbnd && g < g_end) ? Xk[(int64_t)n * npwx + g] : zero;
+      rar[i] = av.x; rai[i] = av.y; rxr[i] = xv.x; rxi[i] = xv.y;
+    }
+  }
+  for (int g0 = g_begin; g0 < g_end; g0 += KC) {
+#pragma unroll
+    for (int i = 0; i < NPT; ++i) {
+      const int t = tid + i * 256;
+      const int r = t / KC, c = t - r * KC;
+      As[r * PITCH + c] = mk<T>(rar[i], rai[i]);
+      Xs[r * PITCH + c] = mk<T>(rxr[i], rxi[i]);
     }
     __syncthreads();
+    if (g0 + KC < g_end) {
+#pragma unroll
+    for (int i = 0; i < NPT; ++i) {
+      const int t = tid + i * 256;
+      const int r = t / KC, c = t - r * KC;
+      const int g = (g0 + KC) + c;
+      const int p = p0 + r, n = n0 + r;
+      const cplx<T> av = (p < P && g < g_end) ? Ak[(int64_t)p * npwx + g] : zero;
+      const cplx<T> xv = (n < nbnd && g < g_end) ? Xk[(int64_t)n * npwx + g] : zero;
+      rar[i] = av.x; rai[i] = av.y; rxr[i] = xv.x; rxi[i] = xv.y;
+    }
+  }
 #pragma unroll
     for (int kk = 0; kk < KC; kk += WaveTile<T>::KS) {
       acc.template step<true>(
@@ -240,15 +268,41 @@ __global__ __launch_bounds__(256) void k_proj_update_mfma(
   const cplx<T> zero = mk<T>(T(0), T(0));
   WaveTile<T> acc;
   acc.zero();
-  for (int pc = 0; pc < P; pc += KC) {
-    for (int t = tid; t < KC * BT; t += 256) {
+  constexpr int NPT = BT * KC / 256;
+  T rcr[NPT], rci[NPT], rar[NPT], rai[NPT];  // split parts: kept in registers
+  {
+#pragma unroll
+    for (int i = 0; i < NPT; ++i) {
+      const int t = tid + i * 256;
       const int kk = t / BT, j = t - kk * BT;
-      const int p = pc + kk;
+      const int p = (0) + kk;
       const int b = b0 + j, g = g0 + j;
-      Cs[kk * PITCH + j] = (p < P && b < nbnd) ? Ck[(int64_t)p * nbnd + b] : zero;
-      As[kk * PITCH + j] = (p < P && g < npwx) ? Ak[(int64_t)p * npwx + g] : zero;
+      const cplx<T> cv = (p < P && b < nbnd) ? Ck[(int64_t)p * nbnd + b] : zero;
+      const cplx<T> av = (p < P && g < npwx) ? Ak[(int64_t)p * npwx + g] : zero;
+      rcr[i] = cv.x; rci[i] = cv.y; rar[i] = av.x; rai[i] = av.y;
+    }
+  }
+  for (int pc = 0; pc < P; pc += KC) {
+#pragma unroll
+    for (int i = 0; i < NPT; ++i) {
+      const int t = tid + i * 256;
+      const int kk = t / BT, j = t - kk * BT;
+      Cs[kk * PITCH + j] = mk<T>(rcr[i], rci[i]);
+      As[kk * PITCH + j] = mk<T>(rar[i], rai[i]);
     }
     __syncthreads();
+    if (pc + KC < P) {
+#pragma unroll
+    for (int i = 0; i < NPT; ++i) {
+      const int t = tid + i * 256;
+      const int kk = t / BT, j = t - kk * BT;
+      const int p = (pc + KC) + kk;
+      const int b = b0 + j, g = g0 + j;
+      const cplx<T> cv = (p < P && b < nbnd) ? Ck[(int64_t)p * nbnd + b] : zero;
+      const cplx<T> av = (p < P && g < npwx) ? Ak[(int64_t)p * npwx + g] : zero;
+      rcr[i] = cv.x; rci[i] = cv.y; rar[i] = av.x; rai[i] = av.y;
+    }
+  }
 #pragma unroll
     for (int kk = 0; kk < KC; kk += WaveTile<T>::KS) {
       acc.template step<false>(
@@ -372,15 +426,39 @@ __global__ __launch_bounds__(256) void k_proj_dot_b3(const float2* __restrict__ 
   const float2 zero = make_float2(0.f, 0.f);
   WaveTileB3 acc;
   acc.zero();
-  for (int g0 = g_begin; g0 < g_end; g0 += KC) {
-    for (int t = tid; t < BT * KC; t += 256) {
+  constexpr int NPT = BT * KC / 256;
+  float2 ra[NPT], rx[NPT];
+  {
+#pragma unroll
+    for (int i = 0; i < NPT; ++i) {
+      const int t = tid + i * 256;
       const int r = t / KC, c = t - r * KC;
-      const int g = g0 + c;
+      const int g = (g_begin) + c;
       const int p = p0 + r, n = n0 + r;
-      As.put(r, c, (p < P && g < g_end) ? Ak[(int64_t)p * npwx + g] : zero);
-      Xs.put(r, c, (n < nbnd && g < g_end) ? Xk[(int64_t)n * npwx + g] : zero);
+      ra[i] = (p < P && g < g_end) ? Ak[(int64_t)p * npwx + g] : zero;
+      rx[i] = (n < nbnd && g < g_end) ? Xk[(int64_t)n * npwx + g] : zero;
+    }
+  }
+  for (int g0 = g_begin; g0 < g_end; g0 += KC) {
+#pragma unroll
+    for (int i = 0; i < NPT; ++i) {
+      const int t = tid + i * 256;
+      const int r = t / KC, c = t - r * KC;
+      As.put(r, c, ra[i]);
+      Xs.put(r, c, rx[i]);
     }
     __syncthreads();
+    if (g0 + KC < g_end) {
+#pragma unroll
+    for (int i = 0; i < NPT; ++i) {
+      const int t = tid + i * 256;
+      const int r = t / KC, c = t - r * KC;
+      const int g = (g0 + KC) + c;
+      const int p = p0 + r, n = n0 + r;
+      ra[i] = (p < P && g < g_end) ? Ak[(int64_t)p * npwx + g] : zero;
+      rx[i] = (n < nbnd && g < g_end) ? Xk[(int64_t)n * npwx + g] : zero;
+    }
+  }
 #pragma unroll
     for (int kk = 0; kk < KC; kk += WaveTileB3::KS) acc.step<true>(l, As, wp, Xs, wn, kk);
     __syncthreads();
@@ -415,15 +493,39 @@ __global__ __launch_bounds__(256) void k_proj_update_b3(
   const float2 zero = make_float2(0.f, 0.f);
   WaveTileB3 acc;
   acc.zero();
-  for (int pc = 0; pc < P; pc += KC) {
-    for (int t = tid; t < KC * BT; t += 256) {
+  constexpr int NPT = BT * KC / 256;
+  float2 rc[NPT], ra[NPT];
+  {
+#pragma unroll
+    for (int i = 0; i < NPT; ++i) {
+      const int t = tid + i * 256;
       const int kk = t / BT, j = t - kk * BT;
-      const int p = pc + kk;
+      const int p = (0) + kk;
       const int b = b0 + j, g = g0 + j;
-      Cs.put(j, kk, (p < P && b < nbnd) ? Ck[(int64_t)p * nbnd + b] : zero);
-      As.put(j, kk, (p < P && g < npwx) ? Ak[(int64_t)p * npwx + g] : zero);
+      rc[i] = (p < P && b < nbnd) ? Ck[(int64_t)p * nbnd + b] : zero;
+      ra[i] = (p < P && g < npwx) ? Ak[(int64_t)p * npwx + g] : zero;
+    }
+  }
+  for (int pc = 0; pc < P; pc += KC) {
+#pragma unroll
+    for (int i = 0; i < NPT; ++i) {
+      const int t = tid + i * 256;
+      const int kk = t / BT, j = t - kk * BT;
+      Cs.put(j, kk, rc[i]);
+      As.put(j, kk, ra[i]);
     }
     __syncthreads();
+    if (pc + KC < P) {
+#pragma unroll
+    for (int i = 0; i < NPT; ++i) {
+      const int t = tid + i * 256;
+      const int kk = t / BT, j = t - kk * BT;
+      const int p = (pc + KC) + kk;
+      const int b = b0 + j, g = g0 + j;
+      rc[i] = (p < P && b < nbnd) ? Ck[(int64_t)p * nbnd + b] : zero;
+      ra[i] = (p < P && g < npwx) ? Ak[(int64_t)p * npwx + g] : zero;
+    }
+  }
 #pragma unroll
     for (int kk = 0; kk < KC; kk += WaveTileB3::KS) acc.step<false>(l, Cs, wb, As, wg, kk);
     __syncthreads();
