@@ -166,21 +166,21 @@ template <int PITCH> struct LayCols {      // every column, stride PITCH
 };
 
 // One pass of a compile-time plan over nbatch <= NBMAX transforms, in place,
-// 256 threads: loads into registers, barrier, stores, barrier.
-template <typename T, int N, int P, int DIR, int NBMAX, typename L>
+// NT threads: loads into registers, barrier, stores, barrier.
+template <typename T, int N, int P, int DIR, int NBMAX, typename L, int NT = 256>
 __device__ __forceinline__ void ct_pass(cplx<T>* lds, const L& lay, int nbatch,
                                         const cplx<T>* tw, int tid) {
   constexpr int R = ct_radix(N, P);
   constexpr int NS = ct_ns(N, P);
   constexpr int M = N / R;
-  constexpr int MAXB = (NBMAX * M + 255) / 256;
+  constexpr int MAXB = (NBMAX * M + NT - 1) / NT;
   const cplx<T>* twp = tw + ct_twoff(N, P);
   const int total = nbatch * M;
   cplx<T> v[MAXB][R];
   int bbase[MAXB], bo[MAXB];
 #pragma unroll
   for (int i = 0; i < MAXB; ++i) {
-    const int t = tid + i * 256;
+    const int t = tid + i * NT;
     if (t < total) {
       const int b = t / M;
       const int j = t - b * M;
@@ -204,7 +204,7 @@ __device__ __forceinline__ void ct_pass(cplx<T>* lds, const L& lay, int nbatch,
   __syncthreads();
 #pragma unroll
   for (int i = 0; i < MAXB; ++i) {
-    const int t = tid + i * 256;
+    const int t = tid + i * NT;
     if (t < total) {
 #pragma unroll
       for (int s = 0; s < R; ++s) lds[bbase[i] + (bo[i] + s * NS) * L::stride] = v[i][s];
@@ -213,13 +213,13 @@ __device__ __forceinline__ void ct_pass(cplx<T>* lds, const L& lay, int nbatch,
   __syncthreads();
 }
 
-template <typename T, int N, int DIR, int NBMAX, typename L>
+template <typename T, int N, int DIR, int NBMAX, typename L, int NT = 256>
 __device__ __forceinline__ void ct_fft(cplx<T>* lds, const L& lay, int nbatch, const cplx<T>* tw,
                                        int tid) {
   static_assert(ct_supported(N), "no compile-time plan for this length");
-  ct_pass<T, N, 0, DIR, NBMAX>(lds, lay, nbatch, tw, tid);
-  if constexpr (ct_npass(N) > 1) ct_pass<T, N, 1, DIR, NBMAX>(lds, lay, nbatch, tw, tid);
-  if constexpr (ct_npass(N) > 2) ct_pass<T, N, 2, DIR, NBMAX>(lds, lay, nbatch, tw, tid);
+  ct_pass<T, N, 0, DIR, NBMAX, L, NT>(lds, lay, nbatch, tw, tid);
+  if constexpr (ct_npass(N) > 1) ct_pass<T, N, 1, DIR, NBMAX, L, NT>(lds, lay, nbatch, tw, tid);
+  if constexpr (ct_npass(N) > 2) ct_pass<T, N, 2, DIR, NBMAX, L, NT>(lds, lay, nbatch, tw, tid);
 }
 
 }  // namespace lz

@@ -26,6 +26,11 @@ namespace lz {
 template <typename T>
 __device__ __forceinline__ cplx<T> czero() { return mk<T>(T(0), T(0)); }
 
+// threads of a plane block: 512 on 96^2 planes (one block per compute unit
+// fits the LDS; twice the waves hide more latency and halve the registers a
+// thread holds), else 256
+template <int N> __host__ __device__ constexpr int plane_threads() { return N == 96 ? 512 : 256; }
+
 struct PlaneArgs {
   int n1, n2, n3, S, nact, pitch;
   const int* si1;
@@ -49,8 +54,8 @@ struct PlaneShm {
       cplx<T>* t = plane + N * P;
       int* r = reinterpret_cast<int*>(t + ct_twsize(N));
       const cplx<T>* tg = reinterpret_cast<const cplx<T>*>(twg);
-      for (int i = tid; i < ct_twsize(N); i += 256) t[i] = tg[i];
-      for (int i = tid; i < a.nact; i += 256) r[i] = a.act[i];
+      for (int i = tid; i < ct_twsize(N); i += plane_threads<N>()) t[i] = tg[i];
+      for (int i = tid; i < a.nact; i += plane_threads<N>()) r[i] = a.act[i];
       tw = t;
       act = r;
     } else {
@@ -71,8 +76,9 @@ template <typename T, int N, int MP, int DIR>
 __device__ __forceinline__ void plane_rows(const PlaneShm<T, N>& sh, const PlaneArgs& a, int nrows,
                                            bool listed, const cplx<T>* tw2, int tid) {
   if constexpr (N > 0) {
-    if (listed) ct_fft<T, N, DIR, N>(sh.plane, LayRows<N + 1>{sh.act}, nrows, sh.tw, tid);
-    else ct_fft<T, N, DIR, N>(sh.plane, LayRowsAll<N + 1>{}, nrows, sh.tw, tid);
+    constexpr int NT = plane_threads<N>();
+    if (listed) ct_fft<T, N, DIR, N, LayRows<N + 1>, NT>(sh.plane, LayRows<N + 1>{sh.act}, nrows, sh.tw, tid);
+    else ct_fft<T, N, DIR, N, LayRowsAll<N + 1>, NT>(sh.plane, LayRowsAll<N + 1>{}, nrows, sh.tw, tid);
   } else {
     fft_lds<T, MP, DIR>(sh.plane, Lay{1, a.pitch, listed ? sh.act : nullptr}, a.p2, nrows, tw2, tid, 256);
   }
@@ -82,7 +88,7 @@ template <typename T, int N, int MP, int DIR>
 __device__ __forceinline__ void plane_cols(const PlaneShm<T, N>& sh, const PlaneArgs& a,
                                            const cplx<T>* tw1, int tid) {
   if constexpr (N > 0) {
-    ct_fft<T, N, DIR, N>(sh.plane, LayCols<N + 1>{}, N, sh.tw, tid);
+    ct_fft<T, N, DIR, N, LayCols<N + 1>, plane_threads<N>()>(sh.plane, LayCols<N + 1>{}, N, sh.tw, tid);
   } else {
     fft_lds<T, MP, DIR>(sh.plane, Lay{a.pitch, 1, nullptr}, a.p1, a.n2, tw1, tid, 256);
   }
@@ -93,9 +99,10 @@ __device__ __forceinline__ void plane_zero_scatter(const PlaneShm<T, N>& sh, con
                                                    const cplx<T>* __restrict__ src, int tid) {
   const int n1 = N > 0 ? N : a.n1;
   const int pitch = N > 0 ? N + 1 : a.pitch;
-  for (int t = tid; t < n1 * pitch; t += 256) sh.plane[t] = czero<T>();
+  constexpr int NT = N > 0 ? plane_threads<N>() : 256;
+  for (int t = tid; t < n1 * pitch; t += NT) sh.plane[t] = czero<T>();
   __syncthreads();
-  for (int s = tid; s < a.S; s += 256) sh.plane[a.si1[s] * pitch + a.si2[s]] = src[s];
+  for (int s = tid; s < a.S; s += NT) sh.plane[a.si1[s] * pitch + a.si2[s]] = src[s];
   __syncthreads();
 }
 
@@ -218,7 +225,7 @@ __global__ __launch_bounds__(256) void k_zfft_fwd(const cplx<T>* __restrict__ st
 // plane pass of a D step: x(r) = IFFT2 sticks, (V x)(r), FFT2 -> sticks
 // ---------------------------------------------------------------------------
 template <typename T, int N, int MP>
-__global__ __launch_bounds__(256) void k_plane_local(const cplx<T>* __restrict__ sin,
+__global__ __launch_bounds__(plane_threads<N>()) void k_plane_local(const cplx<T>* __restrict__ sin,
                                                      cplx<T>* __restrict__ sout,
                                                      const T* __restrict__ vloc, PlaneArgs a,
                                                      const cplx<T>* __restrict__ tw1,
@@ -227,6 +234,7 @@ __global__ __launch_bounds__(256) void k_plane_local(const cplx<T>* __restrict__
   if (st && st->status) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int tid = threadIdx.x;
+  constexpr int NTB = N > 0 ? plane_threads<N>() : 256;
   PlaneShm<T, N> sh(smem_raw, a, tw1, tid);
   const int n1 = N > 0 ? N : a.n1, n2 = N > 0 ? N : a.n2, n3 = N > 0 ? N : a.n3;
   const int pitch = N > 0 ? N + 1 : a.pitch;
@@ -236,7 +244,7 @@ __global__ __launch_bounds__(256) void k_plane_local(const cplx<T>* __restrict__
   plane_rows<T, N, MP, +1>(sh, a, a.nact, true, tw2, tid);
   plane_cols<T, N, MP, +1>(sh, a, tw1, tid);
   const T* vz = vloc + (int64_t)z * n1 * n2;
-  for (int p = tid; p < n1 * n2; p += 256) {
+  for (int p = tid; p < n1 * n2; p += NTB) {
     const int i1 = p / n2, i2 = p - i1 * n2;
     cplx<T>& c = sh.plane[i1 * pitch + i2];
     c = cscale<T>(c, vz[p]);
@@ -244,7 +252,7 @@ __global__ __launch_bounds__(256) void k_plane_local(const cplx<T>* __restrict__
   __syncthreads();
   plane_cols<T, N, MP, -1>(sh, a, tw1, tid);
   plane_rows<T, N, MP, -1>(sh, a, a.nact, true, tw2, tid);
-  for (int s = tid; s < a.S; s += 256) sout[so + s] = sh.plane[a.si1[s] * pitch + a.si2[s]];
+  for (int s = tid; s < a.S; s += NTB) sout[so + s] = sh.plane[a.si1[s] * pitch + a.si2[s]];
 }
 
 // ---------------------------------------------------------------------------
@@ -253,7 +261,7 @@ __global__ __launch_bounds__(256) void k_plane_local(const cplx<T>* __restrict__
 // of u and x, i.e. without the Omega^-1/2 factors, which bandw absorbs).
 // ---------------------------------------------------------------------------
 template <typename T, int N, int MP>
-__global__ __launch_bounds__(256) void k_plane_local_density(
+__global__ __launch_bounds__(plane_threads<N>()) void k_plane_local_density(
     const cplx<T>* __restrict__ sin, cplx<T>* __restrict__ sout, const T* __restrict__ vloc,
     const cplx<T>* __restrict__ ur, const double* __restrict__ bandw, cplx<T>* __restrict__ dpart,
     int nb, int gsize, PlaneArgs a, const cplx<T>* __restrict__ tw1,
@@ -261,15 +269,16 @@ __global__ __launch_bounds__(256) void k_plane_local_density(
   if (st && st->status) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int tid = threadIdx.x;
+  constexpr int NTB = N > 0 ? plane_threads<N>() : 256;
   PlaneShm<T, N> sh(smem_raw, a, tw1, tid);
   const int n1 = N > 0 ? N : a.n1, n2 = N > 0 ? N : a.n2, n3 = N > 0 ? N : a.n3;
   const int pitch = N > 0 ? N + 1 : a.pitch;
-  // large double-precision planes (72^2, 96^2) keep the running sums in
-  // dpart itself (the block's own slice, read and written by the same thread
-  // in band order: the same sums, bitwise, as register accumulators, which
-  // would spill; in single precision the registers measured faster)
-  constexpr bool GACC = sizeof(T) == 8 && N >= 72;
-  constexpr int NIT = N > 0 ? (N * N + 255) / 256 : MP;
+  // large planes (72^2 and 96^2 in double precision, 96^2 in single) keep the
+  // running sums in dpart itself (the block's own slice, read and written by
+  // the same thread in band order: the same sums, bitwise, as register
+  // accumulators, which would spill)
+  constexpr bool GACC = sizeof(T) == 8 ? N >= 72 : N >= 96;
+  constexpr int NIT = N > 0 ? (N * N + NTB - 1) / NTB : MP;
   constexpr int ACC = GACC ? 1 : NIT;
   constexpr int UNR = GACC ? 4 : NIT;
   const int z = blockIdx.x, g = blockIdx.y;
@@ -289,7 +298,7 @@ __global__ __launch_bounds__(256) void k_plane_local_density(
     const T wb = T(bandw[b]);
 #pragma unroll UNR
     for (int i = 0; i < NIT; ++i) {
-      const int p = tid + i * 256;
+      const int p = tid + i * NTB;
       if (p < np) {
         const int i1 = p / n2, i2 = p - i1 * n2;
         cplx<T>& c = sh.plane[i1 * pitch + i2];
@@ -309,13 +318,13 @@ __global__ __launch_bounds__(256) void k_plane_local_density(
     __syncthreads();
     plane_cols<T, N, MP, -1>(sh, a, tw1, tid);
     plane_rows<T, N, MP, -1>(sh, a, a.nact, true, tw2, tid);
-    for (int s = tid; s < a.S; s += 256) sout[so + s] = sh.plane[a.si1[s] * pitch + a.si2[s]];
+    for (int s = tid; s < a.S; s += NTB) sout[so + s] = sh.plane[a.si1[s] * pitch + a.si2[s]];
     __syncthreads();
   }
   if constexpr (!GACC) {
 #pragma unroll
     for (int i = 0; i < ACC; ++i) {
-      const int p = tid + i * 256;
+      const int p = tid + i * NTB;
       if (p < np) dp[p] = acc[i];
     }
   }
@@ -323,12 +332,13 @@ __global__ __launch_bounds__(256) void k_plane_local_density(
 
 // sticks -> real-space plane (set-up: valence orbitals in real space)
 template <typename T, int N, int MP>
-__global__ __launch_bounds__(256) void k_plane_to_real(const cplx<T>* __restrict__ sin,
+__global__ __launch_bounds__(plane_threads<N>()) void k_plane_to_real(const cplx<T>* __restrict__ sin,
                                                        cplx<T>* __restrict__ rout, PlaneArgs a,
                                                        const cplx<T>* __restrict__ tw1,
                                                        const cplx<T>* __restrict__ tw2) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int tid = threadIdx.x;
+  constexpr int NTB = N > 0 ? plane_threads<N>() : 256;
   PlaneShm<T, N> sh(smem_raw, a, tw1, tid);
   const int n1 = N > 0 ? N : a.n1, n2 = N > 0 ? N : a.n2, n3 = N > 0 ? N : a.n3;
   const int pitch = N > 0 ? N + 1 : a.pitch;
@@ -338,7 +348,7 @@ __global__ __launch_bounds__(256) void k_plane_to_real(const cplx<T>* __restrict
   plane_rows<T, N, MP, +1>(sh, a, a.nact, true, tw2, tid);
   plane_cols<T, N, MP, +1>(sh, a, tw1, tid);
   cplx<T>* ro = rout + ((int64_t)b * n3 + z) * np;
-  for (int p = tid; p < np; p += 256) {
+  for (int p = tid; p < np; p += NTB) {
     const int i1 = p / n2, i2 = p - i1 * n2;
     ro[p] = sh.plane[i1 * pitch + i2];
   }
@@ -346,7 +356,7 @@ __global__ __launch_bounds__(256) void k_plane_to_real(const cplx<T>* __restrict
 
 // v'(r) u_b(r) -> FFT2 -> added to the sticks of the same band
 template <typename T, int N, int MP>
-__global__ __launch_bounds__(256) void k_plane_vu(const cplx<T>* __restrict__ ur,
+__global__ __launch_bounds__(plane_threads<N>()) void k_plane_vu(const cplx<T>* __restrict__ ur,
                                                   const cplx<T>* __restrict__ vp,
                                                   cplx<T>* __restrict__ sout, PlaneArgs a,
                                                   const cplx<T>* __restrict__ tw1,
@@ -355,6 +365,7 @@ __global__ __launch_bounds__(256) void k_plane_vu(const cplx<T>* __restrict__ ur
   if (st && st->status) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int tid = threadIdx.x;
+  constexpr int NTB = N > 0 ? plane_threads<N>() : 256;
   PlaneShm<T, N> sh(smem_raw, a, tw1, tid);
   const int n1 = N > 0 ? N : a.n1, n2 = N > 0 ? N : a.n2, n3 = N > 0 ? N : a.n3;
   const int pitch = N > 0 ? N + 1 : a.pitch;
@@ -362,7 +373,7 @@ __global__ __launch_bounds__(256) void k_plane_vu(const cplx<T>* __restrict__ ur
   const int np = n1 * n2;
   const cplx<T>* ub = ur + ((int64_t)b * n3 + z) * np;
   const cplx<T>* vz = vp + (int64_t)z * np;
-  for (int p = tid; p < np; p += 256) {
+  for (int p = tid; p < np; p += NTB) {
     const int i1 = p / n2, i2 = p - i1 * n2;
     sh.plane[i1 * pitch + i2] = cmul<T>(ub[p], vz[p]);
   }
@@ -370,7 +381,7 @@ __global__ __launch_bounds__(256) void k_plane_vu(const cplx<T>* __restrict__ ur
   plane_cols<T, N, MP, -1>(sh, a, tw1, tid);
   plane_rows<T, N, MP, -1>(sh, a, a.nact, true, tw2, tid);
   const int64_t so = ((int64_t)b * n3 + z) * a.S;
-  for (int s = tid; s < a.S; s += 256) {
+  for (int s = tid; s < a.S; s += NTB) {
     const cplx<T> v = sh.plane[a.si1[s] * pitch + a.si2[s]];
     sout[so + s] = cadd<T>(sout[so + s], v);
   }
@@ -381,7 +392,7 @@ __global__ __launch_bounds__(256) void k_plane_vu(const cplx<T>* __restrict__ ur
 // ---------------------------------------------------------------------------
 // (1) n'(r) = sum over band groups (fixed order); 2-D forward transform
 template <typename T, int N, int MP>
-__global__ __launch_bounds__(256) void k_hxc_planes_fwd(const cplx<T>* __restrict__ dpart,
+__global__ __launch_bounds__(plane_threads<N>()) void k_hxc_planes_fwd(const cplx<T>* __restrict__ dpart,
                                                         int ngroups, cplx<T>* __restrict__ nr,
                                                         cplx<T>* __restrict__ work, PlaneArgs a,
                                                         const cplx<T>* __restrict__ tw1,
@@ -390,13 +401,14 @@ __global__ __launch_bounds__(256) void k_hxc_planes_fwd(const cplx<T>* __restric
   if (st && st->status) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int tid = threadIdx.x;
+  constexpr int NTB = N > 0 ? plane_threads<N>() : 256;
   PlaneShm<T, N> sh(smem_raw, a, tw1, tid);
   const int n1 = N > 0 ? N : a.n1, n2 = N > 0 ? N : a.n2, n3 = N > 0 ? N : a.n3;
   const int pitch = N > 0 ? N + 1 : a.pitch;
   const int z = blockIdx.x;
   const int np = n1 * n2;
   const int64_t plane = (int64_t)n3 * np;
-  for (int p = tid; p < np; p += 256) {
+  for (int p = tid; p < np; p += NTB) {
     cplx<T> s = czero<T>();
 #pragma unroll 8
     for (int g = 0; g < ngroups; ++g) s = cadd<T>(s, dpart[g * plane + (int64_t)z * np + p]);
@@ -407,7 +419,7 @@ __global__ __launch_bounds__(256) void k_hxc_planes_fwd(const cplx<T>* __restric
   __syncthreads();
   plane_cols<T, N, MP, -1>(sh, a, tw1, tid);
   plane_rows<T, N, MP, -1>(sh, a, n1, false, tw2, tid);
-  for (int p = tid; p < np; p += 256) {
+  for (int p = tid; p < np; p += NTB) {
     const int i1 = p / n2, i2 = p - i1 * n2;
     work[(int64_t)z * np + p] = sh.plane[i1 * pitch + i2];
   }
@@ -449,7 +461,7 @@ __global__ __launch_bounds__(256) void k_hxc_z(cplx<T>* __restrict__ work,
 
 // (3) 2-D inverse transform, v'(r) = v_H(r) + f_xc(r) n'(r)
 template <typename T, int N, int MP>
-__global__ __launch_bounds__(256) void k_hxc_planes_inv(const cplx<T>* __restrict__ work,
+__global__ __launch_bounds__(plane_threads<N>()) void k_hxc_planes_inv(const cplx<T>* __restrict__ work,
                                                         const cplx<T>* __restrict__ nr,
                                                         const T* __restrict__ fxc, int with_fxc,
                                                         cplx<T>* __restrict__ vp, PlaneArgs a,
@@ -459,19 +471,20 @@ __global__ __launch_bounds__(256) void k_hxc_planes_inv(const cplx<T>* __restric
   if (st && st->status) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int tid = threadIdx.x;
+  constexpr int NTB = N > 0 ? plane_threads<N>() : 256;
   PlaneShm<T, N> sh(smem_raw, a, tw1, tid);
   const int n1 = N > 0 ? N : a.n1, n2 = N > 0 ? N : a.n2;
   const int pitch = N > 0 ? N + 1 : a.pitch;
   const int z = blockIdx.x;
   const int np = n1 * n2;
-  for (int p = tid; p < np; p += 256) {
+  for (int p = tid; p < np; p += NTB) {
     const int i1 = p / n2, i2 = p - i1 * n2;
     sh.plane[i1 * pitch + i2] = work[(int64_t)z * np + p];
   }
   __syncthreads();
   plane_rows<T, N, MP, +1>(sh, a, n1, false, tw2, tid);
   plane_cols<T, N, MP, +1>(sh, a, tw1, tid);
-  for (int p = tid; p < np; p += 256) {
+  for (int p = tid; p < np; p += NTB) {
     const int i1 = p / n2, i2 = p - i1 * n2;
     cplx<T> v = sh.plane[i1 * pitch + i2];
     if (with_fxc) {
@@ -678,7 +691,7 @@ template <typename T> static size_t stick_lds(const Grid3& g) {
       case 48: hipLaunchKernelGGL((KERN<T, 48, 0>), GRID, dim3(256), LDS, STREAM, __VA_ARGS__); break; \
       case 64: hipLaunchKernelGGL((KERN<T, 64, 0>), GRID, dim3(256), LDS, STREAM, __VA_ARGS__); break; \
       case 72: hipLaunchKernelGGL((KERN<T, 72, 0>), GRID, dim3(256), LDS, STREAM, __VA_ARGS__); break; \
-      case 96: hipLaunchKernelGGL((KERN<T, 96, 0>), GRID, dim3(256), LDS, STREAM, __VA_ARGS__); break; \
+      case 96: hipLaunchKernelGGL((KERN<T, 96, 0>), GRID, dim3(plane_threads<96>()), LDS, STREAM, __VA_ARGS__); break; \
       default:                                                                                  \
         switch (plane_mp((G).n1, (G).n2)) {                                                     \
           case 12: hipLaunchKernelGGL((KERN<T, 0, 12>), GRID, dim3(256), LDS, STREAM, __VA_ARGS__); break; \
