@@ -47,6 +47,8 @@ def _args():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--apply-stages", default=None, metavar="CONFIG",
                     help="only time the stages of operator applications on CONFIG (e.g. cfg5r)")
+    ap.add_argument("--batched", type=int, default=0, metavar="N",
+                    help="only time the first N members of the batched uneven workload")
     ap.add_argument("--ground-state", default=None, metavar="CONFIG",
                     help="only time the device ground-state preparation on CONFIG")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -255,6 +257,42 @@ def ground_state_time(config):
     print(json.dumps(out), flush=True)
 
 
+def batched_rate(n_inst, prec="fp32", reps=5):
+    """Instance-applies/s of the batched uneven workload: the first n_inst
+    seeded members (grids in {32, 40, 48, 64, 72}, 8-48 bands, 1-16 k-points,
+    random orthonormal orbitals, so operator applications rather than a
+    recursion) in one context, one instance after another against side by
+    side on the library's streams."""
+    import torch
+
+    import paper_2111_06623_amd as lz
+    from synth import config_system
+    t = time.perf_counter()
+    systems = [config_system("uneven", index=i) for i in range(n_inst)]
+    _log(f"[bench] {n_inst} batched members built in {time.perf_counter() - t:.1f}s")
+    out = {"workload": f"batched uneven: members 0..{n_inst - 1}", "instances": n_inst,
+           "precision": prec, "reps": reps,
+           "grids": [int(s.nr[0]) for s in systems],
+           "band_k_products": [int(s.nks) * int(s.evc_kq.shape[1]) for s in systems]}
+    dt = torch.complex128 if prec == "fp64" else torch.complex64
+    for streams, tag in ((1, "one_stream"), (0, "side_by_side")):
+        ctx = lz.lz_init(systems, prec=prec, max_steps=2, streams=streams)
+        x = torch.randn(sum(ctx.nvec), dtype=dt, device="cuda")
+        qo, po = torch.empty_like(x), torch.empty_like(x)
+        ctx.apply_liouvillian(x, x, qo, po)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            ctx.apply_liouvillian(x, x, qo, po)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        out[tag] = round(n_inst * reps / el, 2)
+        ctx.free()
+        del x, qo, po
+    out["unit"] = "instance-applies/s"
+    print(json.dumps(out), flush=True)
+
+
 def kernel_sources_sha():
     """sha256 over the kernel sources; a change invalidates counter data."""
     import hashlib
@@ -360,6 +398,11 @@ def main():
         sys.exit(2)
     if a.copy_probe_mib:
         copy_probe(a.copy_probe_mib, 8)
+        return
+    if a.batched:
+        import paper_2111_06623_amd as lz
+        lz.load()
+        batched_rate(a.batched, "fp64" if a.prec == "fp64" else "fp32")
         return
     if a.ground_state:
         import paper_2111_06623_amd as lz

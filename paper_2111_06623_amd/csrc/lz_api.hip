@@ -1024,9 +1024,16 @@ lz_status lz_apply_liouvillian(lz_ctx* c, const void* q_in, const void* p_in, vo
       fail(LZ_ERR_ARG, "each half needs both its input and its output (or neither)");
     HIPC(hipSetDevice(c->device));
     c->enter();
+    // instances side by side on their streams, as in lz_step
+    const bool fork = !c->qs.empty();
+    if (fork) {
+      HIPC(hipEventRecord(c->ev_fork, c->stream));
+      for (auto q : c->qs) HIPC(hipStreamWaitEvent(q, c->ev_fork, 0));
+    }
     size_t off = 0;
-    for (auto& ip : c->inst) {
-      Instance& I = *ip;
+    for (size_t ii = 0; ii < c->inst.size(); ++ii) {
+      Instance& I = *c->inst[ii];
+      hipStream_t sq = fork ? c->qs[ii % c->qs.size()] : c->stream;
       const size_t bytes_off = off * I.csz;
       auto at = [&](const void* p) { return p ? (const char*)p + bytes_off : nullptr; };
       auto atw = [&](void* p) { return p ? (char*)p + bytes_off : nullptr; };
@@ -1036,28 +1043,34 @@ lz_status lz_apply_liouvillian(lz_ctx* c, const void* q_in, const void* p_in, vo
       void* po = atw(p_out);
       if (I.fp64) {
         if (pi) {
-          LaunchLin<double>::perm_in(pi, I.tin.p, I.perm.as<int>(), I.npw_kq.as<int>(), I.nks, I.nbnd, I.npwx, c->stream);
-          apply_half<double>(I, I.tin.p, I.tout.p, false, c->stream);
-          LaunchLin<double>::perm_out(I.tout.p, qo, I.perm.as<int>(), I.npw_kq.as<int>(), I.nks, I.nbnd, I.npwx, c->stream);
+          LaunchLin<double>::perm_in(pi, I.tin.p, I.perm.as<int>(), I.npw_kq.as<int>(), I.nks, I.nbnd, I.npwx, sq);
+          apply_half<double>(I, I.tin.p, I.tout.p, false, sq);
+          LaunchLin<double>::perm_out(I.tout.p, qo, I.perm.as<int>(), I.npw_kq.as<int>(), I.nks, I.nbnd, I.npwx, sq);
         }
         if (qi) {
-          LaunchLin<double>::perm_in(qi, I.tin2.p, I.perm.as<int>(), I.npw_kq.as<int>(), I.nks, I.nbnd, I.npwx, c->stream);
-          apply_half<double>(I, I.tin2.p, I.tout2.p, true, c->stream);
-          LaunchLin<double>::perm_out(I.tout2.p, po, I.perm.as<int>(), I.npw_kq.as<int>(), I.nks, I.nbnd, I.npwx, c->stream);
+          LaunchLin<double>::perm_in(qi, I.tin2.p, I.perm.as<int>(), I.npw_kq.as<int>(), I.nks, I.nbnd, I.npwx, sq);
+          apply_half<double>(I, I.tin2.p, I.tout2.p, true, sq);
+          LaunchLin<double>::perm_out(I.tout2.p, po, I.perm.as<int>(), I.npw_kq.as<int>(), I.nks, I.nbnd, I.npwx, sq);
         }
       } else {
         if (pi) {
-          LaunchLin<float>::perm_in(pi, I.tin.p, I.perm.as<int>(), I.npw_kq.as<int>(), I.nks, I.nbnd, I.npwx, c->stream);
-          apply_half<float>(I, I.tin.p, I.tout.p, false, c->stream);
-          LaunchLin<float>::perm_out(I.tout.p, qo, I.perm.as<int>(), I.npw_kq.as<int>(), I.nks, I.nbnd, I.npwx, c->stream);
+          LaunchLin<float>::perm_in(pi, I.tin.p, I.perm.as<int>(), I.npw_kq.as<int>(), I.nks, I.nbnd, I.npwx, sq);
+          apply_half<float>(I, I.tin.p, I.tout.p, false, sq);
+          LaunchLin<float>::perm_out(I.tout.p, qo, I.perm.as<int>(), I.npw_kq.as<int>(), I.nks, I.nbnd, I.npwx, sq);
         }
         if (qi) {
-          LaunchLin<float>::perm_in(qi, I.tin2.p, I.perm.as<int>(), I.npw_kq.as<int>(), I.nks, I.nbnd, I.npwx, c->stream);
-          apply_half<float>(I, I.tin2.p, I.tout2.p, true, c->stream);
-          LaunchLin<float>::perm_out(I.tout2.p, po, I.perm.as<int>(), I.npw_kq.as<int>(), I.nks, I.nbnd, I.npwx, c->stream);
+          LaunchLin<float>::perm_in(qi, I.tin2.p, I.perm.as<int>(), I.npw_kq.as<int>(), I.nks, I.nbnd, I.npwx, sq);
+          apply_half<float>(I, I.tin2.p, I.tout2.p, true, sq);
+          LaunchLin<float>::perm_out(I.tout2.p, po, I.perm.as<int>(), I.npw_kq.as<int>(), I.nks, I.nbnd, I.npwx, sq);
         }
       }
       off += (size_t)I.nvec;
+    }
+    if (fork) {
+      for (size_t q = 0; q < c->qs.size(); ++q) {
+        HIPC(hipEventRecord(c->qdone[q], c->qs[q]));
+        HIPC(hipStreamWaitEvent(c->stream, c->qdone[q], 0));
+      }
     }
     HIPC(hipGetLastError());
     c->leave();
