@@ -158,10 +158,33 @@ __global__ __launch_bounds__(256) void k_zfft_inv(const cplx<T>* __restrict__ x,
   const cplx<T>* tw = stick_tw<T, N, ST>(lds, twg, tid);
   const cplx<T>* xb = x + b * xs;
   const int* mp = map + ((int64_t)k * S + s0) * n3;
-  for (int t = tid; t < nst * n3; t += 256) {
-    const int ls = t / n3, z = t - ls * n3;
-    const int idx = mp[ls * n3 + z];
-    lds[ls * pitch + z] = idx >= 0 ? xb[idx] : czero<T>();
+  if constexpr (N > 0) {
+    // compile-time trip count: every map index, then every gathered value,
+    // is in flight before the first is used
+    constexpr int IT = (ST * N + 255) / 256;
+    int idx[IT];
+    cplx<T> v[IT];
+#pragma unroll
+    for (int i = 0; i < IT; ++i) {
+      const int t = tid + i * 256;
+      idx[i] = t < nst * N ? mp[t] : -1;
+    }
+#pragma unroll
+    for (int i = 0; i < IT; ++i) v[i] = idx[i] >= 0 ? xb[idx[i]] : czero<T>();
+#pragma unroll
+    for (int i = 0; i < IT; ++i) {
+      const int t = tid + i * 256;
+      if (t < nst * N) {
+        const int ls = t / N, z = t - ls * N;
+        lds[ls * pitch + z] = v[i];
+      }
+    }
+  } else {
+    for (int t = tid; t < nst * n3; t += 256) {
+      const int ls = t / n3, z = t - ls * n3;
+      const int idx = mp[ls * n3 + z];
+      lds[ls * pitch + z] = idx >= 0 ? xb[idx] : czero<T>();
+    }
   }
   __syncthreads();
   stick_fft<T, N, ST>(lds, pitch, pz, nst, tw, tid, +1);
@@ -209,14 +232,41 @@ __global__ __launch_bounds__(256) void k_zfft_fwd(const cplx<T>* __restrict__ st
   cplx<T>* yb = y + b * xs;
   const T* kb = kin + (int64_t)k * npwx;
   const T e = T(eps[b]);
-  for (int t = tid; t < nst * n3; t += 256) {
-    const int ls = t / n3, z = t - ls * n3;
-    const int idx = mp[ls * n3 + z];
-    if (idx >= 0) {
-      const cplx<T> f = lds[ls * pitch + z];
-      const cplx<T> xv = xb[idx];
-      const T d = kb[idx] - e;
-      yb[idx] = mk<T>(f.x * scale + d * xv.x, f.y * scale + d * xv.y);
+  if constexpr (N > 0) {
+    constexpr int IT = (ST * N + 255) / 256;
+    int idx[IT];
+    cplx<T> xv[IT];
+    T kv[IT];
+#pragma unroll
+    for (int i = 0; i < IT; ++i) {
+      const int t = tid + i * 256;
+      idx[i] = t < nst * N ? mp[t] : -1;
+    }
+#pragma unroll
+    for (int i = 0; i < IT; ++i) {
+      xv[i] = idx[i] >= 0 ? xb[idx[i]] : czero<T>();
+      kv[i] = idx[i] >= 0 ? kb[idx[i]] : T(0);
+    }
+#pragma unroll
+    for (int i = 0; i < IT; ++i) {
+      const int t = tid + i * 256;
+      if (idx[i] >= 0) {
+        const int ls = t / N, z = t - ls * N;
+        const cplx<T> f = lds[ls * pitch + z];
+        const T d = kv[i] - e;
+        yb[idx[i]] = mk<T>(f.x * scale + d * xv[i].x, f.y * scale + d * xv[i].y);
+      }
+    }
+  } else {
+    for (int t = tid; t < nst * n3; t += 256) {
+      const int ls = t / n3, z = t - ls * n3;
+      const int idx = mp[ls * n3 + z];
+      if (idx >= 0) {
+        const cplx<T> f = lds[ls * pitch + z];
+        const cplx<T> xv = xb[idx];
+        const T d = kb[idx] - e;
+        yb[idx] = mk<T>(f.x * scale + d * xv.x, f.y * scale + d * xv.y);
+      }
     }
   }
 }

@@ -120,35 +120,50 @@ __global__ __launch_bounds__(256) void k_proj_dot(const cplx<T>* __restrict__ A,
 }
 
 // Column n of R[k] (P rows) from the chunk partials [k][chunk][n][p], summed in
-// double in a fixed order: 16 rows at a time, lane l of a row sums chunks
-// l, l+16, ..., then the 16 lane sums are added in lane order.  The result,
-// rounded to T, is left in Rc[0..P).
+// double in a fixed order: lane l of a row sums chunks l, l+16, ..., then the
+// 16 lane sums are added in lane order.  A round covers kRedRows rows (16
+// lanes each, kRedRows / 16 rows per thread, all of their loads in flight);
+// the result, rounded to T, is left in Rc[0..P).
+constexpr int kRedRows = 64;
+
 template <typename T>
 __device__ __forceinline__ void reduce_column(const cplx<T>* __restrict__ partial, int nchunk,
                                               int P, int nbnd, int n, int k, cplx<T>* Rc) {
-  __shared__ double rx[16][17], ry[16][17];
+  constexpr int RB = kRedRows / 16;
+  __shared__ double rx[kRedRows][17], ry[kRedRows][17];
   const int o = threadIdx.x % 16, lane = threadIdx.x / 16;
   const int64_t cs = (int64_t)P * nbnd;
   const cplx<T>* pk = partial + (int64_t)k * nchunk * cs + (int64_t)n * P;
-  for (int p0 = 0; p0 < P; p0 += 16) {
-    const int p = p0 + o;
-    double sx = 0.0, sy = 0.0;
-    if (p < P) {
+  for (int p0 = 0; p0 < P; p0 += kRedRows) {
+    double sx[RB], sy[RB];
+#pragma unroll
+    for (int r = 0; r < RB; ++r) sx[r] = sy[r] = 0.0;
 #pragma unroll 4
-      for (int c = lane; c < nchunk; c += 16) {
-        const cplx<T> v = pk[(int64_t)c * cs + p];
-        sx += double(v.x);
-        sy += double(v.y);
+    for (int c = lane; c < nchunk; c += 16) {
+      cplx<T> v[RB];
+#pragma unroll
+      for (int r = 0; r < RB; ++r) {
+        const int p = p0 + o + 16 * r;
+        v[r] = p < P ? pk[(int64_t)c * cs + p] : czero<T>();
+      }
+#pragma unroll
+      for (int r = 0; r < RB; ++r) {
+        sx[r] += double(v[r].x);
+        sy[r] += double(v[r].y);
       }
     }
-    rx[o][lane] = sx;
-    ry[o][lane] = sy;
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+      rx[o + 16 * r][lane] = sx[r];
+      ry[o + 16 * r][lane] = sy[r];
+    }
     __syncthreads();
-    if (lane == 0 && p < P) {
+    const int p = p0 + threadIdx.x;
+    if (threadIdx.x < kRedRows && p < P) {
       double ax = 0.0, ay = 0.0;
       for (int l = 0; l < 16; ++l) {
-        ax += rx[o][l];
-        ay += ry[o][l];
+        ax += rx[threadIdx.x][l];
+        ay += ry[threadIdx.x][l];
       }
       Rc[p] = mk<T>(T(ax), T(ay));
     }
@@ -195,7 +210,7 @@ __global__ __launch_bounds__(256) void k_reduce_coef_in(const cplx<T>* __restric
       double ax = double(Rc[p].x), ay = double(Rc[p].y);
       if (!skip_pc) {
         const cplx<T>* Mq = M + ((int64_t)k * nproj + q) * nbnd;
-#pragma unroll 4
+#pragma unroll 16
         for (int m = 0; m < nbnd; ++m) {
           const cplx<T> mm = Mq[m], sv = Rc[m];
           ax -= double(mm.x) * double(sv.x) - double(mm.y) * double(sv.y);
@@ -230,7 +245,7 @@ __global__ __launch_bounds__(256) void k_reduce_coef_out(const cplx<T>* __restri
     cplx<T> out;
     if (p < nbnd) {
       double ax = double(Rc[p].x), ay = double(Rc[p].y);
-#pragma unroll 4
+#pragma unroll 16
       for (int q = 0; q < nproj; ++q) {
         const cplx<T> mm = M[((int64_t)k * nproj + q) * nbnd + p];  // conj taken below
         const cplx<T> db = Ck[(nbnd + q) * nbnd + n];

@@ -49,6 +49,52 @@ __device__ __forceinline__ void reg_rows(cplx<T>* planes, int pstride, int nact,
   }
 }
 
+// The sticks of one plane into its LDS rows, and back: a thread's share of
+// the stick table and of the values is in flight before the first store
+// (batches of kRegStickBatch strided by N cover S <= 12 N in one round).
+constexpr int kRegStickBatch = 12;
+
+template <typename T, int N>
+__device__ __forceinline__ void reg_scatter(cplx<T>* pl, const cplx<T>* __restrict__ src,
+                                            const int* __restrict__ soff, int S, int l) {
+  for (int s0 = l; s0 < S; s0 += kRegStickBatch * N) {
+    int o[kRegStickBatch];
+    cplx<T> v[kRegStickBatch];
+#pragma unroll
+    for (int j = 0; j < kRegStickBatch; ++j) {
+      const int s = s0 + j * N;
+      o[j] = s < S ? soff[s] : -1;
+      v[j] = s < S ? src[s] : mk<T>(T(0), T(0));
+    }
+#pragma unroll
+    for (int j = 0; j < kRegStickBatch; ++j)
+      if (o[j] >= 0) pl[o[j]] = v[j];
+  }
+}
+
+template <typename T, int N, bool ADD>
+__device__ __forceinline__ void reg_gather(cplx<T>* __restrict__ dst, const cplx<T>* pl,
+                                           const int* __restrict__ soff, int S, int l) {
+  for (int s0 = l; s0 < S; s0 += kRegStickBatch * N) {
+    int o[kRegStickBatch];
+    cplx<T> v[kRegStickBatch];
+#pragma unroll
+    for (int j = 0; j < kRegStickBatch; ++j) {
+      const int s = s0 + j * N;
+      o[j] = s < S ? soff[s] : -1;
+      if constexpr (ADD) v[j] = s < S ? dst[s] : mk<T>(T(0), T(0));
+    }
+#pragma unroll
+    for (int j = 0; j < kRegStickBatch; ++j) {
+      const int s = s0 + j * N;
+      if (o[j] >= 0) {
+        const cplx<T> w = pl[o[j]];
+        dst[s] = ADD ? cadd<T>(v[j], w) : w;
+      }
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // D step: sticks -> IFFT2 -> V x -> FFT2 -> sticks, for nplanes planes
 // (band-major, z fastest).
@@ -73,19 +119,22 @@ __global__ __launch_bounds__(kRegPlaneThreads) void k_rl_local(const cplx<T>* __
 #pragma unroll
   for (int i = 0; i < N; ++i) pl[i * P + l] = mk<T>(T(0), T(0));
   __syncthreads();
-  if (live)
-    for (int s = l; s < a.S; s += N) pl[a.soff[s]] = sin[so + s];
+  if (live) reg_scatter<T, N>(pl, sin + so, a.soff, a.S, l);
   __syncthreads();
   reg_rows<T, N, +1>(planes, pstride, a.nact, tid, [&](int r) { return a.act[r]; });
   __syncthreads();
   {
+    // the column's potential is loaded before the transform that precedes its use
+    const T* vz = vloc + (int64_t)z * N * N + l;
+    T vv[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) vv[i] = vz[i * N];
     cplx<T> x[N];
 #pragma unroll
     for (int i = 0; i < N; ++i) x[i] = pl[i * P + l];
     reg_fft<T, N, +1>(x);
-    const T* vz = vloc + (int64_t)z * N * N + l;
 #pragma unroll
-    for (int i = 0; i < N; ++i) x[i] = cscale<T>(x[i], vz[i * N]);
+    for (int i = 0; i < N; ++i) x[i] = cscale<T>(x[i], vv[i]);
     reg_fft<T, N, -1>(x);
 #pragma unroll
     for (int i = 0; i < N; ++i) pl[i * P + l] = x[i];
@@ -93,8 +142,7 @@ __global__ __launch_bounds__(kRegPlaneThreads) void k_rl_local(const cplx<T>* __
   __syncthreads();
   reg_rows<T, N, -1>(planes, pstride, a.nact, tid, [&](int r) { return a.act[r]; });
   __syncthreads();
-  if (live)
-    for (int s = l; s < a.S; s += N) sout[so + s] = pl[a.soff[s]];
+  if (live) reg_gather<T, N, false>(sout + so, pl, a.soff, a.S, l);
 }
 
 // ---------------------------------------------------------------------------
@@ -136,8 +184,7 @@ __global__ __launch_bounds__(kRegPlaneThreads) void k_rl_density(
     }
     __syncthreads();
     const int64_t so = ((int64_t)(live ? b : b0) * N + z) * a.S;
-    if (live)
-      for (int s = l; s < a.S; s += N) pl[a.soff[s]] = sin[so + s];
+    if (live) reg_scatter<T, N>(pl, sin + so, a.soff, a.S, l);
     __syncthreads();
     reg_rows<T, N, +1>(planes, pstride, nact, tid, [&](int r) { return a.act[r]; });
     __syncthreads();
@@ -176,8 +223,7 @@ __global__ __launch_bounds__(kRegPlaneThreads) void k_rl_density(
     __syncthreads();
     reg_rows<T, N, -1>(planes, pstride, nact, tid, [&](int r) { return a.act[r]; });
     __syncthreads();
-    if (live)
-      for (int s = l; s < a.S; s += N) sout[so + s] = pl[a.soff[s]];
+    if (live) reg_gather<T, N, false>(sout + so, pl, a.soff, a.S, l);
     __syncthreads();
   }
   cplx<T>* dp = dpart + ((int64_t)g * N + z) * N * N + l;
@@ -220,10 +266,7 @@ __global__ __launch_bounds__(kRegPlaneThreads) void k_rl_vu(const cplx<T>* __res
   __syncthreads();
   reg_rows<T, N, -1>(planes, pstride, a.nact, tid, [&](int r) { return a.act[r]; });
   __syncthreads();
-  if (live) {
-    const int64_t so = (int64_t)pidx * a.S;
-    for (int s = l; s < a.S; s += N) sout[so + s] = cadd<T>(sout[so + s], pl[a.soff[s]]);
-  }
+  if (live) reg_gather<T, N, true>(sout + (int64_t)pidx * a.S, pl, a.soff, a.S, l);
 }
 
 }  // namespace lz
