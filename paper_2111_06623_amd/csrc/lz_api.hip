@@ -187,6 +187,7 @@ struct Instance {
   int chunk = 32, nchunk = 1;  // split of the projector products over G
   int gemm = kGemmValu;        // where the projector products run
   int nlzblk = 1;              // blocks of the output update (Lanczos partial sums)
+  int nlzblk_nl = 1;           // the same for the update over the separable rows only
   int64_t nvec;  // complex elements of one batch
   Grid3 grid;
   DBuf si1, si2, act, map_kq, map_k, perm, npw_kq;
@@ -285,6 +286,22 @@ void output_side(Instance& I, void* out, const void* x, double* lzpart, const Lz
                                   I.nks, x, I.y.p, I.wk.as<double>(), lzpart, st, s, I.gemm));
 }
 
+// Output side of a pseudo-Hermitian step: out <- out + beta D B (D B from the
+// input side of the same step), with the Lanczos sums of (x, out, y).  P_c is
+// not applied to out here: the next step forms w = a out + b x' from it and
+// its input side projects w, which in exact arithmetic is the vector that
+// projecting out first would give (x' is already a conduction vector), and
+// the sums pair out with the conduction vector x, blind to the valence part.
+template <typename T>
+void output_side_nl(Instance& I, void* out, const void* x, double* lzpart, const LzDevState* st,
+                    hipStream_t s) {
+  const cplx<T>* A = static_cast<const cplx<T>*>(I.Aio.p) + (size_t)I.nbnd * I.npwx;
+  const cplx<T>* C = static_cast<const cplx<T>*>(I.Cin.p) + (size_t)I.nbnd * I.nbnd;
+  STAGE(I, ST_PROJ, s,
+        LaunchLin<T>::proj_update(out, A, I.nproj, I.ptot, C, I.ptot, I.nbnd, I.npwx, I.nks, x,
+                                  I.y.p, I.wk.as<double>(), lzpart, st, s, I.gemm));
+}
+
 // FFT part of one half-application: out = (H_loc - eps) in (+ v'u for an
 // upper vector), before the projector terms.
 template <typename T>
@@ -337,9 +354,9 @@ void lanczos_step(Instance& I, int j, hipStream_t s) {
   void* X = (j & 1) ? I.X1.p : I.X0.p;
   input_side<T>(I, X, j > 0 ? I.LW.p : nullptr, j > 0, st, s);
   apply_core<T>(I, X, I.LW.p, (j & 1) != 0, st, s);
-  output_side<T>(I, I.LW.p, X, I.lzpart.as<double>(), st, s);
+  output_side_nl<T>(I, I.LW.p, X, I.lzpart.as<double>(), st, s);
   STAGE(I, ST_LANCZOS, s,
-        launch_lz_finalize(I.lzpart.as<double>(), I.nlzblk, st, I.beta.as<double>(),
+        launch_lz_finalize(I.lzpart.as<double>(), I.nlzblk_nl, st, I.beta.as<double>(),
                            I.z.as<double>(), I.max_steps, kBreakdownTol, (double)I.nbnd, s));
 }
 
@@ -428,6 +445,7 @@ struct LaunchCfg {
   int chunk;    // plane waves per partial of a projector dot
   int nchunk;
   int nlzblk;   // blocks of the output update (Lanczos partial sums)
+  int nlzblk_nl;  // the same for the update over the separable rows only
   int gsize;    // bands per group of the density pass
   int ngroups;
 };
@@ -437,6 +455,7 @@ void set_cfg(Instance& I, const LaunchCfg& c) {
   I.chunk = c.chunk;
   I.nchunk = c.nchunk;
   I.nlzblk = c.nlzblk;
+  I.nlzblk_nl = c.nlzblk_nl;
   I.gsize = c.gsize;
   I.ngroups = c.ngroups;
 }
@@ -452,6 +471,8 @@ LaunchCfg make_cfg(const Instance& I, int gemm, int gsize, int chunk = kProjChun
   c.nchunk = (I.npwx + c.chunk - 1) / c.chunk;
   c.nlzblk = I.fp64 ? LaunchLin<double>::update_blocks(I.ptot, I.nbnd, I.npwx, I.nks, gemm)
                     : LaunchLin<float>::update_blocks(I.ptot, I.nbnd, I.npwx, I.nks, gemm);
+  c.nlzblk_nl = I.fp64 ? LaunchLin<double>::update_blocks(I.nproj, I.nbnd, I.npwx, I.nks, gemm)
+                       : LaunchLin<float>::update_blocks(I.nproj, I.nbnd, I.npwx, I.nks, gemm);
   c.gsize = std::max(1, std::min(gsize, I.nb));
   c.ngroups = (I.nb + c.gsize - 1) / c.gsize;
   return c;
@@ -848,7 +869,7 @@ std::unique_ptr<Instance> build_instance(const lz_system& sys, const lz_options&
   for (const LaunchCfg& c : cands) {
     max_groups = std::max(max_groups, c.ngroups);
     max_chunks = std::max(max_chunks, c.nchunk);
-    max_blk = std::max(max_blk, c.nlzblk);
+    max_blk = std::max(max_blk, std::max(c.nlzblk, c.nlzblk_nl));
   }
   set_cfg(I, cands[0]);
   I.dpart.alloc((size_t)max_groups * I.N * I.csz);
