@@ -103,48 +103,4 @@ __device__ __forceinline__ void reg_fft(cplx<T> (&x)[N]) {
   }
 }
 
-// Value held by the partner lane (lane ^ 1) of a lane pair.
-__device__ __forceinline__ float pair_swap(float v) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xF, 0xF, false));
-}
-__device__ __forceinline__ double pair_swap(double v) {
-  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0xB1, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0xB1, 0xF, 0xF, false);
-  return __hiloint2double(hi, lo);
-}
-template <typename T>
-__device__ __forceinline__ cplx<T> pair_swap(cplx<T> v) {
-  return mk<T>(pair_swap(v.x), pair_swap(v.y));
-}
-
-// Length-N transform shared by a lane pair (h = lane & 1), each lane holding
-// N/2 values: a radix-2 step across the pair and a register transform of
-// length N/2 on each lane.
-//   pair_fft_dit: in x[j] = v[2 j + h], out x[k] = V[h N/2 + k]
-//   pair_fft_dif: in x[k] = v[h N/2 + k], out x[j] = V[2 j + h]
-template <typename T, int N, int DIR>
-__device__ __forceinline__ void pair_fft_dit(cplx<T> (&x)[N / 2], int h) {
-  constexpr int M = N / 2;
-  reg_fft<T, M, DIR>(x);
-  sfor<0, M>([&](auto kc) {
-    constexpr int k = decltype(kc)::value;
-    const cplx<T> t = w192<T, (192 / N) * k, DIR>(x[k]);
-    const cplx<T> own = h ? t : x[k];
-    const cplx<T> other = pair_swap<T>(own);
-    x[k] = h ? csub<T>(other, own) : cadd<T>(own, other);
-  });
-}
-
-template <typename T, int N, int DIR>
-__device__ __forceinline__ void pair_fft_dif(cplx<T> (&x)[N / 2], int h) {
-  constexpr int M = N / 2;
-  sfor<0, M>([&](auto kc) {
-    constexpr int k = decltype(kc)::value;
-    const cplx<T> other = pair_swap<T>(x[k]);
-    const cplx<T> b = w192<T, (192 / N) * k, DIR>(csub<T>(other, x[k]));
-    x[k] = h ? b : cadd<T>(x[k], other);
-  });
-  reg_fft<T, M, DIR>(x);
-}
-
 }  // namespace lz

@@ -141,6 +141,34 @@ def test_tridiagonal_eigenvalues_come_in_pairs_and_z_is_real(cfg1):
     assert m == 60
 
 
+def test_projecting_only_the_new_vector_gives_the_same_recursion(cfg1):
+    """Operators whose output keeps its valence part, with P_c applied only to
+    each new vector, give the coefficients of the recursion that also projects
+    every output: each Lanczos sum pairs an output with a conduction vector,
+    and each new vector is projected before an operator acts on it.  (The
+    device recursion takes this order; the oracle projects both.)"""
+    L = Liouvillian(cfg1)
+
+    def d_raw(x):
+        return L.pack([L.ham[k].apply(b) - L.eps[k][:, None] * b
+                       for k, b in enumerate(L.blocks(x))])
+
+    def dk_raw(x):
+        v = L.hxc_potential(L.density(x))
+        return d_raw(x) + L.pack([L.cell.to_coef(v[None, :] * L.u_r[k], L.nl_kq[k])
+                                  for k in range(L.nks)])
+
+    # the raw operators really leave a valence part in their outputs
+    y = L.rhs()
+    assert np.abs(L.project_c(dk_raw(y)) - dk_raw(y)).max() > 1e-3 * np.abs(dk_raw(y)).max()
+    ref = lanczos.run(L, 40)
+    alt = lanczos.pseudo_hermitian_lanczos(d_raw, dk_raw, L.inner, y, 40, project=L.project_c,
+                                           y_scale=float(L.nbnd))
+    assert alt.steps == ref.steps == 40
+    assert np.max(np.abs(alt.beta - ref.beta) / ref.beta) < 1e-11
+    assert np.abs(alt.z - ref.z).max() < 1e-11 * np.abs(ref.z).max()
+
+
 @pytest.mark.parametrize("approx", ["tddft", "rpa", "ipa"])
 def test_nonhermitian_exhaustive_equals_direct_resolvent(micro, approx):
     """The biorthogonal recursion with two-sided re-biorthogonalisation
