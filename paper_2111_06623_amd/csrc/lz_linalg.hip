@@ -43,7 +43,7 @@ constexpr int kDotK = 32;  // G per LDS tile
 // vector w = a*LW + b*X of its plane waves and writes it back to X (the
 // host uses UPD only when one block spans every row and band of a chunk).
 template <typename T, int TPI, int TNJ, bool UPD>
-__global__ __launch_bounds__(256) void k_proj_dot(const cplx<T>* __restrict__ A, int P,
+__global__ __launch_bounds__(256, TPI * TNJ <= 3 ? 4 : 1) void k_proj_dot(const cplx<T>* __restrict__ A, int P,
                                                   int a_rows, cplx<T>* X,
                                                   const cplx<T>* __restrict__ LW, int nbnd,
                                                   int npwx, int chunk, int nchunk,
@@ -73,28 +73,54 @@ __global__ __launch_bounds__(256) void k_proj_dot(const cplx<T>* __restrict__ A,
   cplx<T>* Xk = X + (int64_t)k * nbnd * npwx;
   const cplx<T>* Lk = UPD ? LW + (int64_t)k * nbnd * npwx : nullptr;
   const int g_end = min(npwx, (ci + 1) * chunk);
-  for (int g0 = ci * chunk; g0 < g_end; g0 += kDotK) {
-    for (int t = tid; t < TP * kDotK; t += 256) {
+  // software pipeline: the next tile's values are loaded into registers while
+  // the current one is multiplied out of LDS (with UPD the Lanczos vector is
+  // formed, and written back, when its tile goes to LDS)
+  constexpr int NA = (TP * kDotK + 255) / 256, NX = (TN * kDotK + 255) / 256;
+  cplx<T> ra[NA], rx[NX], rl[UPD ? NX : 1];
+  auto load = [&](int g0) {
+#pragma unroll
+    for (int i = 0; i < NA; ++i) {
+      const int t = threadIdx.x + i * 256;
       const int r = t / kDotK, c = t - r * kDotK;
       const int g = g0 + c, p = p0 + r;
-      As[r][c] = (p < P && g < g_end) ? Ak[(int64_t)p * npwx + g] : czero<T>();
+      ra[i] = (t < TP * kDotK && p < P && g < g_end) ? Ak[(int64_t)p * npwx + g] : czero<T>();
     }
-    for (int t = tid; t < TN * kDotK; t += 256) {
+#pragma unroll
+    for (int i = 0; i < NX; ++i) {
+      const int t = threadIdx.x + i * 256;
       const int r = t / kDotK, c = t - r * kDotK;
       const int g = g0 + c, n = n0 + r;
-      cplx<T> v = czero<T>();
-      if (n < nbnd && g < g_end) {
-        const int64_t o = (int64_t)n * npwx + g;
-        v = Xk[o];
+      const bool in = t < TN * kDotK && n < nbnd && g < g_end;
+      const int64_t o = (int64_t)n * npwx + g;
+      rx[i] = in ? Xk[o] : czero<T>();
+      if constexpr (UPD) rl[i] = in ? Lk[o] : czero<T>();
+    }
+  };
+  const int g_beg = ci * chunk;
+  if (g_beg < g_end) load(g_beg);
+  for (int g0 = g_beg; g0 < g_end; g0 += kDotK) {
+#pragma unroll
+    for (int i = 0; i < NA; ++i) {
+      const int t = threadIdx.x + i * 256;
+      if (t < TP * kDotK) As[t / kDotK][t % kDotK] = ra[i];
+    }
+#pragma unroll
+    for (int i = 0; i < NX; ++i) {
+      const int t = threadIdx.x + i * 256;
+      if (t < TN * kDotK) {
+        const int r = t / kDotK, c = t - r * kDotK;
+        cplx<T> v = rx[i];
         if constexpr (UPD) {
-          const cplx<T> l = Lk[o];
-          v = mk<T>(ua * l.x + ub * v.x, ua * l.y + ub * v.y);
-          Xk[o] = v;
+          const int g = g0 + c, n = n0 + r;
+          v = mk<T>(ua * rl[i].x + ub * v.x, ua * rl[i].y + ub * v.y);
+          if (n < nbnd && g < g_end) Xk[(int64_t)n * npwx + g] = v;
         }
+        Xs[r][c] = v;
       }
-      Xs[r][c] = v;
     }
     __syncthreads();
+    if (g0 + kDotK < g_end) load(g0 + kDotK);
 #pragma unroll 4
     for (int c = 0; c < kDotK; ++c) {
       cplx<T> a[TPI], x[TNJ];
