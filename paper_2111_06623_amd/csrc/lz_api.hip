@@ -191,7 +191,7 @@ struct Instance {
   int64_t nvec;  // complex elements of one batch
   Grid3 grid;
   DBuf si1, si2, act, map_kq, map_k, perm, npw_kq;
-  DBuf soff_f;
+  DBuf soff_f, soff_c;
   DBuf tw1, tw2, tw3;
   DBuf kin, eps, wk, bandw, vloc, fxc, khart;
   DBuf U, vkb, dkb;
@@ -846,14 +846,20 @@ std::unique_ptr<Instance> build_instance(const lz_system& sys, const lz_options&
   I.grid.tw1 = I.tw1.p; I.grid.tw2 = I.tw2.p; I.grid.tw3 = I.tw3.p;
   // row tables of the register-line plane kernels (cubic grids up to 64)
   I.grid.soff_f = nullptr;
+  I.grid.soff_c = nullptr;
   for (int i = 0; i < 64; ++i) I.grid.slot[i] = -1;
   if (I.n1 == I.n2 && I.n2 == I.n3 && I.n1 <= 64) {
     const int pitch = I.n1 + 1;
     for (int a = 0; a < I.nact; ++a) I.grid.slot[act[a]] = (signed char)a;
-    std::vector<int> sf(I.S);
-    for (int t = 0; t < I.S; ++t) sf[t] = si1[t] * pitch + si2[t];
+    std::vector<int> sf(I.S), sc(I.S);
+    for (int t = 0; t < I.S; ++t) {
+      sf[t] = si1[t] * pitch + si2[t];
+      sc[t] = I.grid.slot[si1[t]] * pitch + si2[t];
+    }
     upload(I.soff_f, sf);
+    upload(I.soff_c, sc);
     I.grid.soff_f = I.soff_f.as<int>();
+    I.grid.soff_c = I.soff_c.as<int>();
   }
   // ---- work buffers
   const size_t vb = nv * I.csz;

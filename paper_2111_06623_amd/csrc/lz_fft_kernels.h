@@ -700,6 +700,7 @@ static inline RegPlaneArgs reg_args(const Grid3& g) {
   a.S = g.S;
   a.nact = g.nact;
   a.soff = g.soff_f;
+  a.soffc = g.soff_c;
   a.act = g.act;
   for (int i = 0; i < 64; ++i) a.slot[i] = g.slot[i];
   return a;
@@ -791,7 +792,7 @@ void LaunchFft<T>::plane_local(const Grid3& g, const void* sin, void* sout, cons
                                int nb, const LzDevState* st, hipStream_t s) {
   if (const int n = reg_plane_size<T>(g)) {
     const int npb = kRegPlaneThreads / n, nplanes = nb * n;
-    const size_t lds = (size_t)npb * n * (n + 1) * sizeof(cplx<T>);
+    const size_t lds = (size_t)npb * (g.nact + 1) * (n + 1) * sizeof(cplx<T>);  // compact planes
     LZ_REG_LAUNCH(k_rl_local, T, n, dim3((nplanes + npb - 1) / npb), lds, s, (const cplx<T>*)sin,
                   (cplx<T>*)sout, (const T*)vloc, reg_args(g), nplanes, st);
     return;
@@ -833,7 +834,7 @@ void LaunchFft<T>::plane_vu(const Grid3& g, const void* ur, const void* vp, void
                             const LzDevState* st, hipStream_t s) {
   if (const int n = reg_plane_size<T>(g)) {
     const int npb = kRegPlaneThreads / n, nplanes = nb * n;
-    const size_t lds = (size_t)npb * n * (n + 1) * sizeof(cplx<T>);
+    const size_t lds = (size_t)npb * (g.nact + 1) * (n + 1) * sizeof(cplx<T>);  // compact planes
     LZ_REG_LAUNCH(k_rl_vu, T, n, dim3((nplanes + npb - 1) / npb), lds, s, (const cplx<T>*)ur,
                   (const cplx<T>*)vp, (cplx<T>*)sout, reg_args(g), nplanes, st);
     return;

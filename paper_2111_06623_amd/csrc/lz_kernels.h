@@ -12,6 +12,7 @@ namespace lz {
 struct RegPlaneArgs {
   int S, nact;
   const int* soff;        // [S] LDS offset of each stick in a plane (row pitch n + 1)
+  const int* soffc;       // [S] the same in a compact plane (active rows only, in act order)
   const int* act;         // [nact] grid row i1 of each stored row
   signed char slot[64];   // index of grid row i1 in act, -1 when it holds no stick
 };
@@ -31,6 +32,7 @@ struct Grid3 {
   const void* tw3;
   // register-line plane kernels (cubic grids, see reg_plane_size)
   const int* soff_f;       // [S] LDS offset si1 (n+1) + si2 of each stick
+  const int* soff_c;       // [S] LDS offset slot[si1] (n+1) + si2 in a compact plane
   signed char slot[64];    // index of each grid row i1 in act, or -1
 };
 

@@ -148,9 +148,9 @@ __global__ __launch_bounds__(256, TPI * TNJ <= 3 ? 4 : 1) void k_proj_dot(const 
 // Column n of R[k] (P rows) from the chunk partials [k][chunk][n][p], summed in
 // double in a fixed order: lane l of a row sums chunks l, l+16, ..., then the
 // 16 lane sums are added in lane order.  A round covers kRedRows rows (16
-// lanes each, kRedRows / 16 rows per thread, all of their loads in flight);
-// the result, rounded to T, is left in Rc[0..P).
-constexpr int kRedRows = 64;
+// lanes each, kRedRows / 16 rows per thread) and kRedBatch chunks per lane,
+// all of their loads in flight; the result, rounded to T, is left in Rc[0..P).
+constexpr int kRedRows = 64, kRedBatch = 8;
 
 template <typename T>
 __device__ __forceinline__ void reduce_column(const cplx<T>* __restrict__ partial, int nchunk,
@@ -164,18 +164,27 @@ __device__ __forceinline__ void reduce_column(const cplx<T>* __restrict__ partia
     double sx[RB], sy[RB];
 #pragma unroll
     for (int r = 0; r < RB; ++r) sx[r] = sy[r] = 0.0;
-#pragma unroll 4
-    for (int c = lane; c < nchunk; c += 16) {
-      cplx<T> v[RB];
+    // kRedBatch chunks per round, all loads of a round in flight at once
+    for (int c0 = lane; c0 < nchunk; c0 += 16 * kRedBatch) {
+      cplx<T> v[kRedBatch][RB];
 #pragma unroll
-      for (int r = 0; r < RB; ++r) {
-        const int p = p0 + o + 16 * r;
-        v[r] = p < P ? pk[(int64_t)c * cs + p] : czero<T>();
+      for (int i = 0; i < kRedBatch; ++i) {
+        const int c = c0 + 16 * i;
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+          const int p = p0 + o + 16 * r;
+          v[i][r] = (c < nchunk && p < P) ? pk[(int64_t)c * cs + p] : czero<T>();
+        }
       }
 #pragma unroll
-      for (int r = 0; r < RB; ++r) {
-        sx[r] += double(v[r].x);
-        sy[r] += double(v[r].y);
+      for (int i = 0; i < kRedBatch; ++i) {
+        if (c0 + 16 * i < nchunk) {
+#pragma unroll
+          for (int r = 0; r < RB; ++r) {
+            sx[r] += double(v[i][r].x);
+            sy[r] += double(v[i][r].y);
+          }
+        }
       }
     }
 #pragma unroll

@@ -95,6 +95,32 @@ __device__ __forceinline__ void reg_gather(cplx<T>* __restrict__ dst, const cplx
   }
 }
 
+// Column l of a compact plane (rows act[0..nact) in that order, then one
+// spare row): in, with zeros for the rows that hold no stick, and out, the
+// active rows.  Rows without a stick read and write the spare row, so that
+// every access is unconditional (no branch per row).
+template <typename T, int N>
+__device__ __forceinline__ void reg_col_in(cplx<T> (&x)[N], const cplx<T>* pl,
+                                           const RegPlaneArgs& a, int l) {
+  constexpr int P = RegPlane<N>::P;
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    const int r = a.slot[i];
+    const cplx<T> v = pl[(r >= 0 ? r : a.nact) * P + l];
+    x[i] = r >= 0 ? v : mk<T>(T(0), T(0));
+  }
+}
+template <typename T, int N>
+__device__ __forceinline__ void reg_col_out(const cplx<T> (&x)[N], cplx<T>* pl,
+                                            const RegPlaneArgs& a, int l) {
+  constexpr int P = RegPlane<N>::P;
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    const int r = a.slot[i];
+    pl[(r >= 0 ? r : a.nact) * P + l] = x[i];
+  }
+}
+
 // ---------------------------------------------------------------------------
 // D step: sticks -> IFFT2 -> V x -> FFT2 -> sticks, for nplanes planes
 // (band-major, z fastest).
@@ -107,7 +133,7 @@ __global__ __launch_bounds__(kRegPlaneThreads) void k_rl_local(const cplx<T>* __
                                                                const LzDevState* st) {
   if (st && st->status) return;
   constexpr int NPB = RegPlane<N>::NPB, P = RegPlane<N>::P;
-  constexpr int pstride = N * P;
+  const int pstride = (a.nact + 1) * P;  // compact planes: the active rows and a spare
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cplx<T>* planes = reinterpret_cast<cplx<T>*>(smem_raw);
   const int tid = threadIdx.x, pp = tid / N, l = tid - pp * N;
@@ -116,12 +142,11 @@ __global__ __launch_bounds__(kRegPlaneThreads) void k_rl_local(const cplx<T>* __
   const int z = pidx % N;
   const int64_t so = (int64_t)pidx * a.S;
   cplx<T>* pl = planes + pp * pstride;
-#pragma unroll
-  for (int i = 0; i < N; ++i) pl[i * P + l] = mk<T>(T(0), T(0));
+  for (int t = l; t < pstride; t += N) pl[t] = mk<T>(T(0), T(0));
   __syncthreads();
-  if (live) reg_scatter<T, N>(pl, sin + so, a.soff, a.S, l);
+  if (live) reg_scatter<T, N>(pl, sin + so, a.soffc, a.S, l);
   __syncthreads();
-  reg_rows<T, N, +1>(planes, pstride, a.nact, tid, [&](int r) { return a.act[r]; });
+  reg_rows<T, N, +1>(planes, pstride, a.nact, tid, [](int r) { return r; });
   __syncthreads();
   {
     // the column's potential is loaded before the transform that precedes its use
@@ -130,19 +155,17 @@ __global__ __launch_bounds__(kRegPlaneThreads) void k_rl_local(const cplx<T>* __
 #pragma unroll
     for (int i = 0; i < N; ++i) vv[i] = vz[i * N];
     cplx<T> x[N];
-#pragma unroll
-    for (int i = 0; i < N; ++i) x[i] = pl[i * P + l];
+    reg_col_in<T, N>(x, pl, a, l);
     reg_fft<T, N, +1>(x);
 #pragma unroll
     for (int i = 0; i < N; ++i) x[i] = cscale<T>(x[i], vv[i]);
     reg_fft<T, N, -1>(x);
-#pragma unroll
-    for (int i = 0; i < N; ++i) pl[i * P + l] = x[i];
+    reg_col_out<T, N>(x, pl, a, l);
   }
   __syncthreads();
-  reg_rows<T, N, -1>(planes, pstride, a.nact, tid, [&](int r) { return a.act[r]; });
+  reg_rows<T, N, -1>(planes, pstride, a.nact, tid, [](int r) { return r; });
   __syncthreads();
-  if (live) reg_gather<T, N, false>(sout + so, pl, a.soff, a.S, l);
+  if (live) reg_gather<T, N, false>(sout + so, pl, a.soffc, a.S, l);
 }
 
 // ---------------------------------------------------------------------------
@@ -244,8 +267,8 @@ __global__ __launch_bounds__(kRegPlaneThreads) void k_rl_vu(const cplx<T>* __res
                                                             RegPlaneArgs a, int nplanes,
                                                             const LzDevState* st) {
   if (st && st->status) return;
-  constexpr int NPB = RegPlane<N>::NPB, P = RegPlane<N>::P;
-  constexpr int pstride = N * P;
+  constexpr int NPB = RegPlane<N>::NPB;
+  const int pstride = (a.nact + 1) * RegPlane<N>::P;  // compact planes
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cplx<T>* planes = reinterpret_cast<cplx<T>*>(smem_raw);
   const int tid = threadIdx.x, pp = tid / N, l = tid - pp * N;
@@ -260,13 +283,12 @@ __global__ __launch_bounds__(kRegPlaneThreads) void k_rl_vu(const cplx<T>* __res
 #pragma unroll
     for (int i = 0; i < N; ++i) x[i] = cmul<T>(ub[i * N], vz[i * N]);
     reg_fft<T, N, -1>(x);
-#pragma unroll
-    for (int i = 0; i < N; ++i) pl[i * P + l] = x[i];
+    reg_col_out<T, N>(x, pl, a, l);
   }
   __syncthreads();
-  reg_rows<T, N, -1>(planes, pstride, a.nact, tid, [&](int r) { return a.act[r]; });
+  reg_rows<T, N, -1>(planes, pstride, a.nact, tid, [](int r) { return r; });
   __syncthreads();
-  if (live) reg_gather<T, N, true>(sout + (int64_t)pidx * a.S, pl, a.soff, a.S, l);
+  if (live) reg_gather<T, N, true>(sout + (int64_t)pidx * a.S, pl, a.soffc, a.S, l);
 }
 
 }  // namespace lz
