@@ -482,8 +482,9 @@ LaunchCfg make_cfg(const Instance& I, int gemm, int gsize, int chunk = kProjChun
 //  - projector products on the matrix cores for many bands and rows (or as
 //    asked; the split-bf16 precision always takes them);
 //  - density band groups of about four blocks per compute unit, or on the
-//    register-line kernels one chunk of 192/N bands per block (the block
-//    count is then a multiple of what the compute units hold at once);
+//    register-line kernels up to N = 64 one chunk of 192/N bands per block
+//    (the block count is then a multiple of what the compute units hold at
+//    once);
 // then, for the autotuner, the other projector path (unless one was asked
 // for), groups of twice the bands and, on the vector ALU, dot chunks of 128
 // and 256 plane waves.
@@ -493,9 +494,9 @@ std::vector<LaunchCfg> launch_candidates(const Instance& I, const lz_options& op
   const int gemm0 = I.prec == LZ_FP32_SPLITBF16 ? kGemmBf16x3 : mc ? kGemmMfma : kGemmValu;
   const int rn = I.fp64 ? reg_plane_size<double>(I.grid) : reg_plane_size<float>(I.grid);
   int g0;
-  if (rn) {
+  if (rn && rn <= 64) {
     g0 = 192 / rn;
-  } else {
+  } else {  // LDS kernels, and the lane-pair kernels of 96^2 planes (a band at a time)
     const int ng = std::max(1, std::min(I.nb, (1024 + I.n3 - 1) / I.n3));
     g0 = (I.nb + ng - 1) / ng;
   }
@@ -844,11 +845,11 @@ std::unique_ptr<Instance> build_instance(const lz_system& sys, const lz_options&
   I.grid.si1 = I.si1.as<int>(); I.grid.si2 = I.si2.as<int>(); I.grid.act = I.act.as<int>();
   I.grid.p1 = p1; I.grid.p2 = p2; I.grid.p3 = p3;
   I.grid.tw1 = I.tw1.p; I.grid.tw2 = I.tw2.p; I.grid.tw3 = I.tw3.p;
-  // row tables of the register-line plane kernels (cubic grids up to 64)
+  // row tables of the register-line plane kernels (cubic grids up to 96)
   I.grid.soff_f = nullptr;
   I.grid.soff_c = nullptr;
-  for (int i = 0; i < 64; ++i) I.grid.slot[i] = -1;
-  if (I.n1 == I.n2 && I.n2 == I.n3 && I.n1 <= 64) {
+  for (int i = 0; i < 128; ++i) I.grid.slot[i] = -1;
+  if (I.n1 == I.n2 && I.n2 == I.n3 && I.n1 <= 96) {
     const int pitch = I.n1 + 1;
     for (int a = 0; a < I.nact; ++a) I.grid.slot[act[a]] = (signed char)a;
     std::vector<int> sf(I.S), sc(I.S);

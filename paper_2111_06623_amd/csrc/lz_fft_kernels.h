@@ -689,6 +689,7 @@ int reg_plane_size(const Grid3& g) {
     case 32: return reg_plane_ok<T, 32>() ? 32 : 0;
     case 48: return reg_plane_ok<T, 48>() ? 48 : 0;
     case 64: return reg_plane_ok<T, 64>() ? 64 : 0;
+    case 96: return reg_pair_ok<T>() ? 96 : 0;
     default: return 0;
   }
 }
@@ -702,7 +703,7 @@ static inline RegPlaneArgs reg_args(const Grid3& g) {
   a.soff = g.soff_f;
   a.soffc = g.soff_c;
   a.act = g.act;
-  for (int i = 0; i < 64; ++i) a.slot[i] = g.slot[i];
+  for (int i = 0; i < 128; ++i) a.slot[i] = g.slot[i];
   return a;
 }
 
@@ -791,8 +792,15 @@ template <typename T>
 void LaunchFft<T>::plane_local(const Grid3& g, const void* sin, void* sout, const void* vloc,
                                int nb, const LzDevState* st, hipStream_t s) {
   if (const int n = reg_plane_size<T>(g)) {
-    const int npb = kRegPlaneThreads / n, nplanes = nb * n;
+    const int npb = n == kPairN ? 1 : kRegPlaneThreads / n, nplanes = nb * n;
     const size_t lds = (size_t)npb * (g.nact + 1) * (n + 1) * sizeof(cplx<T>);  // compact planes
+    if constexpr (reg_pair_ok<T>()) {
+      if (n == kPairN) {
+        hipLaunchKernelGGL(k_rp_local<T>, dim3(nplanes), dim3(kRegPlaneThreads), pair_lds<T>(g.nact), s,
+                           (const cplx<T>*)sin, (cplx<T>*)sout, (const T*)vloc, reg_args(g), st);
+        return;
+      }
+    }
     LZ_REG_LAUNCH(k_rl_local, T, n, dim3((nplanes + npb - 1) / npb), lds, s, (const cplx<T>*)sin,
                   (cplx<T>*)sout, (const T*)vloc, reg_args(g), nplanes, st);
     return;
@@ -809,6 +817,15 @@ void LaunchFft<T>::plane_local_density(const Grid3& g, const void* sin, void* so
                                        hipStream_t s) {
   const int ng = (nb + gsize - 1) / gsize;
   if (const int n = reg_plane_size<T>(g)) {
+    if constexpr (reg_pair_ok<T>()) {
+      if (n == kPairN) {
+        hipLaunchKernelGGL(k_rp_density<T>, dim3(g.n3, ng), dim3(kRegPlaneThreads),
+                           pair_lds<T>(g.nact), s,
+                           (const cplx<T>*)sin, (cplx<T>*)sout, (const T*)vloc, (const cplx<T>*)ur,
+                           bandw, (cplx<T>*)dpart, nb, gsize, reg_args(g), st);
+        return;
+      }
+    }
     const int npb = kRegPlaneThreads / n;
     const size_t lds = (size_t)npb * n * (n + 1) * sizeof(cplx<T>);
     LZ_REG_LAUNCH(k_rl_density, T, n, dim3(g.n3, ng), lds, s, (const cplx<T>*)sin,
@@ -833,8 +850,15 @@ template <typename T>
 void LaunchFft<T>::plane_vu(const Grid3& g, const void* ur, const void* vp, void* sout, int nb,
                             const LzDevState* st, hipStream_t s) {
   if (const int n = reg_plane_size<T>(g)) {
-    const int npb = kRegPlaneThreads / n, nplanes = nb * n;
+    const int npb = n == kPairN ? 1 : kRegPlaneThreads / n, nplanes = nb * n;
     const size_t lds = (size_t)npb * (g.nact + 1) * (n + 1) * sizeof(cplx<T>);  // compact planes
+    if constexpr (reg_pair_ok<T>()) {
+      if (n == kPairN) {
+        hipLaunchKernelGGL(k_rp_vu<T>, dim3(nplanes), dim3(kRegPlaneThreads), lds, s,
+                           (const cplx<T>*)ur, (const cplx<T>*)vp, (cplx<T>*)sout, reg_args(g), st);
+        return;
+      }
+    }
     LZ_REG_LAUNCH(k_rl_vu, T, n, dim3((nplanes + npb - 1) / npb), lds, s, (const cplx<T>*)ur,
                   (const cplx<T>*)vp, (cplx<T>*)sout, reg_args(g), nplanes, st);
     return;
@@ -921,6 +945,14 @@ hipError_t enable_large_lds_fft() {
   LZ_REG_ATTR(k_rl_density)
   LZ_REG_ATTR(k_rl_vu)
 #undef LZ_REG_ATTR
+  if constexpr (reg_pair_ok<T>()) {
+    const void* fns[] = {(const void*)k_rp_local<T>, (const void*)k_rp_density<T>,
+                         (const void*)k_rp_vu<T>};
+    for (const void* f : fns) {
+      hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, big);
+      if (e != hipSuccess) return e;
+    }
+  }
   return hipSuccess;
 }
 

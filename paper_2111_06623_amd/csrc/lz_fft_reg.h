@@ -1,5 +1,5 @@
 // Register-resident FFTs of whole lines for the cubic grid lengths of the
-// production workloads (24, 32, 48, 64).  One thread holds one line of N
+// production workloads (24, 32, 48, 64; 96 as a lane pair of 48-point lines).  One thread holds one line of N
 // complex values and transforms it without any data exchange: N = R1 * R2
 // with R1 in {8, 16} and R2 in {3, 4} is split as a Cooley-Tukey pair,
 //   X[k1 + R1 k2] = sum_n2 W_N^{n2 k1} W_R2^{n2 k2} sum_n1 x[R2 n1 + n2] W_R1^{n1 k1},
@@ -101,6 +101,55 @@ __device__ __forceinline__ void reg_fft(cplx<T> (&x)[N]) {
       for (int k2 = 0; k2 < R2; ++k2) x[k1 + R1 * k2] = b[k2];
     }
   }
+}
+
+// Value held by the partner lane (lane ^ 1) of a lane pair (DPP quad
+// permutation [1, 0, 3, 2]; both lanes of a pair are active wherever it is
+// used).
+__device__ __forceinline__ float pair_swap(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xF, 0xF, false));
+}
+template <typename T>
+__device__ __forceinline__ cplx<T> pair_swap(cplx<T> v) {
+  return mk<T>(pair_swap(v.x), pair_swap(v.y));
+}
+
+// Length-N transform shared by a lane pair (h = lane & 1), each lane holding
+// N/2 values: a radix-2 step across the pair and a register transform of
+// length N/2 on each lane.  With E and O the transforms of the even and odd
+// samples, V[k] = E[k] + W^k O[k] and V[k + N/2] = E[k] - W^k O[k].
+//   pair_fft_dit: in x[j] = v[2 j + h], out x[k] = V[h N/2 + k]
+//   pair_fft_dif: in x[k] = v[h N/2 + k], out x[j] = V[2 j + h]
+// The radix-2 step runs in groups of 8 values between scheduling barriers:
+// scheduled freely, all of its temporaries were live at once (228 registers
+// for a forward and an inverse transform against 136).
+template <typename T, int N, int DIR>
+__device__ __forceinline__ void pair_fft_dit(cplx<T> (&x)[N / 2], int h) {
+  constexpr int M = N / 2;
+  reg_fft<T, M, DIR>(x);
+  sfor<0, M>([&](auto kc) {
+    constexpr int k = decltype(kc)::value;
+    if constexpr (k % 8 == 0) __builtin_amdgcn_sched_barrier(0);
+    const cplx<T> t = w192<T, (192 / N) * k, DIR>(x[k]);
+    const cplx<T> own = h ? t : x[k];
+    const cplx<T> other = pair_swap<T>(own);
+    x[k] = h ? csub<T>(other, own) : cadd<T>(own, other);
+  });
+  __builtin_amdgcn_sched_barrier(0);
+}
+
+template <typename T, int N, int DIR>
+__device__ __forceinline__ void pair_fft_dif(cplx<T> (&x)[N / 2], int h) {
+  constexpr int M = N / 2;
+  __builtin_amdgcn_sched_barrier(0);
+  sfor<0, M>([&](auto kc) {
+    constexpr int k = decltype(kc)::value;
+    if constexpr (k % 8 == 0) __builtin_amdgcn_sched_barrier(0);
+    const cplx<T> other = pair_swap<T>(x[k]);
+    const cplx<T> b = w192<T, (192 / N) * k, DIR>(csub<T>(other, x[k]));
+    x[k] = h ? b : cadd<T>(x[k], other);
+  });
+  reg_fft<T, M, DIR>(x);
 }
 
 }  // namespace lz

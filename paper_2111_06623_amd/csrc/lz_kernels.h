@@ -14,7 +14,7 @@ struct RegPlaneArgs {
   const int* soff;        // [S] LDS offset of each stick in a plane (row pitch n + 1)
   const int* soffc;       // [S] the same in a compact plane (active rows only, in act order)
   const int* act;         // [nact] grid row i1 of each stored row
-  signed char slot[64];   // index of grid row i1 in act, -1 when it holds no stick
+  signed char slot[128];  // index of grid row i1 in act, -1 when it holds no stick
 };
 
 // Geometry of the FFT work shared by the kernels of one instance.
@@ -33,7 +33,7 @@ struct Grid3 {
   // register-line plane kernels (cubic grids, see reg_plane_size)
   const int* soff_f;       // [S] LDS offset si1 (n+1) + si2 of each stick
   const int* soff_c;       // [S] LDS offset slot[si1] (n+1) + si2 in a compact plane
-  signed char slot[64];    // index of each grid row i1 in act, or -1
+  signed char slot[128];   // index of each grid row i1 in act, or -1
 };
 
 template <typename T> struct LaunchFft {

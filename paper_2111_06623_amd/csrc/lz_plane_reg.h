@@ -291,4 +291,214 @@ __global__ __launch_bounds__(kRegPlaneThreads) void k_rl_vu(const cplx<T>* __res
   if (live) reg_gather<T, N, true>(sout + (int64_t)pidx * a.S, pl, a.soffc, a.S, l);
 }
 
+// ---------------------------------------------------------------------------
+// 96^2 planes (single precision): one plane per 192-thread block, a lane pair
+// per line (pair_fft_dit / pair_fft_dif: 48 values per lane, a radix-2 step
+// across the pair).  Rows: pair r < nact transforms compact row r in LDS,
+// natural order in and out.  Columns: pair c reads rows 2 j + h of column c,
+// transforms them to real-space rows h 48 + k, applies the pointwise work
+// there, and transforms back to rows 2 j + h.  Compact planes as above.
+// ---------------------------------------------------------------------------
+template <typename T> __host__ __device__ constexpr bool reg_pair_ok() { return sizeof(T) == 4; }
+constexpr int kPairN = 96, kPairM = 48;
+
+template <typename T, int DIR>
+__device__ __forceinline__ void pair_rows(cplx<T>* pl, int nact, int tid) {
+  constexpr int P = kPairN + 1;
+  if (tid < 2 * nact) {
+    const int h = tid & 1;
+    cplx<T>* row = pl + (tid >> 1) * P;
+    cplx<T> x[kPairM];
+#pragma unroll
+    for (int j = 0; j < kPairM; ++j) x[j] = row[2 * j + h];
+    pair_fft_dit<T, kPairN, DIR>(x, h);
+#pragma unroll
+    for (int k = 0; k < kPairM; ++k) row[h * kPairM + k] = x[k];
+  }
+}
+
+// column c of a compact plane, rows 2 j + h in and out (spare row for the
+// rows without a stick)
+template <typename T>
+__device__ __forceinline__ void pair_col_in(cplx<T> (&x)[kPairM], const cplx<T>* pl,
+                                            const RegPlaneArgs& a, int c, int h) {
+  constexpr int P = kPairN + 1;
+#pragma unroll
+  for (int j = 0; j < kPairM; ++j) {
+    const int r = a.slot[2 * j + h];
+    const cplx<T> v = pl[(r >= 0 ? r : a.nact) * P + c];
+    x[j] = r >= 0 ? v : mk<T>(T(0), T(0));
+  }
+}
+template <typename T>
+__device__ __forceinline__ void pair_col_out(const cplx<T> (&x)[kPairM], cplx<T>* pl,
+                                             const RegPlaneArgs& a, int c, int h) {
+  constexpr int P = kPairN + 1;
+#pragma unroll
+  for (int j = 0; j < kPairM; ++j) {
+    const int r = a.slot[2 * j + h];
+    pl[(r >= 0 ? r : a.nact) * P + c] = x[j];
+  }
+}
+
+// sticks of one plane into its compact LDS rows, and back, by all threads
+template <typename T, bool ADD>
+__device__ __forceinline__ void pair_gather(cplx<T>* __restrict__ dst, const cplx<T>* pl,
+                                            const int* __restrict__ soff, int S, int tid) {
+  reg_gather<T, kRegPlaneThreads, ADD>(dst, pl, soff, S, tid);
+}
+
+// Pointwise work f(k, v) on the 48 values of a lane (real-space rows
+// h 48 + k), in two rounds of 24 through a thread-private LDS area [24][192]:
+// the loop over a round stays rolled (U at a time), so its global loads are
+// not scheduled ahead of the transforms, where they held registers.
+constexpr int kPairRound = kPairM / 2;
+template <typename T>
+__host__ __device__ constexpr size_t pair_lds(int nact) {
+  const size_t plane = (size_t)(nact + 1) * (kPairN + 1);
+  const size_t stage = (size_t)kPairRound * kRegPlaneThreads;
+  return (plane > stage ? plane : stage) * sizeof(cplx<T>);
+}
+template <typename T, int U, typename F>
+__device__ __forceinline__ void pair_pointwise(cplx<T> (&x)[kPairM], cplx<T>* stg, int tid, F f) {
+#pragma unroll
+  for (int r = 0; r < 2; ++r) {
+#pragma unroll
+    for (int k = 0; k < kPairRound; ++k) stg[k * kRegPlaneThreads + tid] = x[r * kPairRound + k];
+#pragma unroll U
+    for (int k = 0; k < kPairRound; ++k) {
+      cplx<T>& v = stg[k * kRegPlaneThreads + tid];
+      v = f(r * kPairRound + k, v);
+    }
+#pragma unroll
+    for (int k = 0; k < kPairRound; ++k) x[r * kPairRound + k] = stg[k * kRegPlaneThreads + tid];
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kRegPlaneThreads) void k_rp_local(const cplx<T>* __restrict__ sin,
+                                                               cplx<T>* __restrict__ sout,
+                                                               const T* __restrict__ vloc,
+                                                               RegPlaneArgs a,
+                                                               const LzDevState* st) {
+  if (st && st->status) return;
+  constexpr int N = kPairN, M = kPairM;
+  const int pstride = (a.nact + 1) * (N + 1);
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cplx<T>* pl = reinterpret_cast<cplx<T>*>(smem_raw);
+  const int tid = threadIdx.x, c = tid >> 1, h = tid & 1;
+  const int pidx = blockIdx.x, z = pidx % N;
+  const int64_t so = (int64_t)pidx * a.S;
+  for (int t = tid; t < pstride; t += kRegPlaneThreads) pl[t] = mk<T>(T(0), T(0));
+  __syncthreads();
+  reg_scatter<T, kRegPlaneThreads>(pl, sin + so, a.soffc, a.S, tid);
+  __syncthreads();
+  pair_rows<T, +1>(pl, a.nact, tid);
+  __syncthreads();
+  {
+    const T* vz = vloc + (int64_t)z * N * N + (int64_t)h * M * N + c;
+    cplx<T> x[M];
+    pair_col_in<T>(x, pl, a, c, h);
+    pair_fft_dit<T, N, +1>(x, h);
+    __syncthreads();  // every column read: the plane area becomes staging
+    pair_pointwise<T, 8>(x, pl, tid, [&](int k, cplx<T> v) { return cscale<T>(v, vz[k * N]); });
+    __syncthreads();
+    pair_fft_dif<T, N, -1>(x, h);
+    pair_col_out<T>(x, pl, a, c, h);
+  }
+  __syncthreads();
+  pair_rows<T, -1>(pl, a.nact, tid);
+  __syncthreads();
+  pair_gather<T, false>(sout + so, pl, a.soffc, a.S, tid);
+}
+
+// D+K step on 96^2 planes: the bands of a group one after the other at one z;
+// the density products go straight into the block's slice of the group
+// partial dpart[g][z] (each thread its own elements, in band order).
+template <typename T>
+__global__ __launch_bounds__(kRegPlaneThreads) void k_rp_density(
+    const cplx<T>* __restrict__ sin, cplx<T>* __restrict__ sout, const T* __restrict__ vloc,
+    const cplx<T>* __restrict__ ur, const double* __restrict__ bandw, cplx<T>* __restrict__ dpart,
+    int nb, int gsize, RegPlaneArgs a, const LzDevState* st) {
+  if (st && st->status) return;
+  constexpr int N = kPairN, M = kPairM;
+  const int pstride = (a.nact + 1) * (N + 1);
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cplx<T>* pl = reinterpret_cast<cplx<T>*>(smem_raw);
+  const int tid = threadIdx.x, c = tid >> 1, h = tid & 1;
+  const int z = blockIdx.x, g = blockIdx.y;
+  const int b0 = g * gsize, b1 = min(nb, b0 + gsize);
+  const int64_t roff = (int64_t)h * M * N + c;  // element (row h M, column c) of a plane
+  const T* vz = vloc + (int64_t)z * N * N + roff;
+  cplx<T>* dp = dpart + ((int64_t)g * N + z) * N * N + roff;
+  for (int b = b0; b < b1; ++b) {
+    for (int t = tid; t < pstride; t += kRegPlaneThreads) pl[t] = mk<T>(T(0), T(0));
+    __syncthreads();
+    const int64_t so = ((int64_t)b * N + z) * a.S;
+    reg_scatter<T, kRegPlaneThreads>(pl, sin + so, a.soffc, a.S, tid);
+    __syncthreads();
+    pair_rows<T, +1>(pl, a.nact, tid);
+    __syncthreads();
+    // the column made opaque in each band: the 48 row addresses of the column
+    // are then formed where they are used instead of being held, loop
+    // invariant, through the whole band loop
+    int cb = c;
+    asm volatile("" : "+v"(cb));
+    cplx<T> x[M];
+    pair_col_in<T>(x, pl, a, cb, h);
+    pair_fft_dit<T, N, +1>(x, h);
+    __syncthreads();  // every column read: the plane area becomes staging
+    {
+      const cplx<T>* ub = ur + ((int64_t)b * N + z) * N * N + roff;
+      const T wb = T(bandw[b]);
+      const bool first = b == b0;
+      pair_pointwise<T, 12>(x, pl, tid, [&](int k, cplx<T> v) {
+        const cplx<T> d = cmulc<T>(ub[k * N], v);
+        cplx<T> sacc = first ? mk<T>(T(0), T(0)) : dp[k * N];
+        sacc.x += wb * d.x;
+        sacc.y += wb * d.y;
+        dp[k * N] = sacc;
+        return cscale<T>(v, vz[k * N]);
+      });
+    }
+    __syncthreads();
+    pair_fft_dif<T, N, -1>(x, h);
+    pair_col_out<T>(x, pl, a, cb, h);
+    __syncthreads();
+    pair_rows<T, -1>(pl, a.nact, tid);
+    __syncthreads();
+    pair_gather<T, false>(sout + so, pl, a.soffc, a.S, tid);
+    __syncthreads();
+  }
+}
+
+// v'(r) u_b(r) -> FFT2 -> added to the sticks of the same band, 96^2 planes
+template <typename T>
+__global__ __launch_bounds__(kRegPlaneThreads) void k_rp_vu(const cplx<T>* __restrict__ ur,
+                                                            const cplx<T>* __restrict__ vp,
+                                                            cplx<T>* __restrict__ sout,
+                                                            RegPlaneArgs a,
+                                                            const LzDevState* st) {
+  if (st && st->status) return;
+  constexpr int N = kPairN, M = kPairM;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cplx<T>* pl = reinterpret_cast<cplx<T>*>(smem_raw);
+  const int tid = threadIdx.x, c = tid >> 1, h = tid & 1;
+  const int pidx = blockIdx.x, z = pidx % N;
+  const int64_t roff = (int64_t)h * M * N + c;
+  {
+    const cplx<T>* ub = ur + (int64_t)pidx * N * N + roff;
+    const cplx<T>* vz = vp + (int64_t)z * N * N + roff;
+    cplx<T> x[M];
+#pragma unroll
+    for (int k = 0; k < M; ++k) x[k] = cmul<T>(ub[k * N], vz[k * N]);
+    pair_fft_dif<T, N, -1>(x, h);
+    pair_col_out<T>(x, pl, a, c, h);
+  }
+  __syncthreads();
+  pair_rows<T, -1>(pl, a.nact, tid);
+  __syncthreads();
+  pair_gather<T, true>(sout + (int64_t)pidx * a.S, pl, a.soffc, a.S, tid);
+}
+
 }  // namespace lz
