@@ -496,7 +496,12 @@ std::vector<LaunchCfg> launch_candidates(const Instance& I, const lz_options& op
   int g0;
   if (rn && rn <= 64) {
     g0 = 192 / rn;
-  } else {  // LDS kernels, and the lane-pair kernels of 96^2 planes (a band at a time)
+  } else if (rn) {
+    // lane-pair kernels of 96^2 planes, a band at a time per block: groups of
+    // 8 bands give 96 x N_b/8 blocks, whole rounds of the two per compute unit
+    // for N_b a multiple of 64 (the group partials then take N_b/8 grids)
+    g0 = std::min(I.nb, 8);
+  } else {  // LDS kernels
     const int ng = std::max(1, std::min(I.nb, (1024 + I.n3 - 1) / I.n3));
     g0 = (I.nb + ng - 1) / ng;
   }

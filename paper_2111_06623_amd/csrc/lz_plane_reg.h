@@ -412,6 +412,14 @@ __global__ __launch_bounds__(kRegPlaneThreads) void k_rp_local(const cplx<T>* __
   pair_gather<T, false>(sout + so, pl, a.soffc, a.S, tid);
 }
 
+// A value streamed from memory once (non-temporal: kept out of the caches,
+// which then hold the partial-density slices the density pass re-reads).
+template <typename T>
+__device__ __forceinline__ cplx<T> ld_stream(const cplx<T>* p) {
+  const T* q = reinterpret_cast<const T*>(p);
+  return mk<T>(__builtin_nontemporal_load(q), __builtin_nontemporal_load(q + 1));
+}
+
 // D+K step on 96^2 planes: the bands of a group one after the other at one z;
 // the density products go straight into the block's slice of the group
 // partial dpart[g][z] (each thread its own elements, in band order).
@@ -453,7 +461,7 @@ __global__ __launch_bounds__(kRegPlaneThreads) void k_rp_density(
       const T wb = T(bandw[b]);
       const bool first = b == b0;
       pair_pointwise<T, 12>(x, pl, tid, [&](int k, cplx<T> v) {
-        const cplx<T> d = cmulc<T>(ub[k * N], v);
+        const cplx<T> d = cmulc<T>(ld_stream<T>(ub + k * N), v);
         cplx<T> sacc = first ? mk<T>(T(0), T(0)) : dp[k * N];
         sacc.x += wb * d.x;
         sacc.y += wb * d.y;
