@@ -496,10 +496,12 @@ std::vector<LaunchCfg> launch_candidates(const Instance& I, const lz_options& op
   int g0;
   if (rn && rn <= 64) {
     g0 = 192 / rn;
-  } else if (rn) {
-    // lane-pair kernels of 96^2 planes, a band at a time per block: groups of
-    // 8 bands give 96 x N_b/8 blocks, whole rounds of the two per compute unit
-    // for N_b a multiple of 64 (the group partials then take N_b/8 grids)
+  } else if (rn || I.n3 >= 72) {
+    // a band at a time per block (the lane-pair kernels of 96^2 planes, and
+    // the LDS kernels of large planes, which add into their slice of the
+    // group partial): groups of 8 bands give n3 x N_b/8 blocks, so that the
+    // last round of blocks is not a small remainder of a few long blocks (the
+    // group partials then take N_b/8 grids)
     g0 = std::min(I.nb, 8);
   } else {  // LDS kernels
     const int ng = std::max(1, std::min(I.nb, (1024 + I.n3 - 1) / I.n3));
