@@ -422,9 +422,12 @@ __device__ __forceinline__ cplx<T> ld_stream(const cplx<T>* p) {
 
 // D+K step on 96^2 planes: the bands of a group one after the other at one z;
 // the density products go straight into the block's slice of the group
-// partial dpart[g][z] (each thread its own elements, in band order).
+// partial dpart[g][z] (each thread its own elements, in band order).  Held to
+// 168 registers (three waves per SIMD, four blocks per compute unit, a spill
+// of three values): the pass waits on memory, and 5.3 ms became 3.85 ms on
+// the 96^3 cell against two blocks per unit at 172 registers.
 template <typename T>
-__global__ __launch_bounds__(kRegPlaneThreads) void k_rp_density(
+__global__ __launch_bounds__(kRegPlaneThreads) __attribute__((amdgpu_waves_per_eu(3))) void k_rp_density(
     const cplx<T>* __restrict__ sin, cplx<T>* __restrict__ sout, const T* __restrict__ vloc,
     const cplx<T>* __restrict__ ur, const double* __restrict__ bandw, cplx<T>* __restrict__ dpart,
     int nb, int gsize, RegPlaneArgs a, const LzDevState* st) {
