@@ -1,5 +1,6 @@
 // Plane passes of the Liouvillian application with register-resident line
-// transforms, for cubic grids N^3 with N in {24, 32, 48, 64}, single
+// transforms, for cubic grids N^3 with N in {24, 32, 48, 64} (a line per
+// thread) and N = 96 (a line per lane pair, at the end of this file), single
 // precision (in double precision a line of 48 no longer fits the register
 // file with room to spare, and the LDS-pass kernels are faster).  The 2-D
 // transform of a z-plane of one band (Sec. 2.4: the local potential applied
@@ -8,10 +9,12 @@
 //   columns along i1, one line per thread, where the pointwise work happens
 //   between the inverse and the forward transform without leaving registers;
 //   rows again, forward.
-// A block of 192 threads holds 192/N planes in LDS (row pitch N + 1), so that
-// every access of a column thread has a compile-time offset.  Row tasks of
-// all the planes of a block are packed onto the first threads, so waves
-// without a row idle instead of issuing masked transforms.
+// A block of 192 threads holds 192/N planes in LDS (row pitch N + 1).  The
+// local and v'u passes keep compact planes (the active rows in list order and
+// a spare row); the density pass keeps full planes, in which every access of
+// a column thread has a compile-time offset.  Row tasks of all the planes of
+// a block are packed onto the first threads, so waves without a row idle
+// instead of issuing masked transforms.
 #pragma once
 #include "lz_fft_reg.h"
 #include "lz_kernels.h"
