@@ -295,50 +295,51 @@ __global__ __launch_bounds__(kRegPlaneThreads) void k_rl_vu(const cplx<T>* __res
 }
 
 // ---------------------------------------------------------------------------
-// 96^2 planes (single precision): one plane per 192-thread block, a lane pair
-// per line (pair_fft_dit / pair_fft_dif: 48 values per lane, a radix-2 step
-// across the pair).  Rows: pair r < nact transforms compact row r in LDS,
-// natural order in and out.  Columns: pair c reads rows 2 j + h of column c,
-// transforms them to real-space rows h 48 + k, applies the pointwise work
-// there, and transforms back to rows 2 j + h.  Compact planes as above.
+// 72^2 and 96^2 planes (single precision): one plane per 192-thread block, a
+// lane pair per line (pair_fft_dit / pair_fft_dif: N/2 values per lane, a
+// radix-2 step across the pair).  Rows: pair r < nact transforms compact row
+// r in LDS, natural order in and out.  Columns: pair c < N reads rows 2 j + h
+// of column c, transforms them to real-space rows h N/2 + k, applies the
+// pointwise work there, and transforms back to rows 2 j + h (on 72^2 planes
+// the last 48 threads have no column).  Compact planes as above.
 // ---------------------------------------------------------------------------
 template <typename T> __host__ __device__ constexpr bool reg_pair_ok() { return sizeof(T) == 4; }
-constexpr int kPairN = 96, kPairM = 48;
+template <int N> __host__ __device__ constexpr bool pair_size() { return N == 72 || N == 96; }
 
-template <typename T, int DIR>
+template <typename T, int N, int DIR>
 __device__ __forceinline__ void pair_rows(cplx<T>* pl, int nact, int tid) {
-  constexpr int P = kPairN + 1;
+  constexpr int P = N + 1, M = N / 2;
   if (tid < 2 * nact) {
     const int h = tid & 1;
     cplx<T>* row = pl + (tid >> 1) * P;
-    cplx<T> x[kPairM];
+    cplx<T> x[M];
 #pragma unroll
-    for (int j = 0; j < kPairM; ++j) x[j] = row[2 * j + h];
-    pair_fft_dit<T, kPairN, DIR>(x, h);
+    for (int j = 0; j < M; ++j) x[j] = row[2 * j + h];
+    pair_fft_dit<T, N, DIR>(x, h);
 #pragma unroll
-    for (int k = 0; k < kPairM; ++k) row[h * kPairM + k] = x[k];
+    for (int k = 0; k < M; ++k) row[h * M + k] = x[k];
   }
 }
 
 // column c of a compact plane, rows 2 j + h in and out (spare row for the
 // rows without a stick)
-template <typename T>
-__device__ __forceinline__ void pair_col_in(cplx<T> (&x)[kPairM], const cplx<T>* pl,
+template <typename T, int N>
+__device__ __forceinline__ void pair_col_in(cplx<T> (&x)[N / 2], const cplx<T>* pl,
                                             const RegPlaneArgs& a, int c, int h) {
-  constexpr int P = kPairN + 1;
+  constexpr int P = N + 1;
 #pragma unroll
-  for (int j = 0; j < kPairM; ++j) {
+  for (int j = 0; j < N / 2; ++j) {
     const int r = a.slot[2 * j + h];
     const cplx<T> v = pl[(r >= 0 ? r : a.nact) * P + c];
     x[j] = r >= 0 ? v : mk<T>(T(0), T(0));
   }
 }
-template <typename T>
-__device__ __forceinline__ void pair_col_out(const cplx<T> (&x)[kPairM], cplx<T>* pl,
+template <typename T, int N>
+__device__ __forceinline__ void pair_col_out(const cplx<T> (&x)[N / 2], cplx<T>* pl,
                                              const RegPlaneArgs& a, int c, int h) {
-  constexpr int P = kPairN + 1;
+  constexpr int P = N + 1;
 #pragma unroll
-  for (int j = 0; j < kPairM; ++j) {
+  for (int j = 0; j < N / 2; ++j) {
     const int r = a.slot[2 * j + h];
     pl[(r >= 0 ? r : a.nact) * P + c] = x[j];
   }
@@ -351,66 +352,71 @@ __device__ __forceinline__ void pair_gather(cplx<T>* __restrict__ dst, const cpl
   reg_gather<T, kRegPlaneThreads, ADD>(dst, pl, soff, S, tid);
 }
 
-// Pointwise work f(k, v) on the 48 values of a lane (real-space rows
-// h 48 + k), in two rounds of 24 through a thread-private LDS area [24][192]:
-// the loop over a round stays rolled (U at a time), so its global loads are
-// not scheduled ahead of the transforms, where they held registers.
-constexpr int kPairRound = kPairM / 2;
-template <typename T>
+// Pointwise work f(k, v) on the N/2 values of a lane (real-space rows
+// h N/2 + k), in two rounds of N/4 through a thread-private LDS area
+// [N/4][192]: the loop over a round stays rolled (U at a time), so its global
+// loads are not scheduled ahead of the transforms, where they held registers.
+template <typename T, int N>
 __host__ __device__ constexpr size_t pair_lds(int nact) {
-  const size_t plane = (size_t)(nact + 1) * (kPairN + 1);
-  const size_t stage = (size_t)kPairRound * kRegPlaneThreads;
+  const size_t plane = (size_t)(nact + 1) * (N + 1);
+  const size_t stage = (size_t)(N / 4) * kRegPlaneThreads;
   return (plane > stage ? plane : stage) * sizeof(cplx<T>);
 }
-template <typename T, int U, typename F>
-__device__ __forceinline__ void pair_pointwise(cplx<T> (&x)[kPairM], cplx<T>* stg, int tid, F f) {
+template <typename T, int N, int U, typename F>
+__device__ __forceinline__ void pair_pointwise(cplx<T> (&x)[N / 2], cplx<T>* stg, int tid, F f) {
+  constexpr int RD = N / 4;
 #pragma unroll
   for (int r = 0; r < 2; ++r) {
 #pragma unroll
-    for (int k = 0; k < kPairRound; ++k) stg[k * kRegPlaneThreads + tid] = x[r * kPairRound + k];
+    for (int k = 0; k < RD; ++k) stg[k * kRegPlaneThreads + tid] = x[r * RD + k];
 #pragma unroll U
-    for (int k = 0; k < kPairRound; ++k) {
+    for (int k = 0; k < RD; ++k) {
       cplx<T>& v = stg[k * kRegPlaneThreads + tid];
-      v = f(r * kPairRound + k, v);
+      v = f(r * RD + k, v);
     }
 #pragma unroll
-    for (int k = 0; k < kPairRound; ++k) x[r * kPairRound + k] = stg[k * kRegPlaneThreads + tid];
+    for (int k = 0; k < RD; ++k) x[r * RD + k] = stg[k * kRegPlaneThreads + tid];
   }
 }
 
-template <typename T>
+template <typename T, int N>
 __global__ __launch_bounds__(kRegPlaneThreads) void k_rp_local(const cplx<T>* __restrict__ sin,
                                                                cplx<T>* __restrict__ sout,
                                                                const T* __restrict__ vloc,
                                                                RegPlaneArgs a,
                                                                const LzDevState* st) {
   if (st && st->status) return;
-  constexpr int N = kPairN, M = kPairM;
+  constexpr int M = N / 2;
   const int pstride = (a.nact + 1) * (N + 1);
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cplx<T>* pl = reinterpret_cast<cplx<T>*>(smem_raw);
   const int tid = threadIdx.x, c = tid >> 1, h = tid & 1;
+  const bool col = 2 * N >= kRegPlaneThreads || c < N;  // every thread on 96^2 planes
   const int pidx = blockIdx.x, z = pidx % N;
   const int64_t so = (int64_t)pidx * a.S;
   for (int t = tid; t < pstride; t += kRegPlaneThreads) pl[t] = mk<T>(T(0), T(0));
   __syncthreads();
   reg_scatter<T, kRegPlaneThreads>(pl, sin + so, a.soffc, a.S, tid);
   __syncthreads();
-  pair_rows<T, +1>(pl, a.nact, tid);
+  pair_rows<T, N, +1>(pl, a.nact, tid);
   __syncthreads();
   {
     const T* vz = vloc + (int64_t)z * N * N + (int64_t)h * M * N + c;
     cplx<T> x[M];
-    pair_col_in<T>(x, pl, a, c, h);
-    pair_fft_dit<T, N, +1>(x, h);
+    if (col) {
+      pair_col_in<T, N>(x, pl, a, c, h);
+      pair_fft_dit<T, N, +1>(x, h);
+    }
     __syncthreads();  // every column read: the plane area becomes staging
-    pair_pointwise<T, 8>(x, pl, tid, [&](int k, cplx<T> v) { return cscale<T>(v, vz[k * N]); });
+    if (col) pair_pointwise<T, N, 8>(x, pl, tid, [&](int k, cplx<T> v) { return cscale<T>(v, vz[k * N]); });
     __syncthreads();
-    pair_fft_dif<T, N, -1>(x, h);
-    pair_col_out<T>(x, pl, a, c, h);
+    if (col) {
+      pair_fft_dif<T, N, -1>(x, h);
+      pair_col_out<T, N>(x, pl, a, c, h);
+    }
   }
   __syncthreads();
-  pair_rows<T, -1>(pl, a.nact, tid);
+  pair_rows<T, N, -1>(pl, a.nact, tid);
   __syncthreads();
   pair_gather<T, false>(sout + so, pl, a.soffc, a.S, tid);
 }
@@ -423,26 +429,29 @@ __device__ __forceinline__ cplx<T> ld_stream(const cplx<T>* p) {
   return mk<T>(__builtin_nontemporal_load(q), __builtin_nontemporal_load(q + 1));
 }
 
-// D+K step on 96^2 planes: the bands of a group one after the other at one z;
-// the density products go straight into the block's slice of the group
-// partial dpart[g][z] (each thread its own elements, in band order).  Held to
-// 168 registers (three waves per SIMD, four blocks per compute unit, a spill
-// of three values): the pass waits on memory, and 5.3 ms became 3.85 ms on
-// the 96^3 cell against two blocks per unit at 172 registers.
-template <typename T>
+// D+K step on 72^2 / 96^2 planes: the bands of a group one after the other at
+// one z; the density products go straight into the block's slice of the
+// group partial dpart[g][z] (each thread its own elements, in band order).
+// Held to 168 registers (three waves per SIMD, four blocks per compute unit;
+// a spill of 3 values at 96, of 15 at 72): the pass waits on memory, and
+// 5.3 ms became 3.85 ms on the 96^3 cell against two blocks per unit at 172
+// registers (the batched workload, with its 72^3 members, gained 7 % against
+// the unbounded 181 registers at 72).
+template <typename T, int N>
 __global__ __launch_bounds__(kRegPlaneThreads) __attribute__((amdgpu_waves_per_eu(3))) void k_rp_density(
     const cplx<T>* __restrict__ sin, cplx<T>* __restrict__ sout, const T* __restrict__ vloc,
     const cplx<T>* __restrict__ ur, const double* __restrict__ bandw, cplx<T>* __restrict__ dpart,
     int nb, int gsize, RegPlaneArgs a, const LzDevState* st) {
   if (st && st->status) return;
-  constexpr int N = kPairN, M = kPairM;
+  constexpr int M = N / 2;
   const int pstride = (a.nact + 1) * (N + 1);
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cplx<T>* pl = reinterpret_cast<cplx<T>*>(smem_raw);
   const int tid = threadIdx.x, c = tid >> 1, h = tid & 1;
+  const bool col = 2 * N >= kRegPlaneThreads || c < N;  // every thread on 96^2 planes
   const int z = blockIdx.x, g = blockIdx.y;
   const int b0 = g * gsize, b1 = min(nb, b0 + gsize);
-  const int64_t roff = (int64_t)h * M * N + c;  // element (row h M, column c) of a plane
+  const int64_t roff = (int64_t)h * M * N + (col ? c : 0);  // element (row h M, column c)
   const T* vz = vloc + (int64_t)z * N * N + roff;
   cplx<T>* dp = dpart + ((int64_t)g * N + z) * N * N + roff;
   for (int b = b0; b < b1; ++b) {
@@ -451,22 +460,24 @@ __global__ __launch_bounds__(kRegPlaneThreads) __attribute__((amdgpu_waves_per_e
     const int64_t so = ((int64_t)b * N + z) * a.S;
     reg_scatter<T, kRegPlaneThreads>(pl, sin + so, a.soffc, a.S, tid);
     __syncthreads();
-    pair_rows<T, +1>(pl, a.nact, tid);
+    pair_rows<T, N, +1>(pl, a.nact, tid);
     __syncthreads();
-    // the column made opaque in each band: the 48 row addresses of the column
+    // the column made opaque in each band: the row addresses of the column
     // are then formed where they are used instead of being held, loop
     // invariant, through the whole band loop
     int cb = c;
     asm volatile("" : "+v"(cb));
     cplx<T> x[M];
-    pair_col_in<T>(x, pl, a, cb, h);
-    pair_fft_dit<T, N, +1>(x, h);
+    if (col) {
+      pair_col_in<T, N>(x, pl, a, cb, h);
+      pair_fft_dit<T, N, +1>(x, h);
+    }
     __syncthreads();  // every column read: the plane area becomes staging
-    {
+    if (col) {
       const cplx<T>* ub = ur + ((int64_t)b * N + z) * N * N + roff;
       const T wb = T(bandw[b]);
       const bool first = b == b0;
-      pair_pointwise<T, 12>(x, pl, tid, [&](int k, cplx<T> v) {
+      pair_pointwise<T, N, 12>(x, pl, tid, [&](int k, cplx<T> v) {
         const cplx<T> d = cmulc<T>(ld_stream<T>(ub + k * N), v);
         cplx<T> sacc = first ? mk<T>(T(0), T(0)) : dp[k * N];
         sacc.x += wb * d.x;
@@ -476,41 +487,43 @@ __global__ __launch_bounds__(kRegPlaneThreads) __attribute__((amdgpu_waves_per_e
       });
     }
     __syncthreads();
-    pair_fft_dif<T, N, -1>(x, h);
-    pair_col_out<T>(x, pl, a, cb, h);
+    if (col) {
+      pair_fft_dif<T, N, -1>(x, h);
+      pair_col_out<T, N>(x, pl, a, cb, h);
+    }
     __syncthreads();
-    pair_rows<T, -1>(pl, a.nact, tid);
+    pair_rows<T, N, -1>(pl, a.nact, tid);
     __syncthreads();
     pair_gather<T, false>(sout + so, pl, a.soffc, a.S, tid);
     __syncthreads();
   }
 }
 
-// v'(r) u_b(r) -> FFT2 -> added to the sticks of the same band, 96^2 planes
-template <typename T>
+// v'(r) u_b(r) -> FFT2 -> added to the sticks of the same band, 72^2 / 96^2
+template <typename T, int N>
 __global__ __launch_bounds__(kRegPlaneThreads) void k_rp_vu(const cplx<T>* __restrict__ ur,
                                                             const cplx<T>* __restrict__ vp,
                                                             cplx<T>* __restrict__ sout,
                                                             RegPlaneArgs a,
                                                             const LzDevState* st) {
   if (st && st->status) return;
-  constexpr int N = kPairN, M = kPairM;
+  constexpr int M = N / 2;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cplx<T>* pl = reinterpret_cast<cplx<T>*>(smem_raw);
   const int tid = threadIdx.x, c = tid >> 1, h = tid & 1;
   const int pidx = blockIdx.x, z = pidx % N;
-  const int64_t roff = (int64_t)h * M * N + c;
-  {
+  if (c < N) {
+    const int64_t roff = (int64_t)h * M * N + c;
     const cplx<T>* ub = ur + (int64_t)pidx * N * N + roff;
     const cplx<T>* vz = vp + (int64_t)z * N * N + roff;
     cplx<T> x[M];
 #pragma unroll
     for (int k = 0; k < M; ++k) x[k] = cmul<T>(ub[k * N], vz[k * N]);
     pair_fft_dif<T, N, -1>(x, h);
-    pair_col_out<T>(x, pl, a, c, h);
+    pair_col_out<T, N>(x, pl, a, c, h);
   }
   __syncthreads();
-  pair_rows<T, -1>(pl, a.nact, tid);
+  pair_rows<T, N, -1>(pl, a.nact, tid);
   __syncthreads();
   pair_gather<T, true>(sout + (int64_t)pidx * a.S, pl, a.soffc, a.S, tid);
 }
