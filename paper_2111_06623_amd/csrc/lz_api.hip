@@ -482,7 +482,7 @@ LaunchCfg make_cfg(const Instance& I, int gemm, int gsize, int chunk = kProjChun
 //  - projector products on the matrix cores for many bands and rows (or as
 //    asked; the split-bf16 precision always takes them);
 //  - density band groups of about four blocks per compute unit, or on the
-//    register-line kernels up to N = 64 one chunk of 192/N bands per block
+//    register-line kernels up to N = 48 one chunk of 192/N bands per block
 //    (the block count is then a multiple of what the compute units hold at
 //    once);
 // then, for the autotuner, the other projector path (unless one was asked
@@ -494,7 +494,7 @@ std::vector<LaunchCfg> launch_candidates(const Instance& I, const lz_options& op
   const int gemm0 = I.prec == LZ_FP32_SPLITBF16 ? kGemmBf16x3 : mc ? kGemmMfma : kGemmValu;
   const int rn = I.fp64 ? reg_plane_size<double>(I.grid) : reg_plane_size<float>(I.grid);
   int g0;
-  if (rn && rn <= 64) {
+  if (rn && rn < 64) {
     g0 = 192 / rn;
   } else if (rn || I.n3 >= 72) {
     // a band at a time per block (the lane-pair kernels of 96^2 planes, and

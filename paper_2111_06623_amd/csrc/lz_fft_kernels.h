@@ -688,7 +688,7 @@ int reg_plane_size(const Grid3& g) {
     case 24: return reg_plane_ok<T, 24>() ? 24 : 0;
     case 32: return reg_plane_ok<T, 32>() ? 32 : 0;
     case 48: return reg_plane_ok<T, 48>() ? 48 : 0;
-    case 64: return reg_plane_ok<T, 64>() ? 64 : 0;
+    case 64: return reg_pair_ok<T>() ? 64 : 0;
     case 72: return reg_pair_ok<T>() ? 72 : 0;
     case 96: return reg_pair_ok<T>() ? 96 : 0;
     default: return 0;
@@ -793,11 +793,15 @@ template <typename T>
 void LaunchFft<T>::plane_local(const Grid3& g, const void* sin, void* sout, const void* vloc,
                                int nb, const LzDevState* st, hipStream_t s) {
   if (const int n = reg_plane_size<T>(g)) {
-    const int npb = n > 64 ? 1 : kRegPlaneThreads / n, nplanes = nb * n;
+    const int npb = n >= 64 ? 1 : kRegPlaneThreads / n, nplanes = nb * n;
     const size_t lds = (size_t)npb * (g.nact + 1) * (n + 1) * sizeof(cplx<T>);  // compact planes
     if constexpr (reg_pair_ok<T>()) {
-      if (n > 64) {
-        if (n == 72)
+      if (n >= 64) {
+        if (n == 64)
+          hipLaunchKernelGGL((k_rp_local<T, 64>), dim3(nplanes), dim3(kRegPlaneThreads),
+                             (pair_lds<T, 64>(g.nact)), s, (const cplx<T>*)sin, (cplx<T>*)sout,
+                             (const T*)vloc, reg_args(g), st);
+        else if (n == 72)
           hipLaunchKernelGGL((k_rp_local<T, 72>), dim3(nplanes), dim3(kRegPlaneThreads),
                              (pair_lds<T, 72>(g.nact)), s, (const cplx<T>*)sin, (cplx<T>*)sout,
                              (const T*)vloc, reg_args(g), st);
@@ -825,8 +829,13 @@ void LaunchFft<T>::plane_local_density(const Grid3& g, const void* sin, void* so
   const int ng = (nb + gsize - 1) / gsize;
   if (const int n = reg_plane_size<T>(g)) {
     if constexpr (reg_pair_ok<T>()) {
-      if (n > 64) {
-        if (n == 72)
+      if (n >= 64) {
+        if (n == 64)
+          hipLaunchKernelGGL((k_rp_density<T, 64>), dim3(g.n3, ng), dim3(kRegPlaneThreads),
+                             (pair_lds<T, 64>(g.nact)), s, (const cplx<T>*)sin, (cplx<T>*)sout,
+                             (const T*)vloc, (const cplx<T>*)ur, bandw, (cplx<T>*)dpart, nb,
+                             gsize, reg_args(g), st);
+        else if (n == 72)
           hipLaunchKernelGGL((k_rp_density<T, 72>), dim3(g.n3, ng), dim3(kRegPlaneThreads),
                              (pair_lds<T, 72>(g.nact)), s, (const cplx<T>*)sin, (cplx<T>*)sout,
                              (const T*)vloc, (const cplx<T>*)ur, bandw, (cplx<T>*)dpart, nb,
@@ -863,11 +872,14 @@ template <typename T>
 void LaunchFft<T>::plane_vu(const Grid3& g, const void* ur, const void* vp, void* sout, int nb,
                             const LzDevState* st, hipStream_t s) {
   if (const int n = reg_plane_size<T>(g)) {
-    const int npb = n > 64 ? 1 : kRegPlaneThreads / n, nplanes = nb * n;
+    const int npb = n >= 64 ? 1 : kRegPlaneThreads / n, nplanes = nb * n;
     const size_t lds = (size_t)npb * (g.nact + 1) * (n + 1) * sizeof(cplx<T>);  // compact planes
     if constexpr (reg_pair_ok<T>()) {
-      if (n > 64) {
-        if (n == 72)
+      if (n >= 64) {
+        if (n == 64)
+          hipLaunchKernelGGL((k_rp_vu<T, 64>), dim3(nplanes), dim3(kRegPlaneThreads), lds, s,
+                             (const cplx<T>*)ur, (const cplx<T>*)vp, (cplx<T>*)sout, reg_args(g), st);
+        else if (n == 72)
           hipLaunchKernelGGL((k_rp_vu<T, 72>), dim3(nplanes), dim3(kRegPlaneThreads), lds, s,
                              (const cplx<T>*)ur, (const cplx<T>*)vp, (cplx<T>*)sout, reg_args(g), st);
         else
@@ -963,7 +975,9 @@ hipError_t enable_large_lds_fft() {
   LZ_REG_ATTR(k_rl_vu)
 #undef LZ_REG_ATTR
   if constexpr (reg_pair_ok<T>()) {
-    const void* fns[] = {(const void*)k_rp_local<T, 72>, (const void*)k_rp_density<T, 72>,
+    const void* fns[] = {(const void*)k_rp_local<T, 64>, (const void*)k_rp_density<T, 64>,
+                         (const void*)k_rp_vu<T, 64>,
+                         (const void*)k_rp_local<T, 72>, (const void*)k_rp_density<T, 72>,
                          (const void*)k_rp_vu<T, 72>, (const void*)k_rp_local<T, 96>,
                          (const void*)k_rp_density<T, 96>, (const void*)k_rp_vu<T, 96>};
     for (const void* f : fns) {

@@ -295,16 +295,15 @@ __global__ __launch_bounds__(kRegPlaneThreads) void k_rl_vu(const cplx<T>* __res
 }
 
 // ---------------------------------------------------------------------------
-// 72^2 and 96^2 planes (single precision): one plane per 192-thread block, a
+// 64^2, 72^2 and 96^2 planes (single precision): one plane per 192-thread block, a
 // lane pair per line (pair_fft_dit / pair_fft_dif: N/2 values per lane, a
 // radix-2 step across the pair).  Rows: pair r < nact transforms compact row
 // r in LDS, natural order in and out.  Columns: pair c < N reads rows 2 j + h
 // of column c, transforms them to real-space rows h N/2 + k, applies the
-// pointwise work there, and transforms back to rows 2 j + h (on 72^2 planes
-// the last 48 threads have no column).  Compact planes as above.
+// pointwise work there, and transforms back to rows 2 j + h (on 64^2 and
+// 72^2 planes the last threads have no column).  Compact planes as above.
 // ---------------------------------------------------------------------------
 template <typename T> __host__ __device__ constexpr bool reg_pair_ok() { return sizeof(T) == 4; }
-template <int N> __host__ __device__ constexpr bool pair_size() { return N == 72 || N == 96; }
 
 template <typename T, int N, int DIR>
 __device__ __forceinline__ void pair_rows(cplx<T>* pl, int nact, int tid) {
