@@ -17,6 +17,8 @@
 // the general form driven by runtime plans.  Both run 256 threads per block.
 // Every reduction has a fixed order, so repeated runs are bitwise identical.
 #pragma once
+#include <stdexcept>
+
 #include "lz_fft_ct.h"
 #include "lz_kernels.h"
 #include "lz_plane_reg.h"
@@ -715,7 +717,7 @@ static inline RegPlaneArgs reg_args(const Grid3& g) {
         case 24: hipLaunchKernelGGL((KERN<T, 24>), GRID, dim3(kRegPlaneThreads), LDS, STREAM, __VA_ARGS__); break; \
         case 32: hipLaunchKernelGGL((KERN<T, 32>), GRID, dim3(kRegPlaneThreads), LDS, STREAM, __VA_ARGS__); break; \
         case 48: hipLaunchKernelGGL((KERN<T, 48>), GRID, dim3(kRegPlaneThreads), LDS, STREAM, __VA_ARGS__); break; \
-        default: hipLaunchKernelGGL((KERN<T, 64>), GRID, dim3(kRegPlaneThreads), LDS, STREAM, __VA_ARGS__); break; \
+        default: throw std::logic_error("no line-per-thread plane kernel for this size");                        \
       }                                                                                        \
     }                                                                                          \
   } while (0)
@@ -950,7 +952,7 @@ hipError_t enable_large_lds_fft() {
 #define LZ_REG_ATTR(KERN)                                                                     \
   if constexpr (reg_plane_ok<T, 48>()) {                                                      \
     const void* fns[] = {(const void*)KERN<T, 24>, (const void*)KERN<T, 32>,                  \
-                         (const void*)KERN<T, 48>, (const void*)KERN<T, 64>};                 \
+                         (const void*)KERN<T, 48>};                                           \
     for (const void* f : fns) {                                                               \
       hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, big); \
       if (e != hipSuccess) return e;                                                          \

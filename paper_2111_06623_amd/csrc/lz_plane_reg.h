@@ -31,7 +31,7 @@ template <int N> struct RegPlane {
 
 template <typename T, int N>
 __host__ __device__ constexpr bool reg_plane_ok() {
-  return sizeof(T) == 4 && (N == 24 || N == 32 || N == 48 || N == 64);
+  return sizeof(T) == 4 && (N == 24 || N == 32 || N == 48);
 }
 
 // Row transforms of the planes of a block: task t < NPB * nact is row a of
