@@ -555,6 +555,7 @@ __global__ __launch_bounds__(plane_threads<N>()) void k_hxc_planes_inv(const cpl
 // blocks per pass instead of N plane blocks), i2 and i1 here, z in k_hxc_z.
 // ---------------------------------------------------------------------------
 constexpr int kLineTile = 8;
+constexpr int kSumBatch = 16;  // group partials per round of loads in the first line pass
 
 // n'(r) = sum over band groups (fixed order); forward transform along i2
 template <typename T, int N>
@@ -571,14 +572,37 @@ __global__ __launch_bounds__(256) void k_hxc_l2_fwd(const cplx<T>* __restrict__ 
   const int tid = threadIdx.x;
   const cplx<T>* tw = stick_tw<T, N>(lds, twg, tid);
   const int64_t l0 = (int64_t)blockIdx.x * kLineTile;
-  for (int t = tid; t < kLineTile * N; t += 256) {
-    const int ll = t / N, i = t - ll * N;
-    const int64_t idx = (l0 + ll) * N + i;
-    cplx<T> v = czero<T>();
-#pragma unroll 8
-    for (int g = 0; g < ngroups; ++g) v = cadd<T>(v, dpart[g * NG + idx]);
-    nr[idx] = v;
-    lds[ll * P + i] = v;
+  // a thread's elements (at most EPT) summed over the groups in order, the
+  // loads of kSumBatch groups of every element in flight together
+  constexpr int EPT = (kLineTile * N + 255) / 256;
+  cplx<T> v[EPT];
+  int64_t idx[EPT];
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) {
+    v[e] = czero<T>();
+    const int t = tid + e * 256;
+    idx[e] = t < kLineTile * N ? l0 * N + t : -1;
+  }
+  for (int g0 = 0; g0 < ngroups; g0 += kSumBatch) {
+    cplx<T> u[EPT][kSumBatch];
+#pragma unroll
+    for (int e = 0; e < EPT; ++e)
+#pragma unroll
+      for (int j = 0; j < kSumBatch; ++j)
+        u[e][j] = idx[e] >= 0 && g0 + j < ngroups ? dpart[(g0 + j) * NG + idx[e]] : czero<T>();
+#pragma unroll
+    for (int e = 0; e < EPT; ++e)
+#pragma unroll
+      for (int j = 0; j < kSumBatch; ++j)
+        if (g0 + j < ngroups) v[e] = cadd<T>(v[e], u[e][j]);
+  }
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) {
+    if (idx[e] >= 0) {
+      const int t = tid + e * 256;
+      nr[idx[e]] = v[e];
+      lds[(t / N) * P + t % N] = v[e];
+    }
   }
   __syncthreads();
   ct_fft<T, N, -1, kStickTile>(lds, LayRowsAll<P>{}, kLineTile, tw, tid);
