@@ -874,6 +874,16 @@ void LaunchFft<T>::plane_local_density(const Grid3& g, const void* sin, void* so
         return;
       }
     }
+    if constexpr (reg_plane_ok<T, 48>()) {
+      if (n == 48 && gsize <= 4) {  // one band per lane of a quad
+        const size_t lds = (size_t)4 * (g.nact + 1) * 49 * sizeof(cplx<T>);  // compact planes
+        hipLaunchKernelGGL((k_rq_density<T, 48>), dim3(g.n3, ng), dim3(kRegPlaneThreads), lds, s,
+                           (const cplx<T>*)sin,
+                           (cplx<T>*)sout, (const T*)vloc, (const cplx<T>*)ur, bandw,
+                           (cplx<T>*)dpart, nb, gsize, reg_args(g), st);
+        return;
+      }
+    }
     const int npb = kRegPlaneThreads / n;
     const size_t lds = (size_t)npb * n * (n + 1) * sizeof(cplx<T>);
     LZ_REG_LAUNCH(k_rl_density, T, n, dim3(g.n3, ng), lds, s, (const cplx<T>*)sin,
@@ -999,6 +1009,11 @@ hipError_t enable_large_lds_fft() {
   LZ_REG_ATTR(k_rl_local)
   LZ_REG_ATTR(k_rl_density)
   LZ_REG_ATTR(k_rl_vu)
+  if constexpr (reg_plane_ok<T, 48>()) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_rq_density<T, 48>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, big);
+    if (e != hipSuccess) return e;
+  }
 #undef LZ_REG_ATTR
   if constexpr (reg_pair_ok<T>()) {
     const void* fns[] = {(const void*)k_rp_local<T, 64>, (const void*)k_rp_density<T, 64>,

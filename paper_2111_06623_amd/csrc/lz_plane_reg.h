@@ -261,6 +261,94 @@ __global__ __launch_bounds__(kRegPlaneThreads) void k_rl_density(
 }
 
 // ---------------------------------------------------------------------------
+// D+K step on 48^2 planes for a group of at most four bands, one band per
+// lane of a quad: thread 4 l + pp holds column l of band b0 + pp (compact
+// planes, as k_rl_local).  The density products of the four bands are added
+// across the quad four rows at a time by a reduce-scatter of two lane
+// permutations, after which lane pp holds row i0 + pp of the column, and
+// writes it into the block's slice of the group partial.  Without the
+// products of all N rows staged in LDS for the band sum (full planes, 75 KB)
+// and the barriers around it, a block needs the compact planes only, and the
+// register count stays within three waves per SIMD: four blocks per compute
+// unit against two.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float quad_xor1(float v) {  // the value of lane pp ^ 1
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xF, 0xF, false));
+}
+__device__ __forceinline__ float quad_xor2(float v) {  // the value of lane pp ^ 2
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x4E, 0xF, 0xF, false));
+}
+template <typename T>
+__device__ __forceinline__ cplx<T> quad_xor1(cplx<T> v) { return mk<T>(quad_xor1(v.x), quad_xor1(v.y)); }
+template <typename T>
+__device__ __forceinline__ cplx<T> quad_xor2(cplx<T> v) { return mk<T>(quad_xor2(v.x), quad_xor2(v.y)); }
+
+// p0..p3: this lane's values of rows 0..3.  Returns row pp summed over the
+// quad: the pairs (pp, pp ^ 1) first, then the two pair sums.
+template <typename T>
+__device__ __forceinline__ cplx<T> quad_reduce_scatter(cplx<T> p0, cplx<T> p1, cplx<T> p2,
+                                                       cplx<T> p3, bool odd, bool high) {
+  // the even lane keeps rows 0 and 2, the odd lane rows 1 and 3
+  const cplx<T> r0 = cadd<T>(odd ? p1 : p0, quad_xor1<T>(odd ? p0 : p1));
+  const cplx<T> r1 = cadd<T>(odd ? p3 : p2, quad_xor1<T>(odd ? p2 : p3));
+  // the low lanes keep rows 0 / 1, the high lanes rows 2 / 3
+  return cadd<T>(high ? r1 : r0, quad_xor2<T>(high ? r0 : r1));
+}
+
+template <typename T, int N>
+__global__ __launch_bounds__(kRegPlaneThreads) void k_rq_density(
+    const cplx<T>* __restrict__ sin, cplx<T>* __restrict__ sout, const T* __restrict__ vloc,
+    const cplx<T>* __restrict__ ur, const double* __restrict__ bandw, cplx<T>* __restrict__ dpart,
+    int nb, int gsize, RegPlaneArgs a, const LzDevState* st) {
+  static_assert(RegPlane<N>::NPB == 4 && sizeof(T) == 4, "four single-precision bands per block");
+  if (st && st->status) return;
+  const int pstride = (a.nact + 1) * RegPlane<N>::P;  // compact planes
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cplx<T>* planes = reinterpret_cast<cplx<T>*>(smem_raw);
+  const int tid = threadIdx.x, pp = tid & 3, l = tid >> 2;
+  const bool odd = pp & 1, high = pp & 2;
+  const int z = blockIdx.x, g = blockIdx.y;
+  const int b0 = g * gsize, b = b0 + pp;
+  const bool live = b < min(nb, b0 + gsize);
+  cplx<T>* pl = planes + pp * pstride;
+  for (int t = l; t < pstride; t += N) pl[t] = mk<T>(T(0), T(0));
+  __syncthreads();
+  const int64_t so = ((int64_t)(live ? b : b0) * N + z) * a.S;
+  if (live) reg_scatter<T, N>(pl, sin + so, a.soffc, a.S, l);
+  __syncthreads();
+  reg_rows<T, N, +1>(planes, pstride, a.nact, tid, [](int r) { return r; });
+  __syncthreads();
+  cplx<T> x[N];
+  reg_col_in<T, N>(x, pl, a, l);
+  reg_fft<T, N, +1>(x);
+  {
+    const cplx<T>* ub = ur + ((int64_t)(live ? b : b0) * N + z) * N * N + l;
+    const T* vz = vloc + (int64_t)z * N * N + l;
+    const T wb = live ? T(bandw[b]) : T(0);
+    cplx<T>* o = dpart + (((int64_t)g * N + z) * N + pp) * N + l;  // rows i0 + pp
+#pragma unroll
+    for (int i0 = 0; i0 < N; i0 += 4) {
+      cplx<T> p[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int i = i0 + j;
+        const cplx<T> d = cmulc<T>(ub[i * N], x[i]);
+        p[j] = mk<T>(wb * d.x, wb * d.y);
+        x[i] = cscale<T>(x[i], vz[i * N]);
+      }
+      o[(int64_t)i0 * N] = quad_reduce_scatter<T>(p[0], p[1], p[2], p[3], odd, high);
+    }
+  }
+  // a thread reads and writes only its own column of its own plane
+  reg_fft<T, N, -1>(x);
+  reg_col_out<T, N>(x, pl, a, l);
+  __syncthreads();
+  reg_rows<T, N, -1>(planes, pstride, a.nact, tid, [](int r) { return r; });
+  __syncthreads();
+  if (live) reg_gather<T, N, false>(sout + so, pl, a.soffc, a.S, l);
+}
+
+// ---------------------------------------------------------------------------
 // v'(r) u_b(r) -> FFT2 -> added to the sticks of the same band
 // ---------------------------------------------------------------------------
 template <typename T, int N>
