@@ -223,18 +223,15 @@ __global__ __launch_bounds__(256) void k_zfft_fwd(const cplx<T>* __restrict__ st
   const int tid = threadIdx.x;
   const cplx<T>* tw = stick_tw<T, N, ST>(lds, twg, tid);
   const cplx<T>* sb = sticks + (int64_t)b * n3 * S + s0;
-  for (int t = tid; t < nst * n3; t += 256) {
-    const int z = t / nst, ls = t - z * nst;
-    lds[ls * pitch + z] = sb[(int64_t)z * S + ls];
-  }
-  __syncthreads();
-  stick_fft<T, N, ST>(lds, pitch, pz, nst, tw, tid, -1);
   const int* mp = map + ((int64_t)k * S + s0) * n3;
   const cplx<T>* xb = x + b * xs;
   cplx<T>* yb = y + b * xs;
   const T* kb = kin + (int64_t)k * npwx;
   const T e = T(eps[b]);
   if constexpr (N > 0) {
+    // the map, then x and the kinetic energies it points to, are loaded
+    // before the transform (they do not depend on it): one memory latency
+    // of the chain overlaps the stick loads and the transform
     constexpr int IT = (ST * N + 255) / 256;
     int idx[IT];
     cplx<T> xv[IT];
@@ -244,11 +241,17 @@ __global__ __launch_bounds__(256) void k_zfft_fwd(const cplx<T>* __restrict__ st
       const int t = tid + i * 256;
       idx[i] = t < nst * N ? mp[t] : -1;
     }
+    for (int t = tid; t < nst * n3; t += 256) {
+      const int z = t / nst, ls = t - z * nst;
+      lds[ls * pitch + z] = sb[(int64_t)z * S + ls];
+    }
 #pragma unroll
     for (int i = 0; i < IT; ++i) {
       xv[i] = idx[i] >= 0 ? xb[idx[i]] : czero<T>();
       kv[i] = idx[i] >= 0 ? kb[idx[i]] : T(0);
     }
+    __syncthreads();
+    stick_fft<T, N, ST>(lds, pitch, pz, nst, tw, tid, -1);
 #pragma unroll
     for (int i = 0; i < IT; ++i) {
       const int t = tid + i * 256;
@@ -260,6 +263,12 @@ __global__ __launch_bounds__(256) void k_zfft_fwd(const cplx<T>* __restrict__ st
       }
     }
   } else {
+    for (int t = tid; t < nst * n3; t += 256) {
+      const int z = t / nst, ls = t - z * nst;
+      lds[ls * pitch + z] = sb[(int64_t)z * S + ls];
+    }
+    __syncthreads();
+    stick_fft<T, N, ST>(lds, pitch, pz, nst, tw, tid, -1);
     for (int t = tid; t < nst * n3; t += 256) {
       const int ls = t / n3, z = t - ls * n3;
       const int idx = mp[ls * n3 + z];
