@@ -316,11 +316,13 @@ def test_large_cell_apply_full_size(cfg5r_ref, prec, tol):
     ctx.free()
 
 
-@pytest.mark.parametrize("grid,nbnd,nk", [(40, 8, 2), (72, 8, 1), (64, 16, 1)])
+@pytest.mark.parametrize("grid,nbnd,nk", [(40, 8, 2), (72, 8, 1), (64, 16, 1), (48, 5, 1)])
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 2e-5)])
 def test_uneven_grid_apply(grid, nbnd, nk, prec, tol):
     """Members of the batched workload: runtime-plan grids (40 = 8 x 5,
-    72 = 8 x 9) and the compile-time 64^3 grid."""
+    72 = 8 x 9), the compile-time 64^3 grid, and a 48^3 member of five
+    orbitals, whose density pass has a last band group of one (three idle
+    lanes of each quad in single precision)."""
     lz = _lz()
     s = config_system("uneven", index=grid, grid=grid, nbnd=nbnd, nk=nk)
     print(f"[uneven] {grid} {prec}", flush=True)
