@@ -1,8 +1,8 @@
 // Plane passes of the Liouvillian application with register-resident line
-// transforms, for cubic grids N^3 with N in {24, 32, 48, 64} (a line per
-// thread) and N = 96 (a line per lane pair, at the end of this file), single
-// precision (in double precision a line of 48 no longer fits the register
-// file with room to spare, and the LDS-pass kernels are faster).  The 2-D
+// transforms, single precision, for cubic grids N^3 with N in {24, 32, 48}
+// (a line per thread) and N in {64, 72, 96} (a line per lane pair, at the end
+// of this file); in double precision a line of 48 no longer fits the register
+// file with room to spare, and the LDS-pass kernels are faster.  The 2-D
 // transform of a z-plane of one band (Sec. 2.4: the local potential applied
 // in real space to every response orbital) runs as
 //   rows along i2 (only the rows that hold a stick), one line per thread;
@@ -11,10 +11,12 @@
 //   rows again, forward.
 // A block of 192 threads holds 192/N planes in LDS (row pitch N + 1).  The
 // local and v'u passes keep compact planes (the active rows in list order and
-// a spare row); the density pass keeps full planes, in which every access of
-// a column thread has a compile-time offset.  Row tasks of all the planes of
-// a block are packed onto the first threads, so waves without a row idle
-// instead of issuing masked transforms.
+// a spare row).  The density pass on 48^2 planes (k_rq_density) does too,
+// with the four bands of a block in the lanes of a quad; the general density
+// pass (k_rl_density) keeps full planes, in which every access of a column
+// thread has a compile-time offset.  Row tasks of all the planes of a block
+// are packed onto the first threads, so waves without a row idle instead of
+// issuing masked transforms.
 #pragma once
 #include "lz_fft_reg.h"
 #include "lz_kernels.h"
