@@ -149,39 +149,63 @@ __global__ __launch_bounds__(256) void k_zfft_inv(const cplx<T>* __restrict__ x,
   if (st && st->status) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw);
-  const int n3 = N > 0 ? N : n3_rt;
-  const int b = blockIdx.y;
-  const int k = b / nbnd;
+  const int tid = threadIdx.x;
   constexpr int ST = zpass_tile(N);
   const int s0 = blockIdx.x * ST;
   const int nst = min(ST, S - s0);
-  const int pitch = n3 + 1;
-  const int tid = threadIdx.x;
-  const cplx<T>* tw = stick_tw<T, N, ST>(lds, twg, tid);
-  const cplx<T>* xb = x + b * xs;
-  const int* mp = map + ((int64_t)k * S + s0) * n3;
   if constexpr (N > 0) {
-    // compile-time trip count: every map index, then every gathered value,
-    // is in flight before the first is used
+    // bands 2 j and 2 j + 1 of k-point k (blockIdx.y = k ceil(nbnd / 2) + j)
+    // share the map of the tile: every map index, then the gathered values
+    // of both bands, are in flight before the first is used; the two tiles
+    // (lines [0, ST) and [ST, 2 ST)) go through one transform
+    constexpr int pitch = N + 1;
+    const int hp = (nbnd + 1) / 2;
+    const int k = blockIdx.y / hp, j = 2 * (blockIdx.y - k * hp);
+    const int b = k * nbnd + j;
+    const bool two = j + 1 < nbnd;
+    const cplx<T>* tw = stick_tw<T, N, 2 * ST>(lds, twg, tid);
+    const cplx<T>* xb = x + b * xs;
+    const int* mp = map + ((int64_t)k * S + s0) * N;
     constexpr int IT = (ST * N + 255) / 256;
     int idx[IT];
-    cplx<T> v[IT];
+    cplx<T> v0[IT], v1[IT];
 #pragma unroll
     for (int i = 0; i < IT; ++i) {
       const int t = tid + i * 256;
       idx[i] = t < nst * N ? mp[t] : -1;
     }
 #pragma unroll
-    for (int i = 0; i < IT; ++i) v[i] = idx[i] >= 0 ? xb[idx[i]] : czero<T>();
+    for (int i = 0; i < IT; ++i) {
+      v0[i] = idx[i] >= 0 ? xb[idx[i]] : czero<T>();
+      v1[i] = two && idx[i] >= 0 ? xb[xs + idx[i]] : czero<T>();
+    }
 #pragma unroll
     for (int i = 0; i < IT; ++i) {
       const int t = tid + i * 256;
       if (t < nst * N) {
         const int ls = t / N, z = t - ls * N;
-        lds[ls * pitch + z] = v[i];
+        lds[ls * pitch + z] = v0[i];
+        lds[(ST + ls) * pitch + z] = v1[i];
       }
     }
-  } else {
+    __syncthreads();
+    stick_fft<T, N, 2 * ST>(lds, pitch, pz, ST + nst, tw, tid, +1);
+    cplx<T>* ob = out + (int64_t)b * N * S + s0;
+    for (int t = tid; t < nst * N; t += 256) {
+      const int z = t / nst, ls = t - z * nst;
+      ob[(int64_t)z * S + ls] = lds[ls * pitch + z];
+      if (two) ob[(int64_t)(N + z) * S + ls] = lds[(ST + ls) * pitch + z];
+    }
+    return;
+  }
+  const int n3 = N > 0 ? N : n3_rt;
+  const int b = blockIdx.y;
+  const int k = b / nbnd;
+  const int pitch = n3 + 1;
+  const cplx<T>* tw = stick_tw<T, N, ST>(lds, twg, tid);
+  const cplx<T>* xb = x + b * xs;
+  const int* mp = map + ((int64_t)k * S + s0) * n3;
+  {
     for (int t = tid; t < nst * n3; t += 256) {
       const int ls = t / n3, z = t - ls * n3;
       const int idx = mp[ls * n3 + z];
@@ -806,9 +830,13 @@ template <typename T> static size_t stick_lds(const Grid3& g) {
 template <typename T>
 void LaunchFft<T>::zfft_inv(const Grid3& g, const void* x, int64_t xs, void* sticks,
                             const int* map, int nb, int nbnd, const LzDevState* st, hipStream_t s) {
-  const int tile = zpass_tile(ct_size(g));
-  dim3 grid((g.S + tile - 1) / tile, nb);
-  LZ_STICK_LAUNCH(k_zfft_inv, T, g, grid, stick_lds<T>(g), s, (const cplx<T>*)x, xs,
+  const int n = ct_size(g), tile = zpass_tile(n);
+  // compile-time grids: a block per tile and pair of bands of one k-point
+  const int nks = nb / nbnd;
+  dim3 grid((g.S + tile - 1) / tile, n ? nks * ((nbnd + 1) / 2) : nb);
+  const size_t lds = n ? (size_t)(2 * tile * (g.n3 + 1) + ct_twsize(n)) * sizeof(cplx<T>)
+                       : stick_lds<T>(g);
+  LZ_STICK_LAUNCH(k_zfft_inv, T, g, grid, lds, s, (const cplx<T>*)x, xs,
                   (cplx<T>*)sticks, map, g.S, g.n3, nbnd, g.p3, (const cplx<T>*)g.tw3, st);
 }
 
