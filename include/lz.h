@@ -61,8 +61,9 @@ typedef enum {   /* levels of theory of Sec. 3.2 */
  * Host arrays in double precision, owned by the caller and deep-copied by
  * lz_init (the caller may free them when lz_init returns).
  *
- *  nr        FFT grid N1, N2, N3.  Each N must factor into 2, 3, 5
- *            (2 <= N <= 128, N1*N2 <= 9216).  Grid point (j1,j2,j3) is at
+ *  nr        FFT grid N1 = N2 = N3 (cubic grids only; the transforms of
+ *            other shapes are not validated and are refused).  N must factor
+ *            into 2, 3, 5 with 2 <= N <= 96.  Grid point (j1,j2,j3) is at
  *            r = sum_i (j_i/N_i) a_i, stored at (j1*N2 + j2)*N3 + j3.
  *  at        lattice vectors, rows a1, a2, a3 (bohr).
  *  q         q in Cartesian bohr^-1;  g0: Miller index of G0 (Q = q + G0).
@@ -134,6 +135,13 @@ typedef struct {
                          0 = min(n_inst, 4), 1 = one instance after another; at most 64.
                          Results do not depend on it (bitwise). */
   lz_projector_gemm projector_gemm;  /* results agree to rounding across the choices */
+  int32_t density_group_bands;  /* bands per group of the response-density pass (the groups'
+                                   partial densities are summed in a fixed order):
+                                   0 = the built-in heuristic (or the autotuner's pick),
+                                   n >= 1 = n (clamped to nks * nbnd); fixed, it is not tuned */
+  int32_t projector_chunk;      /* plane waves per partial of the vector-ALU projector dot:
+                                   0 = the heuristic (64; or the autotuner's pick among 64, 128,
+                                   256), or one of 64, 128, 256; fixed, it is not tuned */
 } lz_options;
 
 /*
@@ -278,10 +286,15 @@ lz_status lz_stage_times(lz_ctx *ctx, int32_t inst, double *total_ms, int32_t *c
  * run): the step count and scalar state, the coefficients
  * computed so far and the Lanczos vectors, in a host buffer the caller
  * owns (lz_checkpoint_size bytes; about 3 vectors of the instance, 4 for the
- * non-Hermitian recursion).  Loading into a context of the same system,
+ * non-Hermitian recursion).  The header carries the level of theory and a
+ * 64-bit fingerprint of the operator the recursion ran with (lattice, q, G0,
+ * spheres, orbitals, energies, potentials, the f_xc kernel where TDDFT
+ * reads it, projectors).  Loading into a context of the same operator,
  * precision and algorithm, with max_steps at least the saved step count,
  * continues the recursion bit for bit.  Errors: LZ_ERR_ARG for a small
- * buffer, another system, precision or algorithm, or a corrupt header.  All three synchronise the context's stream.
+ * buffer, another system (a different fingerprint, e.g. the same crystal
+ * at another q), another level of theory, precision or algorithm, or a
+ * corrupt header.  All three synchronise the context's stream.
  */
 lz_status lz_checkpoint_size(lz_ctx *ctx, int32_t inst, uint64_t *bytes);
 lz_status lz_checkpoint_save(lz_ctx *ctx, int32_t inst, void *buf, uint64_t bytes);
@@ -292,17 +305,19 @@ lz_status lz_checkpoint_load(lz_ctx *ctx, int32_t inst, const void *buf, uint64_
  * Sec. 3.1): the lowest sys->nbnd eigenpairs of the Kohn-Sham Hamiltonian
  * H_{k+q} = -1/2 nabla^2 + V_loc + sum_p |beta_p> D_p <beta_p| on every k+q
  * sphere of sys (for the orbitals at k, pass a system with q = 0 and the k
- * spheres as k+q spheres).  Block Davidson with n_extra guard vectors, the
- * Teter-Payne-Allan kinetic preconditioner and Rayleigh-Ritz in the span of
- * the block and its orthonormalised corrections, in double precision on
+ * spheres as k+q spheres).  LOBPCG with a block of nbnd + n_extra vectors,
+ * the Teter-Payne-Allan kinetic preconditioner and Rayleigh-Ritz in the span
+ * of the block, its orthonormalised preconditioned residuals and the
+ * previous search directions, in double precision on
  * device `device`, ordered after `hip_stream`; it stops when every wanted
  * residual norm ||H u - eps u|| is below tol, or after max_iter iterations.
  * The orbital and energy fields of sys (evc_k, evc_kq, et_k, fxc_r) are not
  * read.  Outputs (host): evc_out [nks][nbnd][npwx] complex (caller order of
  * nl_kq, orthonormal, phases arbitrary), et_out [nks][nbnd] ascending,
  * *iterations and *max_residual (either may be NULL).  Synchronous.  Errors:
- * LZ_ERR_ARG for 2 (nbnd + n_extra) > 256, a sphere smaller than nbnd +
- * n_extra, or the lz_init rules on the remaining fields.
+ * LZ_ERR_ARG for 3 (nbnd + n_extra) > 256 (the order of the dense
+ * Rayleigh-Ritz problem), a sphere smaller than nbnd + n_extra, or the
+ * lz_init rules on the remaining fields.
  */
 lz_status lz_ground_state(const lz_system *sys, int32_t n_extra, double tol, int32_t max_iter,
                           int32_t device, void *hip_stream, double *evc_out, double *et_out,

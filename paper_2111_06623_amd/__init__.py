@@ -52,7 +52,8 @@ class LzOptions(ctypes.Structure):
     _fields_ = [("prec", ctypes.c_int), ("approx", ctypes.c_int), ("max_steps", ctypes.c_int32),
                 ("use_graph", ctypes.c_int32), ("autotune", ctypes.c_int32),
                 ("algorithm", ctypes.c_int), ("streams", ctypes.c_int32),
-                ("projector_gemm", ctypes.c_int)]
+                ("projector_gemm", ctypes.c_int), ("density_group_bands", ctypes.c_int32),
+                ("projector_chunk", ctypes.c_int32)]
 
 
 class LzError(RuntimeError):
@@ -172,11 +173,14 @@ def _stream_handle(device):
 
 
 def lz_init(systems, prec="fp64", approx="tddft", max_steps=1000, use_graph=False, autotune=False,
-            device=0, stream=None, algorithm="ph", streams=0, projector_gemm="auto"):
+            device=0, stream=None, algorithm="ph", streams=0, projector_gemm="auto",
+            density_group_bands=0, projector_chunk=0):
     """Create a context for one system or a list of systems; returns a handle.
     algorithm: "ph" (pseudo-Hermitian) or "nh" (non-Hermitian biorthogonal);
     streams: instances stepped side by side (0: the library default);
-    projector_gemm: "auto", "valu" or "mfma" (where the projector products run)."""
+    projector_gemm: "auto", "valu" or "mfma" (where the projector products run);
+    density_group_bands, projector_chunk: fixed launch parameters (0: heuristic
+    or autotuned)."""
     lib = load()
     systems = systems if isinstance(systems, (list, tuple)) else [systems]
     arr = (LzSystem * len(systems))()
@@ -189,7 +193,8 @@ def lz_init(systems, prec="fp64", approx="tddft", max_steps=1000, use_graph=Fals
                     int(max_steps), int(bool(use_graph)), int(bool(autotune)),
                     ALGORITHM[algorithm] if isinstance(algorithm, str) else int(algorithm),
                     int(streams),
-                    GEMM[projector_gemm] if isinstance(projector_gemm, str) else int(projector_gemm))
+                    GEMM[projector_gemm] if isinstance(projector_gemm, str) else int(projector_gemm),
+                    int(density_group_bands), int(projector_chunk))
     out = ctypes.c_void_p()
     hs = _stream_handle(device) if stream is None else ctypes.c_void_p(stream)
     _check(lib.lz_init(arr, len(systems), ctypes.byref(opt), int(device), hs, ctypes.byref(out)))

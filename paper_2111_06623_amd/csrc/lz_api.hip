@@ -189,6 +189,7 @@ struct Instance {
   int nlzblk = 1;              // blocks of the output update (Lanczos partial sums)
   int nlzblk_nl = 1;           // the same for the update over the separable rows only
   int64_t nvec;  // complex elements of one batch
+  uint64_t fingerprint = 0;  // hash of every input the operator depends on (checkpoints)
   Grid3 grid;
   DBuf si1, si2, act, map_kq, map_k, perm, npw_kq;
   DBuf soff_f, soff_c;
@@ -239,6 +240,43 @@ void upload_real(Instance& I, DBuf& d, const std::vector<double>& h) {
 void upload_cplx(Instance& I, DBuf& d, const std::vector<double>& h) {
   if (I.fp64) to_dev_cplx<double>(d, h); else to_dev_cplx<float>(d, h);
 }
+
+// 64-bit fingerprint of the operator's inputs: every 8-byte word of each
+// array is mixed in turn (a multiply-xorshift finaliser per word), with each
+// array's length mixed in first, so that equal inputs give equal values and
+// a changed word changes the value with overwhelming probability.
+struct Fingerprint {
+  uint64_t h = 0x243F6A8885A308D3ull;
+  void word(uint64_t w) {
+    h ^= w;
+    h *= 0xFF51AFD7ED558CCDull;
+    h ^= h >> 33;
+    h *= 0xC4CEB9FE1A85EC53ull;
+    h ^= h >> 29;
+  }
+  template <typename U>
+  void array(const std::vector<U>& v) {
+    word((uint64_t)v.size() * sizeof(U));
+    const size_t nbytes = v.size() * sizeof(U);
+    const unsigned char* b = reinterpret_cast<const unsigned char*>(v.data());
+    size_t i = 0;
+    for (; i + 8 <= nbytes; i += 8) {
+      uint64_t w;
+      std::memcpy(&w, b + i, 8);
+      word(w);
+    }
+    if (i < nbytes) {
+      uint64_t w = 0;
+      std::memcpy(&w, b + i, nbytes - i);
+      word(w);
+    }
+  }
+  void scalar(double x) {
+    uint64_t w;
+    std::memcpy(&w, &x, 8);
+    word(w);
+  }
+};
 
 bool valid_len(int n) {
   if (n < 2 || n > 128) return false;
@@ -507,17 +545,23 @@ std::vector<LaunchCfg> launch_candidates(const Instance& I, const lz_options& op
     const int ng = std::max(1, std::min(I.nb, (1024 + I.n3 - 1) / I.n3));
     g0 = (I.nb + ng - 1) / ng;
   }
-  std::vector<LaunchCfg> c{make_cfg(I, gemm0, g0)};
+  // a group size or a dot chunk the caller fixes replaces the heuristic and is not tuned
+  if (opt.density_group_bands > 0) g0 = opt.density_group_bands;
+  const int ch0 = opt.projector_chunk > 0 ? opt.projector_chunk : kProjChunk;
+  std::vector<LaunchCfg> c{make_cfg(I, gemm0, g0, ch0)};
   if (!opt.autotune) return c;
   std::vector<int> gemms{gemm0};
   if (opt.projector_gemm == LZ_GEMM_AUTO && I.prec != LZ_FP32_SPLITBF16)
     gemms.push_back(gemm0 == kGemmValu ? kGemmMfma : kGemmValu);
+  std::vector<int> sizes{g0}, chunks{ch0};
+  if (opt.density_group_bands == 0) sizes.push_back(2 * g0);
+  if (opt.projector_chunk == 0) chunks = {kProjChunk, 2 * kProjChunk, 4 * kProjChunk};
   for (int gm : gemms)
-    for (int gs : {g0, 2 * g0}) {
+    for (int gs : sizes) {
       if (gs > I.nb && gs != g0) continue;
-      for (int ch : {kProjChunk, 2 * kProjChunk, 4 * kProjChunk}) {
-        if (gm != kGemmValu && ch != kProjChunk) continue;  // the matrix-core dot sizes its own
-        if (gm == gemm0 && gs == g0 && ch == kProjChunk) continue;
+      for (int ch : chunks) {
+        if (gm != kGemmValu && ch != ch0) continue;  // the matrix-core dot sizes its own
+        if (gm == gemm0 && gs == g0 && ch == ch0) continue;
         c.push_back(make_cfg(I, gm, gs, ch));
       }
     }
@@ -602,6 +646,9 @@ std::unique_ptr<Instance> build_instance(const lz_system& sys, const lz_options&
   for (int i = 0; i < 3; ++i)
     if (!valid_len(sys.nr[i])) fail(LZ_ERR_ARG, "nr[" + std::to_string(i) + "] must factor into 2,3,5 and lie in [2,128]");
   I.n1 = sys.nr[0]; I.n2 = sys.nr[1]; I.n3 = sys.nr[2];
+  // only cubic grids are validated against the oracle (every workload here
+  // is cubic); other shapes are refused rather than run unchecked
+  if (I.n1 != I.n2 || I.n2 != I.n3) fail(LZ_ERR_ARG, "the FFT grid must be cubic (N1 = N2 = N3)");
   if (I.n1 * I.n2 > 36 * 256) fail(LZ_ERR_ARG, "N1*N2 exceeds 9216");
   I.N = I.n1 * I.n2 * I.n3;
   if (sys.nks < 1 || sys.nbnd < 1 || sys.nproj < 0 || sys.npwx < 1)
@@ -798,6 +845,31 @@ std::unique_ptr<Instance> build_instance(const lz_system& sys, const lz_options&
         else kh[dst] = 4.0 * M_PI / (qg2 * (double)I.N);
       }
   if (singular && I.approx != LZ_IPA) fail(LZ_ERR_ARG, "q + G = 0 on the grid: the Hartree kernel is singular");
+  // ---- fingerprint of the operator (refuses checkpoints of another one)
+  {
+    Fingerprint f;
+    f.word(((uint64_t)I.n1 << 40) | ((uint64_t)I.n2 << 20) | (uint64_t)I.n3);
+    f.word(((uint64_t)I.nks << 32) | (uint64_t)I.nbnd);
+    f.word(((uint64_t)I.nproj << 32) | (uint64_t)I.npwx);
+    f.word((uint64_t)I.approx);
+    f.scalar(I.omega);
+    f.scalar(I.q2);
+    f.array(perm);
+    f.array(map_kq);
+    f.array(map_k);
+    f.array(kin);
+    f.array(U);
+    f.array(Y);
+    f.array(EK);
+    f.array(VKB);
+    f.array(dkb);
+    f.array(vl);
+    if (I.approx == LZ_TDDFT) f.array(fx);
+    if (I.approx != LZ_IPA) f.array(kh);
+    f.array(std::vector<double>(sys.et_k, sys.et_k + I.nb));
+    f.array(std::vector<double>(sys.wk, sys.wk + I.nks));
+    I.fingerprint = f.h;
+  }
   // ---- plans
   std::vector<double> tr, ti;
   FftPlan p1, p2, p3;
@@ -1015,6 +1087,10 @@ lz_status lz_init(const lz_system* sys, int32_t n_inst, const lz_options* opt, i
     if (opt->projector_gemm != LZ_GEMM_AUTO && opt->projector_gemm != LZ_GEMM_VALU &&
         opt->projector_gemm != LZ_GEMM_MFMA)
       fail(LZ_ERR_ARG, "unknown projector_gemm");
+    if (opt->density_group_bands < 0) fail(LZ_ERR_ARG, "density_group_bands must be >= 0");
+    if (opt->projector_chunk != 0 && opt->projector_chunk != kProjChunk &&
+        opt->projector_chunk != 2 * kProjChunk && opt->projector_chunk != 4 * kProjChunk)
+      fail(LZ_ERR_ARG, "projector_chunk must be 0, 64, 128 or 256");
     int ndev = 0;
     HIPC(hipGetDeviceCount(&ndev));
     if (device < 0 || device >= ndev) fail(LZ_ERR_ARG, "no such device");
@@ -1356,12 +1432,14 @@ lz_status lz_stage_times(lz_ctx* c, int32_t inst, double* total_ms, int32_t* cou
 
 // ---- checkpoint / restart of the recursion state of one instance ----------
 namespace {
-constexpr uint64_t kCkptMagic = 0x4C5A434B50543032ull;  // "LZCKPT02"
+constexpr uint64_t kCkptMagic = 0x4C5A434B50543033ull;  // "LZCKPT03"
 struct CkptHeader {
   uint64_t magic;
   int32_t prec, nks, nbnd, nproj, npwx, n1, n2, n3;
   int32_t step, alg;
   int64_t nvec;
+  int32_t approx, pad;
+  uint64_t fingerprint;  // of the operator's inputs (Instance::fingerprint)
   LzDevState st;
 };
 // pseudo-Hermitian: beta, z and the vectors X0, X1, LW; non-Hermitian: beta,
@@ -1405,6 +1483,8 @@ lz_status lz_checkpoint_save(lz_ctx* c, int32_t inst, void* buf, uint64_t bytes)
     h.prec = I.prec; h.nks = I.nks; h.nbnd = I.nbnd; h.nproj = I.nproj; h.npwx = I.npwx;
     h.n1 = I.n1; h.n2 = I.n2; h.n3 = I.n3; h.step = step; h.nvec = I.nvec;
     h.alg = I.nh ? LZ_NON_HERMITIAN : LZ_PSEUDO_HERMITIAN;
+    h.approx = I.approx;
+    h.fingerprint = I.fingerprint;
     HIPC(hipMemcpy(&h.st, I.st.p, sizeof(LzDevState), hipMemcpyDeviceToHost));
     char* o = static_cast<char*>(buf);
     std::memcpy(o, &h, sizeof(h));
@@ -1442,6 +1522,9 @@ lz_status lz_checkpoint_load(lz_ctx* c, int32_t inst, const void* buf, uint64_t 
       fail(LZ_ERR_ARG, "checkpoint of a different system or precision");
     if (h.alg != (I.nh ? LZ_NON_HERMITIAN : LZ_PSEUDO_HERMITIAN))
       fail(LZ_ERR_ARG, "checkpoint of the other Lanczos algorithm");
+    if (h.approx != I.approx) fail(LZ_ERR_ARG, "checkpoint of another level of theory");
+    if (h.fingerprint != I.fingerprint)
+      fail(LZ_ERR_ARG, "checkpoint of another system (the operator's inputs differ)");
     if (h.step < 0 || h.step > I.max_steps) fail(LZ_ERR_ARG, "checkpoint exceeds max_steps");
     if (bytes < ckpt_bytes(I, h.step)) fail(LZ_ERR_ARG, "checkpoint truncated");
     const char* o = static_cast<const char*>(buf) + sizeof(h);

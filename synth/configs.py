@@ -21,6 +21,9 @@
   micro small cells for brute-force diagonalisation of the explicit Liouvillian.
   free  free electrons (V=0): one closed shell of 7 bands, Gamma only,
         q = (0.1,0,0) b, G0 = (1,0,0).
+  gapless the micro cell with shallow wells, 3 bands and q = b1/2: an empty
+        state at k+q lies below a filled one at k, so the metric of the
+        pseudo-Hermitian recursion is indefinite.
 
 Every instance is a deterministic function of its name; results are cached
 as .npz under $LZ_SYNTH_CACHE (default /tmp/lz_synth_cache).
@@ -158,6 +161,15 @@ def _spec(name: str, **kw) -> dict:
                     q=[0.17, 0.05, -0.03], g0=kw.get("g0", (0, 0, 0)), xc=kw.get("xc", "pz"),
                     kb=dict(radii=radii, dkb=dkb) if use_kb else None,
                     kq_basis=kw.get("kq_basis", "sphere"))
+    if name == "gapless":
+        # the micro geometry with shallow wells, no projectors, three bands and
+        # q = b1/2: the third band at k lies above the fourth band at k+q, so
+        # some transitions have negative energy and the metric diag(D+K, D) is
+        # indefinite (a system without a gap)
+        sp = _spec("micro", nbnd=3, kb=False)
+        sp["depth"] = 1.0
+        sp["q"] = list(0.5 * 2 * np.pi * np.linalg.inv(sp["at"]).T[0])
+        return sp
     if name == "free":
         a = 8.0
         at = np.eye(3) * a

@@ -354,7 +354,9 @@ def _run_jobs(jobs):
     ncpu = min(len(os.sched_getaffinity(0)), 16)
     if big < 2 or ncpu < 2:
         return [_solve_sphere(j) for j in jobs]
-    ctx = mp.get_context("fork")
+    # spawned workers: the caller may already hold a GPU context, which a
+    # forked child must not inherit
+    ctx = mp.get_context("spawn")
     with ctx.Pool(min(ncpu, len(jobs)), initializer=_pool_init) as pool:
         return pool.map(_solve_sphere, jobs, chunksize=1)
 

@@ -106,3 +106,19 @@ def test_ground_state_arguments_checked_before_device_work():
     lib = lz.load()
     assert lib.lz_ground_state(None, 4, 1e-9, 10, 0, None, None, None, None, None) == lz.LZ_ERR_ARG
     assert "null" in lz.lz_last_error()
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+@pytest.mark.parametrize("field,value,word", [("density_group_bands", -1, "density_group_bands"),
+                                              ("projector_chunk", 96, "projector_chunk")])
+def test_fixed_launch_parameters_checked_before_device_work(field, value, word):
+    import paper_2111_06623_amd as lz
+    from synth import config_system
+    lib = lz.load()
+    sysarr, keep = lz.make_system(config_system("micro"))
+    opt = lz.LzOptions(lz.LZ_FP64, 0, 8, 0, 0, 0, 0, 0)
+    setattr(opt, field, value)
+    out = ctypes.c_void_p()
+    assert lib.lz_init(ctypes.byref(sysarr), 1, ctypes.byref(opt), 0, None,
+                       ctypes.byref(out)) == lz.LZ_ERR_ARG
+    assert word in lz.lz_last_error()

@@ -202,14 +202,16 @@ def test_cfg2_first_50_steps_full_size(cfg2_oracle_50, prec, tol):
 
 
 @pytest.mark.parametrize("name", ["cfg1", "cfg2lo", "cfg2"])
-def test_apply_liouvillian_fp32_matches_oracle(name):
+@pytest.mark.parametrize("prec,tol", [("fp32", 2e-5), ("splitbf16", 5e-5)])
+def test_apply_liouvillian_fp32_matches_oracle(name, prec, tol):
     """Single-precision applications (the kernels of the mixed path, at the
-    benchmark grid for cfg2) against the FP64 oracle: 2e-5 of the largest
-    output element."""
+    benchmark grid for cfg2; projector products on the vector ALU or as split
+    bf16 products on the matrix cores) against the FP64 oracle: 2e-5 (5e-5
+    for split bf16) of the largest output element."""
     lz = _lz()
     s = config_system(name)
-    print(f"[apply32] {name}", flush=True)
-    ctx = lz.lz_init(s, prec="fp32", max_steps=8)
+    print(f"[apply32] {name} {prec}", flush=True)
+    ctx = lz.lz_init(s, prec=prec, max_steps=8)
     L = Liouvillian(s)
     p = random_batch(s, 21)
     q = random_batch(s, 22)
@@ -217,9 +219,56 @@ def test_apply_liouvillian_fp32_matches_oracle(name):
     po = torch.zeros_like(qo)
     ctx.apply_liouvillian(_to_dev(q, torch.complex64), _to_dev(p, torch.complex64), qo, po)
     torch.cuda.synchronize()
-    assert _rel(qo.cpu().numpy(), L.apply_D(p)) < 2e-5
-    assert _rel(po.cpu().numpy(), L.apply_DK(q)) < 2e-5
+    assert _rel(qo.cpu().numpy(), L.apply_D(p)) < tol
+    assert _rel(po.cpu().numpy(), L.apply_DK(q)) < tol
     ctx.free()
+
+
+@pytest.fixture(scope="module")
+def cfg2_apply_ref():
+    """The oracle's D p and (D+K) q on the 48^3 benchmark cell."""
+    import oracle.pw as opw
+    opw.FFT_WORKERS = min(len(__import__("os").sched_getaffinity(0)), 16)
+    s = config_system("cfg2")
+    print("[cfg2] oracle applications", flush=True)
+    L = Liouvillian(s)
+    p = random_batch(s, 61)
+    q = random_batch(s, 62)
+    return s, p, q, L.apply_D(p), L.apply_DK(q)
+
+
+def _apply_case(lz, s, p, q, d_ref, dk_ref, prec, tol, **opts):
+    dt = torch.complex128 if prec == "fp64" else torch.complex64
+    ctx = lz.lz_init(s, prec=prec, max_steps=4, **opts)
+    qo = torch.zeros(p.shape, dtype=dt, device="cuda")
+    po = torch.zeros_like(qo)
+    ctx.apply_liouvillian(_to_dev(q, dt), _to_dev(p, dt), qo, po)
+    torch.cuda.synchronize()
+    tuning = ctx.tuning()
+    assert _rel(qo.cpu().numpy(), d_ref) < tol
+    assert _rel(po.cpu().numpy(), dk_ref) < tol
+    ctx.free()
+    return tuning
+
+
+# every launch configuration the autotuner can pick, forced: density band
+# groups of the heuristic size and twice it (4 takes the quad kernel on 48^2
+# single-precision planes, 8 the line kernel), ragged groups (3, 5), and the
+# three plane-wave chunks of the vector-ALU projector dot
+@pytest.mark.parametrize("prec,tol,gsize,chunk,gemm", [
+    ("fp32", 2e-5, 4, 64, "valu"), ("fp32", 2e-5, 8, 64, "valu"), ("fp32", 2e-5, 3, 128, "valu"),
+    ("fp32", 2e-5, 1, 256, "valu"), ("fp32", 2e-5, 16, 64, "mfma"), ("fp32", 2e-5, 5, 64, "mfma"),
+    ("fp64", 1e-12, 6, 64, "valu"), ("fp64", 1e-12, 12, 128, "valu"), ("fp64", 1e-12, 5, 256, "valu"),
+    ("fp64", 1e-12, 6, 64, "mfma")])
+def test_every_launch_candidate_on_the_benchmark_cell(cfg2_apply_ref, prec, tol, gsize, chunk, gemm):
+    lz = _lz()
+    s, p, q, d_ref, dk_ref = cfg2_apply_ref
+    print(f"[candidate] cfg2 {prec} groups of {gsize}, chunk {chunk}, {gemm}", flush=True)
+    got = _apply_case(lz, s, p, q, d_ref, dk_ref, prec, tol, density_group_bands=gsize,
+                      projector_chunk=chunk, projector_gemm=gemm)
+    assert got[0] == gemm and got[1] == gsize
+    if gemm == "valu":
+        assert got[2] == -(-int(s.npwx) // chunk)
 
 
 def test_reset_restarts_the_recursion(cfg1):
@@ -298,7 +347,7 @@ def cfg5r_ref():
 
 
 @pytest.mark.slow
-@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 2e-5)])
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 2e-5), ("splitbf16", 5e-5)])
 def test_large_cell_apply_full_size(cfg5r_ref, prec, tol):
     """Every kernel at the large-cell size (general 96^3 transforms, projector
     products spanning several tiles) against the oracle."""
@@ -314,6 +363,19 @@ def test_large_cell_apply_full_size(cfg5r_ref, prec, tol):
     assert _rel(qo.cpu().numpy(), d_ref) < tol
     assert _rel(po.cpu().numpy(), dk_ref) < tol
     ctx.free()
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("prec,tol,gsize", [("fp32", 2e-5, 16), ("fp32", 2e-5, 5),
+                                            ("fp64", 1e-12, 16), ("fp64", 1e-12, 3)])
+def test_large_cell_density_groups(cfg5r_ref, prec, tol, gsize):
+    """The large cell with density band groups other than the heuristic 8
+    (twice it, and ragged groups whose last one is shorter)."""
+    lz = _lz()
+    s, p, q, d_ref, dk_ref = cfg5r_ref
+    print(f"[cfg5r] {prec} groups of {gsize}", flush=True)
+    got = _apply_case(lz, s, p, q, d_ref, dk_ref, prec, tol, density_group_bands=gsize)
+    assert got[1] == gsize
 
 
 @pytest.mark.parametrize("grid,nbnd,nk", [(40, 8, 2), (72, 8, 1), (64, 16, 1), (48, 5, 1)])

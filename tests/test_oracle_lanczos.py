@@ -236,3 +236,38 @@ def test_nonhermitian_recursion_amplifies_rounding(cfg1):
     ph = loss_change(lanczos.pseudo_hermitian_lanczos, False)
     nh = loss_change(lanczos.nonhermitian_lanczos, True)
     assert nh > 100 * ph
+
+
+def test_gapless_system_is_not_positive_definite():
+    """Without a gap (an empty state at k+q below a filled one at k) some
+    transition energies are negative, D is indefinite and so is the metric
+    diag(D+K, D) of the pseudo-Hermitian recursion (Sec. 2.5): the recursion
+    must stop with not_pd, and the explicit-matrix recursion agrees."""
+    s = config_system("gapless")
+    b = Brute(s, "tddft")
+    assert b.transition_basis().dE.min() < -0.05
+    L = Liouvillian(s, "tddft")
+    r = lanczos.run(L, 300)
+    assert r.status == "not_pd"
+    assert 2 < r.steps < 300
+    D, K, _ = b.explicit_operators()
+    assert np.linalg.eigvalsh(0.5 * (D + D.conj().T)).min() < 0
+    w = np.concatenate([[s.wk[k]] * (s.nbnd * int(s.npw_kq[k])) for k in range(s.nks)])
+    pcs = []
+    for k in range(s.nks):
+        u = L.u_kq[k]
+        pcs.append(np.eye(u.shape[1]) - u.T @ u.conj())
+
+    def project(v):
+        out, o = [], 0
+        for k in range(s.nks):
+            npw = int(s.npw_kq[k])
+            for _ in range(s.nbnd):
+                out.append(pcs[k] @ v[o:o + npw])
+                o += npw
+        return np.concatenate(out)
+    r_mat = lanczos.pseudo_hermitian_lanczos(
+        lambda v: D @ v, lambda v: (D + K) @ v, lambda a, c: complex(np.sum(w * np.conj(a) * c)),
+        b.flatten(L.rhs()), 300, project=project, y_scale=float(s.nbnd))
+    assert r_mat.status == "not_pd" and r_mat.steps == r.steps
+    assert np.abs(r_mat.beta - r.beta).max() < 1e-9 * np.abs(r.beta).max()
