@@ -254,6 +254,23 @@ lz_status lz_spectrum_ext(lz_ctx *ctx, int32_t inst, int32_t m0, int32_t m,
                           int32_t extrapolation, const double *omega, int32_t n_omega,
                           double eta, double *chi, double *eps_inv, double *loss);
 
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * result as lz_spectrum_ext, bit for bit, with the same arguments and
+ * errors, but no device allocation.  The frequency grid, the outputs and the
+ * extrapolation tail are staged through a fixed device area of 3.1 MB per
+ * device that the library holds from the first lz_init on that device until
+ * the process ends.  Limit: n_omega <= 65536 (LZ_ERR_ARG beyond).  Every
+ * call on one device shares that area: calls that overlap on one device
+ * (from several threads, or on contexts whose streams run concurrently)
+ * race and must be serialised by the caller.  Synchronises the context's
+ * stream.
+ */
+lz_status lz_spectrum_ext_noalloc(lz_ctx *ctx, int32_t inst, int32_t m0, int32_t m,
+                                  int32_t extrapolation, const double *omega, int32_t n_omega,
+                                  double eta, double *chi, double *eps_inv, double *loss);
+
 /* Launch configuration of instance inst (after autotuning, if asked for):
  * where its projector products run (LZ_GEMM_VALU or LZ_GEMM_MFMA; the
  * split-bf16 precision reports LZ_GEMM_MFMA), the bands per group of its

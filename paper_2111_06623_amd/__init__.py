@@ -97,6 +97,9 @@ def load(path: str = LIB_PATH):
                                 ctypes.c_double, _dp, _dp, _dp]
     lib.lz_spectrum_ext.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                     _dp, ctypes.c_int32, ctypes.c_double, _dp, _dp, _dp]
+    lib.lz_spectrum_ext_noalloc.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                            ctypes.c_int32, _dp, ctypes.c_int32, ctypes.c_double,
+                                            _dp, _dp, _dp]
     lib.lz_checkpoint_size.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_uint64)]
     lib.lz_checkpoint_save.argtypes = [vp, ctypes.c_int32, vp, ctypes.c_uint64]
     lib.lz_checkpoint_load.argtypes = [vp, ctypes.c_int32, vp, ctypes.c_uint64]
@@ -109,7 +112,7 @@ def load(path: str = LIB_PATH):
     for f in ("lz_init", "lz_apply_liouvillian", "lz_step", "lz_get_coefficients", "lz_get_gamma",
               "lz_get_tuning", "lz_ground_state",
               "lz_get_state",
-              "lz_spectrum", "lz_spectrum_ext", "lz_checkpoint_size", "lz_checkpoint_save",
+              "lz_spectrum", "lz_spectrum_ext", "lz_spectrum_ext_noalloc", "lz_checkpoint_size", "lz_checkpoint_save",
               "lz_checkpoint_load", "lz_get_rhs", "lz_reset", "lz_stage_timer", "lz_stage_times", "lz_free"):
         getattr(lib, f).restype = ctypes.c_int
     if path == LIB_PATH:
@@ -306,6 +309,23 @@ class Context:
         _check(lib.lz_spectrum_ext(self.handle, int(inst), int(m), mt, scheme, _ptr(omega, _dp),
                                    len(omega), float(eta), _ptr(chi, _dp), _ptr(einv, _dp),
                                    _ptr(loss, _dp)))
+        return chi.view(np.complex128), einv.view(np.complex128), loss
+
+    def spectrum_noalloc(self, omega, eta, m=None, inst=0, m_total=None, extrapolation="no"):
+        """As spectrum(), through lz_spectrum_ext_noalloc (no device allocation;
+        at most 65536 frequencies)."""
+        lib = load()
+        omega = _f64(omega)
+        if m is None:
+            m = self.state(inst)[0]
+        scheme = EXTRAPOLATION[extrapolation] if isinstance(extrapolation, str) else int(extrapolation)
+        mt = int(m if m_total is None else m_total)
+        chi = np.zeros(2 * len(omega))
+        einv = np.zeros(2 * len(omega))
+        loss = np.zeros(len(omega))
+        _check(lib.lz_spectrum_ext_noalloc(self.handle, int(inst), int(m), mt, scheme,
+                                           _ptr(omega, _dp), len(omega), float(eta),
+                                           _ptr(chi, _dp), _ptr(einv, _dp), _ptr(loss, _dp)))
         return chi.view(np.complex128), einv.view(np.complex128), loss
 
     def tuning(self, inst=0):

@@ -8,6 +8,7 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <unordered_map>
 #include <vector>
@@ -17,6 +18,15 @@
 #include "lz_kernels.h"
 
 using namespace lz;
+
+// Staging area of lz_spectrum_ext_noalloc, one copy per device for the life of
+// the process: the frequency grid, then chi, eps^-1 and the loss, then the two
+// tail means of the extrapolation.  Host code never names it in a kernel
+// argument or a copy; it uses the device address that hipGetSymbolAddress
+// returns for the current device (scratch_address).
+constexpr int kNoallocMaxOmega = 65536;
+constexpr size_t kScratchDoubles = 6 * (size_t)kNoallocMaxOmega + 32;
+static __device__ __align__(256) double scratch[kScratchDoubles];
 
 namespace {
 
@@ -987,6 +997,7 @@ std::unique_ptr<Instance> build_instance(const lz_system& sys, const lz_options&
 
 struct lz_ctx {
   int device = 0;
+  double* scratch = nullptr;  // device address of this device's staging area
   hipStream_t user = nullptr;
   hipStream_t stream = nullptr;
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
@@ -1036,6 +1047,22 @@ lz_status guarded(F&& f) {
     g_last_error = "unknown failure";
     return LZ_ERR_HIP;
   }
+}
+
+// Device address of the staging area on the current device, looked up once
+// per device (the first lz_init on it) and kept until the process ends.
+double* scratch_address(int device) {
+  static std::mutex mu;
+  static double* addr[64] = {nullptr};
+  if (device < 0 || device >= 64) fail(LZ_ERR_ARG, "device index beyond 63");
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[device]) {
+    void* p = nullptr;
+    HIPC(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) fail(LZ_ERR_HIP, "no device address for the staging area");
+    addr[device] = static_cast<double*>(p);
+  }
+  return addr[device];
 }
 
 void start_recursion(lz_ctx* c) {
@@ -1097,6 +1124,7 @@ lz_status lz_init(const lz_system* sys, int32_t n_inst, const lz_options* opt, i
     HIPC(hipSetDevice(device));
     auto c = std::make_unique<lz_ctx>();
     c->device = device;
+    c->scratch = scratch_address(device);
     c->opt = *opt;
     c->user = (hipStream_t)hip_stream;
     HIPC(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
@@ -1389,6 +1417,46 @@ lz_status lz_spectrum_ext(lz_ctx* c, int32_t inst, int32_t m0, int32_t m,
 lz_status lz_spectrum(lz_ctx* c, int32_t inst, int32_t m, const double* omega, int32_t n_omega,
                       double eta, double* chi, double* eps_inv, double* loss) {
   return lz_spectrum_ext(c, inst, m, m, LZ_EXTRAP_NONE, omega, n_omega, eta, chi, eps_inv, loss);
+}
+
+lz_status lz_spectrum_ext_noalloc(lz_ctx* c, int32_t inst, int32_t m0, int32_t m,
+                                  int32_t extrapolation, const double* omega, int32_t n_omega,
+                                  double eta, double* chi, double* eps_inv, double* loss) {
+  return guarded([&] {
+    if (!c || inst < 0 || inst >= (int)c->inst.size()) fail(LZ_ERR_ARG, "bad context or instance");
+    if (n_omega < 0 || (n_omega > 0 && !omega)) fail(LZ_ERR_ARG, "bad frequency grid");
+    if (n_omega > kNoallocMaxOmega) fail(LZ_ERR_ARG, "n_omega exceeds 65536 (the staging area)");
+    if (!(eta > 0)) fail(LZ_ERR_ARG, "eta must be > 0");
+    if (extrapolation != LZ_EXTRAP_NONE && extrapolation != LZ_EXTRAP_CONSTANT &&
+        extrapolation != LZ_EXTRAP_OSC)
+      fail(LZ_ERR_ARG, "unknown extrapolation scheme");
+    if (extrapolation == LZ_EXTRAP_NONE) m = m0;
+    if (m < m0) fail(LZ_ERR_ARG, "m must be >= m0");
+    if (m > m0 && m0 < 4) fail(LZ_ERR_ARG, "extrapolation needs at least 4 computed coefficients");
+    HIPC(hipSetDevice(c->device));
+    Instance& I = *c->inst[inst];
+    // the completed steps, read without the stage-timer bookkeeping
+    HIPC(hipStreamSynchronize(c->stream));
+    LzDevState h;
+    HIPC(hipMemcpy(&h, I.st.p, sizeof(h), hipMemcpyDeviceToHost));
+    if (m0 < 0 || m0 > h.step) fail(LZ_ERR_STATE, "m0 exceeds the completed steps");
+    if (I.nh && m > m0) fail(LZ_ERR_ARG, "extrapolation is defined for the pseudo-Hermitian recursion only");
+    if (n_omega == 0) return;
+    double* dw = c->scratch;
+    double* dchi = dw + n_omega;
+    double* dei = dchi + 2 * (size_t)n_omega;
+    double* dl = dei + 2 * (size_t)n_omega;
+    double* dtail = c->scratch + 6 * (size_t)kNoallocMaxOmega;
+    HIPC(hipMemcpyAsync(dw, omega, n_omega * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    launch_spectrum_dev_tail(I.beta.as<double>(), I.nh ? I.gam.as<double>() : nullptr,
+                             I.z.as<double>(), m0, m, extrapolation == LZ_EXTRAP_OSC, dtail, dw,
+                             n_omega, eta, I.pref, I.fq, dchi, dei, dl, c->stream);
+    HIPC(hipGetLastError());
+    HIPC(hipStreamSynchronize(c->stream));
+    if (chi) HIPC(hipMemcpy(chi, dchi, 2 * n_omega * sizeof(double), hipMemcpyDeviceToHost));
+    if (eps_inv) HIPC(hipMemcpy(eps_inv, dei, 2 * n_omega * sizeof(double), hipMemcpyDeviceToHost));
+    if (loss) HIPC(hipMemcpy(loss, dl, n_omega * sizeof(double), hipMemcpyDeviceToHost));
+  });
 }
 
 lz_status lz_get_rhs(lz_ctx* c, int32_t inst, void* y_out) {

@@ -121,6 +121,13 @@ void launch_spectrum(const double* beta, const double* gam, const double* z, int
                      double tail_even, double tail_odd, const double* omega, int nw, double eta,
                      double pref, double fq, double* chi, double* einv, double* loss,
                      hipStream_t s);
+// the same with the tail means (beta beyond m0) computed on the device into
+// tail[2] from the first m0 coefficients ('osc': per index parity); no host
+// round trip
+void launch_spectrum_dev_tail(const double* beta, const double* gam, const double* z, int m0,
+                              int m, int osc, double* tail, const double* omega, int nw,
+                              double eta, double pref, double fq, double* chi, double* einv,
+                              double* loss, hipStream_t s);
 // non-Hermitian recursion: ||y||^2 partials (kNhNormBlocks x 4) and the
 // scalar decisions of one step
 constexpr int kNhNormBlocks = 256;

@@ -705,6 +705,7 @@ __global__ __launch_bounds__(256) void k_spectrum(const double* __restrict__ bet
                                                   const double* __restrict__ gam,
                                                   const double* __restrict__ z, int m0, int m,
                                                   double tail_even, double tail_odd,
+                                                  const double* __restrict__ tail,
                                                   const double* __restrict__ omega, int nw,
                                                   double eta, double pref, double fq,
                                                   double* __restrict__ chi,
@@ -712,6 +713,10 @@ __global__ __launch_bounds__(256) void k_spectrum(const double* __restrict__ bet
                                                   double* __restrict__ loss) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nw) return;
+  if (tail) {  // the tail means computed on the device (k_tail_means)
+    tail_even = tail[0];
+    tail_odd = tail[1];
+  }
   auto bet = [&](int k) {  // beta_k, 1-based
     return k <= m0 ? beta[k - 1] : ((k & 1) ? tail_odd : tail_even);
   };
@@ -736,6 +741,30 @@ __global__ __launch_bounds__(256) void k_spectrum(const double* __restrict__ bet
   einv[2 * i] = 1.0 + fq * ch.x;
   einv[2 * i + 1] = fq * ch.y;
   loss[i] = -fq * ch.y;
+}
+
+// Tail of the extrapolated tridiagonal matrix (Sec. 3.3): the mean of
+// beta_lo..beta_m0 with lo = max(2, m0/2 + 1), over all of them ('constant')
+// or over those of each index parity ('osc').  One thread adds in index
+// order, the order of the host form in lz_spectrum_ext, so both give the
+// same bits.  out[0] is the value for even indices, out[1] for odd ones.
+__global__ void k_tail_means(const double* __restrict__ beta, int m0, int osc,
+                             double* __restrict__ out) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  const int lo = m0 / 2 + 1 > 2 ? m0 / 2 + 1 : 2;
+  double sum[2] = {0.0, 0.0}, all = 0.0;
+  int cnt[2] = {0, 0};
+  for (int k = lo; k <= m0; ++k) {
+    sum[k & 1] += beta[k - 1];
+    cnt[k & 1] += 1;
+    all += beta[k - 1];
+  }
+  if (osc) {
+    out[0] = sum[0] / cnt[0];
+    out[1] = sum[1] / cnt[1];
+  } else {
+    out[0] = out[1] = all / (cnt[0] + cnt[1]);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -955,7 +984,16 @@ void launch_spectrum(const double* beta, const double* gam, const double* z, int
                      double pref, double fq, double* chi, double* einv, double* loss,
                      hipStream_t s) {
   hipLaunchKernelGGL(k_spectrum, dim3((nw + 63) / 64), dim3(64), 0, s, beta, gam, z, m0, m,
-                     tail_even, tail_odd, omega, nw, eta, pref, fq, chi, einv, loss);
+                     tail_even, tail_odd, nullptr, omega, nw, eta, pref, fq, chi, einv, loss);
+}
+
+void launch_spectrum_dev_tail(const double* beta, const double* gam, const double* z, int m0,
+                              int m, int osc, double* tail, const double* omega, int nw,
+                              double eta, double pref, double fq, double* chi, double* einv,
+                              double* loss, hipStream_t s) {
+  if (m > m0) hipLaunchKernelGGL(k_tail_means, dim3(1), dim3(64), 0, s, beta, m0, osc, tail);
+  hipLaunchKernelGGL(k_spectrum, dim3((nw + 63) / 64), dim3(64), 0, s, beta, gam, z, m0, m, 0.0,
+                     0.0, m > m0 ? tail : nullptr, omega, nw, eta, pref, fq, chi, einv, loss);
 }
 
 template <typename T>

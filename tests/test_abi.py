@@ -122,3 +122,11 @@ def test_fixed_launch_parameters_checked_before_device_work(field, value, word):
     assert lib.lz_init(ctypes.byref(sysarr), 1, ctypes.byref(opt), 0, None,
                        ctypes.byref(out)) == lz.LZ_ERR_ARG
     assert word in lz.lz_last_error()
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_noalloc_spectrum_checks_arguments_before_device_work():
+    import paper_2111_06623_amd as lz
+    lib = lz.load()
+    assert lib.lz_spectrum_ext_noalloc(None, 0, 1, 1, 0, None, 1, 0.01, None, None,
+                                       None) == lz.LZ_ERR_ARG
