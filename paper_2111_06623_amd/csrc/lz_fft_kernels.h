@@ -944,6 +944,18 @@ void LaunchFft<T>::plane_to_real(const Grid3& g, const void* sin, void* rout, in
 template <typename T>
 void LaunchFft<T>::plane_vu(const Grid3& g, const void* ur, const void* vp, void* sout, int nb,
                             const LzDevState* st, hipStream_t s) {
+  if constexpr (rp_ok<T, 48>()) {
+    // double precision on 48^2 planes: lane pairs (77.5 us against 86.9 for the
+    // LDS pass on the 48^3 cell; the local and density passes stay on LDS,
+    // where their lane-pair forms were slower: 125 and 377 us against 110 and
+    // 164)
+    if (ct_size(g) == 48 && g.soff_c) {
+      hipLaunchKernelGGL((k_rp_vu<T, 48>), dim3(nb * 48), dim3(rp_threads<T, 48>()),
+                         (size_t)(g.nact + 1) * 49 * sizeof(cplx<T>), s, (const cplx<T>*)ur,
+                         (const cplx<T>*)vp, (cplx<T>*)sout, reg_args(g), st);
+      return;
+    }
+  }
   if (const int n = reg_plane_size<T>(g)) {
     const int npb = n >= 64 ? 1 : kRegPlaneThreads / n, nplanes = nb * n;
     const size_t lds = (size_t)npb * (g.nact + 1) * (n + 1) * sizeof(cplx<T>);  // compact planes
@@ -1052,6 +1064,13 @@ hipError_t enable_large_lds_fft() {
     if (e != hipSuccess) return e;
   }
 #undef LZ_REG_ATTR
+  if constexpr (rp_ok<T, 48>()) {
+    const void* fns[] = {(const void*)k_rp_vu<T, 48>};
+    for (const void* f : fns) {
+      hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, big);
+      if (e != hipSuccess) return e;
+    }
+  }
   if constexpr (reg_pair_ok<T>()) {
     const void* fns[] = {(const void*)k_rp_local<T, 64>, (const void*)k_rp_density<T, 64>,
                          (const void*)k_rp_vu<T, 64>,

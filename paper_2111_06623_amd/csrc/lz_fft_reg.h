@@ -175,6 +175,13 @@ __device__ __forceinline__ void reg_fft(cplx<T> (&x)[N]) {
 __device__ __forceinline__ float pair_swap(float v) {
   return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xF, 0xF, false));
 }
+__device__ __forceinline__ double pair_swap(double v) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)b, 0xB1, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), 0xB1, 0xF, 0xF, false);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) |
+                                          (unsigned long long)(unsigned)lo));
+}
 template <typename T>
 __device__ __forceinline__ cplx<T> pair_swap(cplx<T> v) {
   return mk<T>(pair_swap(v.x), pair_swap(v.y));

@@ -1,8 +1,9 @@
 // Plane passes of the Liouvillian application with register-resident line
 // transforms, single precision, for cubic grids N^3 with N in {24, 32, 48}
 // (a line per thread) and N in {64, 72, 96} (a line per lane pair, at the end
-// of this file); in double precision a line of 48 no longer fits the register
-// file with room to spare, and the LDS-pass kernels are faster.  The 2-D
+// of this file); in double precision a line of 48 does not fit the register
+// file with room to spare: the v'u pass on 48^2 planes takes lane pairs, the
+// local and density passes keep the LDS-pass kernels, which were faster.  The 2-D
 // transform of a z-plane of one band (Sec. 2.4: the local potential applied
 // in real space to every response orbital) runs as
 //   rows along i2 (only the rows that hold a stick), one line per thread;
@@ -395,6 +396,16 @@ __global__ __launch_bounds__(kRegPlaneThreads) void k_rl_vu(const cplx<T>* __res
 // ---------------------------------------------------------------------------
 template <typename T> __host__ __device__ constexpr bool reg_pair_ok() { return sizeof(T) == 4; }
 
+// Double precision on 48^2 planes takes lane pairs too in the v'u pass (24
+// values per lane, the register footprint of a single-precision 48-point
+// line), one plane per block of 96 threads so that every thread has a column.
+template <typename T, int N> __host__ __device__ constexpr bool rp_ok() {
+  return sizeof(T) == 4 ? (N == 64 || N == 72 || N == 96) : N == 48;
+}
+template <typename T, int N> __host__ __device__ constexpr int rp_threads() {
+  return sizeof(T) == 8 && N == 48 ? 2 * N : kRegPlaneThreads;
+}
+
 template <typename T, int N, int DIR>
 __device__ __forceinline__ void pair_rows(cplx<T>* pl, int nact, int tid) {
   constexpr int P = N + 1, M = N / 2;
@@ -434,58 +445,58 @@ __device__ __forceinline__ void pair_col_out(const cplx<T> (&x)[N / 2], cplx<T>*
   }
 }
 
-// sticks of one plane into its compact LDS rows, and back, by all threads
-template <typename T, bool ADD>
+// sticks of one plane into its compact LDS rows, and back, by all NT threads
+template <typename T, int NT, bool ADD>
 __device__ __forceinline__ void pair_gather(cplx<T>* __restrict__ dst, const cplx<T>* pl,
                                             const int* __restrict__ soff, int S, int tid) {
-  reg_gather<T, kRegPlaneThreads, ADD>(dst, pl, soff, S, tid);
+  reg_gather<T, NT, ADD>(dst, pl, soff, S, tid);
 }
 
 // Pointwise work f(k, v) on the N/2 values of a lane (real-space rows
 // h N/2 + k), in two rounds of N/4 through a thread-private LDS area
-// [N/4][192]: the loop over a round stays rolled (U at a time), so its global
+// [N/4][NT]: the loop over a round stays rolled (U at a time), so its global
 // loads are not scheduled ahead of the transforms, where they held registers.
 template <typename T, int N>
 __host__ __device__ constexpr size_t pair_lds(int nact) {
   const size_t plane = (size_t)(nact + 1) * (N + 1);
-  const size_t stage = (size_t)(N / 4) * kRegPlaneThreads;
+  const size_t stage = (size_t)(N / 4) * rp_threads<T, N>();
   return (plane > stage ? plane : stage) * sizeof(cplx<T>);
 }
 template <typename T, int N, int U, typename F>
 __device__ __forceinline__ void pair_pointwise(cplx<T> (&x)[N / 2], cplx<T>* stg, int tid, F f) {
-  constexpr int RD = N / 4;
+  constexpr int RD = N / 4, NT = rp_threads<T, N>();
 #pragma unroll
   for (int r = 0; r < 2; ++r) {
 #pragma unroll
-    for (int k = 0; k < RD; ++k) stg[k * kRegPlaneThreads + tid] = x[r * RD + k];
+    for (int k = 0; k < RD; ++k) stg[k * NT + tid] = x[r * RD + k];
 #pragma unroll U
     for (int k = 0; k < RD; ++k) {
-      cplx<T>& v = stg[k * kRegPlaneThreads + tid];
+      cplx<T>& v = stg[k * NT + tid];
       v = f(r * RD + k, v);
     }
 #pragma unroll
-    for (int k = 0; k < RD; ++k) x[r * RD + k] = stg[k * kRegPlaneThreads + tid];
+    for (int k = 0; k < RD; ++k) x[r * RD + k] = stg[k * NT + tid];
   }
 }
 
 template <typename T, int N>
-__global__ __launch_bounds__(kRegPlaneThreads) void k_rp_local(const cplx<T>* __restrict__ sin,
-                                                               cplx<T>* __restrict__ sout,
-                                                               const T* __restrict__ vloc,
-                                                               RegPlaneArgs a,
-                                                               const LzDevState* st) {
+__global__ __launch_bounds__((rp_threads<T, N>())) void k_rp_local(const cplx<T>* __restrict__ sin,
+                                                                 cplx<T>* __restrict__ sout,
+                                                                 const T* __restrict__ vloc,
+                                                                 RegPlaneArgs a,
+                                                                 const LzDevState* st) {
   if (st && st->status) return;
-  constexpr int M = N / 2;
+  constexpr int M = N / 2, NT = rp_threads<T, N>();
   const int pstride = (a.nact + 1) * (N + 1);
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cplx<T>* pl = reinterpret_cast<cplx<T>*>(smem_raw);
   const int tid = threadIdx.x, c = tid >> 1, h = tid & 1;
-  const bool col = 2 * N >= kRegPlaneThreads || c < N;  // every thread on 96^2 planes
+  const bool col = 2 * N >= NT || c < N;  // every thread on 96^2 planes and in 96-thread blocks
   const int pidx = blockIdx.x, z = pidx % N;
   const int64_t so = (int64_t)pidx * a.S;
-  for (int t = tid; t < pstride; t += kRegPlaneThreads) pl[t] = mk<T>(T(0), T(0));
+  for (int t = tid; t < pstride; t += NT) pl[t] = mk<T>(T(0), T(0));
   __syncthreads();
-  reg_scatter<T, kRegPlaneThreads>(pl, sin + so, a.soffc, a.S, tid);
+  reg_scatter<T, NT>(pl, sin + so, a.soffc, a.S, tid);
   __syncthreads();
   pair_rows<T, N, +1>(pl, a.nact, tid);
   __syncthreads();
@@ -507,7 +518,7 @@ __global__ __launch_bounds__(kRegPlaneThreads) void k_rp_local(const cplx<T>* __
   __syncthreads();
   pair_rows<T, N, -1>(pl, a.nact, tid);
   __syncthreads();
-  pair_gather<T, false>(sout + so, pl, a.soffc, a.S, tid);
+  pair_gather<T, NT, false>(sout + so, pl, a.soffc, a.S, tid);
 }
 
 // A value streamed from memory once (non-temporal: kept out of the caches,
@@ -527,27 +538,27 @@ __device__ __forceinline__ cplx<T> ld_stream(const cplx<T>* p) {
 // registers (the batched workload, with its 72^3 members, gained 7 % against
 // the unbounded 181 registers at 72).
 template <typename T, int N>
-__global__ __launch_bounds__(kRegPlaneThreads) __attribute__((amdgpu_waves_per_eu(3))) void k_rp_density(
+__global__ __launch_bounds__((rp_threads<T, N>())) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 2 : 3))) void k_rp_density(
     const cplx<T>* __restrict__ sin, cplx<T>* __restrict__ sout, const T* __restrict__ vloc,
     const cplx<T>* __restrict__ ur, const double* __restrict__ bandw, cplx<T>* __restrict__ dpart,
     int nb, int gsize, RegPlaneArgs a, const LzDevState* st) {
   if (st && st->status) return;
-  constexpr int M = N / 2;
+  constexpr int M = N / 2, NT = rp_threads<T, N>();
   const int pstride = (a.nact + 1) * (N + 1);
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cplx<T>* pl = reinterpret_cast<cplx<T>*>(smem_raw);
   const int tid = threadIdx.x, c = tid >> 1, h = tid & 1;
-  const bool col = 2 * N >= kRegPlaneThreads || c < N;  // every thread on 96^2 planes
+  const bool col = 2 * N >= NT || c < N;  // every thread on 96^2 planes and in 96-thread blocks
   const int z = blockIdx.x, g = blockIdx.y;
   const int b0 = g * gsize, b1 = min(nb, b0 + gsize);
   const int64_t roff = (int64_t)h * M * N + (col ? c : 0);  // element (row h M, column c)
   const T* vz = vloc + (int64_t)z * N * N + roff;
   cplx<T>* dp = dpart + ((int64_t)g * N + z) * N * N + roff;
   for (int b = b0; b < b1; ++b) {
-    for (int t = tid; t < pstride; t += kRegPlaneThreads) pl[t] = mk<T>(T(0), T(0));
+    for (int t = tid; t < pstride; t += NT) pl[t] = mk<T>(T(0), T(0));
     __syncthreads();
     const int64_t so = ((int64_t)b * N + z) * a.S;
-    reg_scatter<T, kRegPlaneThreads>(pl, sin + so, a.soffc, a.S, tid);
+    reg_scatter<T, NT>(pl, sin + so, a.soffc, a.S, tid);
     __syncthreads();
     pair_rows<T, N, +1>(pl, a.nact, tid);
     __syncthreads();
@@ -583,14 +594,14 @@ __global__ __launch_bounds__(kRegPlaneThreads) __attribute__((amdgpu_waves_per_e
     __syncthreads();
     pair_rows<T, N, -1>(pl, a.nact, tid);
     __syncthreads();
-    pair_gather<T, false>(sout + so, pl, a.soffc, a.S, tid);
+    pair_gather<T, NT, false>(sout + so, pl, a.soffc, a.S, tid);
     __syncthreads();
   }
 }
 
 // v'(r) u_b(r) -> FFT2 -> added to the sticks of the same band, 72^2 / 96^2
 template <typename T, int N>
-__global__ __launch_bounds__(kRegPlaneThreads) void k_rp_vu(const cplx<T>* __restrict__ ur,
+__global__ __launch_bounds__((rp_threads<T, N>())) void k_rp_vu(const cplx<T>* __restrict__ ur,
                                                             const cplx<T>* __restrict__ vp,
                                                             cplx<T>* __restrict__ sout,
                                                             RegPlaneArgs a,
@@ -614,7 +625,7 @@ __global__ __launch_bounds__(kRegPlaneThreads) void k_rp_vu(const cplx<T>* __res
   __syncthreads();
   pair_rows<T, N, -1>(pl, a.nact, tid);
   __syncthreads();
-  pair_gather<T, true>(sout + (int64_t)pidx * a.S, pl, a.soffc, a.S, tid);
+  pair_gather<T, rp_threads<T, N>(), true>(sout + (int64_t)pidx * a.S, pl, a.soffc, a.S, tid);
 }
 
 }  // namespace lz
