@@ -65,6 +65,9 @@ def _args():
                     help="only time the first N members of the batched uneven workload")
     ap.add_argument("--ground-state", default=None, metavar="CONFIG",
                     help="only time the device ground-state preparation on CONFIG")
+    ap.add_argument("--large-cell", type=int, default=0, metavar="STEPS",
+                    help="only the large cell (96^3, 128 bands, 4 k) from device-prepared orbitals: "
+                         "recursions of STEPS steps in FP64, FP32 and split bf16")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a plain device copy of this size (counter calibration)")
     ap.add_argument("--nh-steps", type=int, default=60,
@@ -327,26 +330,43 @@ def ground_state_time(config):
     print(json.dumps(out), flush=True)
 
 
-def batched_rate(n_inst, prec="fp32", reps=5):
+def batched_rate(n_inst, prec="fp32", reps=5, steps=100):
     """Instance-applies/s of the batched uneven workload: the first n_inst
-    seeded members (grids in {32, 40, 48, 64, 72}, 8-48 bands, 1-16 k-points,
-    random orthonormal orbitals, so operator applications rather than a
-    recursion) in one context, one instance after another against side by
-    side on the library's streams."""
+    seeded members (grids in {32, 40, 48, 64, 72}, 8-48 bands, 1-16 k-points;
+    seeded orthonormal orbitals with energies below a lower bound of H, so
+    that D is positive definite) in one context: recursions of `steps` steps
+    of every member (lz_step), and operator applications
+    (lz_apply_liouvillian), one instance after another on one stream against
+    side by side on the library's streams."""
     import torch
 
     import paper_2111_06623_amd as lz
     from synth import config_system
     t = time.perf_counter()
-    systems = [config_system("uneven", index=i) for i in range(n_inst)]
-    _log(f"[bench] {n_inst} batched members built in {time.perf_counter() - t:.1f}s")
+    systems = []
+    for i in range(n_inst):
+        systems.append(config_system("uneven", index=i))
+        if i % 8 == 7:
+            _log(f"[bench] {i + 1} batched members built in {time.perf_counter() - t:.1f}s")
     out = {"workload": f"batched uneven: members 0..{n_inst - 1}", "instances": n_inst,
-           "precision": prec, "reps": reps,
+           "precision": prec, "steps": steps, "reps": reps,
            "grids": [int(s.nr[0]) for s in systems],
            "band_k_products": [int(s.nks) * int(s.evc_kq.shape[1]) for s in systems]}
     dt = torch.complex128 if prec == "fp64" else torch.complex64
     for streams, tag in ((1, "one_stream"), (0, "side_by_side")):
-        ctx = lz.lz_init(systems, prec=prec, max_steps=2, streams=streams)
+        ctx = lz.lz_init(systems, prec=prec, max_steps=steps + 4, streams=streams)
+        ctx.step(2)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        try:
+            ctx.step(steps)
+        except lz.LzError as e:  # an instance whose metric is indefinite stops; the rest go on
+            _log(f"[bench] {tag}: {e}")
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        done = [ctx.state(i) for i in range(n_inst)]
+        out[f"recursion_{tag}"] = round(sum(min(d, steps + 2) - 2 for d, _ in done) / 2 / el, 2)
+        out[f"recursion_{tag}_stopped"] = [i for i, (d, st) in enumerate(done) if st != 0]
         x = torch.randn(sum(ctx.nvec), dtype=dt, device="cuda")
         qo, po = torch.empty_like(x), torch.empty_like(x)
         ctx.apply_liouvillian(x, x, qo, po)
@@ -356,10 +376,77 @@ def batched_rate(n_inst, prec="fp32", reps=5):
             ctx.apply_liouvillian(x, x, qo, po)
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
-        out[tag] = round(n_inst * reps / el, 2)
+        out[f"apply_{tag}"] = round(n_inst * reps / el, 2)
         ctx.free()
         del x, qo, po
     out["unit"] = "instance-applies/s"
+    print(json.dumps(out), flush=True)
+
+
+def large_cell(steps):
+    """The large cell end to end: the lowest 128 eigenpairs of its k and k+q
+    spheres, the density and f_xc on the device, then one recursion of
+    `steps` steps per precision with its spectrum.  Reported: the ground-state
+    time, applies/s per precision, per-stage times and their fraction of the
+    HBM peak on the stick-model bytes, and the loss error of the mixed paths
+    against the FP64 path (the oracle's own run of this length is out of
+    reach on the host; its first 50 steps pin the FP64 path, tests)."""
+    import copy
+
+    import numpy as np
+    import torch
+
+    from synth import config_system, k_sphere_system
+    s = config_system("cfg5r")
+    sk = k_sphere_system("cfg5r")
+    import paper_2111_06623_amd as lz
+    lz.load()
+    out = {"workload": "cfg5: SC a=20.5 bohr, 96^3 grid, ecut 25 Ha, 64 wells + 256 s/p projectors, "
+                       "128 bands, 4 k-points, q=(0.2,0.1,0)(2pi/a), PZ-ALDA; orbitals, density and "
+                       "f_xc prepared on the device", "steps": steps}
+    t0 = time.perf_counter()
+    evc_kq, eps_kq, it1, res1 = lz.lz_ground_state(s, n_extra=4, tol=1e-9)
+    evc_k, eps_k, it2, res2 = lz.lz_ground_state(sk, n_extra=4, tol=1e-9)
+    g = copy.copy(s)
+    g.evc_k, g.evc_kq, g.et_k = evc_k, evc_kq, eps_k
+    n0, fxc = lz.lz_ground_density(g, xc="pz")
+    g.fxc_r = fxc
+    torch.cuda.synchronize()
+    out["ground_state"] = {"seconds": round(time.perf_counter() - t0, 2), "iterations": [it1, it2],
+                           "max_residual": max(res1, res2)}
+    _log(f"[bench] large cell: ground state in {out['ground_state']['seconds']} s "
+         f"({it1}, {it2} iterations)")
+    om = np.linspace(*OMEGA)
+    losses = {}
+    for prec in ("fp64", "fp32", "splitbf16"):
+        ctx = lz.lz_init(g, prec=prec, max_steps=steps + 24)
+        ctx.step(2)
+        ctx.stage_timer(True)
+        ctx.step(20)
+        ms, cnt = ctx.stage_times()
+        ctx.stage_timer(False)
+        ctx.reset()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        done, _ = ctx.step(steps)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t1
+        if done != steps:
+            raise RuntimeError(f"{prec} recursion stopped at {done} of {steps} steps")
+        losses[prec] = ctx.spectrum(om, ETA, m=steps)[2]
+        gsize = ctx.tuning()[1]
+        ctx.free()
+        ngroups = -(-(s.nks * s.nbnd) // gsize)
+        model, impl, _ = stage_bytes(s, prec, ngroups)
+        per_launch = {lz.STAGES[i]: (ms[i] / cnt[i] if cnt[i] else 0.0) for i in range(8)}
+        out[prec] = {"applies_per_s": round((steps / 2) / dt, 3), "ms_per_apply": round(2e3 * dt / steps, 3),
+                     "stage_ms_per_launch": {k: round(v, 4) for k, v in per_launch.items()},
+                     "stage_frac_of_hbm_peak_model_bytes":
+                         {k: round(model[k] / (per_launch[k] * 1e-3) / 8e12, 4)
+                          for k in model if per_launch.get(k, 0) > 0}}
+        if prec != "fp64":
+            out[prec]["loss_err_vs_fp64_gpu"] = loss_err(losses[prec], losses["fp64"])
+        _log(f"[bench] large cell {prec}: {out[prec]['applies_per_s']} applies/s")
     print(json.dumps(out), flush=True)
 
 
@@ -518,6 +605,9 @@ def main():
         import paper_2111_06623_amd as lz
         lz.load()
         ground_state_time(a.ground_state)
+        return
+    if a.large_cell:
+        large_cell(a.large_cell)
         return
     if a.apply_stages:
         import paper_2111_06623_amd as lz

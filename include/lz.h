@@ -332,13 +332,35 @@ lz_status lz_checkpoint_load(lz_ctx *ctx, int32_t inst, const void *buf, uint64_
  * read.  Outputs (host): evc_out [nks][nbnd][npwx] complex (caller order of
  * nl_kq, orthonormal, phases arbitrary), et_out [nks][nbnd] ascending,
  * *iterations and *max_residual (either may be NULL).  Synchronous.  Errors:
- * LZ_ERR_ARG for 3 (nbnd + n_extra) > 256 (the order of the dense
+ * LZ_ERR_ARG for 3 (nbnd + n_extra) > 512 (the order of the dense
  * Rayleigh-Ritz problem), a sphere smaller than nbnd + n_extra, or the
  * lz_init rules on the remaining fields.
  */
 lz_status lz_ground_state(const lz_system *sys, int32_t n_extra, double tol, int32_t max_iter,
                           int32_t device, void *hip_stream, double *evc_out, double *et_out,
                           int32_t *iterations, double *max_residual);
+
+typedef enum {    /* adiabatic LDA kernels */
+  LZ_XC_X = 0,    /* Slater exchange only */
+  LZ_XC_PZ = 1    /* Slater exchange + Perdew-Zunger (1981) correlation, the paper's functional */
+} lz_xc;
+
+/*
+ * Ground-state density and adiabatic xc kernel on the device (Sec. 3.1: the
+ * ground state the response starts from; f_xc of the xc response potential,
+ * eq. V_HXC_resp_1):
+ *   n0(r) = 2 sum_k w_k sum_n |u_nk(r)|^2   (spin-unpolarised; orbitals
+ *            normalised over the cell, u(r) = Omega^-1/2 sum_G u(G) e^{iG.r}),
+ *   f_xc(r) = d^2 (n eps_xc(n)) / dn^2 at n0(r), 0 where n0 < 1e-10 bohr^-3.
+ * Reads nr, at, nks, nbnd, npwx, xk, wk, npw_k, nl_k and evc_k of sys (the
+ * orbitals at k, e.g. from lz_ground_state on a system with q = 0) and the
+ * lz_init rules on them; q, the k+q fields, the energies, fxc_r and the
+ * projectors are not read.  Outputs (host, either may be NULL): n0_out[N]
+ * (bohr^-3) and fxc_out[N] (Ha bohr^3) in the grid order of vloc_r.
+ * Synchronous; ordered after `hip_stream` on device `device`.
+ */
+lz_status lz_ground_density(const lz_system *sys, int32_t xc, int32_t device, void *hip_stream,
+                            double *n0_out, double *fxc_out);
 
 /* Release every resource of the context (NULL is accepted). */
 lz_status lz_free(lz_ctx *ctx);

@@ -93,6 +93,8 @@ def load(path: str = LIB_PATH):
     lib.lz_get_tuning.argtypes = [vp, ctypes.c_int32, _ip, _ip, _ip]
     lib.lz_ground_state.argtypes = [ctypes.POINTER(LzSystem), ctypes.c_int32, ctypes.c_double,
                                     ctypes.c_int32, ctypes.c_int32, vp, _dp, _dp, _ip, _dp]
+    lib.lz_ground_density.argtypes = [ctypes.POINTER(LzSystem), ctypes.c_int32, ctypes.c_int32, vp,
+                                      _dp, _dp]
     lib.lz_spectrum.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, _dp, ctypes.c_int32,
                                 ctypes.c_double, _dp, _dp, _dp]
     lib.lz_spectrum_ext.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
@@ -110,7 +112,7 @@ def load(path: str = LIB_PATH):
     lib.lz_free.argtypes = [vp]
     lib.lz_last_error.restype = ctypes.c_char_p
     for f in ("lz_init", "lz_apply_liouvillian", "lz_step", "lz_get_coefficients", "lz_get_gamma",
-              "lz_get_tuning", "lz_ground_state",
+              "lz_get_tuning", "lz_ground_state", "lz_ground_density",
               "lz_get_state",
               "lz_spectrum", "lz_spectrum_ext", "lz_spectrum_ext_noalloc", "lz_checkpoint_size", "lz_checkpoint_save",
               "lz_checkpoint_load", "lz_get_rhs", "lz_reset", "lz_stage_timer", "lz_stage_times", "lz_free"):
@@ -231,6 +233,31 @@ def lz_ground_state(system, nbnd=None, n_extra=4, tol=1e-9, max_iter=300, device
                                ctypes.byref(res)))
     return (evc.view(np.complex128).reshape(nks, nb, npwx), eps.reshape(nks, nb), int(it.value),
             float(res.value))
+
+
+XC = {"x": 0, "pz": 1}
+
+
+def lz_ground_density(system, xc="pz", device=0, stream=None):
+    """Ground-state density n0 and the LDA kernel f_xc(n0) from the orbitals
+    at k of `system` (lz_ground_density); returns (n0, fxc), grid order of
+    vloc_r."""
+    import copy
+    lib = load()
+    s = copy.copy(system)
+    nks, nb = (int(v) for v in np.asarray(s.evc_k).shape[:2])
+    # placeholders of the right shapes for the fields the call does not read
+    s.evc_kq = s.evc_k
+    s.et_k = np.zeros((nks, nb))
+    s.fxc_r = np.zeros_like(np.asarray(s.vloc_r))
+    arr, keep = make_system(s)
+    N = int(np.prod(np.asarray(s.nr)))
+    n0 = np.zeros(N)
+    fxc = np.zeros(N)
+    hs = _stream_handle(device) if stream is None else ctypes.c_void_p(stream)
+    _check(lib.lz_ground_density(ctypes.byref(arr), XC[xc] if isinstance(xc, str) else int(xc),
+                                 int(device), hs, _ptr(n0, _dp), _ptr(fxc, _dp)))
+    return n0, fxc
 
 
 class Context:

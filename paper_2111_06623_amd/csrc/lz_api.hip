@@ -1640,13 +1640,26 @@ struct GsBuffers {
   DBuf X, HX, R, W, HW, P, HP, Z, HZ, Zc, HZc, V, HV, part, G, Tm, Ym, Cm, wv, keep, theta;
 };
 
+// Block products of the eigensolver run on the matrix cores once both sides
+// hold many vectors (the 128-band large cell: Gram matrices of order 396 over
+// 51k plane waves), on the vector ALU for the small blocks.
+int gs_gemm(int P, int nb) { return P >= 64 && nb >= 32 ? kGemmMfma : kGemmValu; }
+int gs_chunk(const Instance& I, int P, int nb) {
+  return gs_gemm(P, nb) == kGemmMfma ? LaunchLin<double>::mfma_chunk(P, nb, I.npwx, I.nks)
+                                     : kProjChunk;
+}
+// partials of a Gram product of P x nb (complex elements)
+size_t gs_part_elems(const Instance& I, int P, int nb) {
+  const int ch = gs_chunk(I, P, nb);
+  return (size_t)I.nks * ((I.npwx + ch - 1) / ch) * P * nb;
+}
+
 void gs_gram(Instance& I, GsBuffers& b, const void* A, int P, const void* B, int nb, void* out,
              hipStream_t s) {
-  LaunchLin<double>::proj_dot(A, P, P, const_cast<void*>(B), nullptr, nb, I.npwx, I.nks,
-                              kProjChunk, (I.npwx + kProjChunk - 1) / kProjChunk, b.part.p,
-                              nullptr, s);
-  LaunchLin<double>::reduce(b.part.p, (I.npwx + kProjChunk - 1) / kProjChunk, P, nb, I.nks, out,
-                            s);
+  const int gm = gs_gemm(P, nb), ch = gs_chunk(I, P, nb), nch = (I.npwx + ch - 1) / ch;
+  LaunchLin<double>::proj_dot(A, P, P, const_cast<void*>(B), nullptr, nb, I.npwx, I.nks, ch, nch,
+                              b.part.p, nullptr, s, gm);
+  LaunchLin<double>::reduce(b.part.p, nch, P, nb, I.nks, out, s);
 }
 
 // Y[k][nb] (+)= A[k][P]^T C[k][P][nb]
@@ -1655,7 +1668,7 @@ void gs_comb(Instance& I, void* Y, const void* A, int P, const void* C, int nb, 
   if (!accumulate)
     HIPC(hipMemsetAsync(Y, 0, (size_t)I.nks * nb * I.npwx * sizeof(double2), s));
   LaunchLin<double>::proj_update(Y, A, P, P, C, P, nb, I.npwx, I.nks, nullptr, nullptr, nullptr,
-                                 nullptr, nullptr, s);
+                                 nullptr, nullptr, s, gs_gemm(P, nb));
 }
 
 // rows [0, ra) of V[k] = A[k], rows [ra, ra + rb) = B[k]
@@ -1665,6 +1678,141 @@ void gs_stack(Instance& I, void* V, const void* A, int ra, const void* B, int rb
   HIPC(hipMemcpy2DAsync(V, pitch, A, ra * row, ra * row, I.nks, hipMemcpyDeviceToDevice, s));
   HIPC(hipMemcpy2DAsync((char*)V + ra * row, pitch, B, rb * row, rb * row, I.nks,
                         hipMemcpyDeviceToDevice, s));
+}
+
+// Rayleigh-Ritz of LOBPCG up to this order (3 (nbnd + n_extra)); larger
+// blocks take the Chebyshev-filtered subspace iteration, whose dense problems
+// are of the block's own order
+constexpr int kLobpcgOrderMax = 256;
+constexpr int kChebDegree = 40;
+
+// Chebyshev-filtered subspace iteration (Zhou and Saad, 2007) for the lowest
+// m eigenpairs, from the Ritz block (X, HX, theta) left by the start: each
+// iteration applies the degree-kChebDegree Chebyshev polynomial of H that is
+// small on [a, ub] (a the largest Ritz value of the block, ub an upper bound
+// of the spectrum) and normalised at the lowest Ritz value, then
+// orthonormalises the block (Jacobi on its Gram matrix) and does
+// Rayleigh-Ritz in its span.  Only products by H and dense problems of order
+// m.  ub = max kinetic energy of the sphere + max V_loc + a Gershgorin bound
+// of sum_p max(D_p, 0) |beta_p><beta_p| (Weyl: the three are Hermitian).
+void chebyshev_ground_state(const lz_system& sys, Instance& I, GsBuffers& b, int m, int nb_out,
+                            const std::vector<double>& kin, double tol, int max_iter, int& it,
+                            double& worst, hipStream_t s) {
+  const int nks = I.nks, npwx = I.npwx;
+  // the upper bound per sphere
+  std::vector<double> ub(nks, 0.0);
+  double vmax = -1e300;
+  for (int i = 0; i < I.N; ++i) vmax = std::max(vmax, sys.vloc_r[i]);
+  std::vector<double> gersh(nks, 0.0);
+  if (I.nproj > 0) {
+    const int np = I.nproj;
+    DBuf bc, gram;
+    bc.alloc((size_t)nks * np * npwx * sizeof(double2));
+    gram.alloc((size_t)nks * np * np * sizeof(double2));
+    const size_t row = (size_t)npwx * sizeof(double2);
+    HIPC(hipMemcpy2DAsync(bc.p, np * row, (const char*)I.Aio.p + (size_t)m * row, I.ptot * row,
+                          np * row, nks, hipMemcpyDeviceToDevice, s));
+    DBuf part;
+    part.alloc(gs_part_elems(I, np, np) * sizeof(double2));
+    std::swap(part.p, b.part.p);
+    gs_gram(I, b, bc.p, np, bc.p, np, gram.p, s);
+    std::swap(part.p, b.part.p);
+    std::vector<double2> g((size_t)nks * np * np);
+    std::vector<double> dkb(np);
+    HIPC(hipMemcpyAsync(g.data(), gram.p, g.size() * sizeof(double2), hipMemcpyDeviceToHost, s));
+    HIPC(hipMemcpyAsync(dkb.data(), I.dkb.p, np * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPC(hipStreamSynchronize(s));
+    for (int k = 0; k < nks; ++k)
+      for (int p = 0; p < np; ++p) {
+        double r = 0.0;
+        for (int q = 0; q < np; ++q) {
+          const double2 x = g[((size_t)k * np + p) * np + q];
+          r += std::sqrt(std::max(dkb[p], 0.0) * std::max(dkb[q], 0.0)) * std::hypot(x.x, x.y);
+        }
+        gersh[k] = std::max(gersh[k], r);
+      }
+  }
+  for (int k = 0; k < nks; ++k) {
+    double kmax = 0.0;
+    for (int i = 0; i < sys.npw_kq[k]; ++i) kmax = std::max(kmax, kin[(size_t)k * npwx + i]);
+    ub[k] = 1.01 * (kmax + std::max(vmax, 0.0) + gersh[k]) + 0.01;
+  }
+  std::vector<double> theta((size_t)nks * m), coef((size_t)kChebDegree * nks * 3);
+  std::vector<double2> rr((size_t)nks * m * m);
+  DBuf dcoef, dscale;
+  dcoef.alloc(coef.size() * sizeof(double));
+  dscale.alloc((size_t)nks * m * sizeof(double));
+  for (it = 0;; ++it) {
+    // residual norms of the wanted pairs
+    launch_gs_residual(b.X.p, b.HX.p, b.theta.as<double>(), I.kin.p, m, npwx, nks, 1.0, b.R.p,
+                       b.W.p, s);
+    gs_gram(I, b, b.R.p, m, b.R.p, m, b.G.p, s);
+    HIPC(hipMemcpyAsync(rr.data(), b.G.p, rr.size() * sizeof(double2), hipMemcpyDeviceToHost, s));
+    HIPC(hipMemcpyAsync(theta.data(), b.theta.p, theta.size() * sizeof(double),
+                        hipMemcpyDeviceToHost, s));
+    HIPC(hipStreamSynchronize(s));
+    worst = 0.0;
+    for (int k = 0; k < nks; ++k)
+      for (int n = 0; n < nb_out; ++n)
+        worst = std::max(worst, std::sqrt(std::max(0.0, rr[((size_t)k * m + n) * m + n].x)));
+    if (worst < tol || it >= max_iter) break;
+    // coefficients of the filter steps per sphere
+    for (int k = 0; k < nks; ++k) {
+      const double a = theta[(size_t)k * m + m - 1], a0 = theta[(size_t)k * m];
+      const double e = 0.5 * (ub[k] - a), c = 0.5 * (ub[k] + a);
+      double sig = e / (a0 - c);
+      const double sig1 = sig;
+      for (int d = 0; d < kChebDegree; ++d) {
+        double* cf = &coef[((size_t)d * nks + k) * 3];
+        if (d == 0) {
+          cf[0] = sig1 / e;
+          cf[1] = -c * sig1 / e;
+          cf[2] = 0.0;
+        } else {
+          const double sn = 1.0 / (2.0 / sig1 - sig);
+          cf[0] = 2.0 * sn / e;
+          cf[1] = -2.0 * sn * c / e;
+          cf[2] = -sig * sn;
+          sig = sn;
+        }
+      }
+    }
+    HIPC(hipMemcpyAsync(dcoef.p, coef.data(), coef.size() * sizeof(double), hipMemcpyHostToDevice,
+                        s));
+    // filter: Y_0 = X, Y_1 = c0 H X + c1 X, Y_d = c0 H Y_{d-1} + c1 Y_{d-1} + c2 Y_{d-2}
+    void* prev = b.X.p;  // Y_{d-2}
+    void* cur = b.W.p;   // Y_{d-1}
+    launch_cheb_step(cur, b.HX.p, b.X.p, nullptr, dcoef.as<double>(), m, npwx, nks, s);
+    for (int d = 1; d < kChebDegree; ++d) {
+      apply_half<double>(I, cur, b.HW.p, false, s);
+      launch_cheb_step(prev, b.HW.p, cur, prev, dcoef.as<double>() + (size_t)d * nks * 3, m, npwx,
+                       nks, s);
+      std::swap(prev, cur);
+    }
+    // cur = filtered block: orthonormalise it (columns scaled to unit norm
+    // first; twice, the second pass removing what rounding leaves of the
+    // first), through prev
+    for (int pass = 0; pass < 2; ++pass) {
+      gs_gram(I, b, cur, m, cur, m, b.G.p, s);
+      launch_gram_unit(b.G.p, m, dscale.as<double>(), nks, s);
+      launch_heev(b.G.p, m, m, b.wv.as<double>(), b.Ym.p, nks, s);
+      launch_orth_coef(b.Ym.p, b.wv.as<double>(), m, 1e-13, b.Cm.p, b.keep.as<int>(), nks, s);
+      launch_row_scale(b.Cm.p, m, dscale.as<double>(), nks, s);
+      gs_comb(I, prev, cur, m, b.Cm.p, m, false, s);
+      std::swap(prev, cur);
+    }
+    std::swap(prev, cur);  // the orthonormal block in prev, cur free
+    // Rayleigh-Ritz in its span: X = V Y, HX = HV Y
+    apply_half<double>(I, prev, b.HW.p, false, s);
+    gs_gram(I, b, prev, m, b.HW.p, m, b.Tm.p, s);
+    launch_mask_dropped(b.Tm.p, m, 0, m, b.keep.as<int>(), nks, s);
+    launch_heev(b.Tm.p, m, m, b.theta.as<double>(), b.Ym.p, nks, s);
+    gs_comb(I, cur, prev, m, b.Ym.p, m, false, s);
+    gs_comb(I, b.HX.p, b.HW.p, m, b.Ym.p, m, false, s);
+    // the new block is in cur: make it b.X (the buffers of b.X and b.W hold
+    // prev and cur in some order)
+    if (cur != b.X.p) std::swap(b.X.p, b.W.p);
+  }
 }
 
 }  // namespace
@@ -1679,7 +1827,7 @@ lz_status lz_ground_state(const lz_system* sys, int32_t n_extra, double tol, int
     if (n_extra < 0 || !(tol > 0) || max_iter < 1) fail(LZ_ERR_ARG, "bad solver parameters");
     const int nb_out = sys->nbnd;
     const int m = nb_out + n_extra;
-    if (nb_out < 1 || 3 * m > kSmallOrderMax) fail(LZ_ERR_ARG, "3 (nbnd + n_extra) must lie in [3, 256]");
+    if (nb_out < 1 || 3 * m > kSmallOrderMax) fail(LZ_ERR_ARG, "3 (nbnd + n_extra) must lie in [3, 512]");
     if (!sys->vloc_r || !sys->wk || !sys->xk || !sys->npw_kq || !sys->nl_kq || !sys->npw_k ||
         !sys->nl_k)
       fail(LZ_ERR_ARG, "null array in the system");
@@ -1731,8 +1879,12 @@ lz_status lz_ground_state(const lz_system* sys, int32_t n_extra, double tol, int
     for (DBuf* d : {&b.Z, &b.HZ, &b.Zc, &b.HZc}) d->alloc(2 * vb);
     b.V.alloc(3 * vb);
     b.HV.alloc(3 * vb);
-    const int nch = (npwx + kProjChunk - 1) / kProjChunk;
-    b.part.alloc((size_t)nks * nch * n3 * n3 * sizeof(double2));
+    {
+      size_t pe = 0;  // the largest partials of the Gram products below
+      const int dims[4][2] = {{m, m}, {m, n2}, {n2, n2}, {n3, n3}};
+      for (const auto& d : dims) pe = std::max(pe, gs_part_elems(I, d[0], d[1]));
+      b.part.alloc(pe * sizeof(double2));
+    }
     for (DBuf* d : {&b.G, &b.Tm, &b.Ym, &b.Cm}) d->alloc((size_t)nks * n3 * n3 * sizeof(double2));
     b.wv.alloc((size_t)nks * n3 * sizeof(double));
     b.keep.alloc((size_t)nks * n2 * sizeof(int));
@@ -1782,7 +1934,9 @@ lz_status lz_ground_state(const lz_system* sys, int32_t n_extra, double tol, int
     std::vector<double2> rr((size_t)nks * m * m);
     int it = 0;
     double worst = 0.0;
-    for (;; ++it) {
+    if (3 * m > kLobpcgOrderMax) {
+      chebyshev_ground_state(*sys, I, b, m, nb_out, kin, tol, max_iter, it, worst, s);
+    } else for (;; ++it) {
       // residuals, their norms, the preconditioned corrections and H W
       launch_gs_residual(b.X.p, b.HX.p, b.theta.as<double>(), I.kin.p, m, npwx, nks, 1.0, b.R.p,
                          b.W.p, s);
@@ -1854,6 +2008,83 @@ lz_status lz_ground_state(const lz_system* sys, int32_t n_extra, double tol, int
     }
     if (iterations) *iterations = it;
     if (max_residual) *max_residual = worst;
+  });
+}
+
+lz_status lz_ground_density(const lz_system* sys, int32_t xc, int32_t device, void* hip_stream,
+                            double* n0_out, double* fxc_out) {
+  return guarded([&] {
+    if (!sys || (!n0_out && !fxc_out)) fail(LZ_ERR_ARG, "null argument");
+    if (xc != LZ_XC_X && xc != LZ_XC_PZ) fail(LZ_ERR_ARG, "unknown xc kernel");
+    if (!sys->evc_k || !sys->wk || !sys->xk || !sys->npw_k || !sys->nl_k || !sys->vloc_r)
+      fail(LZ_ERR_ARG, "null array in the system");
+    int ndev = 0;
+    HIPC(hipGetDeviceCount(&ndev));
+    if (device < 0 || device >= ndev) fail(LZ_ERR_ARG, "no such device");
+    HIPC(hipSetDevice(device));
+    HIPC(enable_large_lds_fft<double>());
+    hipStream_t s = nullptr;
+    hipEvent_t ev = nullptr;
+    HIPC(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    struct Guard {
+      hipStream_t& s;
+      hipEvent_t& e;
+      ~Guard() {
+        if (s) { (void)hipStreamSynchronize(s); (void)hipStreamDestroy(s); }
+        if (e) (void)hipEventDestroy(e);
+      }
+    } guard{s, ev};
+    HIPC(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    HIPC(hipEventRecord(ev, (hipStream_t)hip_stream));
+    HIPC(hipStreamWaitEvent(s, ev, 0));
+    // an internal instance whose valence orbitals are the orbitals at k (its
+    // real-space orbitals are what the density needs; no projectors, no
+    // Hartree kernel, and any nonzero Q passes the checks)
+    const int nks = sys->nks, nbnd = sys->nbnd;
+    const int N = sys->nr[0] * sys->nr[1] * sys->nr[2];
+    std::vector<double> zet((size_t)nks * nbnd, 0.0), zf((size_t)N, 0.0);
+    lz_system g = *sys;
+    g.q[0] = g.q[1] = g.q[2] = 0.0;
+    g.g0[0] = 1;
+    g.g0[1] = 0;
+    g.g0[2] = 0;
+    g.npw_kq = sys->npw_k;
+    g.nl_kq = sys->nl_k;
+    g.evc_kq = sys->evc_k;
+    g.et_k = zet.data();
+    g.fxc_r = zf.data();
+    g.nproj = 0;
+    g.vkb_kq = nullptr;
+    g.dkb = nullptr;
+    lz_options o{};
+    o.prec = LZ_FP64;
+    o.approx = LZ_IPA;
+    o.max_steps = 1;
+    o.projector_gemm = LZ_GEMM_VALU;
+    std::unique_ptr<Instance> Ip = build_instance(g, o, s);
+    Instance& I = *Ip;
+    std::vector<double> w((size_t)I.nb);
+    for (int b = 0; b < I.nb; ++b) w[b] = 2.0 * sys->wk[b / nbnd] / I.omega;
+    DBuf dw, dn, df;
+    upload(dw, w);
+    dn.alloc((size_t)N * sizeof(double));
+    df.alloc((size_t)N * sizeof(double));
+    launch_ground_density(I.ur.p, dw.as<double>(), I.nb, N, xc == LZ_XC_PZ ? 1 : 0,
+                          dn.as<double>(), df.as<double>(), s);
+    HIPC(hipGetLastError());
+    std::vector<double> hn(N), hf(N);
+    HIPC(hipMemcpyAsync(hn.data(), dn.p, N * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPC(hipMemcpyAsync(hf.data(), df.p, N * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPC(hipStreamSynchronize(s));
+    // plane-major [i3][i1][i2] -> the caller's (i1 N2 + i2) N3 + i3
+    for (int i1 = 0; i1 < I.n1; ++i1)
+      for (int i2 = 0; i2 < I.n2; ++i2)
+        for (int i3 = 0; i3 < I.n3; ++i3) {
+          const size_t src = ((size_t)i3 * I.n1 + i1) * I.n2 + i2;
+          const size_t dst = ((size_t)i1 * I.n2 + i2) * I.n3 + i3;
+          if (n0_out) n0_out[dst] = hn[src];
+          if (fxc_out) fxc_out[dst] = hf[src];
+        }
   });
 }
 

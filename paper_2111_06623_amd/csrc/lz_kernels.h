@@ -140,7 +140,7 @@ void launch_set_state(LzDevState* st, hipStream_t s);
 
 // small dense kernels of the ground-state eigensolver (double precision,
 // one block per k; lz_small.h)
-constexpr int kSmallOrderMax = 256;
+constexpr int kSmallOrderMax = 512;
 void launch_heev(void* A, int n, int ld, double* w, void* V, int nks, hipStream_t s);
 void launch_small_take(void* dst, const void* src, int rows, int cols, int lds, int col0,
                        int src_stride, double alpha, int nks, hipStream_t s);
@@ -148,6 +148,18 @@ void launch_orth_coef(const void* Q, const double* lam, int m, double tol, void*
                       int nks, hipStream_t s);
 void launch_mask_dropped(void* T, int n2, int off, int cnt, const int* keep, int nks,
                          hipStream_t s);
+// out = c0 HY + c1 Y + c2 Xold with (c0, c1, c2) = coef[k][3] per sphere (the
+// Chebyshev filter of the eigensolver; out may alias Xold)
+void launch_cheb_step(void* out, const void* HY, const void* Y, const void* Xold,
+                      const double* coef, int m, int npwx, int nks, hipStream_t s);
+// unit-diagonal form of Gram matrices G[k] (m x m) with the column scales
+// d[k] = 1/sqrt(diag), and the rows of coefficients C[k] scaled by d[k]
+void launch_gram_unit(void* G, int m, double* dscale, int nks, hipStream_t s);
+void launch_row_scale(void* C, int m, const double* dscale, int nks, hipStream_t s);
+// ground-state density n0 = sum_b w[b] |ur[b]|^2 and the LDA kernel f_xc(n0)
+// (xc = 1 Perdew-Zunger, 0 exchange only) on np grid points (lz_small.h)
+void launch_ground_density(const void* ur, const double* w, int nb, int64_t np, int xc,
+                           double* n0, double* fxc, hipStream_t s);
 void launch_gs_residual(const void* X, const void* HX, const double* theta, const void* kin, int m,
                         int npwx, int nks, double e0, void* R, void* W, hipStream_t s);
 

@@ -1016,7 +1016,7 @@ void launch_set_state(LzDevState* st, hipStream_t s) {
 }
 
 void launch_heev(void* A, int n, int ld, double* w, void* V, int nks, hipStream_t s) {
-  hipLaunchKernelGGL(k_heev_jacobi, dim3(nks), dim3(256), 0, s, (double2*)A, n, ld, w, (double2*)V,
+  hipLaunchKernelGGL(k_heev_jacobi, dim3(nks), dim3(kHeevThreads), 0, s, (double2*)A, n, ld, w, (double2*)V,
                      30);
 }
 void launch_small_take(void* dst, const void* src, int rows, int cols, int lds, int col0,
@@ -1038,6 +1038,25 @@ void launch_gs_residual(const void* X, const void* HX, const double* theta, cons
   hipLaunchKernelGGL(k_gs_residual, dim3(1024), dim3(256), 0, s, (const double2*)X,
                      (const double2*)HX, theta, (const double*)kin, m, npwx, nks, e0, (double2*)R,
                      (double2*)W);
+}
+
+void launch_cheb_step(void* out, const void* HY, const void* Y, const void* Xold,
+                      const double* coef, int m, int npwx, int nks, hipStream_t s) {
+  hipLaunchKernelGGL(k_cheb_step, dim3(1024), dim3(256), 0, s, (double2*)out, (const double2*)HY,
+                     (const double2*)Y, (const double2*)Xold, coef, m, npwx, nks);
+}
+
+void launch_gram_unit(void* G, int m, double* dscale, int nks, hipStream_t s) {
+  hipLaunchKernelGGL(k_gram_unit, dim3(nks), dim3(256), 0, s, (double2*)G, m, dscale);
+}
+void launch_row_scale(void* C, int m, const double* dscale, int nks, hipStream_t s) {
+  hipLaunchKernelGGL(k_row_scale, dim3(nks), dim3(256), 0, s, (double2*)C, m, dscale);
+}
+
+void launch_ground_density(const void* ur, const double* w, int nb, int64_t np, int xc,
+                           double* n0, double* fxc, hipStream_t s) {
+  hipLaunchKernelGGL(k_ground_density, dim3(1024), dim3(256), 0, s, (const double2*)ur, w, nb, np,
+                     xc, n0, fxc);
 }
 
 template struct LaunchLin<double>;

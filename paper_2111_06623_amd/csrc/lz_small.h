@@ -12,7 +12,8 @@ __device__ __forceinline__ double2 zmul(double2 a, double2 b) {
 }
 __device__ __forceinline__ double2 zconj(double2 a) { return make_double2(a.x, -a.y); }
 
-constexpr int kSmallMax = 256;  // largest matrix order of the small kernels
+constexpr int kSmallMax = 512;  // largest matrix order of the small kernels
+constexpr int kHeevThreads = 1024;  // threads of the one block per matrix of k_heev_jacobi
 
 // Eigen-decomposition of the Hermitian part of A[k] (n x n, leading dimension
 // ld) by two-sided cyclic Jacobi with the round-robin parallel ordering: in
@@ -25,13 +26,13 @@ constexpr int kSmallMax = 256;  // largest matrix order of the small kernels
 // stop when the off-diagonal norm is below 1e-15 of the matrix norm (or
 // after max_sweeps).  Eigenvalues ascending into w[k][0..n), eigenvectors
 // into the columns of V[k]; A[k] is destroyed.
-__global__ __launch_bounds__(256) void k_heev_jacobi(double2* __restrict__ A, int n, int ld,
+__global__ __launch_bounds__(kHeevThreads) void k_heev_jacobi(double2* __restrict__ A, int n, int ld,
                                                      double* __restrict__ w,
                                                      double2* __restrict__ V, int max_sweeps) {
   __shared__ double rc[kSmallMax / 2], rs[kSmallMax / 2];
   __shared__ double2 ru[kSmallMax / 2];
   __shared__ int rp[kSmallMax / 2], rq[kSmallMax / 2];
-  __shared__ double red[256];
+  __shared__ double red[kHeevThreads];
   __shared__ int idx[kSmallMax];
   __shared__ double dsort[kSmallMax];
   __shared__ int stop;
@@ -41,7 +42,7 @@ __global__ __launch_bounds__(256) void k_heev_jacobi(double2* __restrict__ A, in
   const int ne = n + (n & 1);
   const int npair = ne / 2;
   // Hermitian part, V = I
-  for (int t = tid; t < n * n; t += 256) {
+  for (int t = tid; t < n * n; t += kHeevThreads) {
     const int i = t / n, j = t - i * n;
     if (i <= j) {
       const double2 x = a[i * ld + j], y = a[j * ld + i];
@@ -55,7 +56,7 @@ __global__ __launch_bounds__(256) void k_heev_jacobi(double2* __restrict__ A, in
   for (int sweep = 0; sweep < max_sweeps; ++sweep) {
     // convergence: off-diagonal against total Frobenius norm
     double off = 0.0, tot = 0.0;
-    for (int t = tid; t < n * n; t += 256) {
+    for (int t = tid; t < n * n; t += kHeevThreads) {
       const int i = t / n, j = t - i * n;
       const double2 x = a[i * ld + j];
       const double m2 = x.x * x.x + x.y * x.y;
@@ -64,7 +65,7 @@ __global__ __launch_bounds__(256) void k_heev_jacobi(double2* __restrict__ A, in
     }
     red[tid] = off;
     __syncthreads();
-    for (int h = 128; h > 0; h >>= 1) {
+    for (int h = kHeevThreads / 2; h > 0; h >>= 1) {
       if (tid < h) red[tid] += red[tid + h];
       __syncthreads();
     }
@@ -72,7 +73,7 @@ __global__ __launch_bounds__(256) void k_heev_jacobi(double2* __restrict__ A, in
     __syncthreads();
     red[tid] = tot;
     __syncthreads();
-    for (int h = 128; h > 0; h >>= 1) {
+    for (int h = kHeevThreads / 2; h > 0; h >>= 1) {
       if (tid < h) red[tid] += red[tid + h];
       __syncthreads();
     }
@@ -112,7 +113,7 @@ __global__ __launch_bounds__(256) void k_heev_jacobi(double2* __restrict__ A, in
       }
       __syncthreads();
       // columns of A and V: [x_p, x_q] <- [x_p c - x_q u* s, x_p s + x_q u* c]
-      for (int t = tid; t < npair * n; t += 256) {
+      for (int t = tid; t < npair * n; t += kHeevThreads) {
         const int pr = t / n, i = t - pr * n;
         const int p = rp[pr], q = rq[pr];
         if (q < 0 || rs[pr] == 0.0) continue;
@@ -129,7 +130,7 @@ __global__ __launch_bounds__(256) void k_heev_jacobi(double2* __restrict__ A, in
       }
       __syncthreads();
       // rows of A: [x_p; x_q] <- [c x_p - u s x_q; s x_p + u c x_q]
-      for (int t = tid; t < npair * n; t += 256) {
+      for (int t = tid; t < npair * n; t += kHeevThreads) {
         const int pr = t / n, j = t - pr * n;
         const int p = rp[pr], q = rq[pr];
         if (q < 0 || rs[pr] == 0.0) continue;
@@ -169,13 +170,13 @@ __global__ __launch_bounds__(256) void k_heev_jacobi(double2* __restrict__ A, in
     }
   }
   __syncthreads();
-  for (int i = tid; i < n; i += 256) w[(int64_t)k * n + i] = dsort[i];
-  for (int t = tid; t < n * n; t += 256) {
+  for (int i = tid; i < n; i += kHeevThreads) w[(int64_t)k * n + i] = dsort[i];
+  for (int t = tid; t < n * n; t += kHeevThreads) {
     const int i = t / n, j = t - i * n;
     a[i * ld + j] = v[i * ld + idx[j]];
   }
   __syncthreads();
-  for (int t = tid; t < n * n; t += 256) {
+  for (int t = tid; t < n * n; t += kHeevThreads) {
     const int i = t / n, j = t - i * n;
     v[i * ld + j] = a[i * ld + j];
   }
@@ -274,6 +275,121 @@ __global__ __launch_bounds__(256) void k_gs_residual(const double2* __restrict__
     const double num = 27.0 + y * (18.0 + y * (12.0 + 8.0 * y));
     const double p = num / (num + 16.0 * y * y * y * y);
     W[i] = make_double2(p * r.x, p * r.y);
+  }
+}
+
+// One step of the Chebyshev filter of the eigensolver (the three-term
+// recurrence of scaled Chebyshev polynomials of H):
+//   out = c0 HY + c1 Y + c2 Xold,   (c0, c1, c2) = coef[k][0..3) per sphere k
+// on nks blocks of m vectors of npwx plane waves; out may alias Xold.
+__global__ __launch_bounds__(256) void k_cheb_step(double2* out, const double2* __restrict__ HY,
+                                                   const double2* __restrict__ Y,
+                                                   const double2* Xold,
+                                                   const double* __restrict__ coef, int m,
+                                                   int npwx, int nks) {
+  const int64_t total = (int64_t)nks * m * npwx;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int k = (int)(i / ((int64_t)m * npwx));
+    const double c0 = coef[3 * k], c1 = coef[3 * k + 1], c2 = coef[3 * k + 2];
+    const double2 h = HY[i], y = Y[i];
+    double2 r = make_double2(c0 * h.x + c1 * y.x, c0 * h.y + c1 * y.y);
+    if (c2 != 0.0) {
+      const double2 x = Xold[i];
+      r.x += c2 * x.x;
+      r.y += c2 * x.y;
+    }
+    out[i] = r;
+  }
+}
+
+// Unit-diagonal form of a Gram matrix (the Gram matrix of the block with its
+// columns scaled to unit norm): d_j = 1/sqrt(G_jj), G_ij <- d_i G_ij d_j, and
+// d into dscale[k][m].  A filtered block whose columns differ in norm by many
+// orders (the filter damps the upper columns of the block) keeps their
+// distinct directions through this scaling.
+__global__ __launch_bounds__(256) void k_gram_unit(double2* __restrict__ G, int m,
+                                                   double* __restrict__ dscale) {
+  const int k = blockIdx.x;
+  double2* g = G + (int64_t)k * m * m;
+  double* d = dscale + (int64_t)k * m;
+  for (int j = threadIdx.x; j < m; j += 256) {
+    const double x = g[(int64_t)j * m + j].x;
+    d[j] = x > 0.0 ? 1.0 / sqrt(x) : 0.0;
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < m * m; t += 256) {
+    const int i = t / m, j = t - i * m;
+    const double f = d[i] * d[j];
+    g[t] = make_double2(f * g[t].x, f * g[t].y);
+  }
+}
+
+// C[k][i][j] *= d[k][i] (rows of coefficients, after k_gram_unit)
+__global__ __launch_bounds__(256) void k_row_scale(double2* __restrict__ C, int m,
+                                                   const double* __restrict__ dscale) {
+  const int k = blockIdx.x;
+  for (int t = threadIdx.x; t < m * m; t += 256) {
+    const int i = t / m;
+    const double f = dscale[(int64_t)k * m + i];
+    double2& c = C[(int64_t)k * m * m + t];
+    c = make_double2(f * c.x, f * c.y);
+  }
+}
+
+// Ground-state density and adiabatic LDA kernel (Sec. 3.1; the kernel of
+// the xc response potential, Sec. 2.2): from the valence orbitals on the
+// grid, raw sums ur[b][p] = sum_G u_b(G) e^{iG.r_p} (the Omega^-1/2 of the
+// cell normalisation is in w), n0[p] = sum_b w[b] |ur[b][p]|^2 with
+// w[b] = 2 w_k / Omega (spin-unpolarised), bands added in index order; then
+// f_xc(n0) = d^2(n eps_xc)/dn^2, zero where n0 < 1e-10 bohr^-3.
+//   exchange (Slater): n eps_x = -(3/4)(3/pi)^(1/3) n^(4/3),
+//                      f_x = -(1/3)(3/pi)^(1/3) n^(-2/3);
+//   correlation (Perdew-Zunger 1981, unpolarised, Hartree units), with
+//   r_s = (3/(4 pi n))^(1/3) and dr_s/dn = -r_s/(3n):
+//     r_s >= 1: eps_c = gamma / (1 + beta1 sqrt(r_s) + beta2 r_s)
+//     r_s <  1: eps_c = A ln r_s + B + C r_s ln r_s + D r_s
+//     f_c = (r_s^2 eps_c'' - 2 r_s eps_c') / (9 n)   (derivatives in r_s).
+// xc = 1: exchange and correlation; xc = 0: exchange only.
+__device__ __forceinline__ double lda_fxc(double n, int xc) {
+  if (!(n >= 1e-10)) return 0.0;
+  const double third = 1.0 / 3.0;
+  double f = -third * cbrt(3.0 / M_PI) * pow(n, -2.0 * third);
+  if (xc) {
+    const double rs = cbrt(3.0 / (4.0 * M_PI * n));
+    double e1, e2;
+    if (rs >= 1.0) {
+      const double gam = -0.1423, b1 = 1.0529, b2 = 0.3334;
+      const double sr = sqrt(rs);
+      const double den = 1.0 + b1 * sr + b2 * rs;
+      const double d1 = 0.5 * b1 / sr + b2;
+      const double d2 = -0.25 * b1 / (rs * sr);
+      e1 = -gam * d1 / (den * den);
+      e2 = -gam * d2 / (den * den) + 2.0 * gam * d1 * d1 / (den * den * den);
+    } else {
+      const double A = 0.0311, C = 0.0020, D = -0.0116;
+      e1 = A / rs + C * (log(rs) + 1.0) + D;
+      e2 = -A / (rs * rs) + C / rs;
+    }
+    f += (rs * rs * e2 - 2.0 * rs * e1) / (9.0 * n);
+  }
+  return f;
+}
+
+__global__ __launch_bounds__(256) void k_ground_density(const double2* __restrict__ ur,
+                                                        const double* __restrict__ w, int nb,
+                                                        int64_t np, int xc,
+                                                        double* __restrict__ n0,
+                                                        double* __restrict__ fxc) {
+  for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < np;
+       p += (int64_t)gridDim.x * blockDim.x) {
+    double acc = 0.0;
+    for (int b = 0; b < nb; ++b) {
+      const double2 u = ur[(int64_t)b * np + p];
+      acc += w[b] * (u.x * u.x + u.y * u.y);
+    }
+    n0[p] = acc;
+    fxc[p] = lda_fxc(acc, xc);
   }
 }
 

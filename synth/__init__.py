@@ -23,5 +23,5 @@ from .system import (  # noqa: F401
     SystemArrays, build_system, reciprocal, sphere_miller, linear_index,
     mp_kpoints, gaussian_wells_r, kb_projectors, pz_lda_fxc, x_lda_fxc,
 )
-from .configs import config_system, CONFIGS, QSWEEP_FRACS, q_sweep  # noqa: F401
+from .configs import config_system, CONFIGS, QSWEEP_FRACS, q_sweep, k_sphere_system  # noqa: F401
 from .vectors import random_batch  # noqa: F401

@@ -13,6 +13,9 @@
         2x2x1 mesh, q = (0.2, 0.1, 0) 2pi/a) with seeded random orthonormal
         orbitals in place of eigenstates: operator-level parity and
         throughput at the full size.
+  cfg5  the same large cell with its lowest 128 eigenpairs at every k and
+        k+q (block Davidson on the host: tens of minutes; the oracle's
+        reference recursion of this cell is stored, tests/golden).
   uneven members of the batched workload (seeded grids in {32, 40, 48, 64,
         72} with a = 10.26 N/48 bohr, ecut 25 Ha, wells with 4 projectors
         each, random orthonormal orbitals); `uneven_sizes` trims bands and k.
@@ -125,6 +128,14 @@ def _spec(name: str, **kw) -> dict:
                     nbnd=nbnd, kpts=mp_kpoints(at, (2, 2, 1), shift)[:nk],
                     q=[0.2 * 2 * np.pi / a, 0.1 * 2 * np.pi / a, 0.0], xc="pz",
                     kb=dict(radii=radii, dkb=dkb), orbitals="random", seed=5, extra_bands=0)
+    if name == "cfg5":
+        # the large cell with its valence states: the lowest 128 eigenpairs of
+        # every k and k+q sphere (the geometry, spheres, potential and
+        # projectors of cfg5r)
+        sp = _spec("cfg5r", **kw)
+        sp["orbitals"] = "eigen"
+        sp["extra_bands"] = 2
+        return sp
     if name == "uneven":
         i = kw.get("index", 0)
         rng = np.random.default_rng(4000 + i)
@@ -206,6 +217,35 @@ def config_system(name: str, use_cache: bool = True, **kw) -> SystemArrays:
         np.savez(tmp, **{f: getattr(s, f) for f in _FIELDS}, ecut=s.ecut,
                  info=json.dumps(s.info, default=lambda o: o.tolist() if hasattr(o, "tolist") else str(o)))
         os.replace(tmp, path)
+    return s
+
+
+def k_sphere_system(name: str, **kw) -> SystemArrays:
+    """The system `name` seen from its k spheres: q = 0, the k spheres in the
+    k+q fields and the separable projectors evaluated at k + G, i.e. the
+    Hamiltonian H_k whose lowest eigenpairs are the orbitals u_nk (the input
+    of a ground-state solver on the k spheres)."""
+    import copy
+
+    from .system import kb_projectors
+    s = copy.copy(config_system(name, **kw))
+    spec = _spec(name, **kw)
+    s.q = np.zeros(3)
+    s.nl_kq, s.npw_kq = s.nl_k, s.npw_k
+    s.evc_kq = s.evc_k
+    if spec.get("kb") is not None and len(s.dkb):
+        at = np.asarray(spec["at"], dtype=np.float64)
+        tau = np.asarray(spec["tau_frac"], dtype=np.float64) @ at
+        radii = np.asarray(spec["kb"]["radii"], dtype=np.float64)
+        vkb = np.zeros_like(s.vkb_kq)
+        for k in range(s.nks):
+            npw = int(s.npw_k[k])
+            nl = np.asarray(s.nl_k[k, :npw], dtype=np.int64)
+            n1, n2, n3 = (int(v) for v in s.nr)
+            m = np.stack([nl // (n2 * n3), (nl // n3) % n2, nl % n3], axis=1)
+            m = np.where(m >= (np.array([n1, n2, n3]) + 1) // 2, m - np.array([n1, n2, n3]), m)
+            vkb[k, :, :npw] = kb_projectors(at, m, s.xk[k], tau, radii)
+        s.vkb_kq = vkb
     return s
 
 

@@ -116,3 +116,46 @@ def test_non_hermitian_instances_side_by_side():
         assert _same(got[i], ref[i])
     par.free()
 
+
+
+# members of the batched uneven workload (seeded; grid, bands, k-points): the
+# eight smallest by bands x grid points and the two largest
+SMALLEST = (60, 58, 49, 32, 62, 16, 3, 22)   # 32^3..48^3, 8-48 bands, 1-8 k
+LARGEST = (29, 12)                            # 72^3: 40 bands x 9 k, 48 bands x 16 k
+
+
+@pytest.mark.slow
+def test_uneven_members_recursions_in_one_context():
+    """Ten members of the batched uneven workload (grids 32^3 to 72^3, up to
+    768 band-k products) advance their recursions side by side in one
+    context; the eight smallest members' first 40 coefficients and the two
+    largest members' first 6 equal the oracle's: beta to 1e-10 relative, z to
+    1e-10 of max|z| over the first 20 steps and 1e-9 beyond (these members'
+    orbitals are seeded orthonormal sets with energies placed below the
+    spectrum of H, not eigenstates; rounding grows along their recursions --
+    the oracle's own Im z, zero in exact arithmetic, doubles every two steps
+    on the 40^3 member, and the GPU's z of step 40 differs from the oracle's
+    by 1.8e-10 of max|z|)."""
+    import os
+
+    import oracle.pw as opw
+    lz = _lz()
+    opw.FFT_WORKERS = min(len(os.sched_getaffinity(0)), 16)
+    idx = SMALLEST + LARGEST
+    systems = [config_system("uneven", index=i) for i in idx]
+    print("[uneven] members built", flush=True)
+    ctx = lz.lz_init(systems, prec="fp64", max_steps=48)
+    done, st = ctx.step(40)
+    assert st == lz.LZ_OK
+    for j, (i, s) in enumerate(zip(idx, systems)):
+        n = 40 if i in SMALLEST else 6
+        print(f"[uneven] member {i}: grid {int(s.nr[0])}, {s.nbnd} bands, {s.nks} k, oracle {n} steps",
+              flush=True)
+        ref = lanczos.run(Liouvillian(s), n)
+        beta, _, z = ctx.coefficients(inst=j)
+        assert ctx.state(j)[0] == 40
+        assert np.max(np.abs(beta[:n] - ref.beta) / ref.beta) < 1e-10
+        zmax = np.abs(ref.z).max()
+        assert np.abs(z[:min(n, 20)] - ref.z[:20]).max() < 1e-10 * zmax
+        assert np.abs(z[:n] - ref.z).max() < 1e-9 * zmax
+    ctx.free()

@@ -15,7 +15,8 @@ pytestmark = pytest.mark.gpu
 
 from oracle import lanczos  # noqa: E402
 from oracle.liouvillian import Liouvillian  # noqa: E402
-from synth import config_system  # noqa: E402
+from synth import config_system, k_sphere_system  # noqa: E402
+from synth.system import pz_lda_fxc, x_lda_fxc  # noqa: E402
 
 
 def _lz():
@@ -94,7 +95,109 @@ def test_ground_state_argument_errors():
     lz = _lz()
     s = config_system("micro")
     with pytest.raises(lz.LzError) as e:
-        lz.lz_ground_state(s, n_extra=100)
+        lz.lz_ground_state(s, n_extra=200)
     assert e.value.status == lz.LZ_ERR_ARG
     with pytest.raises(lz.LzError):
         lz.lz_ground_state(s, tol=-1.0)
+
+
+def _pz_energy_density(n):
+    """n (eps_x + eps_c) of the unpolarised LDA, Hartree units: Slater
+    exchange and the Perdew-Zunger (1981) parametrisation of the correlation
+    energy per particle (r_s >= 1: gamma / (1 + beta1 sqrt(r_s) + beta2 r_s);
+    r_s < 1: A ln r_s + B + C r_s ln r_s + D r_s)."""
+    n = np.asarray(n, dtype=np.float64)
+    ex = -0.75 * (3.0 / np.pi) ** (1.0 / 3.0) * n ** (1.0 / 3.0)
+    rs = (3.0 / (4.0 * np.pi * n)) ** (1.0 / 3.0)
+    hi = -0.1423 / (1.0 + 1.0529 * np.sqrt(rs) + 0.3334 * rs)
+    lo = 0.0311 * np.log(rs) - 0.048 + 0.0020 * rs * np.log(rs) - 0.0116 * rs
+    return n * (ex + np.where(rs >= 1.0, hi, lo))
+
+
+@pytest.mark.parametrize("name", ["cfg1", "cfg2lo"])
+def test_ground_density_and_xc_kernel(name):
+    """n0 = 2 sum_k w_k sum_n |u_nk(r)|^2 from the device equals the same sum
+    over the oracle's real-space orbitals; it integrates to 2 N_b; f_xc is the
+    second derivative of n eps_xc(n) (central differences of the energy
+    density written out above) and equals the input preparation's kernel."""
+    lz = _lz()
+    s = config_system(name)
+    print(f"[density] {name}", flush=True)
+    L = Liouvillian(s, "ipa")
+    ref = np.zeros(L.cell.ntot)
+    for k in range(s.nks):
+        ref += 2.0 * s.wk[k] * np.sum(np.abs(L.u_r[k]) ** 2, axis=0)
+    for xc in ("pz", "x"):
+        n0, fxc = lz.lz_ground_density(s, xc=xc)
+        assert np.abs(n0 - ref).max() < 1e-12 * ref.max()
+        assert abs(n0.sum() * L.cell.omega / L.cell.ntot - 2 * s.nbnd) < 1e-10 * s.nbnd
+        want = pz_lda_fxc(n0) if xc == "pz" else x_lda_fxc(n0)
+        assert np.abs(fxc - want).max() < 1e-12 * np.abs(want).max()
+    n0, fxc = lz.lz_ground_density(s, xc="pz")
+    rs = (3.0 / (4.0 * np.pi * n0)) ** (1.0 / 3.0)
+    sel = (n0 > 1e-6) & (np.abs(rs - 1.0) > 1e-2)
+    h = 1e-4 * n0[sel]
+    fd = (_pz_energy_density(n0[sel] + h) - 2 * _pz_energy_density(n0[sel]) +
+          _pz_energy_density(n0[sel] - h)) / h ** 2
+    assert np.max(np.abs(fxc[sel] - fd) / np.abs(fd)) < 1e-5
+
+
+CFG5_REF = __import__("os").path.join(__import__("os").path.dirname(__import__("os").path.abspath(__file__)),
+                                      "golden", "cfg5_oracle_reference.npz")
+
+
+@pytest.mark.slow
+@pytest.mark.skipif(not __import__("os").path.exists(CFG5_REF),
+                    reason="the oracle's large-cell reference has not been written "
+                           "(tests/golden/make_cfg5_reference.py)")
+def test_large_cell_ground_state_drives_the_recursion():
+    """The 96^3 cell with 128 bands, 256 projectors and 4 k: the lowest 128
+    eigenpairs of every k and k+q sphere, the density and f_xc from the
+    device, then 50 Lanczos steps; the band energies and the coefficients
+    against the oracle's run on the input preparation's orbitals
+    (tests/golden/cfg5_oracle_reference.npz): energies to 1e-9 Ha, beta and
+    z to 1e-7 (the orbitals agree to the solver tolerance, up to rotations
+    inside the valence manifold, which the coefficients do not see)."""
+    lz = _lz()
+    r = np.load(CFG5_REF, allow_pickle=False)
+    s = config_system("cfg5r")   # geometry, spheres, potential, projectors
+    assert np.array_equal(r["npw_kq"], s.npw_kq) and np.array_equal(r["npw_k"], s.npw_k)
+    nb = s.nbnd
+    print("[cfg5] ground state at k+q", flush=True)
+    evc_kq, eps_kq, it1, res1 = lz.lz_ground_state(s, n_extra=4, tol=1e-9)
+    print(f"[cfg5] {it1} iterations, residual {res1:.1e}; ground state at k", flush=True)
+    sk = k_sphere_system("cfg5r")
+    evc_k, eps_k, it2, res2 = lz.lz_ground_state(sk, n_extra=4, tol=1e-9)
+    print(f"[cfg5] {it2} iterations, residual {res2:.1e}", flush=True)
+    assert np.abs(eps_kq - r["et_kq"][:, :nb]).max() < 1e-9
+    assert np.abs(eps_k - r["et_k"]).max() < 1e-9
+    g = copy.copy(s)
+    g.evc_k, g.evc_kq, g.et_k = evc_k, evc_kq, eps_k
+    n0, fxc = lz.lz_ground_density(g, xc="pz")
+    assert abs(n0.sum() * s.omega / n0.size - float(r["n0_sum"])) < 1e-9 * float(r["n0_sum"])
+    g.fxc_r = fxc
+    ctx = lz.lz_init(g, prec="fp64", max_steps=64)
+    done, _ = ctx.step(50)
+    assert done == 50
+    beta, _, z = ctx.coefficients()
+    print(f"[cfg5] beta err {np.max(np.abs(beta - r['beta']) / r['beta']):.2e}", flush=True)
+    assert np.max(np.abs(beta - r["beta"]) / r["beta"]) < 1e-7
+    assert np.abs(z - r["z"]).max() < 1e-7 * np.abs(r["z"]).max()
+    ctx.free()
+
+
+def test_free_electrons_many_bands_closed_form():
+    """89 bands at once (3 (89 + 4) > 256: the Chebyshev-filtered subspace
+    iteration): the eigenvalues are the 89 lowest kinetic energies of the
+    sphere (a gap of 0.12 Ha above the 89th), orthonormal orbitals."""
+    lz = _lz()
+    s = config_system("free", ecut=8.0)
+    evc, eps, it, res = lz.lz_ground_state(s, nbnd=89, n_extra=4, tol=1e-9)
+    print(f"[ground] free, 89 bands: {it} iterations, residual {res:.1e}", flush=True)
+    from oracle import pw
+    m = pw.miller_from_index(s.nl_kq[0, :s.npw_kq[0]], s.nr)
+    kin = np.sort(0.5 * np.sum((s.xk[0] + s.q + m @ pw.reciprocal(s.at)) ** 2, axis=1))[:89]
+    assert res < 1e-9
+    assert np.abs(eps[0] - kin).max() < 1e-9
+    g = evc[0].conj() @ evc[0].T
+    assert np.abs(g - np.eye(89)).max() < 1e-10
