@@ -8,8 +8,9 @@
         (32 in total), 16 bands, 8 k on a 2x2x2 mesh with a seeded shift,
         q = 0.2 (2pi/a) along [100], Perdew-Zunger ALDA, 1000 Lanczos steps.
   cfg3  cfg2 run in mixed precision (3000 steps).
-  cfg5r the large cell (64 wells = the 2x2x2 supercell of cfg2's sites, a=20.5
-        bohr, 96^3 grid at ecut 25 Ha, 256 projectors, 128 bands, 4 k on a
+  cfg5r the large cell (64 wells = the 2x2x2 supercell of cfg2's sites and
+        projectors, a=20.5 bohr, 96^3 grid at ecut 25 Ha, 256 projectors, 128
+        bands, 4 k on a
         2x2x1 mesh, q = (0.2, 0.1, 0) 2pi/a) with seeded random orthonormal
         orbitals in place of eigenstates: operator-level parity and
         throughput at the full size.
@@ -117,9 +118,15 @@ def _spec(name: str, **kw) -> dict:
                           for o in [(0, 0, 0), (0, 0, 1), (0, 1, 0), (0, 1, 1),
                                     (1, 0, 0), (1, 0, 1), (1, 1, 0), (1, 1, 1)]
                           for i in range(8)])
+        # every image of a site of the 8-atom cell carries that site's
+        # projector radii and energies (those of cfg2), so that the cell is a
+        # supercell of cfg2's crystal (scaled to a = 20.5): independently
+        # drawn energies for the 64 sites left a gap of 1.7 mHa at 128 bands
+        rng2 = np.random.default_rng(2)
+        radii = np.tile(rng2.uniform(0.8, 1.2, (8, 2)), (8, 1))
+        dkb = np.tile(np.stack([rng2.uniform(3.0, 8.0, 8), rng2.uniform(0.1, 0.5, 8)], axis=1),
+                      (8, 1))
         rng = np.random.default_rng(5)
-        radii = rng.uniform(0.8, 1.2, (64, 2))
-        dkb = np.stack([rng.uniform(3.0, 8.0, 64), rng.uniform(0.1, 0.5, 64)], axis=1)
         shift = rng.random(3)
         shift[2] = 0.0
         nbnd = kw.get("nbnd", 128)

@@ -129,13 +129,15 @@ def test_uneven_members_recursions_in_one_context():
     """Ten members of the batched uneven workload (grids 32^3 to 72^3, up to
     768 band-k products) advance their recursions side by side in one
     context; the eight smallest members' first 40 coefficients and the two
-    largest members' first 6 equal the oracle's: beta to 1e-10 relative, z to
-    1e-10 of max|z| over the first 20 steps and 1e-9 beyond (these members'
-    orbitals are seeded orthonormal sets with energies placed below the
-    spectrum of H, not eigenstates; rounding grows along their recursions --
-    the oracle's own Im z, zero in exact arithmetic, doubles every two steps
-    on the 40^3 member, and the GPU's z of step 40 differs from the oracle's
-    by 1.8e-10 of max|z|)."""
+    largest members' first 6 against the oracle: beta to 1e-10 relative and z
+    to 1e-10 of max|z| at every step.  These members' orbitals are seeded
+    orthonormal sets with energies below the spectrum of H (not eigenstates:
+    D is positive definite by construction), so the check runs in the RPA,
+    whose Hartree kernel keeps D + K positive definite too; with the ALDA
+    kernel of their random densities the metric of several members is close
+    to indefinite and their recursions amplify rounding (by about 10 per step
+    on three of them, where the oracle's own Im z, zero in exact arithmetic,
+    grows at the same rate), which no two implementations reproduce alike."""
     import os
 
     import oracle.pw as opw
@@ -144,18 +146,20 @@ def test_uneven_members_recursions_in_one_context():
     idx = SMALLEST + LARGEST
     systems = [config_system("uneven", index=i) for i in idx]
     print("[uneven] members built", flush=True)
-    ctx = lz.lz_init(systems, prec="fp64", max_steps=48)
+    ctx = lz.lz_init(systems, prec="fp64", approx="rpa", max_steps=48)
     done, st = ctx.step(40)
     assert st == lz.LZ_OK
+    worst_b, worst_z = 0.0, 0.0
     for j, (i, s) in enumerate(zip(idx, systems)):
         n = 40 if i in SMALLEST else 6
-        print(f"[uneven] member {i}: grid {int(s.nr[0])}, {s.nbnd} bands, {s.nks} k, oracle {n} steps",
-              flush=True)
-        ref = lanczos.run(Liouvillian(s), n)
+        ref = lanczos.run(Liouvillian(s, "rpa"), n)
         beta, _, z = ctx.coefficients(inst=j)
         assert ctx.state(j)[0] == 40
-        assert np.max(np.abs(beta[:n] - ref.beta) / ref.beta) < 1e-10
-        zmax = np.abs(ref.z).max()
-        assert np.abs(z[:min(n, 20)] - ref.z[:20]).max() < 1e-10 * zmax
-        assert np.abs(z[:n] - ref.z).max() < 1e-9 * zmax
+        eb = float(np.max(np.abs(beta[:n] - ref.beta) / ref.beta))
+        ez = float(np.abs(z[:n] - ref.z).max() / np.abs(ref.z).max())
+        print(f"[uneven] member {i}: grid {int(s.nr[0])}, {s.nbnd} bands, {s.nks} k, {n} steps: "
+              f"beta {eb:.1e}, z {ez:.1e}", flush=True)
+        worst_b, worst_z = max(worst_b, eb), max(worst_z, ez)
     ctx.free()
+    assert worst_b < 1e-10
+    assert worst_z < 1e-10
