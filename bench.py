@@ -230,29 +230,31 @@ def q_sweep_rate(systems, prec, steps):
     """Instance-applies/s of a q-dispersion sweep (the 32^3 crystal at eight
     q along [100], one instance per q, in one context): the instances one
     after another on one stream against side by side on the library's
-    default streams, each with and without graph replay.  Outside the timed
-    region of the headline metric."""
+    default streams, each with and without graph replay, and one launch per
+    kernel of a step over all eight (batched).  Outside the timed region of
+    the headline metric."""
     import torch
 
     import paper_2111_06623_amd as lz
     out = {"workload": "q sweep: 32^3 cell (cfg2 crystal at ecut 8 Ha, 16 bands, 2 k) at "
                        "q = (0.05..0.6) 2pi/a [100], 8 instances", "precision": prec,
            "instances": len(systems), "steps": steps}
-    for streams, tag in ((1, "one_stream"), (0, "side_by_side")):
-        for graph in (False, True):
-            ctx = lz.lz_init(systems, prec=prec, max_steps=steps + 8, use_graph=graph,
-                             streams=streams)
-            ctx.step(4)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            done, _ = ctx.step(steps)
-            torch.cuda.synchronize()
-            dt = time.perf_counter() - t0
-            if done != steps + 4:
-                raise RuntimeError(f"sweep stopped at {done} steps")
-            key = f"{tag}{'_graph' if graph else ''}"
-            out[key] = round(len(systems) * steps / 2 / dt, 1)
-            ctx.free()
+    modes = [(1, False, False, "one_stream"), (1, True, False, "one_stream_graph"),
+             (0, False, False, "side_by_side"), (0, True, False, "side_by_side_graph"),
+             (1, False, True, "one_launch"), (1, True, True, "one_launch_graph")]
+    for streams, graph, batched, key in modes:
+        ctx = lz.lz_init(systems, prec=prec, max_steps=steps + 8, use_graph=graph,
+                         streams=streams, batched=batched)
+        ctx.step(4)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        done, _ = ctx.step(steps)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        if done != steps + 4:
+            raise RuntimeError(f"sweep stopped at {done} steps")
+        out[key] = round(len(systems) * steps / 2 / dt, 1)
+        ctx.free()
     out["unit"] = "instance-applies/s"
     return out
 
@@ -337,7 +339,10 @@ def batched_rate(n_inst, prec="fp32", reps=5, steps=100):
     that D is positive definite) in one context: recursions of `steps` steps
     of every member (lz_step), and operator applications
     (lz_apply_liouvillian), one instance after another on one stream against
-    side by side on the library's streams."""
+    side by side on the library's streams; the recursions also with one
+    launch per kernel of a step over every member of a group of instances
+    that issue the same kernels (batched), the groups one after another or
+    side by side."""
     import torch
 
     import paper_2111_06623_amd as lz
@@ -353,8 +358,10 @@ def batched_rate(n_inst, prec="fp32", reps=5, steps=100):
            "grids": [int(s.nr[0]) for s in systems],
            "band_k_products": [int(s.nks) * int(s.evc_kq.shape[1]) for s in systems]}
     dt = torch.complex128 if prec == "fp64" else torch.complex64
-    for streams, tag in ((1, "one_stream"), (0, "side_by_side")):
-        ctx = lz.lz_init(systems, prec=prec, max_steps=steps + 4, streams=streams)
+    modes = [(1, False, "one_stream"), (0, False, "side_by_side"), (1, True, "one_launch"),
+             (0, True, "one_launch_side_by_side")]
+    for streams, batched, tag in modes:
+        ctx = lz.lz_init(systems, prec=prec, max_steps=steps + 4, streams=streams, batched=batched)
         ctx.step(2)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -367,6 +374,9 @@ def batched_rate(n_inst, prec="fp32", reps=5, steps=100):
         done = [ctx.state(i) for i in range(n_inst)]
         out[f"recursion_{tag}"] = round(sum(min(d, steps + 2) - 2 for d, _ in done) / 2 / el, 2)
         out[f"recursion_{tag}_stopped"] = [i for i, (d, st) in enumerate(done) if st != 0]
+        if batched:  # operator applications are not batched: the per-instance figures hold
+            ctx.free()
+            continue
         x = torch.randn(sum(ctx.nvec), dtype=dt, device="cuda")
         qo, po = torch.empty_like(x), torch.empty_like(x)
         ctx.apply_liouvillian(x, x, qo, po)
@@ -706,7 +716,7 @@ def main():
         "config": {"workload": wl, "precision": head, "lanczos_steps_per_recursion": M,
                    "timing": f"median of {WINDOWS} windows of {r['applies']} applies",
                    "graph": a.graph, "autotune": not a.no_autotune,
-                   "tuning": {p: dict(zip(("projector_gemm", "density_group_bands", "projector_chunks"),
+                   "tuning": {p: dict(zip(("projector_gemm", "density_group_bands", "projector_chunks", "fft_planes"),
                                           res[p]["tuning"])) for p in res},
                    "spectrum": "2000 frequencies in [0, 2] Ha, eta 0.01 Ha"},
         "roofline": roof,

@@ -121,12 +121,15 @@ typedef struct {
   int32_t max_steps;  /* capacity of the coefficient arrays (>= 1) */
   int32_t use_graph;  /* nonzero: lz_step replays every pair of steps after the first as one
                          captured hipGraph (built on first use; not while the stage timer is
-                         on); results are bitwise identical to the eager launches */
+                         on; with batched, one graph holds the pair of every group); results
+                         are bitwise identical to the eager launches */
   int32_t autotune;   /* 0: the built-in launch heuristics.  1: lz_init times, per instance,
                          candidate launch configurations (projector products on the vector
                          ALU or the matrix cores, unless projector_gemm asks for one; two
                          sizes of the density band groups; three plane-wave chunk lengths of
-                         the vector-ALU projector dot) on a few operator applications
+                         the vector-ALU projector dot; the register-line or lane-pair plane
+                         transforms against LDS Stockham passes, see fft_planes) on a few
+                         operator applications
                          and keeps the fastest (lz_get_tuning reports it).  Candidates agree
                          to rounding, so with 1 the bits of a run may depend on the timing. */
   lz_algorithm algorithm;
@@ -142,6 +145,21 @@ typedef struct {
   int32_t projector_chunk;      /* plane waves per partial of the vector-ALU projector dot:
                                    0 = the heuristic (64; or the autotuner's pick among 64, 128,
                                    256), or one of 64, 128, 256; fixed, it is not tuned */
+  int32_t fft_planes;  /* schedule of the 2-D plane transforms: 0 = register-line (one thread
+                          per line: 24^2-48^2 planes in FP32) or lane-pair (64^2-96^2 in FP32,
+                          the v'u pass on 48^2 in FP64) kernels where they exist, else LDS
+                          Stockham passes, and with autotune the autotuner also times the
+                          other; 1 = the former, 2 = the LDS passes everywhere; fixed (1, 2)
+                          it is not tuned.  Results agree to rounding across the choices. */
+  int32_t batched;  /* 1: lz_step advances the pseudo-Hermitian recursions of all instances
+                       with one launch per kernel of a step over all of them (a work list of
+                       (instance, block) items; instances whose steps issue different kernels
+                       -- other grids, precisions or projector paths -- form groups, each
+                       group launched as one, groups side by side on the `streams` streams).
+                       Applies while every running instance is at the same step, no stage
+                       timer is on and the algorithm is pseudo-Hermitian; otherwise, and with
+                       0, every instance issues its own launches.  Results do not depend on
+                       it (bitwise). */
 } lz_options;
 
 /*
@@ -277,7 +295,8 @@ lz_status lz_spectrum_ext_noalloc(lz_ctx *ctx, int32_t inst, int32_t m0, int32_t
  * density pass and the plane-wave chunks of its projector dots.  Any output
  * may be NULL. */
 lz_status lz_get_tuning(lz_ctx *ctx, int32_t inst, int32_t *projector_gemm,
-                        int32_t *density_group_bands, int32_t *projector_chunks);
+                        int32_t *density_group_bands, int32_t *projector_chunks,
+                        int32_t *fft_planes);
 
 /* Copy the right-hand side y of instance inst to a device array in the
  * caller's layout and precision (as lz_apply_liouvillian). */

@@ -27,6 +27,7 @@ LZ_PSEUDO_HERMITIAN, LZ_NON_HERMITIAN = 0, 1
 ALGORITHM = {"ph": LZ_PSEUDO_HERMITIAN, "nh": LZ_NON_HERMITIAN}
 LZ_GEMM_AUTO, LZ_GEMM_VALU, LZ_GEMM_MFMA = 0, 1, 2
 GEMM = {"auto": LZ_GEMM_AUTO, "valu": LZ_GEMM_VALU, "mfma": LZ_GEMM_MFMA}
+FFT_PLANES = {"auto": 0, "registers": 1, "lds": 2}
 STATUS_NAMES = {0: "ok", 1: "arg", 2: "hip", 3: "oom", 4: "not_pd", 5: "state", 6: "breakdown"}
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "liblz.so")
@@ -53,7 +54,8 @@ class LzOptions(ctypes.Structure):
                 ("use_graph", ctypes.c_int32), ("autotune", ctypes.c_int32),
                 ("algorithm", ctypes.c_int), ("streams", ctypes.c_int32),
                 ("projector_gemm", ctypes.c_int), ("density_group_bands", ctypes.c_int32),
-                ("projector_chunk", ctypes.c_int32)]
+                ("projector_chunk", ctypes.c_int32), ("fft_planes", ctypes.c_int32),
+                ("batched", ctypes.c_int32)]
 
 
 class LzError(RuntimeError):
@@ -90,7 +92,7 @@ def load(path: str = LIB_PATH):
     lib.lz_get_coefficients.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _dp, _dp, _dp]
     lib.lz_get_state.argtypes = [vp, ctypes.c_int32, _ip, _ip]
     lib.lz_get_gamma.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _dp]
-    lib.lz_get_tuning.argtypes = [vp, ctypes.c_int32, _ip, _ip, _ip]
+    lib.lz_get_tuning.argtypes = [vp, ctypes.c_int32, _ip, _ip, _ip, _ip]
     lib.lz_ground_state.argtypes = [ctypes.POINTER(LzSystem), ctypes.c_int32, ctypes.c_double,
                                     ctypes.c_int32, ctypes.c_int32, vp, _dp, _dp, _ip, _dp]
     lib.lz_ground_density.argtypes = [ctypes.POINTER(LzSystem), ctypes.c_int32, ctypes.c_int32, vp,
@@ -179,13 +181,15 @@ def _stream_handle(device):
 
 def lz_init(systems, prec="fp64", approx="tddft", max_steps=1000, use_graph=False, autotune=False,
             device=0, stream=None, algorithm="ph", streams=0, projector_gemm="auto",
-            density_group_bands=0, projector_chunk=0):
+            density_group_bands=0, projector_chunk=0, fft_planes="auto", batched=False):
     """Create a context for one system or a list of systems; returns a handle.
     algorithm: "ph" (pseudo-Hermitian) or "nh" (non-Hermitian biorthogonal);
     streams: instances stepped side by side (0: the library default);
+    batched: lz_step runs one launch per kernel over all instances (work list);
     projector_gemm: "auto", "valu" or "mfma" (where the projector products run);
     density_group_bands, projector_chunk: fixed launch parameters (0: heuristic
-    or autotuned)."""
+    or autotuned); fft_planes: "auto", "registers" (register-line / lane-pair
+    plane transforms where they exist) or "lds" (LDS Stockham passes)."""
     lib = load()
     systems = systems if isinstance(systems, (list, tuple)) else [systems]
     arr = (LzSystem * len(systems))()
@@ -199,7 +203,9 @@ def lz_init(systems, prec="fp64", approx="tddft", max_steps=1000, use_graph=Fals
                     ALGORITHM[algorithm] if isinstance(algorithm, str) else int(algorithm),
                     int(streams),
                     GEMM[projector_gemm] if isinstance(projector_gemm, str) else int(projector_gemm),
-                    int(density_group_bands), int(projector_chunk))
+                    int(density_group_bands), int(projector_chunk),
+                    FFT_PLANES[fft_planes] if isinstance(fft_planes, str) else int(fft_planes),
+                    int(bool(batched)))
     out = ctypes.c_void_p()
     hs = _stream_handle(device) if stream is None else ctypes.c_void_p(stream)
     _check(lib.lz_init(arr, len(systems), ctypes.byref(opt), int(device), hs, ctypes.byref(out)))
@@ -356,12 +362,14 @@ class Context:
         return chi.view(np.complex128), einv.view(np.complex128), loss
 
     def tuning(self, inst=0):
-        """(projector path name, density band-group size, projector dot chunks)
-        of one instance (lz_get_tuning)."""
-        g, b, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        """(projector path name, density band-group size, projector dot chunks,
+        plane-transform schedule "registers" or "lds") of one instance
+        (lz_get_tuning)."""
+        g, b, c, f = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
         _check(load().lz_get_tuning(self.handle, int(inst), ctypes.byref(g), ctypes.byref(b),
-                                    ctypes.byref(c)))
-        return {LZ_GEMM_VALU: "valu", LZ_GEMM_MFMA: "mfma"}[g.value], int(b.value), int(c.value)
+                                    ctypes.byref(c), ctypes.byref(f)))
+        return ({LZ_GEMM_VALU: "valu", LZ_GEMM_MFMA: "mfma"}[g.value], int(b.value), int(c.value),
+                {1: "registers", 2: "lds"}[f.value])
 
     def checkpoint(self, inst=0):
         """The recursion state of one instance as bytes (lz_checkpoint_save)."""

@@ -486,6 +486,103 @@ void build_pair_graph(Instance& I, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------------------
+// work-list launches over the instances of a context
+// ---------------------------------------------------------------------------
+// One kernel of a step, merged over the members of a group: the launch runs
+// nblocks work items, item[b] naming the member and its block (lz_batch.h).
+struct MergedLaunch {
+  const void* fn = nullptr;
+  dim3 block;
+  size_t lds = 0;
+  unsigned nblocks = 0;
+  int stride = 0;
+  DBuf tab, item;
+  std::vector<unsigned char> args0;  // argument bytes of the first member (the kernel's P slot)
+};
+
+// Instances whose steps issue the same kernels (with the same block shapes),
+// advanced together: the merged launches of a first step (j = 0, no update),
+// an odd step (D+K on an upper vector) and an even step (D).
+struct BatchGroup {
+  std::vector<int> members;
+  std::vector<std::unique_ptr<MergedLaunch>> plan[3];
+};
+
+int plan_of_step(int j) { return j == 0 ? 0 : (j & 1) ? 1 : 2; }
+
+// The launches step j of instance I issues, recorded instead of run.  The
+// recording runs inside a capture of the private stream s, so that anything
+// issued around the recorder would land in the captured graph rather than on
+// the device; a non-empty graph is an error.
+std::vector<LaunchRec> record_step(Instance& I, int j, hipStream_t s) {
+  std::vector<LaunchRec> rec;
+  HIPC(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+  t_launch_rec = &rec;
+  try {
+    if (I.fp64) lanczos_step<double>(I, j, s);
+    else lanczos_step<float>(I, j, s);
+  } catch (...) {
+    t_launch_rec = nullptr;
+    hipGraph_t g = nullptr;
+    (void)hipStreamEndCapture(s, &g);
+    if (g) (void)hipGraphDestroy(g);
+    throw;
+  }
+  t_launch_rec = nullptr;
+  hipGraph_t g = nullptr;
+  HIPC(hipStreamEndCapture(s, &g));
+  size_t nodes = 0;
+  const hipError_t e = hipGraphGetNodes(g, nullptr, &nodes);
+  (void)hipGraphDestroy(g);
+  HIPC(e);
+  if (nodes != 0) fail(LZ_ERR_HIP, "a step issued work outside the launch recorder");
+  return rec;
+}
+
+bool same_kernels(const std::vector<LaunchRec>& a, const std::vector<LaunchRec>& b) {
+  if (a.size() != b.size()) return false;
+  for (size_t i = 0; i < a.size(); ++i)
+    if (a[i].fn != b[i].fn || a[i].fnb != b[i].fnb || a[i].block.x != b[i].block.x || a[i].block.y != b[i].block.y ||
+        a[i].block.z != b[i].block.z || a[i].args.size() != b[i].args.size())
+      return false;
+  return true;
+}
+
+// Launch l of the recorded sequences of the members, merged.
+std::unique_ptr<MergedLaunch> merge_launch(const std::vector<const std::vector<LaunchRec>*>& recs,
+                                           size_t l) {
+  auto m = std::make_unique<MergedLaunch>();
+  const LaunchRec& r0 = (*recs[0])[l];
+  if (!r0.fnb) fail(LZ_ERR_HIP, "a kernel of the step has no work-list form");
+  m->fn = r0.fnb;
+  m->block = r0.block;
+  m->args0 = r0.args;
+  m->stride = (int)((sizeof(BatchGrid) + r0.args.size() + 15) / 16 * 16);
+  std::vector<unsigned char> tab(recs.size() * (size_t)m->stride, 0);
+  std::vector<unsigned> item;
+  for (size_t i = 0; i < recs.size(); ++i) {
+    const LaunchRec& r = (*recs[i])[l];
+    const BatchGrid g{(int)r.grid.x, (int)r.grid.y, (int)r.grid.z, 0};
+    std::memcpy(tab.data() + i * m->stride, &g, sizeof(g));
+    std::memcpy(tab.data() + i * m->stride + sizeof(g), r.args.data(), r.args.size());
+    const uint64_t nb = (uint64_t)r.grid.x * r.grid.y * r.grid.z;
+    if (nb > kBatchLocalMask) fail(LZ_ERR_ARG, "an instance's launch exceeds 2^24 blocks");
+    for (unsigned b = 0; b < (unsigned)nb; ++b) item.push_back(((unsigned)i << 24) | b);
+    m->lds = std::max(m->lds, r.lds);
+  }
+  m->nblocks = (unsigned)item.size();
+  upload(m->tab, tab);
+  upload(m->item, item);
+  return m;
+}
+
+// Group the instances by the kernels of their three kinds of step and merge
+// each group's launches (once, after the autotuner has fixed every launch
+// configuration; the argument structs hold only buffers and sizes that do
+// not change later, the step's coefficients are read from device state).
+void build_batch(lz_ctx* c);
+
+// ---------------------------------------------------------------------------
 // launch configurations and the autotuner
 // ---------------------------------------------------------------------------
 struct LaunchCfg {
@@ -496,9 +593,11 @@ struct LaunchCfg {
   int nlzblk_nl;  // the same for the update over the separable rows only
   int gsize;    // bands per group of the density pass
   int ngroups;
+  int lds_planes;  // 1: LDS Stockham plane kernels in place of register lines / lane pairs
 };
 
 void set_cfg(Instance& I, const LaunchCfg& c) {
+  I.grid.lds_planes = c.lds_planes;
   I.gemm = c.gemm;
   I.chunk = c.chunk;
   I.nchunk = c.nchunk;
@@ -508,9 +607,11 @@ void set_cfg(Instance& I, const LaunchCfg& c) {
   I.ngroups = c.ngroups;
 }
 
-LaunchCfg make_cfg(const Instance& I, int gemm, int gsize, int chunk = kProjChunk) {
+LaunchCfg make_cfg(const Instance& I, int gemm, int gsize, int chunk = kProjChunk,
+                   int lds_planes = 0) {
   LaunchCfg c;
   c.gemm = gemm;
+  c.lds_planes = lds_planes;
   if (gemm != kGemmValu)
     c.chunk = I.fp64 ? LaunchLin<double>::mfma_chunk(I.ptot, I.nbnd, I.npwx, I.nks)
                      : LaunchLin<float>::mfma_chunk(I.ptot, I.nbnd, I.npwx, I.nks);
@@ -534,31 +635,40 @@ LaunchCfg make_cfg(const Instance& I, int gemm, int gsize, int chunk = kProjChun
 //    (the block count is then a multiple of what the compute units hold at
 //    once);
 // then, for the autotuner, the other projector path (unless one was asked
-// for), groups of twice the bands and, on the vector ALU, dot chunks of 128
-// and 256 plane waves.
-std::vector<LaunchCfg> launch_candidates(const Instance& I, const lz_options& opt) {
-  const bool mc = opt.projector_gemm == LZ_GEMM_MFMA ||
-                  (opt.projector_gemm == LZ_GEMM_AUTO && I.nbnd >= 32 && I.ptot >= 64);
-  const int gemm0 = I.prec == LZ_FP32_SPLITBF16 ? kGemmBf16x3 : mc ? kGemmMfma : kGemmValu;
-  const int rn = I.fp64 ? reg_plane_size<double>(I.grid) : reg_plane_size<float>(I.grid);
-  int g0;
-  if (rn && rn < 64) {
-    g0 = 192 / rn;
-  } else if (rn || I.n3 >= 72) {
+// for), groups of twice the bands, on the vector ALU dot chunks of 128 and
+// 256 plane waves, and the other schedule of the 2-D plane transforms
+// (register lines or lane pairs against LDS Stockham passes) where both exist.
+int heuristic_group(const Instance& I, int rn) {
+  if (rn && rn < 64) return 192 / rn;
+  if (rn || I.n3 >= 72) {
     // a band at a time per block (the lane-pair kernels of 96^2 planes, and
     // the LDS kernels of large planes, which add into their slice of the
     // group partial): groups of 8 bands give n3 x N_b/8 blocks, so that the
     // last round of blocks is not a small remainder of a few long blocks (the
     // group partials then take N_b/8 grids)
-    g0 = std::min(I.nb, 8);
-  } else {  // LDS kernels
-    const int ng = std::max(1, std::min(I.nb, (1024 + I.n3 - 1) / I.n3));
-    g0 = (I.nb + ng - 1) / ng;
+    return std::min(I.nb, 8);
   }
+  // LDS kernels
+  const int ng = std::max(1, std::min(I.nb, (1024 + I.n3 - 1) / I.n3));
+  return (I.nb + ng - 1) / ng;
+}
+
+std::vector<LaunchCfg> launch_candidates(Instance& I, const lz_options& opt) {
+  const bool mc = opt.projector_gemm == LZ_GEMM_MFMA ||
+                  (opt.projector_gemm == LZ_GEMM_AUTO && I.nbnd >= 32 && I.ptot >= 64);
+  const int gemm0 = I.prec == LZ_FP32_SPLITBF16 ? kGemmBf16x3 : mc ? kGemmMfma : kGemmValu;
+  // register-line / lane-pair kernels exist for this grid and precision?
+  I.grid.lds_planes = 0;
+  const int rn_reg = I.fp64 ? reg_plane_size<double>(I.grid) : reg_plane_size<float>(I.grid);
+  const bool reg_avail = rn_reg != 0 || (I.fp64 && I.n1 == 48 && I.n2 == 48 && I.n3 == 48 &&
+                                         I.grid.soff_c != nullptr);
+  const int lds0 = opt.fft_planes == 2 ? 1 : 0;
+  const int g_reg = heuristic_group(I, rn_reg), g_lds = heuristic_group(I, 0);
+  int g0 = lds0 ? g_lds : g_reg;
   // a group size or a dot chunk the caller fixes replaces the heuristic and is not tuned
   if (opt.density_group_bands > 0) g0 = opt.density_group_bands;
   const int ch0 = opt.projector_chunk > 0 ? opt.projector_chunk : kProjChunk;
-  std::vector<LaunchCfg> c{make_cfg(I, gemm0, g0, ch0)};
+  std::vector<LaunchCfg> c{make_cfg(I, gemm0, g0, ch0, lds0)};
   if (!opt.autotune) return c;
   std::vector<int> gemms{gemm0};
   if (opt.projector_gemm == LZ_GEMM_AUTO && I.prec != LZ_FP32_SPLITBF16)
@@ -572,9 +682,11 @@ std::vector<LaunchCfg> launch_candidates(const Instance& I, const lz_options& op
       for (int ch : chunks) {
         if (gm != kGemmValu && ch != ch0) continue;  // the matrix-core dot sizes its own
         if (gm == gemm0 && gs == g0 && ch == ch0) continue;
-        c.push_back(make_cfg(I, gm, gs, ch));
+        c.push_back(make_cfg(I, gm, gs, ch, lds0));
       }
     }
+  if (opt.fft_planes == 0 && reg_avail)
+    c.push_back(make_cfg(I, gemm0, opt.density_group_bands > 0 ? g0 : g_lds, ch0, 1));
   return c;
 }
 
@@ -937,6 +1049,7 @@ std::unique_ptr<Instance> build_instance(const lz_system& sys, const lz_options&
   // row tables of the register-line plane kernels (cubic grids up to 96)
   I.grid.soff_f = nullptr;
   I.grid.soff_c = nullptr;
+  I.grid.lds_planes = 0;
   for (int i = 0; i < 128; ++i) I.grid.slot[i] = -1;
   if (I.n1 == I.n2 && I.n2 == I.n3 && I.n1 <= 96) {
     const int pitch = I.n1 + 1;
@@ -1009,8 +1122,17 @@ struct lz_ctx {
   lz_options opt{};
   std::vector<std::unique_ptr<Instance>> inst;
   bool started = false;
+  // work-list launches (opt.batched): groups of instances and their merged
+  // steps, built at the first batched lz_step
+  std::vector<std::unique_ptr<BatchGroup>> groups;
+  bool batch_built = false;
+  hipStream_t capture = nullptr;  // private stream of the launch recorder
+  hipGraphExec_t batch_pair = nullptr;  // a pair of batched steps (use_graph)
   ~lz_ctx() {
+    if (batch_pair) (void)hipGraphExecDestroy(batch_pair);
+    groups.clear();
     inst.clear();
+    if (capture) (void)hipStreamDestroy(capture);
     for (auto e : qdone) (void)hipEventDestroy(e);
     for (auto q : qs) (void)hipStreamDestroy(q);
     if (ev_fork) (void)hipEventDestroy(ev_fork);
@@ -1092,6 +1214,64 @@ void read_state(lz_ctx* c) {
   }
 }
 
+void build_batch(lz_ctx* c) {
+  c->groups.clear();
+  if (!c->capture) HIPC(hipStreamCreateWithFlags(&c->capture, hipStreamNonBlocking));
+  const int ni = (int)c->inst.size();
+  std::vector<std::vector<LaunchRec>> rec[3];
+  for (int k = 0; k < 3; ++k) rec[k].resize(ni);
+  for (int i = 0; i < ni; ++i)
+    for (int k = 0; k < 3; ++k) rec[k][i] = record_step(*c->inst[i], k, c->capture);
+  std::vector<int> group_of(ni, -1);
+  for (int i = 0; i < ni; ++i) {
+    for (size_t g = 0; g < c->groups.size() && group_of[i] < 0; ++g) {
+      const int r = c->groups[g]->members[0];
+      if ((int)c->groups[g]->members.size() < kBatchMaxInst && same_kernels(rec[0][i], rec[0][r]) &&
+          same_kernels(rec[1][i], rec[1][r]) && same_kernels(rec[2][i], rec[2][r])) {
+        c->groups[g]->members.push_back(i);
+        group_of[i] = (int)g;
+      }
+    }
+    if (group_of[i] < 0) {
+      c->groups.push_back(std::make_unique<BatchGroup>());
+      c->groups.back()->members.push_back(i);
+      group_of[i] = (int)c->groups.size() - 1;
+    }
+  }
+  for (auto& gp : c->groups) {
+    for (int k = 0; k < 3; ++k) {
+      std::vector<const std::vector<LaunchRec>*> recs;
+      for (int i : gp->members) recs.push_back(&rec[k][i]);
+      for (size_t l = 0; l < recs[0]->size(); ++l) gp->plan[k].push_back(merge_launch(recs, l));
+    }
+  }
+  c->batch_built = true;
+}
+
+// One step of every member of group g (all at step j) on stream s.
+void batched_step(const BatchGroup& g, int j, hipStream_t s) {
+  for (const auto& m : g.plan[plan_of_step(j)]) {
+    if (m->nblocks == 0) continue;
+    BatchRef br{m->tab.as<unsigned char>(), m->item.as<unsigned>(), m->stride, 0};
+    void* args[2] = {const_cast<unsigned char*>(m->args0.data()), &br};
+    HIPC(hipLaunchKernel(m->fn, dim3(m->nblocks), m->block, args, m->lds, s));
+  }
+}
+
+// The work-list path serves a step of the pseudo-Hermitian recursion when
+// every running instance is at the same step and no stage timer is on.
+bool batch_applies(const lz_ctx* c) {
+  if (!c->opt.batched) return false;
+  int j = -1;
+  for (const auto& ip : c->inst) {
+    if (ip->nh || ip->timer.on) return false;
+    if (ip->status_host != 0) continue;
+    if (j >= 0 && ip->steps_host != j) return false;
+    j = ip->steps_host;
+  }
+  return true;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1115,6 +1295,8 @@ lz_status lz_init(const lz_system* sys, int32_t n_inst, const lz_options* opt, i
         opt->projector_gemm != LZ_GEMM_MFMA)
       fail(LZ_ERR_ARG, "unknown projector_gemm");
     if (opt->density_group_bands < 0) fail(LZ_ERR_ARG, "density_group_bands must be >= 0");
+    if (opt->batched != 0 && opt->batched != 1) fail(LZ_ERR_ARG, "batched must be 0 or 1");
+    if (opt->fft_planes < 0 || opt->fft_planes > 2) fail(LZ_ERR_ARG, "fft_planes must be 0, 1 or 2");
     if (opt->projector_chunk != 0 && opt->projector_chunk != kProjChunk &&
         opt->projector_chunk != 2 * kProjChunk && opt->projector_chunk != 4 * kProjChunk)
       fail(LZ_ERR_ARG, "projector_chunk must be 0, 64, 128 or 256");
@@ -1237,11 +1419,63 @@ lz_status lz_step(lz_ctx* c, int32_t n_steps, int32_t* steps_done) {
       if (ip->status_host == 0 && ip->steps_host + n_steps > ip->max_steps)
         fail(LZ_ERR_STATE, "max_steps would be exceeded");
     c->enter();
+    const int ni = (int)c->inst.size();
+    if (batch_applies(c)) {
+      // work-list launches: one launch per kernel of the step over every
+      // member of a group (groups side by side on the context's streams)
+      if (!c->batch_built) build_batch(c);
+      int j0 = -1;
+      for (auto& ip : c->inst)
+        if (ip->status_host == 0) j0 = ip->steps_host;
+      const int ng = (int)c->groups.size();
+      const bool gfork = ng > 1 && !c->qs.empty();
+      // steps j .. j + n - 1 of every group, forked from and joined back to
+      // the context stream
+      auto issue = [&](int j, int n) {
+        if (gfork) {
+          HIPC(hipEventRecord(c->ev_fork, c->stream));
+          for (auto q : c->qs) HIPC(hipStreamWaitEvent(q, c->ev_fork, 0));
+        }
+        for (int jj = j; jj < j + n; ++jj)
+          for (int g = 0; g < ng; ++g)
+            batched_step(*c->groups[g], jj, gfork ? c->qs[g % c->qs.size()] : c->stream);
+        if (gfork) {
+          for (size_t q = 0; q < c->qs.size(); ++q) {
+            HIPC(hipEventRecord(c->qdone[q], c->qs[q]));
+            HIPC(hipStreamWaitEvent(c->stream, c->qdone[q], 0));
+          }
+        }
+      };
+      const int end = j0 + n_steps;
+      for (int j = j0; j0 >= 0 && j < end;) {
+        if (c->opt.use_graph && (j & 1) && j + 1 < end) {
+          // an odd and an even step of every group as one captured graph
+          // (the kernels read the step from the device state: one graph
+          // serves every pair)
+          if (!c->batch_pair) {
+            hipGraph_t gr = nullptr;
+            HIPC(hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed));
+            issue(1, 2);
+            HIPC(hipStreamEndCapture(c->stream, &gr));
+            const hipError_t ei = hipGraphInstantiate(&c->batch_pair, gr, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(gr);
+            if (ei != hipSuccess) {
+              c->batch_pair = nullptr;
+              fail(LZ_ERR_HIP, std::string("graph instantiation: ") + hipGetErrorString(ei));
+            }
+          }
+          HIPC(hipGraphLaunch(c->batch_pair, c->stream));
+          j += 2;
+        } else {
+          issue(j, 1);
+          ++j;
+        }
+      }
+    } else {
     // With several streams the instances advance side by side: their steps
     // are issued round-robin, one unit (a step or a replayed pair) per
     // instance per round, each instance on its own stream, so the small
     // kernels of one instance overlap with the work of the others.
-    const int ni = (int)c->inst.size();
     const bool fork = !c->qs.empty();
     if (fork) {
       HIPC(hipEventRecord(c->ev_fork, c->stream));
@@ -1282,6 +1516,7 @@ lz_status lz_step(lz_ctx* c, int32_t n_steps, int32_t* steps_done) {
       for (int i = 0; i < ni; ++i)
         while (issue(i, c->stream)) {
         }
+    }
     }
     HIPC(hipGetLastError());
     c->leave();
@@ -1327,10 +1562,12 @@ lz_status lz_get_coefficients(lz_ctx* c, int32_t inst, int32_t first, int32_t co
 }
 
 lz_status lz_get_tuning(lz_ctx* c, int32_t inst, int32_t* projector_gemm,
-                        int32_t* density_group_bands, int32_t* projector_chunks) {
+                        int32_t* density_group_bands, int32_t* projector_chunks,
+                        int32_t* fft_planes) {
   return guarded([&] {
     if (!c || inst < 0 || inst >= (int)c->inst.size()) fail(LZ_ERR_ARG, "bad context or instance");
     const Instance& I = *c->inst[inst];
+    if (fft_planes) *fft_planes = I.grid.lds_planes ? 2 : 1;
     if (projector_gemm) *projector_gemm = I.gemm == kGemmValu ? LZ_GEMM_VALU : LZ_GEMM_MFMA;
     if (density_group_bands) *density_group_bands = I.gsize;
     if (projector_chunks) *projector_chunks = I.nchunk;
@@ -1685,10 +1922,11 @@ void gs_stack(Instance& I, void* V, const void* A, int ra, const void* B, int rb
 // are of the block's own order
 constexpr int kLobpcgOrderMax = 256;
 constexpr int kChebDegree = 40;
+constexpr int kChebMinDegree = 4;
 
 // Chebyshev-filtered subspace iteration (Zhou and Saad, 2007) for the lowest
 // m eigenpairs, from the Ritz block (X, HX, theta) left by the start: each
-// iteration applies the degree-kChebDegree Chebyshev polynomial of H that is
+// iteration applies a Chebyshev polynomial of H (degree up to kChebDegree) that is
 // small on [a, ub] (a the largest Ritz value of the block, ub an upper bound
 // of the spectrum) and normalised at the lowest Ritz value, then
 // orthonormalises the block (Jacobi on its Gram matrix) and does
@@ -1756,13 +1994,31 @@ void chebyshev_ground_state(const lz_system& sys, Instance& I, GsBuffers& b, int
       for (int n = 0; n < nb_out; ++n)
         worst = std::max(worst, std::sqrt(std::max(0.0, rr[((size_t)k * m + n) * m + n].x)));
     if (worst < tol || it >= max_iter) break;
+    // Degree of this iteration's filter.  Normalised at the lowest Ritz value
+    // a0, the filter scales the component along the highest wanted one (at
+    // theta_t) down by T_d(x(a0)) / T_d(x(theta_t)), x mapping [a, ub] to
+    // [-1, 1]; a column then keeps its own direction only against the
+    // admixture of lower ones that it carries, and beyond about 1e8 that is
+    // lost to rounding in the orthonormalisation (89 free-electron bands:
+    // degree 40 would scale by 1e-15 and the upper eight directions were
+    // dropped).  So d stays below ln(1e8) / (acosh|x(a0)| - acosh|x(theta_t)|).
+    int deg = kChebDegree;
+    for (int k = 0; k < nks; ++k) {
+      const double a = theta[(size_t)k * m + m - 1], a0 = theta[(size_t)k * m];
+      const double at = theta[(size_t)k * m + nb_out - 1];
+      const double e = 0.5 * (ub[k] - a), c = 0.5 * (ub[k] + a);
+      const double x0 = std::max(1.0, std::fabs((a0 - c) / e));
+      const double xt = std::max(1.0, std::fabs((at - c) / e));
+      const double gap = std::acosh(x0) - std::acosh(xt);
+      if (gap > 0.0) deg = std::min(deg, std::max(kChebMinDegree, (int)(std::log(1e8) / gap)));
+    }
     // coefficients of the filter steps per sphere
     for (int k = 0; k < nks; ++k) {
       const double a = theta[(size_t)k * m + m - 1], a0 = theta[(size_t)k * m];
       const double e = 0.5 * (ub[k] - a), c = 0.5 * (ub[k] + a);
       double sig = e / (a0 - c);
       const double sig1 = sig;
-      for (int d = 0; d < kChebDegree; ++d) {
+      for (int d = 0; d < deg; ++d) {
         double* cf = &coef[((size_t)d * nks + k) * 3];
         if (d == 0) {
           cf[0] = sig1 / e;
@@ -1783,7 +2039,7 @@ void chebyshev_ground_state(const lz_system& sys, Instance& I, GsBuffers& b, int
     void* prev = b.X.p;  // Y_{d-2}
     void* cur = b.W.p;   // Y_{d-1}
     launch_cheb_step(cur, b.HX.p, b.X.p, nullptr, dcoef.as<double>(), m, npwx, nks, s);
-    for (int d = 1; d < kChebDegree; ++d) {
+    for (int d = 1; d < deg; ++d) {
       apply_half<double>(I, cur, b.HW.p, false, s);
       launch_cheb_step(prev, b.HW.p, cur, prev, dcoef.as<double>() + (size_t)d * nks * 3, m, npwx,
                        nks, s);

@@ -18,6 +18,7 @@
 // Every reduction has a fixed order, so repeated runs are bitwise identical.
 #pragma once
 #include <stdexcept>
+#include <vector>
 
 #include "lz_fft_ct.h"
 #include "lz_kernels.h"
@@ -139,28 +140,42 @@ __device__ __forceinline__ const cplx<T>* stick_tw(cplx<T>* lds, const cplx<T>* 
   }
 }
 
+template <typename T>
+struct ZfftInvArgs {
+  const cplx<T>* x;
+  int64_t xs;
+  cplx<T>* out;
+  const int* map;
+  int S;
+  int n3_rt;
+  int nbnd;
+  FftPlan pz;
+  const cplx<T>* twg;
+  const LzDevState* st;
+};
+
 template <typename T, int N>
-__global__ __launch_bounds__(256) void k_zfft_inv(const cplx<T>* __restrict__ x, int64_t xs,
-                                                  cplx<T>* __restrict__ out,
-                                                  const int* __restrict__ map, int S, int n3_rt,
-                                                  int nbnd, FftPlan pz,
-                                                  const cplx<T>* __restrict__ twg,
-                                                  const LzDevState* st) {
+__device__ __forceinline__ void zfft_inv_block(const cplx<T>* __restrict__ x, int64_t xs,
+                                               cplx<T>* __restrict__ out,
+                                               const int* __restrict__ map, int S, int n3_rt,
+                                               int nbnd, const FftPlan& pz,
+                                               const cplx<T>* __restrict__ twg,
+                                               const LzDevState* st, const VBlock& vb) {
   if (st && st->status) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw);
   const int tid = threadIdx.x;
   constexpr int ST = zpass_tile(N);
-  const int s0 = blockIdx.x * ST;
+  const int s0 = vb.x * ST;
   const int nst = min(ST, S - s0);
   if constexpr (N > 0) {
-    // bands 2 j and 2 j + 1 of k-point k (blockIdx.y = k ceil(nbnd / 2) + j)
+    // bands 2 j and 2 j + 1 of k-point k (vb.y = k ceil(nbnd / 2) + j)
     // share the map of the tile: every map index, then the gathered values
     // of both bands, are in flight before the first is used; the two tiles
     // (lines [0, ST) and [ST, 2 ST)) go through one transform
     constexpr int pitch = N + 1;
     const int hp = (nbnd + 1) / 2;
-    const int k = blockIdx.y / hp, j = 2 * (blockIdx.y - k * hp);
+    const int k = vb.y / hp, j = 2 * (vb.y - k * hp);
     const int b = k * nbnd + j;
     const bool two = j + 1 < nbnd;
     const cplx<T>* tw = stick_tw<T, N, 2 * ST>(lds, twg, tid);
@@ -199,7 +214,7 @@ __global__ __launch_bounds__(256) void k_zfft_inv(const cplx<T>* __restrict__ x,
     return;
   }
   const int n3 = N > 0 ? N : n3_rt;
-  const int b = blockIdx.y;
+  const int b = vb.y;
   const int k = b / nbnd;
   const int pitch = n3 + 1;
   const cplx<T>* tw = stick_tw<T, N, ST>(lds, twg, tid);
@@ -221,27 +236,52 @@ __global__ __launch_bounds__(256) void k_zfft_inv(const cplx<T>* __restrict__ x,
   }
 }
 
+template <typename T, int N, bool BAT = false>
+__global__ __launch_bounds__(256) void k_zfft_inv(ZfftInvArgs<T> p, BatchRef br) {
+  LZ_BATCHED(BAT, p, br,
+             (zfft_inv_block<T, N>(a_.x, a_.xs, a_.out, a_.map, a_.S, a_.n3_rt, a_.nbnd, a_.pz,
+                                   a_.twg, a_.st, vb)));
+}
+
 // ---------------------------------------------------------------------------
 // z pass, forward: sticks -> sphere; y = x_fft/N + (kin - eps) x
 // ---------------------------------------------------------------------------
+template <typename T>
+struct ZfftFwdArgs {
+  const cplx<T>* sticks;
+  const cplx<T>* x;
+  int64_t xs;
+  cplx<T>* y;
+  const int* map;
+  const T* kin;
+  const double* eps;
+  int S;
+  int n3_rt;
+  int nbnd;
+  int npwx;
+  T scale;
+  FftPlan pz;
+  const cplx<T>* twg;
+  const LzDevState* st;
+};
+
 template <typename T, int N>
-__global__ __launch_bounds__(256) void k_zfft_fwd(const cplx<T>* __restrict__ sticks,
-                                                  const cplx<T>* __restrict__ x, int64_t xs,
-                                                  cplx<T>* __restrict__ y,
-                                                  const int* __restrict__ map,
-                                                  const T* __restrict__ kin,
-                                                  const double* __restrict__ eps, int S, int n3_rt,
-                                                  int nbnd, int npwx, T scale, FftPlan pz,
-                                                  const cplx<T>* __restrict__ twg,
-                                                  const LzDevState* st) {
+__device__ __forceinline__ void zfft_fwd_block(const cplx<T>* __restrict__ sticks,
+                                               const cplx<T>* __restrict__ x, int64_t xs,
+                                               cplx<T>* __restrict__ y, const int* __restrict__ map,
+                                               const T* __restrict__ kin,
+                                               const double* __restrict__ eps, int S, int n3_rt,
+                                               int nbnd, int npwx, T scale, const FftPlan& pz,
+                                               const cplx<T>* __restrict__ twg,
+                                               const LzDevState* st, const VBlock& vb) {
   if (st && st->status) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw);
   const int n3 = N > 0 ? N : n3_rt;
-  const int b = blockIdx.y;
+  const int b = vb.y;
   const int k = b / nbnd;
   constexpr int ST = zpass_tile(N);
-  const int s0 = blockIdx.x * ST;
+  const int s0 = vb.x * ST;
   const int nst = min(ST, S - s0);
   const int pitch = n3 + 1;
   const int tid = threadIdx.x;
@@ -306,16 +346,35 @@ __global__ __launch_bounds__(256) void k_zfft_fwd(const cplx<T>* __restrict__ st
   }
 }
 
+template <typename T, int N, bool BAT = false>
+__global__ __launch_bounds__(256) void k_zfft_fwd(ZfftFwdArgs<T> p, BatchRef br) {
+  LZ_BATCHED(BAT, p, br,
+             (zfft_fwd_block<T, N>(a_.sticks, a_.x, a_.xs, a_.y, a_.map, a_.kin, a_.eps, a_.S,
+                                   a_.n3_rt, a_.nbnd, a_.npwx, a_.scale, a_.pz, a_.twg, a_.st,
+                                   vb)));
+}
+
 // ---------------------------------------------------------------------------
 // plane pass of a D step: x(r) = IFFT2 sticks, (V x)(r), FFT2 -> sticks
 // ---------------------------------------------------------------------------
+template <typename T>
+struct PlaneLocalArgs {
+  const cplx<T>* sin;
+  cplx<T>* sout;
+  const T* vloc;
+  PlaneArgs a;
+  const cplx<T>* tw1;
+  const cplx<T>* tw2;
+  const LzDevState* st;
+};
+
 template <typename T, int N, int MP>
-__global__ __launch_bounds__(plane_threads<N>()) void k_plane_local(const cplx<T>* __restrict__ sin,
-                                                     cplx<T>* __restrict__ sout,
-                                                     const T* __restrict__ vloc, PlaneArgs a,
-                                                     const cplx<T>* __restrict__ tw1,
-                                                     const cplx<T>* __restrict__ tw2,
-                                                     const LzDevState* st) {
+__device__ __forceinline__ void plane_local_block(const cplx<T>* __restrict__ sin,
+                                                  cplx<T>* __restrict__ sout,
+                                                  const T* __restrict__ vloc, const PlaneArgs& a,
+                                                  const cplx<T>* __restrict__ tw1,
+                                                  const cplx<T>* __restrict__ tw2,
+                                                  const LzDevState* st, const VBlock& vb) {
   if (st && st->status) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int tid = threadIdx.x;
@@ -323,7 +382,7 @@ __global__ __launch_bounds__(plane_threads<N>()) void k_plane_local(const cplx<T
   PlaneShm<T, N> sh(smem_raw, a, tw1, tid);
   const int n1 = N > 0 ? N : a.n1, n2 = N > 0 ? N : a.n2, n3 = N > 0 ? N : a.n3;
   const int pitch = N > 0 ? N + 1 : a.pitch;
-  const int z = blockIdx.x, b = blockIdx.y;
+  const int z = vb.x, b = vb.y;
   const int64_t so = ((int64_t)b * n3 + z) * a.S;
   plane_zero_scatter<T, N>(sh, a, sin + so, tid);
   plane_rows<T, N, MP, +1>(sh, a, a.nact, true, tw2, tid);
@@ -340,17 +399,46 @@ __global__ __launch_bounds__(plane_threads<N>()) void k_plane_local(const cplx<T
   for (int s = tid; s < a.S; s += NTB) sout[so + s] = sh.plane[a.si1[s] * pitch + a.si2[s]];
 }
 
+template <typename T, int N, int MP, bool BAT = false>
+__global__ __launch_bounds__(plane_threads<N>()) void k_plane_local(PlaneLocalArgs<T> p,
+                                                                    BatchRef br) {
+  LZ_BATCHED(BAT, p, br,
+             (plane_local_block<T, N, MP>(a_.sin, a_.sout, a_.vloc, a_.a, a_.tw1, a_.tw2, a_.st,
+                                          vb)));
+}
+
 // ---------------------------------------------------------------------------
 // plane pass of a D+K step: as above for a group of bands, accumulating the
 // response density  n'(r) += (4 w_k / Omega) conj(u_b(r)) x_b(r)  (raw values
 // of u and x, i.e. without the Omega^-1/2 factors, which bandw absorbs).
 // ---------------------------------------------------------------------------
+template <typename T>
+struct PlaneLocalDensityArgs {
+  const cplx<T>* sin;
+  cplx<T>* sout;
+  const T* vloc;
+  const cplx<T>* ur;
+  const double* bandw;
+  cplx<T>* dpart;
+  int nb;
+  int gsize;
+  PlaneArgs a;
+  const cplx<T>* tw1;
+  const cplx<T>* tw2;
+  const LzDevState* st;
+};
+
 template <typename T, int N, int MP>
-__global__ __launch_bounds__(plane_threads<N>()) void k_plane_local_density(
-    const cplx<T>* __restrict__ sin, cplx<T>* __restrict__ sout, const T* __restrict__ vloc,
-    const cplx<T>* __restrict__ ur, const double* __restrict__ bandw, cplx<T>* __restrict__ dpart,
-    int nb, int gsize, PlaneArgs a, const cplx<T>* __restrict__ tw1,
-    const cplx<T>* __restrict__ tw2, const LzDevState* st) {
+__device__ __forceinline__ void plane_local_density_block(const cplx<T>* __restrict__ sin,
+                                                          cplx<T>* __restrict__ sout,
+                                                          const T* __restrict__ vloc,
+                                                          const cplx<T>* __restrict__ ur,
+                                                          const double* __restrict__ bandw,
+                                                          cplx<T>* __restrict__ dpart, int nb,
+                                                          int gsize, const PlaneArgs& a,
+                                                          const cplx<T>* __restrict__ tw1,
+                                                          const cplx<T>* __restrict__ tw2,
+                                                          const LzDevState* st, const VBlock& vb) {
   if (st && st->status) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int tid = threadIdx.x;
@@ -366,7 +454,7 @@ __global__ __launch_bounds__(plane_threads<N>()) void k_plane_local_density(
   constexpr int NIT = N > 0 ? (N * N + NTB - 1) / NTB : MP;
   constexpr int ACC = GACC ? 1 : NIT;
   constexpr int UNR = GACC ? 4 : NIT;
-  const int z = blockIdx.x, g = blockIdx.y;
+  const int z = vb.x, g = vb.y;
   const int np = n1 * n2;
   const T* vz = vloc + (int64_t)z * np;
   cplx<T>* dp = dpart + ((int64_t)g * n3 + z) * np;
@@ -415,19 +503,38 @@ __global__ __launch_bounds__(plane_threads<N>()) void k_plane_local_density(
   }
 }
 
+template <typename T, int N, int MP, bool BAT = false>
+__global__ __launch_bounds__(plane_threads<N>()) void k_plane_local_density(
+    PlaneLocalDensityArgs<T> p, BatchRef br) {
+  LZ_BATCHED(BAT, p, br,
+             (plane_local_density_block<T, N, MP>(a_.sin, a_.sout, a_.vloc, a_.ur, a_.bandw,
+                                                  a_.dpart, a_.nb, a_.gsize, a_.a, a_.tw1, a_.tw2,
+                                                  a_.st, vb)));
+}
+
 // sticks -> real-space plane (set-up: valence orbitals in real space)
+template <typename T>
+struct PlaneToRealArgs {
+  const cplx<T>* sin;
+  cplx<T>* rout;
+  PlaneArgs a;
+  const cplx<T>* tw1;
+  const cplx<T>* tw2;
+};
+
 template <typename T, int N, int MP>
-__global__ __launch_bounds__(plane_threads<N>()) void k_plane_to_real(const cplx<T>* __restrict__ sin,
-                                                       cplx<T>* __restrict__ rout, PlaneArgs a,
-                                                       const cplx<T>* __restrict__ tw1,
-                                                       const cplx<T>* __restrict__ tw2) {
+__device__ __forceinline__ void plane_to_real_block(const cplx<T>* __restrict__ sin,
+                                                    cplx<T>* __restrict__ rout, const PlaneArgs& a,
+                                                    const cplx<T>* __restrict__ tw1,
+                                                    const cplx<T>* __restrict__ tw2,
+                                                    const VBlock& vb) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int tid = threadIdx.x;
   constexpr int NTB = N > 0 ? plane_threads<N>() : 256;
   PlaneShm<T, N> sh(smem_raw, a, tw1, tid);
   const int n1 = N > 0 ? N : a.n1, n2 = N > 0 ? N : a.n2, n3 = N > 0 ? N : a.n3;
   const int pitch = N > 0 ? N + 1 : a.pitch;
-  const int z = blockIdx.x, b = blockIdx.y;
+  const int z = vb.x, b = vb.y;
   const int np = n1 * n2;
   plane_zero_scatter<T, N>(sh, a, sin + ((int64_t)b * n3 + z) * a.S, tid);
   plane_rows<T, N, MP, +1>(sh, a, a.nact, true, tw2, tid);
@@ -439,14 +546,32 @@ __global__ __launch_bounds__(plane_threads<N>()) void k_plane_to_real(const cplx
   }
 }
 
+template <typename T, int N, int MP, bool BAT = false>
+__global__ __launch_bounds__(plane_threads<N>()) void k_plane_to_real(PlaneToRealArgs<T> p,
+                                                                      BatchRef br) {
+  LZ_BATCHED(BAT, p, br,
+             (plane_to_real_block<T, N, MP>(a_.sin, a_.rout, a_.a, a_.tw1, a_.tw2, vb)));
+}
+
 // v'(r) u_b(r) -> FFT2 -> added to the sticks of the same band
+template <typename T>
+struct PlaneVuArgs {
+  const cplx<T>* ur;
+  const cplx<T>* vp;
+  cplx<T>* sout;
+  PlaneArgs a;
+  const cplx<T>* tw1;
+  const cplx<T>* tw2;
+  const LzDevState* st;
+};
+
 template <typename T, int N, int MP>
-__global__ __launch_bounds__(plane_threads<N>()) void k_plane_vu(const cplx<T>* __restrict__ ur,
-                                                  const cplx<T>* __restrict__ vp,
-                                                  cplx<T>* __restrict__ sout, PlaneArgs a,
-                                                  const cplx<T>* __restrict__ tw1,
-                                                  const cplx<T>* __restrict__ tw2,
-                                                  const LzDevState* st) {
+__device__ __forceinline__ void plane_vu_block(const cplx<T>* __restrict__ ur,
+                                               const cplx<T>* __restrict__ vp,
+                                               cplx<T>* __restrict__ sout, const PlaneArgs& a,
+                                               const cplx<T>* __restrict__ tw1,
+                                               const cplx<T>* __restrict__ tw2,
+                                               const LzDevState* st, const VBlock& vb) {
   if (st && st->status) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int tid = threadIdx.x;
@@ -454,7 +579,7 @@ __global__ __launch_bounds__(plane_threads<N>()) void k_plane_vu(const cplx<T>* 
   PlaneShm<T, N> sh(smem_raw, a, tw1, tid);
   const int n1 = N > 0 ? N : a.n1, n2 = N > 0 ? N : a.n2, n3 = N > 0 ? N : a.n3;
   const int pitch = N > 0 ? N + 1 : a.pitch;
-  const int z = blockIdx.x, b = blockIdx.y;
+  const int z = vb.x, b = vb.y;
   const int np = n1 * n2;
   const cplx<T>* ub = ur + ((int64_t)b * n3 + z) * np;
   const cplx<T>* vz = vp + (int64_t)z * np;
@@ -472,17 +597,35 @@ __global__ __launch_bounds__(plane_threads<N>()) void k_plane_vu(const cplx<T>* 
   }
 }
 
+template <typename T, int N, int MP, bool BAT = false>
+__global__ __launch_bounds__(plane_threads<N>()) void k_plane_vu(PlaneVuArgs<T> p, BatchRef br) {
+  LZ_BATCHED(BAT, p, br,
+             (plane_vu_block<T, N, MP>(a_.ur, a_.vp, a_.sout, a_.a, a_.tw1, a_.tw2, a_.st, vb)));
+}
+
 // ---------------------------------------------------------------------------
 // response Hartree + xc potential of one instance
 // ---------------------------------------------------------------------------
 // (1) n'(r) = sum over band groups (fixed order); 2-D forward transform
+template <typename T>
+struct HxcPlanesFwdArgs {
+  const cplx<T>* dpart;
+  int ngroups;
+  cplx<T>* nr;
+  cplx<T>* work;
+  PlaneArgs a;
+  const cplx<T>* tw1;
+  const cplx<T>* tw2;
+  const LzDevState* st;
+};
+
 template <typename T, int N, int MP>
-__global__ __launch_bounds__(plane_threads<N>()) void k_hxc_planes_fwd(const cplx<T>* __restrict__ dpart,
-                                                        int ngroups, cplx<T>* __restrict__ nr,
-                                                        cplx<T>* __restrict__ work, PlaneArgs a,
-                                                        const cplx<T>* __restrict__ tw1,
-                                                        const cplx<T>* __restrict__ tw2,
-                                                        const LzDevState* st) {
+__device__ __forceinline__ void hxc_planes_fwd_block(const cplx<T>* __restrict__ dpart, int ngroups,
+                                                     cplx<T>* __restrict__ nr,
+                                                     cplx<T>* __restrict__ work, const PlaneArgs& a,
+                                                     const cplx<T>* __restrict__ tw1,
+                                                     const cplx<T>* __restrict__ tw2,
+                                                     const LzDevState* st, const VBlock& vb) {
   if (st && st->status) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int tid = threadIdx.x;
@@ -490,7 +633,7 @@ __global__ __launch_bounds__(plane_threads<N>()) void k_hxc_planes_fwd(const cpl
   PlaneShm<T, N> sh(smem_raw, a, tw1, tid);
   const int n1 = N > 0 ? N : a.n1, n2 = N > 0 ? N : a.n2, n3 = N > 0 ? N : a.n3;
   const int pitch = N > 0 ? N + 1 : a.pitch;
-  const int z = blockIdx.x;
+  const int z = vb.x;
   const int np = n1 * n2;
   const int64_t plane = (int64_t)n3 * np;
   for (int p = tid; p < np; p += NTB) {
@@ -510,17 +653,36 @@ __global__ __launch_bounds__(plane_threads<N>()) void k_hxc_planes_fwd(const cpl
   }
 }
 
+template <typename T, int N, int MP, bool BAT = false>
+__global__ __launch_bounds__(plane_threads<N>()) void k_hxc_planes_fwd(HxcPlanesFwdArgs<T> p,
+                                                                       BatchRef br) {
+  LZ_BATCHED(BAT, p, br,
+             (hxc_planes_fwd_block<T, N, MP>(a_.dpart, a_.ngroups, a_.nr, a_.work, a_.a, a_.tw1,
+                                             a_.tw2, a_.st, vb)));
+}
+
 // (2) along z: forward, times 4 pi / (|q+G|^2 N), inverse
+template <typename T>
+struct HxcZArgs {
+  cplx<T>* work;
+  const T* khart;
+  int np;
+  int n3_rt;
+  FftPlan pz;
+  const cplx<T>* twg;
+  const LzDevState* st;
+};
+
 template <typename T, int N>
-__global__ __launch_bounds__(256) void k_hxc_z(cplx<T>* __restrict__ work,
-                                               const T* __restrict__ khart, int np, int n3_rt,
-                                               FftPlan pz, const cplx<T>* __restrict__ twg,
-                                               const LzDevState* st) {
+__device__ __forceinline__ void hxc_z_block(cplx<T>* __restrict__ work, const T* __restrict__ khart,
+                                            int np, int n3_rt, const FftPlan& pz,
+                                            const cplx<T>* __restrict__ twg, const LzDevState* st,
+                                            const VBlock& vb) {
   if (st && st->status) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw);
   const int n3 = N > 0 ? N : n3_rt;
-  const int c0 = blockIdx.x * kColTile;
+  const int c0 = vb.x * kColTile;
   const int nc = min(kColTile, np - c0);
   const int pitch = n3 + 1;
   const int tid = threadIdx.x;
@@ -544,15 +706,34 @@ __global__ __launch_bounds__(256) void k_hxc_z(cplx<T>* __restrict__ work,
   }
 }
 
+template <typename T, int N, bool BAT = false>
+__global__ __launch_bounds__(256) void k_hxc_z(HxcZArgs<T> p, BatchRef br) {
+  LZ_BATCHED(BAT, p, br,
+             (hxc_z_block<T, N>(a_.work, a_.khart, a_.np, a_.n3_rt, a_.pz, a_.twg, a_.st, vb)));
+}
+
 // (3) 2-D inverse transform, v'(r) = v_H(r) + f_xc(r) n'(r)
+template <typename T>
+struct HxcPlanesInvArgs {
+  const cplx<T>* work;
+  const cplx<T>* nr;
+  const T* fxc;
+  int with_fxc;
+  cplx<T>* vp;
+  PlaneArgs a;
+  const cplx<T>* tw1;
+  const cplx<T>* tw2;
+  const LzDevState* st;
+};
+
 template <typename T, int N, int MP>
-__global__ __launch_bounds__(plane_threads<N>()) void k_hxc_planes_inv(const cplx<T>* __restrict__ work,
-                                                        const cplx<T>* __restrict__ nr,
-                                                        const T* __restrict__ fxc, int with_fxc,
-                                                        cplx<T>* __restrict__ vp, PlaneArgs a,
-                                                        const cplx<T>* __restrict__ tw1,
-                                                        const cplx<T>* __restrict__ tw2,
-                                                        const LzDevState* st) {
+__device__ __forceinline__ void hxc_planes_inv_block(const cplx<T>* __restrict__ work,
+                                                     const cplx<T>* __restrict__ nr,
+                                                     const T* __restrict__ fxc, int with_fxc,
+                                                     cplx<T>* __restrict__ vp, const PlaneArgs& a,
+                                                     const cplx<T>* __restrict__ tw1,
+                                                     const cplx<T>* __restrict__ tw2,
+                                                     const LzDevState* st, const VBlock& vb) {
   if (st && st->status) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int tid = threadIdx.x;
@@ -560,7 +741,7 @@ __global__ __launch_bounds__(plane_threads<N>()) void k_hxc_planes_inv(const cpl
   PlaneShm<T, N> sh(smem_raw, a, tw1, tid);
   const int n1 = N > 0 ? N : a.n1, n2 = N > 0 ? N : a.n2;
   const int pitch = N > 0 ? N + 1 : a.pitch;
-  const int z = blockIdx.x;
+  const int z = vb.x;
   const int np = n1 * n2;
   for (int p = tid; p < np; p += NTB) {
     const int i1 = p / n2, i2 = p - i1 * n2;
@@ -582,6 +763,14 @@ __global__ __launch_bounds__(plane_threads<N>()) void k_hxc_planes_inv(const cpl
   }
 }
 
+template <typename T, int N, int MP, bool BAT = false>
+__global__ __launch_bounds__(plane_threads<N>()) void k_hxc_planes_inv(HxcPlanesInvArgs<T> p,
+                                                                       BatchRef br) {
+  LZ_BATCHED(BAT, p, br,
+             (hxc_planes_inv_block<T, N, MP>(a_.work, a_.nr, a_.fxc, a_.with_fxc, a_.vp, a_.a,
+                                             a_.tw1, a_.tw2, a_.st, vb)));
+}
+
 // ---------------------------------------------------------------------------
 // response potential on compile-time grids: the 3-D transform of the single
 // density grid runs as line passes of kLineTile lines per block (N^2/8
@@ -591,12 +780,22 @@ constexpr int kLineTile = 8;
 constexpr int kSumBatch = 16;  // group partials per round of loads in the first line pass
 
 // n'(r) = sum over band groups (fixed order); forward transform along i2
+template <typename T>
+struct HxcL2FwdArgs {
+  const cplx<T>* dpart;
+  int ngroups;
+  cplx<T>* nr;
+  cplx<T>* work;
+  const cplx<T>* twg;
+  const LzDevState* st;
+};
+
 template <typename T, int N>
-__global__ __launch_bounds__(256) void k_hxc_l2_fwd(const cplx<T>* __restrict__ dpart, int ngroups,
-                                                    cplx<T>* __restrict__ nr,
-                                                    cplx<T>* __restrict__ work,
-                                                    const cplx<T>* __restrict__ twg,
-                                                    const LzDevState* st) {
+__device__ __forceinline__ void hxc_l2_fwd_block(const cplx<T>* __restrict__ dpart, int ngroups,
+                                                 cplx<T>* __restrict__ nr,
+                                                 cplx<T>* __restrict__ work,
+                                                 const cplx<T>* __restrict__ twg,
+                                                 const LzDevState* st, const VBlock& vb) {
   if (st && st->status) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw);
@@ -604,7 +803,7 @@ __global__ __launch_bounds__(256) void k_hxc_l2_fwd(const cplx<T>* __restrict__ 
   constexpr int64_t NG = (int64_t)N * N * N;
   const int tid = threadIdx.x;
   const cplx<T>* tw = stick_tw<T, N>(lds, twg, tid);
-  const int64_t l0 = (int64_t)blockIdx.x * kLineTile;
+  const int64_t l0 = (int64_t)vb.x * kLineTile;
   // a thread's elements (at most EPT) summed over the groups in order, the
   // loads of kSumBatch groups of every element in flight together
   constexpr int EPT = (kLineTile * N + 255) / 256;
@@ -645,11 +844,24 @@ __global__ __launch_bounds__(256) void k_hxc_l2_fwd(const cplx<T>* __restrict__ 
   }
 }
 
+template <typename T, int N, bool BAT = false>
+__global__ __launch_bounds__(256) void k_hxc_l2_fwd(HxcL2FwdArgs<T> p, BatchRef br) {
+  LZ_BATCHED(BAT, p, br,
+             (hxc_l2_fwd_block<T, N>(a_.dpart, a_.ngroups, a_.nr, a_.work, a_.twg, a_.st, vb)));
+}
+
 // transform along i1 (lines (z, i2), stride N), in place
+template <typename T>
+struct HxcL1Args {
+  cplx<T>* work;
+  const cplx<T>* twg;
+  const LzDevState* st;
+};
+
 template <typename T, int N, int DIR>
-__global__ __launch_bounds__(256) void k_hxc_l1(cplx<T>* __restrict__ work,
-                                                const cplx<T>* __restrict__ twg,
-                                                const LzDevState* st) {
+__device__ __forceinline__ void hxc_l1_block(cplx<T>* __restrict__ work,
+                                             const cplx<T>* __restrict__ twg, const LzDevState* st,
+                                             const VBlock& vb) {
   if (st && st->status) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw);
@@ -657,8 +869,8 @@ __global__ __launch_bounds__(256) void k_hxc_l1(cplx<T>* __restrict__ work,
   constexpr int TPZ = N / kLineTile;
   const int tid = threadIdx.x;
   const cplx<T>* tw = stick_tw<T, N>(lds, twg, tid);
-  const int z = blockIdx.x / TPZ;
-  const int i20 = (blockIdx.x - z * TPZ) * kLineTile;
+  const int z = vb.x / TPZ;
+  const int i20 = (vb.x - z * TPZ) * kLineTile;
   cplx<T>* base = work + (int64_t)z * N * N + i20;
   for (int t = tid; t < kLineTile * N; t += 256) {
     const int i1 = t / kLineTile, ll = t - i1 * kLineTile;
@@ -672,21 +884,37 @@ __global__ __launch_bounds__(256) void k_hxc_l1(cplx<T>* __restrict__ work,
   }
 }
 
+template <typename T, int N, int DIR, bool BAT = false>
+__global__ __launch_bounds__(256) void k_hxc_l1(HxcL1Args<T> p, BatchRef br) {
+  LZ_BATCHED(BAT, p, br, (hxc_l1_block<T, N, DIR>(a_.work, a_.twg, a_.st, vb)));
+}
+
 // inverse along i2, then v'(r) = v_H(r) + f_xc(r) n'(r)
+template <typename T>
+struct HxcL2InvArgs {
+  const cplx<T>* work;
+  const cplx<T>* nr;
+  const T* fxc;
+  int with_fxc;
+  cplx<T>* vp;
+  const cplx<T>* twg;
+  const LzDevState* st;
+};
+
 template <typename T, int N>
-__global__ __launch_bounds__(256) void k_hxc_l2_inv(const cplx<T>* __restrict__ work,
-                                                    const cplx<T>* __restrict__ nr,
-                                                    const T* __restrict__ fxc, int with_fxc,
-                                                    cplx<T>* __restrict__ vp,
-                                                    const cplx<T>* __restrict__ twg,
-                                                    const LzDevState* st) {
+__device__ __forceinline__ void hxc_l2_inv_block(const cplx<T>* __restrict__ work,
+                                                 const cplx<T>* __restrict__ nr,
+                                                 const T* __restrict__ fxc, int with_fxc,
+                                                 cplx<T>* __restrict__ vp,
+                                                 const cplx<T>* __restrict__ twg,
+                                                 const LzDevState* st, const VBlock& vb) {
   if (st && st->status) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw);
   constexpr int P = N + 1;
   const int tid = threadIdx.x;
   const cplx<T>* tw = stick_tw<T, N>(lds, twg, tid);
-  const int64_t l0 = (int64_t)blockIdx.x * kLineTile;
+  const int64_t l0 = (int64_t)vb.x * kLineTile;
   for (int t = tid; t < kLineTile * N; t += 256) {
     const int ll = t / N, i = t - ll * N;
     lds[ll * P + i] = work[(l0 + ll) * N + i];
@@ -707,6 +935,13 @@ __global__ __launch_bounds__(256) void k_hxc_l2_inv(const cplx<T>* __restrict__ 
   }
 }
 
+template <typename T, int N, bool BAT = false>
+__global__ __launch_bounds__(256) void k_hxc_l2_inv(HxcL2InvArgs<T> p, BatchRef br) {
+  LZ_BATCHED(BAT, p, br,
+             (hxc_l2_inv_block<T, N>(a_.work, a_.nr, a_.fxc, a_.with_fxc, a_.vp, a_.twg, a_.st,
+                                     vb)));
+}
+
 template <typename T, int N>
 static void hxc_lines(const Grid3& g, const void* dpart, int ngroups, void* nr, void* work,
                       const void* khart, const void* fxc, bool with_fxc, void* vp,
@@ -714,13 +949,18 @@ static void hxc_lines(const Grid3& g, const void* dpart, int ngroups, void* nr, 
   const int nlb = N * N / kLineTile;
   const size_t ll = (size_t)(kStickTile * (N + 1) + ct_twsize(N)) * sizeof(cplx<T>);
   const cplx<T>* tw = (const cplx<T>*)g.tw1;
-  hipLaunchKernelGGL((k_hxc_l2_fwd<T, N>), dim3(nlb), dim3(256), ll, s, (const cplx<T>*)dpart,
+  lz_launch((k_hxc_l2_fwd<T, N>), (k_hxc_l2_fwd<T, N, true>), dim3(nlb), dim3(256), ll, s,
+            (const cplx<T>*)dpart,
                      ngroups, (cplx<T>*)nr, (cplx<T>*)work, tw, st);
-  hipLaunchKernelGGL((k_hxc_l1<T, N, -1>), dim3(nlb), dim3(256), ll, s, (cplx<T>*)work, tw, st);
-  hipLaunchKernelGGL((k_hxc_z<T, N>), dim3(N * N / kColTile), dim3(256), ll, s, (cplx<T>*)work,
+  lz_launch((k_hxc_l1<T, N, -1>), (k_hxc_l1<T, N, -1, true>), dim3(nlb), dim3(256), ll, s,
+            (cplx<T>*)work, tw, st);
+  lz_launch((k_hxc_z<T, N>), (k_hxc_z<T, N, true>), dim3(N * N / kColTile), dim3(256), ll, s,
+            (cplx<T>*)work,
                      (const T*)khart, N * N, N, g.p3, tw, st);
-  hipLaunchKernelGGL((k_hxc_l1<T, N, +1>), dim3(nlb), dim3(256), ll, s, (cplx<T>*)work, tw, st);
-  hipLaunchKernelGGL((k_hxc_l2_inv<T, N>), dim3(nlb), dim3(256), ll, s, (const cplx<T>*)work,
+  lz_launch((k_hxc_l1<T, N, +1>), (k_hxc_l1<T, N, +1, true>), dim3(nlb), dim3(256), ll, s,
+            (cplx<T>*)work, tw, st);
+  lz_launch((k_hxc_l2_inv<T, N>), (k_hxc_l2_inv<T, N, true>), dim3(nlb), dim3(256), ll, s,
+            (const cplx<T>*)work,
                      (const cplx<T>*)nr, (const T*)fxc, with_fxc ? 1 : 0, (cplx<T>*)vp, tw, st);
 }
 
@@ -742,7 +982,7 @@ static inline int ct_size(const Grid3& g) {
 // size N of the register-line plane kernels for this grid (0 = not used)
 template <typename T>
 int reg_plane_size(const Grid3& g) {
-  if (!g.soff_f) return 0;
+  if (!g.soff_f || g.lds_planes) return 0;
   switch (ct_size(g)) {
     case 24: return reg_plane_ok<T, 24>() ? 24 : 0;
     case 32: return reg_plane_ok<T, 32>() ? 32 : 0;
@@ -755,6 +995,7 @@ int reg_plane_size(const Grid3& g) {
 }
 template int reg_plane_size<double>(const Grid3&);
 template int reg_plane_size<float>(const Grid3&);
+
 
 static inline RegPlaneArgs reg_args(const Grid3& g) {
   RegPlaneArgs a;
@@ -771,9 +1012,9 @@ static inline RegPlaneArgs reg_args(const Grid3& g) {
   do {                                                                                         \
     if constexpr (reg_plane_ok<T, 48>()) {                                                     \
       switch (N) {                                                                             \
-        case 24: hipLaunchKernelGGL((KERN<T, 24>), GRID, dim3(kRegPlaneThreads), LDS, STREAM, __VA_ARGS__); break; \
-        case 32: hipLaunchKernelGGL((KERN<T, 32>), GRID, dim3(kRegPlaneThreads), LDS, STREAM, __VA_ARGS__); break; \
-        case 48: hipLaunchKernelGGL((KERN<T, 48>), GRID, dim3(kRegPlaneThreads), LDS, STREAM, __VA_ARGS__); break; \
+        case 24: lz_launch((KERN<T, 24>), (KERN<T, 24, true>), GRID, dim3(kRegPlaneThreads), LDS, STREAM, __VA_ARGS__); break; \
+        case 32: lz_launch((KERN<T, 32>), (KERN<T, 32, true>), GRID, dim3(kRegPlaneThreads), LDS, STREAM, __VA_ARGS__); break; \
+        case 48: lz_launch((KERN<T, 48>), (KERN<T, 48, true>), GRID, dim3(kRegPlaneThreads), LDS, STREAM, __VA_ARGS__); break; \
         default: throw std::logic_error("no line-per-thread plane kernel for this size");                        \
       }                                                                                        \
     }                                                                                          \
@@ -797,18 +1038,18 @@ template <typename T> static size_t stick_lds(const Grid3& g) {
 #define LZ_PLANE_LAUNCH(KERN, T, G, GRID, LDS, STREAM, ...)                                     \
   do {                                                                                          \
     switch (ct_size(G)) {                                                                       \
-      case 24: hipLaunchKernelGGL((KERN<T, 24, 0>), GRID, dim3(256), LDS, STREAM, __VA_ARGS__); break; \
-      case 32: hipLaunchKernelGGL((KERN<T, 32, 0>), GRID, dim3(256), LDS, STREAM, __VA_ARGS__); break; \
-      case 40: hipLaunchKernelGGL((KERN<T, 40, 0>), GRID, dim3(256), LDS, STREAM, __VA_ARGS__); break; \
-      case 48: hipLaunchKernelGGL((KERN<T, 48, 0>), GRID, dim3(256), LDS, STREAM, __VA_ARGS__); break; \
-      case 64: hipLaunchKernelGGL((KERN<T, 64, 0>), GRID, dim3(256), LDS, STREAM, __VA_ARGS__); break; \
-      case 72: hipLaunchKernelGGL((KERN<T, 72, 0>), GRID, dim3(256), LDS, STREAM, __VA_ARGS__); break; \
-      case 96: hipLaunchKernelGGL((KERN<T, 96, 0>), GRID, dim3(plane_threads<96>()), LDS, STREAM, __VA_ARGS__); break; \
+      case 24: lz_launch((KERN<T, 24, 0>), (KERN<T, 24, 0, true>), GRID, dim3(256), LDS, STREAM, __VA_ARGS__); break; \
+      case 32: lz_launch((KERN<T, 32, 0>), (KERN<T, 32, 0, true>), GRID, dim3(256), LDS, STREAM, __VA_ARGS__); break; \
+      case 40: lz_launch((KERN<T, 40, 0>), (KERN<T, 40, 0, true>), GRID, dim3(256), LDS, STREAM, __VA_ARGS__); break; \
+      case 48: lz_launch((KERN<T, 48, 0>), (KERN<T, 48, 0, true>), GRID, dim3(256), LDS, STREAM, __VA_ARGS__); break; \
+      case 64: lz_launch((KERN<T, 64, 0>), (KERN<T, 64, 0, true>), GRID, dim3(256), LDS, STREAM, __VA_ARGS__); break; \
+      case 72: lz_launch((KERN<T, 72, 0>), (KERN<T, 72, 0, true>), GRID, dim3(256), LDS, STREAM, __VA_ARGS__); break; \
+      case 96: lz_launch((KERN<T, 96, 0>), (KERN<T, 96, 0, true>), GRID, dim3(plane_threads<96>()), LDS, STREAM, __VA_ARGS__); break; \
       default:                                                                                  \
         switch (plane_mp((G).n1, (G).n2)) {                                                     \
-          case 12: hipLaunchKernelGGL((KERN<T, 0, 12>), GRID, dim3(256), LDS, STREAM, __VA_ARGS__); break; \
-          case 24: hipLaunchKernelGGL((KERN<T, 0, 24>), GRID, dim3(256), LDS, STREAM, __VA_ARGS__); break; \
-          default: hipLaunchKernelGGL((KERN<T, 0, 36>), GRID, dim3(256), LDS, STREAM, __VA_ARGS__); break; \
+          case 12: lz_launch((KERN<T, 0, 12>), (KERN<T, 0, 12, true>), GRID, dim3(256), LDS, STREAM, __VA_ARGS__); break; \
+          case 24: lz_launch((KERN<T, 0, 24>), (KERN<T, 0, 24, true>), GRID, dim3(256), LDS, STREAM, __VA_ARGS__); break; \
+          default: lz_launch((KERN<T, 0, 36>), (KERN<T, 0, 36, true>), GRID, dim3(256), LDS, STREAM, __VA_ARGS__); break; \
         }                                                                                       \
     }                                                                                           \
   } while (0)
@@ -816,14 +1057,14 @@ template <typename T> static size_t stick_lds(const Grid3& g) {
 #define LZ_STICK_LAUNCH(KERN, T, G, GRID, LDS, STREAM, ...)                                   \
   do {                                                                                        \
     switch (ct_size(G)) {                                                                     \
-      case 24: hipLaunchKernelGGL((KERN<T, 24>), GRID, dim3(256), LDS, STREAM, __VA_ARGS__); break; \
-      case 32: hipLaunchKernelGGL((KERN<T, 32>), GRID, dim3(256), LDS, STREAM, __VA_ARGS__); break; \
-      case 40: hipLaunchKernelGGL((KERN<T, 40>), GRID, dim3(256), LDS, STREAM, __VA_ARGS__); break; \
-      case 48: hipLaunchKernelGGL((KERN<T, 48>), GRID, dim3(256), LDS, STREAM, __VA_ARGS__); break; \
-      case 64: hipLaunchKernelGGL((KERN<T, 64>), GRID, dim3(256), LDS, STREAM, __VA_ARGS__); break; \
-      case 72: hipLaunchKernelGGL((KERN<T, 72>), GRID, dim3(256), LDS, STREAM, __VA_ARGS__); break; \
-      case 96: hipLaunchKernelGGL((KERN<T, 96>), GRID, dim3(256), LDS, STREAM, __VA_ARGS__); break; \
-      default: hipLaunchKernelGGL((KERN<T, 0>), GRID, dim3(256), LDS, STREAM, __VA_ARGS__); break; \
+      case 24: lz_launch((KERN<T, 24>), (KERN<T, 24, true>), GRID, dim3(256), LDS, STREAM, __VA_ARGS__); break; \
+      case 32: lz_launch((KERN<T, 32>), (KERN<T, 32, true>), GRID, dim3(256), LDS, STREAM, __VA_ARGS__); break; \
+      case 40: lz_launch((KERN<T, 40>), (KERN<T, 40, true>), GRID, dim3(256), LDS, STREAM, __VA_ARGS__); break; \
+      case 48: lz_launch((KERN<T, 48>), (KERN<T, 48, true>), GRID, dim3(256), LDS, STREAM, __VA_ARGS__); break; \
+      case 64: lz_launch((KERN<T, 64>), (KERN<T, 64, true>), GRID, dim3(256), LDS, STREAM, __VA_ARGS__); break; \
+      case 72: lz_launch((KERN<T, 72>), (KERN<T, 72, true>), GRID, dim3(256), LDS, STREAM, __VA_ARGS__); break; \
+      case 96: lz_launch((KERN<T, 96>), (KERN<T, 96, true>), GRID, dim3(256), LDS, STREAM, __VA_ARGS__); break; \
+      default: lz_launch((KERN<T, 0>), (KERN<T, 0, true>), GRID, dim3(256), LDS, STREAM, __VA_ARGS__); break; \
     }                                                                                         \
   } while (0)
 
@@ -861,15 +1102,18 @@ void LaunchFft<T>::plane_local(const Grid3& g, const void* sin, void* sout, cons
     if constexpr (reg_pair_ok<T>()) {
       if (n >= 64) {
         if (n == 64)
-          hipLaunchKernelGGL((k_rp_local<T, 64>), dim3(nplanes), dim3(kRegPlaneThreads),
+          lz_launch((k_rp_local<T, 64>), (k_rp_local<T, 64, true>), dim3(nplanes),
+                    dim3(kRegPlaneThreads),
                              (pair_lds<T, 64>(g.nact)), s, (const cplx<T>*)sin, (cplx<T>*)sout,
                              (const T*)vloc, reg_args(g), st);
         else if (n == 72)
-          hipLaunchKernelGGL((k_rp_local<T, 72>), dim3(nplanes), dim3(kRegPlaneThreads),
+          lz_launch((k_rp_local<T, 72>), (k_rp_local<T, 72, true>), dim3(nplanes),
+                    dim3(kRegPlaneThreads),
                              (pair_lds<T, 72>(g.nact)), s, (const cplx<T>*)sin, (cplx<T>*)sout,
                              (const T*)vloc, reg_args(g), st);
         else
-          hipLaunchKernelGGL((k_rp_local<T, 96>), dim3(nplanes), dim3(kRegPlaneThreads),
+          lz_launch((k_rp_local<T, 96>), (k_rp_local<T, 96, true>), dim3(nplanes),
+                    dim3(kRegPlaneThreads),
                              (pair_lds<T, 96>(g.nact)), s, (const cplx<T>*)sin, (cplx<T>*)sout,
                              (const T*)vloc, reg_args(g), st);
         return;
@@ -894,17 +1138,20 @@ void LaunchFft<T>::plane_local_density(const Grid3& g, const void* sin, void* so
     if constexpr (reg_pair_ok<T>()) {
       if (n >= 64) {
         if (n == 64)
-          hipLaunchKernelGGL((k_rp_density<T, 64>), dim3(g.n3, ng), dim3(kRegPlaneThreads),
+          lz_launch((k_rp_density<T, 64>), (k_rp_density<T, 64, true>), dim3(g.n3, ng),
+                    dim3(kRegPlaneThreads),
                              (pair_lds<T, 64>(g.nact)), s, (const cplx<T>*)sin, (cplx<T>*)sout,
                              (const T*)vloc, (const cplx<T>*)ur, bandw, (cplx<T>*)dpart, nb,
                              gsize, reg_args(g), st);
         else if (n == 72)
-          hipLaunchKernelGGL((k_rp_density<T, 72>), dim3(g.n3, ng), dim3(kRegPlaneThreads),
+          lz_launch((k_rp_density<T, 72>), (k_rp_density<T, 72, true>), dim3(g.n3, ng),
+                    dim3(kRegPlaneThreads),
                              (pair_lds<T, 72>(g.nact)), s, (const cplx<T>*)sin, (cplx<T>*)sout,
                              (const T*)vloc, (const cplx<T>*)ur, bandw, (cplx<T>*)dpart, nb,
                              gsize, reg_args(g), st);
         else
-          hipLaunchKernelGGL((k_rp_density<T, 96>), dim3(g.n3, ng), dim3(kRegPlaneThreads),
+          lz_launch((k_rp_density<T, 96>), (k_rp_density<T, 96, true>), dim3(g.n3, ng),
+                    dim3(kRegPlaneThreads),
                              (pair_lds<T, 96>(g.nact)), s, (const cplx<T>*)sin, (cplx<T>*)sout,
                              (const T*)vloc, (const cplx<T>*)ur, bandw, (cplx<T>*)dpart, nb,
                              gsize, reg_args(g), st);
@@ -914,7 +1161,8 @@ void LaunchFft<T>::plane_local_density(const Grid3& g, const void* sin, void* so
     if constexpr (reg_plane_ok<T, 48>()) {
       if (n == 48 && gsize <= 4) {  // one band per lane of a quad
         const size_t lds = (size_t)4 * (g.nact + 1) * 49 * sizeof(cplx<T>);  // compact planes
-        hipLaunchKernelGGL((k_rq_density<T, 48>), dim3(g.n3, ng), dim3(kRegPlaneThreads), lds, s,
+        lz_launch((k_rq_density<T, 48>), (k_rq_density<T, 48, true>), dim3(g.n3, ng),
+                  dim3(kRegPlaneThreads), lds, s,
                            (const cplx<T>*)sin,
                            (cplx<T>*)sout, (const T*)vloc, (const cplx<T>*)ur, bandw,
                            (cplx<T>*)dpart, nb, gsize, reg_args(g), st);
@@ -949,10 +1197,10 @@ void LaunchFft<T>::plane_vu(const Grid3& g, const void* ur, const void* vp, void
     // LDS pass on the 48^3 cell; the local and density passes stay on LDS,
     // where their lane-pair forms were slower: 125 and 377 us against 110 and
     // 164)
-    if (ct_size(g) == 48 && g.soff_c) {
-      hipLaunchKernelGGL((k_rp_vu<T, 48>), dim3(nb * 48), dim3(rp_threads<T, 48>()),
-                         (size_t)(g.nact + 1) * 49 * sizeof(cplx<T>), s, (const cplx<T>*)ur,
-                         (const cplx<T>*)vp, (cplx<T>*)sout, reg_args(g), st);
+    if (ct_size(g) == 48 && g.soff_c && !g.lds_planes) {
+      lz_launch((k_rp_vu<T, 48>), (k_rp_vu<T, 48, true>), dim3(nb * 48), dim3(rp_threads<T, 48>()),
+                (size_t)(g.nact + 1) * 49 * sizeof(cplx<T>), s, (const cplx<T>*)ur,
+                (const cplx<T>*)vp, (cplx<T>*)sout, reg_args(g), st);
       return;
     }
   }
@@ -962,13 +1210,16 @@ void LaunchFft<T>::plane_vu(const Grid3& g, const void* ur, const void* vp, void
     if constexpr (reg_pair_ok<T>()) {
       if (n >= 64) {
         if (n == 64)
-          hipLaunchKernelGGL((k_rp_vu<T, 64>), dim3(nplanes), dim3(kRegPlaneThreads), lds, s,
+          lz_launch((k_rp_vu<T, 64>), (k_rp_vu<T, 64, true>), dim3(nplanes), dim3(kRegPlaneThreads),
+                    lds, s,
                              (const cplx<T>*)ur, (const cplx<T>*)vp, (cplx<T>*)sout, reg_args(g), st);
         else if (n == 72)
-          hipLaunchKernelGGL((k_rp_vu<T, 72>), dim3(nplanes), dim3(kRegPlaneThreads), lds, s,
+          lz_launch((k_rp_vu<T, 72>), (k_rp_vu<T, 72, true>), dim3(nplanes), dim3(kRegPlaneThreads),
+                    lds, s,
                              (const cplx<T>*)ur, (const cplx<T>*)vp, (cplx<T>*)sout, reg_args(g), st);
         else
-          hipLaunchKernelGGL((k_rp_vu<T, 96>), dim3(nplanes), dim3(kRegPlaneThreads), lds, s,
+          lz_launch((k_rp_vu<T, 96>), (k_rp_vu<T, 96, true>), dim3(nplanes), dim3(kRegPlaneThreads),
+                    lds, s,
                              (const cplx<T>*)ur, (const cplx<T>*)vp, (cplx<T>*)sout, reg_args(g), st);
         return;
       }
@@ -1009,78 +1260,51 @@ void LaunchFft<T>::hxc(const Grid3& g, const void* dpart, int ngroups, void* nr,
                   plane_args(g), (const cplx<T>*)g.tw1, (const cplx<T>*)g.tw2, st);
 }
 
-// Kernels whose LDS may exceed the default dynamic limit opt in once.
+// Kernels whose LDS may exceed the default dynamic limit opt in once (each
+// kernel and its work-list twin).
 template <typename T>
 hipError_t enable_large_lds_fft() {
-  const int big = 160 * 1024;
-#define LZ_LDS_ATTR(KERN)                                                                     \
-  {                                                                                           \
-    const void* fns[] = {(const void*)KERN<T, 0, 12>, (const void*)KERN<T, 0, 24>,            \
-                         (const void*)KERN<T, 0, 36>, (const void*)KERN<T, 24, 0>,            \
-                         (const void*)KERN<T, 32, 0>, (const void*)KERN<T, 40, 0>,            \
-                         (const void*)KERN<T, 48, 0>, (const void*)KERN<T, 64, 0>,            \
-                         (const void*)KERN<T, 72, 0>, (const void*)KERN<T, 96, 0>};           \
-    for (const void* f : fns) {                                                               \
-      hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, big); \
-      if (e != hipSuccess) return e;                                                          \
-    }                                                                                         \
-  }
-  LZ_LDS_ATTR(k_plane_local)
-  LZ_LDS_ATTR(k_plane_local_density)
-  LZ_LDS_ATTR(k_plane_to_real)
-  LZ_LDS_ATTR(k_plane_vu)
-  LZ_LDS_ATTR(k_hxc_planes_fwd)
-  LZ_LDS_ATTR(k_hxc_planes_inv)
-#undef LZ_LDS_ATTR
-#define LZ_REG_ATTR(KERN)                                                                     \
-  if constexpr (reg_plane_ok<T, 48>()) {                                                      \
-    const void* fns[] = {(const void*)KERN<T, 24>, (const void*)KERN<T, 32>,                  \
-                         (const void*)KERN<T, 48>};                                           \
-    for (const void* f : fns) {                                                               \
-      hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, big); \
-      if (e != hipSuccess) return e;                                                          \
-    }                                                                                         \
-  }
-  {
-    const void* fns[] = {(const void*)k_zfft_inv<T, 24>, (const void*)k_zfft_inv<T, 32>,
-                         (const void*)k_zfft_inv<T, 40>, (const void*)k_zfft_inv<T, 48>,
-                         (const void*)k_zfft_inv<T, 64>, (const void*)k_zfft_inv<T, 72>,
-                         (const void*)k_zfft_inv<T, 96>,
-                         (const void*)k_zfft_fwd<T, 24>, (const void*)k_zfft_fwd<T, 32>,
-                         (const void*)k_zfft_fwd<T, 40>, (const void*)k_zfft_fwd<T, 48>,
-                         (const void*)k_zfft_fwd<T, 64>, (const void*)k_zfft_fwd<T, 72>,
-                         (const void*)k_zfft_fwd<T, 96>};
-    for (const void* f : fns) {
-      hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, big);
-      if (e != hipSuccess) return e;
-    }
-  }
-  LZ_REG_ATTR(k_rl_local)
-  LZ_REG_ATTR(k_rl_density)
-  LZ_REG_ATTR(k_rl_vu)
+  std::vector<const void*> fns;
+#define LZ_BOTH(...) \
+  fns.push_back((const void*)__VA_ARGS__>); \
+  fns.push_back((const void*)__VA_ARGS__, true>);
+#define LZ_PLANE_KERNS(KERN)                                                   \
+  LZ_BOTH(KERN<T, 0, 12) LZ_BOTH(KERN<T, 0, 24) LZ_BOTH(KERN<T, 0, 36)       \
+  LZ_BOTH(KERN<T, 24, 0) LZ_BOTH(KERN<T, 32, 0) LZ_BOTH(KERN<T, 40, 0)       \
+  LZ_BOTH(KERN<T, 48, 0) LZ_BOTH(KERN<T, 64, 0) LZ_BOTH(KERN<T, 72, 0)       \
+  LZ_BOTH(KERN<T, 96, 0)
+  LZ_PLANE_KERNS(k_plane_local)
+  LZ_PLANE_KERNS(k_plane_local_density)
+  LZ_PLANE_KERNS(k_plane_to_real)
+  LZ_PLANE_KERNS(k_plane_vu)
+  LZ_PLANE_KERNS(k_hxc_planes_fwd)
+  LZ_PLANE_KERNS(k_hxc_planes_inv)
+#undef LZ_PLANE_KERNS
+#define LZ_STICK_KERNS(KERN)                                                   \
+  LZ_BOTH(KERN<T, 24) LZ_BOTH(KERN<T, 32) LZ_BOTH(KERN<T, 40) LZ_BOTH(KERN<T, 48) \
+  LZ_BOTH(KERN<T, 64) LZ_BOTH(KERN<T, 72) LZ_BOTH(KERN<T, 96)
+  LZ_STICK_KERNS(k_zfft_inv)
+  LZ_STICK_KERNS(k_zfft_fwd)
+#undef LZ_STICK_KERNS
   if constexpr (reg_plane_ok<T, 48>()) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_rq_density<T, 48>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, big);
-    if (e != hipSuccess) return e;
+    LZ_BOTH(k_rl_local<T, 24) LZ_BOTH(k_rl_local<T, 32) LZ_BOTH(k_rl_local<T, 48)
+    LZ_BOTH(k_rl_density<T, 24) LZ_BOTH(k_rl_density<T, 32) LZ_BOTH(k_rl_density<T, 48)
+    LZ_BOTH(k_rl_vu<T, 24) LZ_BOTH(k_rl_vu<T, 32) LZ_BOTH(k_rl_vu<T, 48)
+    LZ_BOTH(k_rq_density<T, 48)
   }
-#undef LZ_REG_ATTR
   if constexpr (rp_ok<T, 48>()) {
-    const void* fns[] = {(const void*)k_rp_vu<T, 48>};
-    for (const void* f : fns) {
-      hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, big);
-      if (e != hipSuccess) return e;
-    }
+    LZ_BOTH(k_rp_vu<T, 48)
   }
   if constexpr (reg_pair_ok<T>()) {
-    const void* fns[] = {(const void*)k_rp_local<T, 64>, (const void*)k_rp_density<T, 64>,
-                         (const void*)k_rp_vu<T, 64>,
-                         (const void*)k_rp_local<T, 72>, (const void*)k_rp_density<T, 72>,
-                         (const void*)k_rp_vu<T, 72>, (const void*)k_rp_local<T, 96>,
-                         (const void*)k_rp_density<T, 96>, (const void*)k_rp_vu<T, 96>};
-    for (const void* f : fns) {
-      hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, big);
-      if (e != hipSuccess) return e;
-    }
+    LZ_BOTH(k_rp_local<T, 64) LZ_BOTH(k_rp_density<T, 64) LZ_BOTH(k_rp_vu<T, 64)
+    LZ_BOTH(k_rp_local<T, 72) LZ_BOTH(k_rp_density<T, 72) LZ_BOTH(k_rp_vu<T, 72)
+    LZ_BOTH(k_rp_local<T, 96) LZ_BOTH(k_rp_density<T, 96) LZ_BOTH(k_rp_vu<T, 96)
+  }
+#undef LZ_BOTH
+  const int big = 160 * 1024;
+  for (const void* f : fns) {
+    const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, big);
+    if (e != hipSuccess) return e;
   }
   return hipSuccess;
 }

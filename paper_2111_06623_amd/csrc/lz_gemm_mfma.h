@@ -102,17 +102,31 @@ constexpr int kMfmaTile = 64;  // block output tile (both dimensions)
 // dot: block = (p tile, n tile) x G chunk x k
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(256) void k_proj_dot_mfma(const cplx<T>* __restrict__ A, int P,
-                                                       int a_rows, const cplx<T>* __restrict__ X,
-                                                       int nbnd, int npwx, int chunk, int nchunk,
-                                                       cplx<T>* __restrict__ partial,
-                                                       const LzDevState* st) {
+struct ProjDotMfmaArgs {
+  const cplx<T>* A;
+  int P;
+  int a_rows;
+  const cplx<T>* X;
+  int nbnd;
+  int npwx;
+  int chunk;
+  int nchunk;
+  cplx<T>* partial;
+  const LzDevState* st;
+};
+
+template <typename T>
+__device__ __forceinline__ void proj_dot_mfma_block(const cplx<T>* __restrict__ A, int P,
+                                                    int a_rows, const cplx<T>* __restrict__ X,
+                                                    int nbnd, int npwx, int chunk, int nchunk,
+                                                    cplx<T>* __restrict__ partial,
+                                                    const LzDevState* st, const VBlock& vb) {
   if (st && st->status) return;
   constexpr int BT = kMfmaTile, KC = mfma_kc<T>(), PITCH = KC + 1;
   __shared__ cplx<T> As[BT * PITCH], Xs[BT * PITCH];
   const int tilesN = (nbnd + BT - 1) / BT;
-  const int p0 = (blockIdx.x / tilesN) * BT, n0 = (blockIdx.x % tilesN) * BT;
-  const int ci = blockIdx.y, k = blockIdx.z;
+  const int p0 = (vb.x / tilesN) * BT, n0 = (vb.x % tilesN) * BT;
+  const int ci = vb.y, k = vb.z;
   const int tid = threadIdx.x, l = tid % 64, wave = tid / 64;
   const int wp = (wave / 2) * 32, wn = (wave % 2) * 32;
   const cplx<T>* Ak = A + (int64_t)k * a_rows * npwx;
@@ -173,6 +187,13 @@ __global__ __launch_bounds__(256) void k_proj_dot_mfma(const cplx<T>* __restrict
   }
 }
 
+template <typename T, bool BAT = false>
+__global__ __launch_bounds__(256) void k_proj_dot_mfma(ProjDotMfmaArgs<T> p, BatchRef br) {
+  LZ_BATCHED(BAT, p, br,
+             (proj_dot_mfma_block<T>(a_.A, a_.P, a_.a_rows, a_.X, a_.nbnd, a_.npwx, a_.chunk,
+                                     a_.nchunk, a_.partial, a_.st, vb)));
+}
+
 // Epilogue of an update tile (MODE as k_proj_update): the wave's outputs
 // at band bw + row, plane wave gw + col; block sums into lzpart.
 template <typename T, int MODE, typename TILE>
@@ -184,7 +205,7 @@ __device__ __forceinline__ void update_epilogue(const TILE& acc, cplx<T>* __rest
                                                 const double* __restrict__ wk,
                                                 double* __restrict__ lzpart, const LzDevState* st,
                                                 int bw, int gw, int k, int l,
-                                                double (*red)[256]) {
+                                                double (*red)[256], const VBlock& vb) {
   constexpr bool DOTS = MODE == kUpdDots || MODE == kUpdNhV;
   constexpr int NR = MODE == kUpdNhV ? 4 : 3;
   const int tid = threadIdx.x;
@@ -239,7 +260,7 @@ __device__ __forceinline__ void update_epilogue(const TILE& acc, cplx<T>* __rest
       __syncthreads();
     }
     if (tid == 0) {
-      const int blk = (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+      const int blk = (vb.z * vb.ny + vb.y) * vb.nx + vb.x;
 #pragma unroll
       for (int r = 0; r < NR; ++r) lzpart[NR * blk + r] = red[r][0];
     }
@@ -249,18 +270,41 @@ __device__ __forceinline__ void update_epilogue(const TILE& acc, cplx<T>* __rest
 // ---------------------------------------------------------------------------
 // update: block = (G tile, band tile, k); epilogue MODE as k_proj_update
 // ---------------------------------------------------------------------------
+template <typename T>
+struct ProjUpdateMfmaArgs {
+  cplx<T>* Y;
+  const cplx<T>* A;
+  int P;
+  int a_rows;
+  const cplx<T>* C;
+  int c_rows;
+  int nbnd;
+  int npwx;
+  cplx<T>* X;
+  const cplx<T>* yv;
+  const cplx<T>* U2;
+  const double* wk;
+  double* lzpart;
+  const LzDevState* st;
+};
+
 template <typename T, int MODE>
-__global__ __launch_bounds__(256) void k_proj_update_mfma(
-    cplx<T>* __restrict__ Y, const cplx<T>* __restrict__ A, int P, int a_rows,
-    const cplx<T>* __restrict__ C, int c_rows, int nbnd, int npwx, cplx<T>* __restrict__ X,
-    const cplx<T>* __restrict__ yv, const cplx<T>* __restrict__ U2,
-    const double* __restrict__ wk, double* __restrict__ lzpart, const LzDevState* st) {
+__device__ __forceinline__ void proj_update_mfma_block(cplx<T>* __restrict__ Y,
+                                                       const cplx<T>* __restrict__ A, int P,
+                                                       int a_rows, const cplx<T>* __restrict__ C,
+                                                       int c_rows, int nbnd, int npwx,
+                                                       cplx<T>* __restrict__ X,
+                                                       const cplx<T>* __restrict__ yv,
+                                                       const cplx<T>* __restrict__ U2,
+                                                       const double* __restrict__ wk,
+                                                       double* __restrict__ lzpart,
+                                                       const LzDevState* st, const VBlock& vb) {
   constexpr int NR = MODE == kUpdNhV ? 4 : 3;
   if (st && st->status) return;
   constexpr int BT = kMfmaTile, KC = mfma_kc<T>(), PITCH = BT + 1;
   __shared__ cplx<T> Cs[KC * PITCH], As[KC * PITCH];
   __shared__ double red[NR][256];
-  const int g0 = blockIdx.x * BT, b0 = blockIdx.y * BT, k = blockIdx.z;
+  const int g0 = vb.x * BT, b0 = vb.y * BT, k = vb.z;
   const int tid = threadIdx.x, l = tid % 64, wave = tid / 64;
   const int wb = (wave / 2) * 32, wg = (wave % 2) * 32;
   const cplx<T>* Ak = A + (int64_t)k * a_rows * npwx;
@@ -312,7 +356,15 @@ __global__ __launch_bounds__(256) void k_proj_update_mfma(
     __syncthreads();
   }
   update_epilogue<T, MODE, WaveTile<T>>(acc, Y, nbnd, npwx, X, yv, U2, wk, lzpart, st, b0 + wb,
-                                        g0 + wg, k, l, red);
+                                        g0 + wg, k, l, red, vb);
+}
+
+template <typename T, int MODE, bool BAT = false>
+__global__ __launch_bounds__(256) void k_proj_update_mfma(ProjUpdateMfmaArgs<T> p, BatchRef br) {
+  LZ_BATCHED(BAT, p, br,
+             (proj_update_mfma_block<T, MODE>(a_.Y, a_.A, a_.P, a_.a_rows, a_.C, a_.c_rows, a_.nbnd,
+                                              a_.npwx, a_.X, a_.yv, a_.U2, a_.wk, a_.lzpart, a_.st,
+                                              vb)));
 }
 
 
@@ -406,18 +458,31 @@ struct WaveTileB3 {
 };
 
 // dot with split-bf16 products (contract of k_proj_dot_mfma, FP32)
-__global__ __launch_bounds__(256) void k_proj_dot_b3(const float2* __restrict__ A, int P,
-                                                     int a_rows, const float2* __restrict__ X,
-                                                     int nbnd, int npwx, int chunk, int nchunk,
-                                                     float2* __restrict__ partial,
-                                                     const LzDevState* st) {
+struct ProjDotB3Args {
+  const float2* A;
+  int P;
+  int a_rows;
+  const float2* X;
+  int nbnd;
+  int npwx;
+  int chunk;
+  int nchunk;
+  float2* partial;
+  const LzDevState* st;
+};
+
+__device__ __forceinline__ void proj_dot_b3_block(const float2* __restrict__ A, int P, int a_rows,
+                                                  const float2* __restrict__ X, int nbnd, int npwx,
+                                                  int chunk, int nchunk,
+                                                  float2* __restrict__ partial,
+                                                  const LzDevState* st, const VBlock& vb) {
   if (st && st->status) return;
   constexpr int BT = kMfmaTile, KC = kB3Kc;
   __shared__ __align__(16) unsigned short lds[2 * 4 * 64 * kB3Pitch];
   const B3Planes As{lds}, Xs{lds + 4 * 64 * kB3Pitch};
   const int tilesN = (nbnd + BT - 1) / BT;
-  const int p0 = (blockIdx.x / tilesN) * BT, n0 = (blockIdx.x % tilesN) * BT;
-  const int ci = blockIdx.y, k = blockIdx.z;
+  const int p0 = (vb.x / tilesN) * BT, n0 = (vb.x % tilesN) * BT;
+  const int ci = vb.y, k = vb.z;
   const int tid = threadIdx.x, l = tid % 64, wave = tid / 64;
   const int wp = (wave / 2) * 32, wn = (wave % 2) * 32;
   const float2* Ak = A + (int64_t)k * a_rows * npwx;
@@ -471,21 +536,50 @@ __global__ __launch_bounds__(256) void k_proj_dot_b3(const float2* __restrict__ 
   }
 }
 
+template <bool BAT = false>
+__global__ __launch_bounds__(256) void k_proj_dot_b3(ProjDotB3Args p, BatchRef br) {
+  LZ_BATCHED(BAT, p, br,
+             (proj_dot_b3_block(a_.A, a_.P, a_.a_rows, a_.X, a_.nbnd, a_.npwx, a_.chunk, a_.nchunk,
+                                a_.partial, a_.st, vb)));
+}
+
 // update with split-bf16 products (contract of k_proj_update_mfma, FP32):
 // C^T rows (bands) and A^T rows (plane waves) staged with p contiguous
+struct ProjUpdateB3Args {
+  float2* Y;
+  const float2* A;
+  int P;
+  int a_rows;
+  const float2* C;
+  int c_rows;
+  int nbnd;
+  int npwx;
+  float2* X;
+  const float2* yv;
+  const float2* U2;
+  const double* wk;
+  double* lzpart;
+  const LzDevState* st;
+};
+
 template <int MODE>
-__global__ __launch_bounds__(256) void k_proj_update_b3(
-    float2* __restrict__ Y, const float2* __restrict__ A, int P, int a_rows,
-    const float2* __restrict__ C, int c_rows, int nbnd, int npwx, float2* __restrict__ X,
-    const float2* __restrict__ yv, const float2* __restrict__ U2, const double* __restrict__ wk,
-    double* __restrict__ lzpart, const LzDevState* st) {
+__device__ __forceinline__ void proj_update_b3_block(float2* __restrict__ Y,
+                                                     const float2* __restrict__ A, int P,
+                                                     int a_rows, const float2* __restrict__ C,
+                                                     int c_rows, int nbnd, int npwx,
+                                                     float2* __restrict__ X,
+                                                     const float2* __restrict__ yv,
+                                                     const float2* __restrict__ U2,
+                                                     const double* __restrict__ wk,
+                                                     double* __restrict__ lzpart,
+                                                     const LzDevState* st, const VBlock& vb) {
   constexpr int NR = MODE == kUpdNhV ? 4 : 3;
   if (st && st->status) return;
   constexpr int BT = kMfmaTile, KC = kB3Kc;
   __shared__ __align__(16) unsigned short lds[2 * 4 * 64 * kB3Pitch];
   __shared__ double red[NR][256];
   const B3Planes Cs{lds}, As{lds + 4 * 64 * kB3Pitch};
-  const int g0 = blockIdx.x * BT, b0 = blockIdx.y * BT, k = blockIdx.z;
+  const int g0 = vb.x * BT, b0 = vb.y * BT, k = vb.z;
   const int tid = threadIdx.x, l = tid % 64, wave = tid / 64;
   const int wb = (wave / 2) * 32, wg = (wave % 2) * 32;
   const float2* Ak = A + (int64_t)k * a_rows * npwx;
@@ -531,7 +625,15 @@ __global__ __launch_bounds__(256) void k_proj_update_b3(
     __syncthreads();
   }
   update_epilogue<float, MODE, WaveTileB3>(acc, Y, nbnd, npwx, X, yv, U2, wk, lzpart, st,
-                                           b0 + wb, g0 + wg, k, l, red);
+                                           b0 + wb, g0 + wg, k, l, red, vb);
+}
+
+template <int MODE, bool BAT = false>
+__global__ __launch_bounds__(256) void k_proj_update_b3(ProjUpdateB3Args p, BatchRef br) {
+  LZ_BATCHED(BAT, p, br,
+             (proj_update_b3_block<MODE>(a_.Y, a_.A, a_.P, a_.a_rows, a_.C, a_.c_rows, a_.nbnd,
+                                         a_.npwx, a_.X, a_.yv, a_.U2, a_.wk, a_.lzpart, a_.st,
+                                         vb)));
 }
 
 }  // namespace lz

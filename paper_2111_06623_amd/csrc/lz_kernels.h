@@ -4,6 +4,7 @@
 
 #include <cstdint>
 
+#include "lz_batch.h"
 #include "lz_device.h"
 
 namespace lz {
@@ -34,6 +35,8 @@ struct Grid3 {
   const int* soff_f;       // [S] LDS offset si1 (n+1) + si2 of each stick
   const int* soff_c;       // [S] LDS offset slot[si1] (n+1) + si2 in a compact plane
   signed char slot[128];   // index of each grid row i1 in act, or -1
+  int lds_planes;          // 1: the LDS Stockham plane kernels even where register-line or
+                           // lane-pair kernels exist (a launch schedule the autotuner times)
 };
 
 template <typename T> struct LaunchFft {

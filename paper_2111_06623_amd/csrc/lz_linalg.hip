@@ -3,10 +3,28 @@
 // projector products (P_c and separable projectors), Lanczos vector updates
 // and deterministic reductions, the spectrum solve, and layout permutations.
 #include <algorithm>
+#include <stdexcept>
+#include <string>
 
 #include "lz_kernels.h"
 
 namespace lz {
+
+thread_local std::vector<LaunchRec>* t_launch_rec = nullptr;
+
+void launch_args(const void* fn, const void* fnb, dim3 grid, dim3 block, size_t lds,
+                 hipStream_t s, const void* p, size_t bytes) {
+  if (t_launch_rec) {
+    const unsigned char* b = static_cast<const unsigned char*>(p);
+    t_launch_rec->push_back(
+        LaunchRec{fn, fnb, grid, block, lds, std::vector<unsigned char>(b, b + bytes)});
+    return;
+  }
+  BatchRef br{nullptr, nullptr, 0, 0};
+  void* args[2] = {const_cast<void*>(p), &br};
+  const hipError_t e = hipLaunchKernel(fn, grid, block, args, lds, s);
+  if (e != hipSuccess) throw std::runtime_error(std::string("kernel launch: ") + hipGetErrorString(e));
+}
 
 // complex values per thread of a 256-thread plane pass (general form)
 int plane_mp(int n1, int n2) {
@@ -42,21 +60,35 @@ constexpr int kDotK = 32;  // G per LDS tile
 // `chunk` plane waves of one k.  UPD: the block first forms the Lanczos
 // vector w = a*LW + b*X of its plane waves and writes it back to X (the
 // host uses UPD only when one block spans every row and band of a chunk).
+template <typename T>
+struct ProjDotArgs {
+  const cplx<T>* A;
+  int P;
+  int a_rows;
+  cplx<T>* X;
+  const cplx<T>* LW;
+  int nbnd;
+  int npwx;
+  int chunk;
+  int nchunk;
+  cplx<T>* partial;
+  const LzDevState* st;
+};
+
 template <typename T, int TPI, int TNJ, bool UPD>
-__global__ __launch_bounds__(256, TPI * TNJ <= 3 ? 4 : 1) void k_proj_dot(const cplx<T>* __restrict__ A, int P,
-                                                  int a_rows, cplx<T>* X,
-                                                  const cplx<T>* __restrict__ LW, int nbnd,
-                                                  int npwx, int chunk, int nchunk,
-                                                  cplx<T>* __restrict__ partial,
-                                                  const LzDevState* st) {
+__device__ __forceinline__ void proj_dot_block(const cplx<T>* __restrict__ A, int P, int a_rows,
+                                               cplx<T>* X, const cplx<T>* __restrict__ LW, int nbnd,
+                                               int npwx, int chunk, int nchunk,
+                                               cplx<T>* __restrict__ partial, const LzDevState* st,
+                                               const VBlock& vb) {
   if (st && st->status) return;
   constexpr int TP = 16 * TPI, TN = 16 * TNJ;
   __shared__ cplx<T> As[TP][kDotK + 1];
   __shared__ cplx<T> Xs[TN][kDotK + 1];
   const int ntn = (nbnd + TN - 1) / TN;
-  const int p0 = (blockIdx.x / ntn) * TP;
-  const int n0 = (blockIdx.x % ntn) * TN;
-  const int ci = blockIdx.y, k = blockIdx.z;
+  const int p0 = (vb.x / ntn) * TP;
+  const int n0 = (vb.x % ntn) * TN;
+  const int ci = vb.y, k = vb.z;
   const int tid = threadIdx.x;
   const int ty = tid / 16, tx = tid % 16;
   T ua = T(0), ub = T(0);
@@ -145,6 +177,14 @@ __global__ __launch_bounds__(256, TPI * TNJ <= 3 ? 4 : 1) void k_proj_dot(const 
     }
 }
 
+template <typename T, int TPI, int TNJ, bool UPD, bool BAT = false>
+__global__ __launch_bounds__(256, TPI * TNJ <= 3 ? 4 : 1) void k_proj_dot(ProjDotArgs<T> p,
+                                                                          BatchRef br) {
+  LZ_BATCHED(BAT, p, br,
+             (proj_dot_block<T, TPI, TNJ, UPD>(a_.A, a_.P, a_.a_rows, a_.X, a_.LW, a_.nbnd, a_.npwx,
+                                               a_.chunk, a_.nchunk, a_.partial, a_.st, vb)));
+}
+
 // Column n of R[k] (P rows) from the chunk partials [k][chunk][n][p], summed in
 // double in a fixed order: lane l of a row sums chunks l, l+16, ..., then the
 // 16 lane sums are added in lane order.  A round covers kRedRows rows (16
@@ -223,16 +263,29 @@ __global__ __launch_bounds__(256) void k_reduce_plain(const cplx<T>* __restrict_
 // with skip_pc (the start vector, or an operator application on a vector the
 // caller did not project) S is not applied: C_in = [0; D B'].
 template <typename T>
-__global__ __launch_bounds__(256) void k_reduce_coef_in(const cplx<T>* __restrict__ partial,
-                                                        int nchunk, const cplx<T>* __restrict__ M,
-                                                        const double* __restrict__ dkb, int nbnd,
-                                                        int nproj, int skip_pc,
-                                                        cplx<T>* __restrict__ C,
-                                                        const LzDevState* st) {
+struct ReduceCoefInArgs {
+  const cplx<T>* partial;
+  int nchunk;
+  const cplx<T>* M;
+  const double* dkb;
+  int nbnd;
+  int nproj;
+  int skip_pc;
+  cplx<T>* C;
+  const LzDevState* st;
+};
+
+template <typename T>
+__device__ __forceinline__ void reduce_coef_in_block(const cplx<T>* __restrict__ partial,
+                                                     int nchunk, const cplx<T>* __restrict__ M,
+                                                     const double* __restrict__ dkb, int nbnd,
+                                                     int nproj, int skip_pc,
+                                                     cplx<T>* __restrict__ C, const LzDevState* st,
+                                                     const VBlock& vb) {
   if (st && st->status) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cplx<T>* Rc = reinterpret_cast<cplx<T>*>(smem_raw);  // [P]
-  const int n = blockIdx.x, k = blockIdx.y;
+  const int n = vb.x, k = vb.y;
   const int P = nbnd + nproj;
   reduce_column<T>(partial, nchunk, P, nbnd, n, k, Rc);
   cplx<T>* Ck = C + (int64_t)k * P * nbnd;
@@ -259,19 +312,37 @@ __global__ __launch_bounds__(256) void k_reduce_coef_in(const cplx<T>* __restric
   }
 }
 
+template <typename T, bool BAT = false>
+__global__ __launch_bounds__(256) void k_reduce_coef_in(ReduceCoefInArgs<T> p, BatchRef br) {
+  LZ_BATCHED(BAT, p, br,
+             (reduce_coef_in_block<T>(a_.partial, a_.nchunk, a_.M, a_.dkb, a_.nbnd, a_.nproj,
+                                      a_.skip_pc, a_.C, a_.st, vb)));
+}
+
 // Output side, block (n, k): Rout[:, n] = (U^H Y)[:, n] reduced, DB = rows
 // nbnd.. of C_in:  C_out[:, n] = [-(Rout + M^H DB); DB][:, n].
 template <typename T>
-__global__ __launch_bounds__(256) void k_reduce_coef_out(const cplx<T>* __restrict__ partial,
-                                                         int nchunk,
-                                                         const cplx<T>* __restrict__ Cin,
-                                                         const cplx<T>* __restrict__ M, int nbnd,
-                                                         int nproj, cplx<T>* __restrict__ C,
-                                                         const LzDevState* st) {
+struct ReduceCoefOutArgs {
+  const cplx<T>* partial;
+  int nchunk;
+  const cplx<T>* Cin;
+  const cplx<T>* M;
+  int nbnd;
+  int nproj;
+  cplx<T>* C;
+  const LzDevState* st;
+};
+
+template <typename T>
+__device__ __forceinline__ void reduce_coef_out_block(const cplx<T>* __restrict__ partial,
+                                                      int nchunk, const cplx<T>* __restrict__ Cin,
+                                                      const cplx<T>* __restrict__ M, int nbnd,
+                                                      int nproj, cplx<T>* __restrict__ C,
+                                                      const LzDevState* st, const VBlock& vb) {
   if (st && st->status) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cplx<T>* Rc = reinterpret_cast<cplx<T>*>(smem_raw);  // [nbnd]
-  const int n = blockIdx.x, k = blockIdx.y;
+  const int n = vb.x, k = vb.y;
   const int P = nbnd + nproj;
   reduce_column<T>(partial, nchunk, nbnd, nbnd, n, k, Rc);
   const cplx<T>* Ck = Cin + (int64_t)k * P * nbnd;
@@ -295,6 +366,13 @@ __global__ __launch_bounds__(256) void k_reduce_coef_out(const cplx<T>* __restri
   }
 }
 
+template <typename T, bool BAT = false>
+__global__ __launch_bounds__(256) void k_reduce_coef_out(ReduceCoefOutArgs<T> p, BatchRef br) {
+  LZ_BATCHED(BAT, p, br,
+             (reduce_coef_out_block<T>(a_.partial, a_.nchunk, a_.Cin, a_.M, a_.nbnd, a_.nproj, a_.C,
+                                       a_.st, vb)));
+}
+
 // Y[k][n][G] += sum_{p<P} A[k][p][G] C[k][p][n], and what the recursion does
 // with the updated element Y' (MODE):
 //   kUpdPlain  Y <- Y'
@@ -312,12 +390,35 @@ __global__ __launch_bounds__(256) void k_reduce_coef_out(const cplx<T>* __restri
 // bands.
 constexpr int kUpdPlain = 0, kUpdDots = 1, kUpdNhU = 2, kUpdNhV = 3;
 
+template <typename T>
+struct ProjUpdateArgs {
+  cplx<T>* Y;
+  const cplx<T>* A;
+  int P;
+  int a_rows;
+  const cplx<T>* C;
+  int c_rows;
+  int nbnd;
+  int npwx;
+  cplx<T>* X;
+  const cplx<T>* yv;
+  const cplx<T>* U2;
+  const double* wk;
+  double* lzpart;
+  int qn;
+  const LzDevState* st;
+};
+
 template <typename T, int NBT, int MODE>
-__global__ __launch_bounds__(256) void k_proj_update(
-    cplx<T>* __restrict__ Y, const cplx<T>* __restrict__ A, int P, int a_rows,
-    const cplx<T>* __restrict__ C, int c_rows, int nbnd, int npwx, cplx<T>* __restrict__ X,
-    const cplx<T>* __restrict__ yv, const cplx<T>* __restrict__ U2,
-    const double* __restrict__ wk, double* __restrict__ lzpart, int qn, const LzDevState* st) {
+__device__ __forceinline__ void proj_update_block(cplx<T>* __restrict__ Y,
+                                                  const cplx<T>* __restrict__ A, int P, int a_rows,
+                                                  const cplx<T>* __restrict__ C, int c_rows,
+                                                  int nbnd, int npwx, cplx<T>* __restrict__ X,
+                                                  const cplx<T>* __restrict__ yv,
+                                                  const cplx<T>* __restrict__ U2,
+                                                  const double* __restrict__ wk,
+                                                  double* __restrict__ lzpart, int qn,
+                                                  const LzDevState* st, const VBlock& vb) {
   constexpr bool DOTS = MODE == kUpdDots || MODE == kUpdNhV;
   constexpr int NR = MODE == kUpdNhV ? 4 : 3;
   if (st && st->status) return;
@@ -326,8 +427,8 @@ __global__ __launch_bounds__(256) void k_proj_update(
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cplx<T>* Cs = reinterpret_cast<cplx<T>*>(smem_raw);  // [P][NB]
   __shared__ double red[NR][256];
-  const int k = blockIdx.z;
-  const int nb0 = blockIdx.y * NB;
+  const int k = vb.z;
+  const int nb0 = vb.y * NB;
   const int nbb = min(NB, nbnd - nb0);
   const cplx<T>* Ck = C + (int64_t)k * c_rows * nbnd;
   for (int t = threadIdx.x; t < P * NB; t += 256) {
@@ -336,7 +437,7 @@ __global__ __launch_bounds__(256) void k_proj_update(
   }
   __syncthreads();
   const int q = threadIdx.x / npt;
-  const int g = blockIdx.x * npt + (threadIdx.x % npt);
+  const int g = vb.x * npt + (threadIdx.x % npt);
   const int n0 = nb0 + q * NBT;
   const int nbt = min(NBT, nbnd - n0);
   double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
@@ -422,11 +523,19 @@ __global__ __launch_bounds__(256) void k_proj_update(
       __syncthreads();
     }
     if (threadIdx.x == 0) {
-      const int blk = (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+      const int blk = (vb.z * vb.ny + vb.y) * vb.nx + vb.x;
 #pragma unroll
       for (int r = 0; r < NR; ++r) lzpart[NR * blk + r] = red[r][0];
     }
   }
+}
+
+template <typename T, int NBT, int MODE, bool BAT = false>
+__global__ __launch_bounds__(256) void k_proj_update(ProjUpdateArgs<T> p, BatchRef br) {
+  LZ_BATCHED(BAT, p, br,
+             (proj_update_block<T, NBT, MODE>(a_.Y, a_.A, a_.P, a_.a_rows, a_.C, a_.c_rows, a_.nbnd,
+                                              a_.npwx, a_.X, a_.yv, a_.U2, a_.wk, a_.lzpart, a_.qn,
+                                              a_.st, vb)));
 }
 
 }  // namespace lz
@@ -438,15 +547,29 @@ namespace lz {
 // Lanczos vectors and scalars
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(256) void k_lz_update(cplx<T>* __restrict__ w, const cplx<T>* __restrict__ lw, int64_t n,
-                            const LzDevState* st) {
+struct LzUpdateArgs {
+  cplx<T>* w;
+  const cplx<T>* lw;
+  int64_t n;
+  const LzDevState* st;
+};
+
+template <typename T>
+__device__ __forceinline__ void lz_update_block(cplx<T>* __restrict__ w,
+                                                const cplx<T>* __restrict__ lw, int64_t n,
+                                                const LzDevState* st, const VBlock& vb) {
   if (st->status) return;
   const T a = T(st->a), b = T(st->b);
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x) {
+  for (int64_t i = vb.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)vb.nx * blockDim.x) {
     const cplx<T> l = lw[i], v = w[i];
     w[i] = mk<T>(a * l.x + b * v.x, a * l.y + b * v.y);
   }
+}
+
+template <typename T, bool BAT = false>
+__global__ __launch_bounds__(256) void k_lz_update(LzUpdateArgs<T> p, BatchRef br) {
+  LZ_BATCHED(BAT, p, br, (lz_update_block<T>(a_.w, a_.lw, a_.n, a_.st, vb)));
 }
 
 constexpr int kDotThreads = 256;
@@ -455,9 +578,22 @@ constexpr int kDotThreads = 256;
 //   j = st->step; b2 = Re<w_j, L w_j>_w; beta_{j+1} = sqrt(b2);
 //   z_{j+1} = <y, w_j>_w / beta_{j+1} for odd j (upper vector), else 0.
 // Step 0 (w_0 = y) first checks for a vanished right-hand side.
-__global__ __launch_bounds__(256) void k_lz_finalize(const double* __restrict__ partial, int nblk,
-                              LzDevState* __restrict__ st, double* __restrict__ beta,
-                              double* __restrict__ z, int max_steps, double tol, double yscale) {
+struct LzFinalizeArgs {
+  const double* partial;
+  int nblk;
+  LzDevState* st;
+  double* beta;
+  double* z;
+  int max_steps;
+  double tol;
+  double yscale;
+};
+
+__device__ __forceinline__ void lz_finalize_block(const double* __restrict__ partial, int nblk,
+                                                  LzDevState* __restrict__ st,
+                                                  double* __restrict__ beta, double* __restrict__ z,
+                                                  int max_steps, double tol, double yscale,
+                                                  const VBlock& vb) {
   __shared__ double red[3][kDotThreads];
   if (st->status) return;
   double s0 = 0.0, s1 = 0.0, s2 = 0.0;
@@ -513,6 +649,13 @@ __global__ __launch_bounds__(256) void k_lz_finalize(const double* __restrict__ 
   st->b = -bt / st->beta_prev;
   st->beta_prev = bt;
   st->step = j + 1;
+}
+
+template <bool BAT = false>
+__global__ __launch_bounds__(256) void k_lz_finalize(LzFinalizeArgs p, BatchRef br) {
+  LZ_BATCHED(BAT, p, br,
+             (lz_finalize_block(a_.partial, a_.nblk, a_.st, a_.beta, a_.z, a_.max_steps, a_.tol,
+                                a_.yscale, vb)));
 }
 
 // ---------------------------------------------------------------------------
@@ -778,13 +921,14 @@ void LaunchLin<T>::proj_dot(const void* A, int P, int a_rows, void* X, const voi
     const int tiles = ((P + kMfmaTile - 1) / kMfmaTile) * ((nbnd + kMfmaTile - 1) / kMfmaTile);
     if constexpr (sizeof(T) == 4) {
       if (gemm == kGemmBf16x3) {
-        hipLaunchKernelGGL(k_proj_dot_b3, dim3(tiles, nchunk, nks), dim3(256), 0, s,
+        lz_launch(k_proj_dot_b3<>, k_proj_dot_b3<true>, dim3(tiles, nchunk, nks), dim3(256), 0, s,
                            (const float2*)A, P, a_rows, (const float2*)X, nbnd, npwx, chunk,
                            nchunk, (float2*)partial, st);
         return;
       }
     }
-    hipLaunchKernelGGL(k_proj_dot_mfma<T>, dim3(tiles, nchunk, nks), dim3(256), 0, s,
+    lz_launch(k_proj_dot_mfma<T>, k_proj_dot_mfma<T, true>, dim3(tiles, nchunk, nks), dim3(256), 0,
+              s,
                        (const cplx<T>*)A, P, a_rows, (const cplx<T>*)X, nbnd, npwx, chunk, nchunk,
                        (cplx<T>*)partial, st);
     return;
@@ -796,11 +940,11 @@ void LaunchLin<T>::proj_dot(const void* A, int P, int a_rows, void* X, const voi
   dim3 grid(tiles, nchunk, nks);
 #define LZ_DOT(TPI, TNJ)                                                                       \
   if (upd)                                                                                     \
-    hipLaunchKernelGGL((k_proj_dot<T, TPI, TNJ, true>), grid, dim3(256), 0, s, (const cplx<T>*)A, \
+    lz_launch((k_proj_dot<T, TPI, TNJ, true>), (k_proj_dot<T, TPI, TNJ, true, true>), grid, dim3(256), 0, s, (const cplx<T>*)A, \
                        P, a_rows, (cplx<T>*)X, (const cplx<T>*)LW, nbnd, npwx, chunk, nchunk,  \
                        (cplx<T>*)partial, st);                                                 \
   else                                                                                         \
-    hipLaunchKernelGGL((k_proj_dot<T, TPI, TNJ, false>), grid, dim3(256), 0, s, (const cplx<T>*)A, \
+    lz_launch((k_proj_dot<T, TPI, TNJ, false>), (k_proj_dot<T, TPI, TNJ, false, true>), grid, dim3(256), 0, s, (const cplx<T>*)A, \
                        P, a_rows, (cplx<T>*)X, nullptr, nbnd, npwx, chunk, nchunk,             \
                        (cplx<T>*)partial, st);
   if (tnj == 1) {
@@ -841,7 +985,7 @@ void LaunchLin<T>::reduce_coef_in(const void* partial, int nchunk, const void* M
                                   const double* dkb, int nbnd, int nproj, int nks, bool skip_pc,
                                   void* C, const LzDevState* st, hipStream_t s) {
   const size_t lds = (size_t)(nbnd + nproj) * sizeof(cplx<T>);
-  hipLaunchKernelGGL(k_reduce_coef_in<T>, dim3(nbnd, nks), dim3(256), lds, s,
+  lz_launch(k_reduce_coef_in<T>, k_reduce_coef_in<T, true>, dim3(nbnd, nks), dim3(256), lds, s,
                      (const cplx<T>*)partial, nchunk, (const cplx<T>*)M, dkb, nbnd, nproj,
                      skip_pc ? 1 : 0, (cplx<T>*)C, st);
 }
@@ -851,7 +995,7 @@ void LaunchLin<T>::reduce_coef_out(const void* partial, int nchunk, const void* 
                                    const void* M, int nbnd, int nproj, int nks, void* C,
                                    const LzDevState* st, hipStream_t s) {
   const size_t lds = (size_t)nbnd * sizeof(cplx<T>);
-  hipLaunchKernelGGL(k_reduce_coef_out<T>, dim3(nbnd, nks), dim3(256), lds, s,
+  lz_launch(k_reduce_coef_out<T>, k_reduce_coef_out<T, true>, dim3(nbnd, nks), dim3(256), lds, s,
                      (const cplx<T>*)partial, nchunk, (const cplx<T>*)Cin, (const cplx<T>*)M,
                      nbnd, nproj, (cplx<T>*)C, st);
 }
@@ -883,7 +1027,7 @@ static void launch_update(int mode, void* Y, const void* A, int P, int a_rows, c
     if constexpr (sizeof(T) == 4) {
       if (gemm == kGemmBf16x3) {
 #define LZ_UPDB(MODE)                                                                            \
-  hipLaunchKernelGGL((k_proj_update_b3<MODE>), grid, dim3(256), 0, s, (float2*)Y,                \
+  lz_launch((k_proj_update_b3<MODE>), (k_proj_update_b3<MODE, true>), grid, dim3(256), 0, s, (float2*)Y,                \
                      (const float2*)A, P, a_rows, (const float2*)C, c_rows, nbnd, npwx,          \
                      (float2*)X, (const float2*)y, (const float2*)U2, wk, lzpart, st);
         switch (mode) {
@@ -897,7 +1041,7 @@ static void launch_update(int mode, void* Y, const void* A, int P, int a_rows, c
       }
     }
 #define LZ_UPDM(MODE)                                                                            \
-  hipLaunchKernelGGL((k_proj_update_mfma<T, MODE>), grid, dim3(256), 0, s, (cplx<T>*)Y,          \
+  lz_launch((k_proj_update_mfma<T, MODE>), (k_proj_update_mfma<T, MODE, true>), grid, dim3(256), 0, s, (cplx<T>*)Y,          \
                      (const cplx<T>*)A, P, a_rows, (const cplx<T>*)C, c_rows, nbnd, npwx,        \
                      (cplx<T>*)X, (const cplx<T>*)y, (const cplx<T>*)U2, wk, lzpart, st);
     switch (mode) {
@@ -915,7 +1059,7 @@ static void launch_update(int mode, void* Y, const void* A, int P, int a_rows, c
   dim3 grid((npwx + npt - 1) / npt, (nbnd + qn * nbt - 1) / (qn * nbt), nks);
   const size_t lds = (size_t)P * qn * nbt * sizeof(cplx<T>);
 #define LZ_UPD(NBT, MODE)                                                                        \
-  hipLaunchKernelGGL((k_proj_update<T, NBT, MODE>), grid, dim3(256), lds, s, (cplx<T>*)Y,        \
+  lz_launch((k_proj_update<T, NBT, MODE>), (k_proj_update<T, NBT, MODE, true>), grid, dim3(256), lds, s, (cplx<T>*)Y,        \
                      (const cplx<T>*)A, P, a_rows, (const cplx<T>*)C, c_rows, nbnd, npwx,        \
                      (cplx<T>*)X, (const cplx<T>*)y, (const cplx<T>*)U2, wk, lzpart, qn, st);
 #define LZ_UPD_MODES(NBT)                                          \
@@ -950,7 +1094,7 @@ void LaunchLin<T>::nh_form(bool v_chain, void* LY, const void* A, int P, const v
 
 template <typename T>
 void LaunchLin<T>::lz_update(void* w, const void* lw, int64_t n, const LzDevState* st, hipStream_t s) {
-  hipLaunchKernelGGL(k_lz_update<T>, dim3(1024), dim3(256), 0, s, (cplx<T>*)w,
+  lz_launch(k_lz_update<T>, k_lz_update<T, true>, dim3(1024), dim3(256), 0, s, (cplx<T>*)w,
                      (const cplx<T>*)lw, n, st);
 }
 
@@ -975,7 +1119,8 @@ void LaunchLin<T>::copy(void* dst, const void* src, int64_t n, hipStream_t s) {
 
 void launch_lz_finalize(const double* partial, int nblk, LzDevState* st, double* beta, double* z,
                         int max_steps, double tol, double yscale, hipStream_t s) {
-  hipLaunchKernelGGL(k_lz_finalize, dim3(1), dim3(kDotThreads), 0, s, partial, nblk, st, beta, z,
+  lz_launch(k_lz_finalize<>, k_lz_finalize<true>, dim3(1), dim3(kDotThreads), 0, s, partial, nblk,
+            st, beta, z,
                      max_steps, tol, yscale);
 }
 

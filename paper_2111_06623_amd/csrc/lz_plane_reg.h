@@ -131,19 +131,29 @@ __device__ __forceinline__ void reg_col_out(const cplx<T> (&x)[N], cplx<T>* pl,
 // D step: sticks -> IFFT2 -> V x -> FFT2 -> sticks, for nplanes planes
 // (band-major, z fastest).
 // ---------------------------------------------------------------------------
+template <typename T>
+struct RlLocalArgs {
+  const cplx<T>* sin;
+  cplx<T>* sout;
+  const T* vloc;
+  RegPlaneArgs a;
+  int nplanes;
+  const LzDevState* st;
+};
+
 template <typename T, int N>
-__global__ __launch_bounds__(kRegPlaneThreads) void k_rl_local(const cplx<T>* __restrict__ sin,
-                                                               cplx<T>* __restrict__ sout,
-                                                               const T* __restrict__ vloc,
-                                                               RegPlaneArgs a, int nplanes,
-                                                               const LzDevState* st) {
+__device__ __forceinline__ void rl_local_block(const cplx<T>* __restrict__ sin,
+                                               cplx<T>* __restrict__ sout,
+                                               const T* __restrict__ vloc, const RegPlaneArgs& a,
+                                               int nplanes, const LzDevState* st,
+                                               const VBlock& vb) {
   if (st && st->status) return;
   constexpr int NPB = RegPlane<N>::NPB, P = RegPlane<N>::P;
   const int pstride = (a.nact + 1) * P;  // compact planes: the active rows and a spare
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cplx<T>* planes = reinterpret_cast<cplx<T>*>(smem_raw);
   const int tid = threadIdx.x, pp = tid / N, l = tid - pp * N;
-  const int pidx = blockIdx.x * NPB + pp;
+  const int pidx = vb.x * NPB + pp;
   const bool live = pidx < nplanes;
   const int z = pidx % N;
   const int64_t so = (int64_t)pidx * a.S;
@@ -174,6 +184,12 @@ __global__ __launch_bounds__(kRegPlaneThreads) void k_rl_local(const cplx<T>* __
   if (live) reg_gather<T, N, false>(sout + so, pl, a.soffc, a.S, l);
 }
 
+template <typename T, int N, bool BAT = false>
+__global__ __launch_bounds__(kRegPlaneThreads) void k_rl_local(RlLocalArgs<T> p, BatchRef br) {
+  LZ_BATCHED(BAT, p, br,
+             (rl_local_block<T, N>(a_.sin, a_.sout, a_.vloc, a_.a, a_.nplanes, a_.st, vb)));
+}
+
 // ---------------------------------------------------------------------------
 // D+K step: as k_rl_local for the bands of a group at one z, NPB bands at a
 // time, also accumulating the response density
@@ -184,11 +200,29 @@ __global__ __launch_bounds__(kRegPlaneThreads) void k_rl_local(const cplx<T>* __
 // registers.  Rows without a stick are not cleared between bands; the column
 // threads read them as zero.
 // ---------------------------------------------------------------------------
+template <typename T>
+struct RlDensityArgs {
+  const cplx<T>* sin;
+  cplx<T>* sout;
+  const T* vloc;
+  const cplx<T>* ur;
+  const double* bandw;
+  cplx<T>* dpart;
+  int nb;
+  int gsize;
+  RegPlaneArgs a;
+  const LzDevState* st;
+};
+
 template <typename T, int N>
-__global__ __launch_bounds__(kRegPlaneThreads) void k_rl_density(
-    const cplx<T>* __restrict__ sin, cplx<T>* __restrict__ sout, const T* __restrict__ vloc,
-    const cplx<T>* __restrict__ ur, const double* __restrict__ bandw, cplx<T>* __restrict__ dpart,
-    int nb, int gsize, RegPlaneArgs a, const LzDevState* st) {
+__device__ __forceinline__ void rl_density_block(const cplx<T>* __restrict__ sin,
+                                                 cplx<T>* __restrict__ sout,
+                                                 const T* __restrict__ vloc,
+                                                 const cplx<T>* __restrict__ ur,
+                                                 const double* __restrict__ bandw,
+                                                 cplx<T>* __restrict__ dpart, int nb, int gsize,
+                                                 const RegPlaneArgs& a, const LzDevState* st,
+                                                 const VBlock& vb) {
   if (st && st->status) return;
   constexpr int NPB = RegPlane<N>::NPB, P = RegPlane<N>::P, R = RegPlane<N>::R;
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -196,7 +230,7 @@ __global__ __launch_bounds__(kRegPlaneThreads) void k_rl_density(
   constexpr int pstride = N * P;
   const int nact = a.nact;
   const int tid = threadIdx.x, pp = tid / N, l = tid - pp * N;
-  const int z = blockIdx.x, g = blockIdx.y;
+  const int z = vb.x, g = vb.y;
   const int b0 = g * gsize, b1 = min(nb, b0 + gsize);
   cplx<T>* pl = planes + pp * pstride;
   cplx<T> acc[R];
@@ -263,6 +297,13 @@ __global__ __launch_bounds__(kRegPlaneThreads) void k_rl_density(
   }
 }
 
+template <typename T, int N, bool BAT = false>
+__global__ __launch_bounds__(kRegPlaneThreads) void k_rl_density(RlDensityArgs<T> p, BatchRef br) {
+  LZ_BATCHED(BAT, p, br,
+             (rl_density_block<T, N>(a_.sin, a_.sout, a_.vloc, a_.ur, a_.bandw, a_.dpart, a_.nb,
+                                     a_.gsize, a_.a, a_.st, vb)));
+}
+
 // ---------------------------------------------------------------------------
 // D+K step on 48^2 planes for a group of at most four bands, one band per
 // lane of a quad: thread 4 l + pp holds column l of band b0 + pp (compact
@@ -298,11 +339,29 @@ __device__ __forceinline__ cplx<T> quad_reduce_scatter(cplx<T> p0, cplx<T> p1, c
   return cadd<T>(high ? r1 : r0, quad_xor2<T>(high ? r0 : r1));
 }
 
+template <typename T>
+struct RqDensityArgs {
+  const cplx<T>* sin;
+  cplx<T>* sout;
+  const T* vloc;
+  const cplx<T>* ur;
+  const double* bandw;
+  cplx<T>* dpart;
+  int nb;
+  int gsize;
+  RegPlaneArgs a;
+  const LzDevState* st;
+};
+
 template <typename T, int N>
-__global__ __launch_bounds__(kRegPlaneThreads) void k_rq_density(
-    const cplx<T>* __restrict__ sin, cplx<T>* __restrict__ sout, const T* __restrict__ vloc,
-    const cplx<T>* __restrict__ ur, const double* __restrict__ bandw, cplx<T>* __restrict__ dpart,
-    int nb, int gsize, RegPlaneArgs a, const LzDevState* st) {
+__device__ __forceinline__ void rq_density_block(const cplx<T>* __restrict__ sin,
+                                                 cplx<T>* __restrict__ sout,
+                                                 const T* __restrict__ vloc,
+                                                 const cplx<T>* __restrict__ ur,
+                                                 const double* __restrict__ bandw,
+                                                 cplx<T>* __restrict__ dpart, int nb, int gsize,
+                                                 const RegPlaneArgs& a, const LzDevState* st,
+                                                 const VBlock& vb) {
   static_assert(RegPlane<N>::NPB == 4 && sizeof(T) == 4, "four single-precision bands per block");
   if (st && st->status) return;
   const int pstride = (a.nact + 1) * RegPlane<N>::P;  // compact planes
@@ -310,7 +369,7 @@ __global__ __launch_bounds__(kRegPlaneThreads) void k_rq_density(
   cplx<T>* planes = reinterpret_cast<cplx<T>*>(smem_raw);
   const int tid = threadIdx.x, pp = tid & 3, l = tid >> 2;
   const bool odd = pp & 1, high = pp & 2;
-  const int z = blockIdx.x, g = blockIdx.y;
+  const int z = vb.x, g = vb.y;
   const int b0 = g * gsize, b = b0 + pp;
   const bool live = b < min(nb, b0 + gsize);
   cplx<T>* pl = planes + pp * pstride;
@@ -351,22 +410,38 @@ __global__ __launch_bounds__(kRegPlaneThreads) void k_rq_density(
   if (live) reg_gather<T, N, false>(sout + so, pl, a.soffc, a.S, l);
 }
 
+template <typename T, int N, bool BAT = false>
+__global__ __launch_bounds__(kRegPlaneThreads) void k_rq_density(RqDensityArgs<T> p, BatchRef br) {
+  LZ_BATCHED(BAT, p, br,
+             (rq_density_block<T, N>(a_.sin, a_.sout, a_.vloc, a_.ur, a_.bandw, a_.dpart, a_.nb,
+                                     a_.gsize, a_.a, a_.st, vb)));
+}
+
 // ---------------------------------------------------------------------------
 // v'(r) u_b(r) -> FFT2 -> added to the sticks of the same band
 // ---------------------------------------------------------------------------
+template <typename T>
+struct RlVuArgs {
+  const cplx<T>* ur;
+  const cplx<T>* vp;
+  cplx<T>* sout;
+  RegPlaneArgs a;
+  int nplanes;
+  const LzDevState* st;
+};
+
 template <typename T, int N>
-__global__ __launch_bounds__(kRegPlaneThreads) void k_rl_vu(const cplx<T>* __restrict__ ur,
-                                                            const cplx<T>* __restrict__ vp,
-                                                            cplx<T>* __restrict__ sout,
-                                                            RegPlaneArgs a, int nplanes,
-                                                            const LzDevState* st) {
+__device__ __forceinline__ void rl_vu_block(const cplx<T>* __restrict__ ur,
+                                            const cplx<T>* __restrict__ vp,
+                                            cplx<T>* __restrict__ sout, const RegPlaneArgs& a,
+                                            int nplanes, const LzDevState* st, const VBlock& vb) {
   if (st && st->status) return;
   constexpr int NPB = RegPlane<N>::NPB;
   const int pstride = (a.nact + 1) * RegPlane<N>::P;  // compact planes
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cplx<T>* planes = reinterpret_cast<cplx<T>*>(smem_raw);
   const int tid = threadIdx.x, pp = tid / N, l = tid - pp * N;
-  const int pidx = blockIdx.x * NPB + pp;
+  const int pidx = vb.x * NPB + pp;
   const bool live = pidx < nplanes;
   const int z = pidx % N;
   cplx<T>* pl = planes + pp * pstride;
@@ -383,6 +458,11 @@ __global__ __launch_bounds__(kRegPlaneThreads) void k_rl_vu(const cplx<T>* __res
   reg_rows<T, N, -1>(planes, pstride, a.nact, tid, [](int r) { return r; });
   __syncthreads();
   if (live) reg_gather<T, N, true>(sout + (int64_t)pidx * a.S, pl, a.soffc, a.S, l);
+}
+
+template <typename T, int N, bool BAT = false>
+__global__ __launch_bounds__(kRegPlaneThreads) void k_rl_vu(RlVuArgs<T> p, BatchRef br) {
+  LZ_BATCHED(BAT, p, br, (rl_vu_block<T, N>(a_.ur, a_.vp, a_.sout, a_.a, a_.nplanes, a_.st, vb)));
 }
 
 // ---------------------------------------------------------------------------
@@ -479,12 +559,20 @@ __device__ __forceinline__ void pair_pointwise(cplx<T> (&x)[N / 2], cplx<T>* stg
   }
 }
 
+template <typename T>
+struct RpLocalArgs {
+  const cplx<T>* sin;
+  cplx<T>* sout;
+  const T* vloc;
+  RegPlaneArgs a;
+  const LzDevState* st;
+};
+
 template <typename T, int N>
-__global__ __launch_bounds__((rp_threads<T, N>())) void k_rp_local(const cplx<T>* __restrict__ sin,
-                                                                 cplx<T>* __restrict__ sout,
-                                                                 const T* __restrict__ vloc,
-                                                                 RegPlaneArgs a,
-                                                                 const LzDevState* st) {
+__device__ __forceinline__ void rp_local_block(const cplx<T>* __restrict__ sin,
+                                               cplx<T>* __restrict__ sout,
+                                               const T* __restrict__ vloc, const RegPlaneArgs& a,
+                                               const LzDevState* st, const VBlock& vb) {
   if (st && st->status) return;
   constexpr int M = N / 2, NT = rp_threads<T, N>();
   const int pstride = (a.nact + 1) * (N + 1);
@@ -492,7 +580,7 @@ __global__ __launch_bounds__((rp_threads<T, N>())) void k_rp_local(const cplx<T>
   cplx<T>* pl = reinterpret_cast<cplx<T>*>(smem_raw);
   const int tid = threadIdx.x, c = tid >> 1, h = tid & 1;
   const bool col = 2 * N >= NT || c < N;  // every thread on 96^2 planes and in 96-thread blocks
-  const int pidx = blockIdx.x, z = pidx % N;
+  const int pidx = vb.x, z = pidx % N;
   const int64_t so = (int64_t)pidx * a.S;
   for (int t = tid; t < pstride; t += NT) pl[t] = mk<T>(T(0), T(0));
   __syncthreads();
@@ -521,6 +609,11 @@ __global__ __launch_bounds__((rp_threads<T, N>())) void k_rp_local(const cplx<T>
   pair_gather<T, NT, false>(sout + so, pl, a.soffc, a.S, tid);
 }
 
+template <typename T, int N, bool BAT = false>
+__global__ __launch_bounds__((rp_threads<T, N>())) void k_rp_local(RpLocalArgs<T> p, BatchRef br) {
+  LZ_BATCHED(BAT, p, br, (rp_local_block<T, N>(a_.sin, a_.sout, a_.vloc, a_.a, a_.st, vb)));
+}
+
 // A value streamed from memory once (non-temporal: kept out of the caches,
 // which then hold the partial-density slices the density pass re-reads).
 template <typename T>
@@ -537,11 +630,29 @@ __device__ __forceinline__ cplx<T> ld_stream(const cplx<T>* p) {
 // 5.3 ms became 3.85 ms on the 96^3 cell against two blocks per unit at 172
 // registers (the batched workload, with its 72^3 members, gained 7 % against
 // the unbounded 181 registers at 72).
+template <typename T>
+struct RpDensityArgs {
+  const cplx<T>* sin;
+  cplx<T>* sout;
+  const T* vloc;
+  const cplx<T>* ur;
+  const double* bandw;
+  cplx<T>* dpart;
+  int nb;
+  int gsize;
+  RegPlaneArgs a;
+  const LzDevState* st;
+};
+
 template <typename T, int N>
-__global__ __launch_bounds__((rp_threads<T, N>())) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 2 : 3))) void k_rp_density(
-    const cplx<T>* __restrict__ sin, cplx<T>* __restrict__ sout, const T* __restrict__ vloc,
-    const cplx<T>* __restrict__ ur, const double* __restrict__ bandw, cplx<T>* __restrict__ dpart,
-    int nb, int gsize, RegPlaneArgs a, const LzDevState* st) {
+__device__ __forceinline__ void rp_density_block(const cplx<T>* __restrict__ sin,
+                                                 cplx<T>* __restrict__ sout,
+                                                 const T* __restrict__ vloc,
+                                                 const cplx<T>* __restrict__ ur,
+                                                 const double* __restrict__ bandw,
+                                                 cplx<T>* __restrict__ dpart, int nb, int gsize,
+                                                 const RegPlaneArgs& a, const LzDevState* st,
+                                                 const VBlock& vb) {
   if (st && st->status) return;
   constexpr int M = N / 2, NT = rp_threads<T, N>();
   const int pstride = (a.nact + 1) * (N + 1);
@@ -549,7 +660,7 @@ __global__ __launch_bounds__((rp_threads<T, N>())) __attribute__((amdgpu_waves_p
   cplx<T>* pl = reinterpret_cast<cplx<T>*>(smem_raw);
   const int tid = threadIdx.x, c = tid >> 1, h = tid & 1;
   const bool col = 2 * N >= NT || c < N;  // every thread on 96^2 planes and in 96-thread blocks
-  const int z = blockIdx.x, g = blockIdx.y;
+  const int z = vb.x, g = vb.y;
   const int b0 = g * gsize, b1 = min(nb, b0 + gsize);
   const int64_t roff = (int64_t)h * M * N + (col ? c : 0);  // element (row h M, column c)
   const T* vz = vloc + (int64_t)z * N * N + roff;
@@ -599,19 +710,35 @@ __global__ __launch_bounds__((rp_threads<T, N>())) __attribute__((amdgpu_waves_p
   }
 }
 
+template <typename T, int N, bool BAT = false>
+__global__ __launch_bounds__((rp_threads<T, N>())) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 2 : 3))) void k_rp_density(
+    RpDensityArgs<T> p, BatchRef br) {
+  LZ_BATCHED(BAT, p, br,
+             (rp_density_block<T, N>(a_.sin, a_.sout, a_.vloc, a_.ur, a_.bandw, a_.dpart, a_.nb,
+                                     a_.gsize, a_.a, a_.st, vb)));
+}
+
 // v'(r) u_b(r) -> FFT2 -> added to the sticks of the same band, 72^2 / 96^2
+template <typename T>
+struct RpVuArgs {
+  const cplx<T>* ur;
+  const cplx<T>* vp;
+  cplx<T>* sout;
+  RegPlaneArgs a;
+  const LzDevState* st;
+};
+
 template <typename T, int N>
-__global__ __launch_bounds__((rp_threads<T, N>())) void k_rp_vu(const cplx<T>* __restrict__ ur,
-                                                            const cplx<T>* __restrict__ vp,
-                                                            cplx<T>* __restrict__ sout,
-                                                            RegPlaneArgs a,
-                                                            const LzDevState* st) {
+__device__ __forceinline__ void rp_vu_block(const cplx<T>* __restrict__ ur,
+                                            const cplx<T>* __restrict__ vp,
+                                            cplx<T>* __restrict__ sout, const RegPlaneArgs& a,
+                                            const LzDevState* st, const VBlock& vb) {
   if (st && st->status) return;
   constexpr int M = N / 2;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cplx<T>* pl = reinterpret_cast<cplx<T>*>(smem_raw);
   const int tid = threadIdx.x, c = tid >> 1, h = tid & 1;
-  const int pidx = blockIdx.x, z = pidx % N;
+  const int pidx = vb.x, z = pidx % N;
   if (c < N) {
     const int64_t roff = (int64_t)h * M * N + c;
     const cplx<T>* ub = ur + (int64_t)pidx * N * N + roff;
@@ -626,6 +753,11 @@ __global__ __launch_bounds__((rp_threads<T, N>())) void k_rp_vu(const cplx<T>* _
   pair_rows<T, N, -1>(pl, a.nact, tid);
   __syncthreads();
   pair_gather<T, rp_threads<T, N>(), true>(sout + (int64_t)pidx * a.S, pl, a.soffc, a.S, tid);
+}
+
+template <typename T, int N, bool BAT = false>
+__global__ __launch_bounds__((rp_threads<T, N>())) void k_rp_vu(RpVuArgs<T> p, BatchRef br) {
+  LZ_BATCHED(BAT, p, br, (rp_vu_block<T, N>(a_.ur, a_.vp, a_.sout, a_.a, a_.st, vb)));
 }
 
 }  // namespace lz

@@ -110,7 +110,9 @@ def test_ground_state_arguments_checked_before_device_work():
 
 @pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
 @pytest.mark.parametrize("field,value,word", [("density_group_bands", -1, "density_group_bands"),
-                                              ("projector_chunk", 96, "projector_chunk")])
+                                              ("projector_chunk", 96, "projector_chunk"),
+                                              ("fft_planes", 3, "fft_planes"),
+                                              ("batched", 2, "batched")])
 def test_fixed_launch_parameters_checked_before_device_work(field, value, word):
     import paper_2111_06623_amd as lz
     from synth import config_system

@@ -31,9 +31,10 @@ def test_autotuned_apply_matches_oracle(name, prec, tol, kw):
     lz = _lz()
     s = config_system(name, **kw)
     ctx = lz.lz_init(s, prec=prec, max_steps=4, autotune=True)
-    gemm, bands, chunks = ctx.tuning()
-    print(f"[autotune] {name} {prec}: {gemm} groups of {bands} bands, {chunks} chunks", flush=True)
-    assert gemm in ("valu", "mfma") and bands >= 1 and chunks >= 1
+    gemm, bands, chunks, planes = ctx.tuning()
+    print(f"[autotune] {name} {prec}: {gemm} groups of {bands} bands, {chunks} chunks, "
+          f"{planes} planes", flush=True)
+    assert gemm in ("valu", "mfma") and bands >= 1 and chunks >= 1 and planes in ("registers", "lds")
     dt = torch.complex128 if prec == "fp64" else torch.complex64
     p = torch.from_numpy(random_batch(s, 5)).to("cuda", dt)
     q = torch.from_numpy(random_batch(s, 6)).to("cuda", dt)

@@ -254,19 +254,25 @@ def _apply_case(lz, s, p, q, d_ref, dk_ref, prec, tol, **opts):
 # every launch configuration the autotuner can pick, forced: density band
 # groups of the heuristic size and twice it (4 takes the quad kernel on 48^2
 # single-precision planes, 8 the line kernel), ragged groups (3, 5), and the
-# three plane-wave chunks of the vector-ALU projector dot
-@pytest.mark.parametrize("prec,tol,gsize,chunk,gemm", [
-    ("fp32", 2e-5, 4, 64, "valu"), ("fp32", 2e-5, 8, 64, "valu"), ("fp32", 2e-5, 3, 128, "valu"),
-    ("fp32", 2e-5, 1, 256, "valu"), ("fp32", 2e-5, 16, 64, "mfma"), ("fp32", 2e-5, 5, 64, "mfma"),
-    ("fp64", 1e-12, 6, 64, "valu"), ("fp64", 1e-12, 12, 128, "valu"), ("fp64", 1e-12, 5, 256, "valu"),
-    ("fp64", 1e-12, 6, 64, "mfma")])
-def test_every_launch_candidate_on_the_benchmark_cell(cfg2_apply_ref, prec, tol, gsize, chunk, gemm):
+# three plane-wave chunks of the vector-ALU projector dot, and both schedules
+# of the plane transforms (register lines / lane pairs, LDS Stockham passes)
+@pytest.mark.parametrize("prec,tol,gsize,chunk,gemm,planes", [
+    ("fp32", 2e-5, 4, 64, "valu", "registers"), ("fp32", 2e-5, 8, 64, "valu", "registers"),
+    ("fp32", 2e-5, 3, 128, "valu", "registers"), ("fp32", 2e-5, 1, 256, "valu", "registers"),
+    ("fp32", 2e-5, 16, 64, "mfma", "registers"), ("fp32", 2e-5, 5, 64, "mfma", "registers"),
+    ("fp32", 2e-5, 6, 64, "valu", "lds"), ("fp32", 2e-5, 4, 64, "valu", "lds"),
+    ("fp64", 1e-12, 6, 64, "valu", "registers"), ("fp64", 1e-12, 12, 128, "valu", "registers"),
+    ("fp64", 1e-12, 5, 256, "valu", "registers"), ("fp64", 1e-12, 6, 64, "mfma", "registers"),
+    ("fp64", 1e-12, 6, 64, "valu", "lds")])
+def test_every_launch_candidate_on_the_benchmark_cell(cfg2_apply_ref, prec, tol, gsize, chunk, gemm,
+                                                      planes):
     lz = _lz()
     s, p, q, d_ref, dk_ref = cfg2_apply_ref
-    print(f"[candidate] cfg2 {prec} groups of {gsize}, chunk {chunk}, {gemm}", flush=True)
+    print(f"[candidate] cfg2 {prec} groups of {gsize}, chunk {chunk}, {gemm}, {planes} planes",
+          flush=True)
     got = _apply_case(lz, s, p, q, d_ref, dk_ref, prec, tol, density_group_bands=gsize,
-                      projector_chunk=chunk, projector_gemm=gemm)
-    assert got[0] == gemm and got[1] == gsize
+                      projector_chunk=chunk, projector_gemm=gemm, fft_planes=planes)
+    assert got[0] == gemm and got[1] == gsize and got[3] == planes
     if gemm == "valu":
         assert got[2] == -(-int(s.npwx) // chunk)
 
