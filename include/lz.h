@@ -341,19 +341,27 @@ lz_status lz_checkpoint_load(lz_ctx *ctx, int32_t inst, const void *buf, uint64_
  * Sec. 3.1): the lowest sys->nbnd eigenpairs of the Kohn-Sham Hamiltonian
  * H_{k+q} = -1/2 nabla^2 + V_loc + sum_p |beta_p> D_p <beta_p| on every k+q
  * sphere of sys (for the orbitals at k, pass a system with q = 0 and the k
- * spheres as k+q spheres).  LOBPCG with a block of nbnd + n_extra vectors,
- * the Teter-Payne-Allan kinetic preconditioner and Rayleigh-Ritz in the span
- * of the block, its orthonormalised preconditioned residuals and the
- * previous search directions, in double precision on
- * device `device`, ordered after `hip_stream`; it stops when every wanted
- * residual norm ||H u - eps u|| is below tol, or after max_iter iterations.
+ * spheres as k+q spheres), on a block of m = nbnd + n_extra vectors in
+ * double precision on device `device`, ordered after `hip_stream`:
+ *   3 m <= 256: LOBPCG (Knyazev 2001) with the Teter-Payne-Allan kinetic
+ *     preconditioner and Rayleigh-Ritz in the span of the block, its
+ *     orthonormalised preconditioned residuals and the previous search
+ *     directions;
+ *   256 < 3 m <= 512: Chebyshev-filtered subspace iteration (Zhou and Saad
+ *     2007): per iteration a Chebyshev polynomial of H (degree up to 40,
+ *     bounded so that the filter keeps the highest wanted direction within
+ *     1e8 of the lowest) small on [largest Ritz value, an upper bound of the
+ *     spectrum from the kinetic energies, max V_loc and a Gershgorin bound of
+ *     the projectors], orthonormalisation and Rayleigh-Ritz of order m.
+ * It stops when every wanted residual norm ||H u - eps u|| is below tol, or
+ * after max_iter iterations.
  * The orbital and energy fields of sys (evc_k, evc_kq, et_k, fxc_r) are not
  * read.  Outputs (host): evc_out [nks][nbnd][npwx] complex (caller order of
  * nl_kq, orthonormal, phases arbitrary), et_out [nks][nbnd] ascending,
  * *iterations and *max_residual (either may be NULL).  Synchronous.  Errors:
- * LZ_ERR_ARG for 3 (nbnd + n_extra) > 512 (the order of the dense
- * Rayleigh-Ritz problem), a sphere smaller than nbnd + n_extra, or the
- * lz_init rules on the remaining fields.
+ * LZ_ERR_ARG for 3 (nbnd + n_extra) > 512 (the dense problems run in one
+ * 1024-thread block per sphere), a sphere smaller than 3 (nbnd + n_extra),
+ * or the lz_init rules on the remaining fields.
  */
 lz_status lz_ground_state(const lz_system *sys, int32_t n_extra, double tol, int32_t max_iter,
                           int32_t device, void *hip_stream, double *evc_out, double *et_out,
