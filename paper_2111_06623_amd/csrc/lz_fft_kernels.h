@@ -29,6 +29,14 @@ namespace lz {
 template <typename T>
 __device__ __forceinline__ cplx<T> czero() { return mk<T>(T(0), T(0)); }
 
+// LDS row pitch of a compile-time plane: 48^2 planes take N + 3 (51 complex
+// values, 204 dwords = 12 mod 32 and mod 64), so that the lanes of the radix-16
+// row pass (three butterflies per row) and the column passes fall in distinct
+// banks; N + 1 elsewhere
+template <int N> __host__ __device__ constexpr int ct_plane_pitch() {
+  return N == 48 ? N + 3 : N + 1;
+}
+
 // threads of a plane block: 512 on 96^2 planes (one block per compute unit
 // fits the LDS; twice the waves hide more latency and halve the registers a
 // thread holds), else 256
@@ -53,7 +61,7 @@ struct PlaneShm {
                                       int tid) {
     plane = reinterpret_cast<cplx<T>*>(raw);
     if constexpr (N > 0) {
-      constexpr int P = N + 1;
+      constexpr int P = ct_plane_pitch<N>();
       cplx<T>* t = plane + N * P;
       int* r = reinterpret_cast<int*>(t + ct_twsize(N));
       const cplx<T>* tg = reinterpret_cast<const cplx<T>*>(twg);
@@ -70,7 +78,8 @@ struct PlaneShm {
 
 template <typename T, int N>
 __host__ __device__ constexpr size_t plane_shm_bytes_ct() {
-  return (size_t)(N * (N + 1) + ct_twsize(N)) * sizeof(cplx<T>) + (size_t)N * sizeof(int);
+  return (size_t)(N * ct_plane_pitch<N>() + ct_twsize(N)) * sizeof(cplx<T>) +
+         (size_t)N * sizeof(int);
 }
 
 // 1-D transforms of a plane: rows listed in act (along i2) or all columns
@@ -79,9 +88,9 @@ template <typename T, int N, int MP, int DIR>
 __device__ __forceinline__ void plane_rows(const PlaneShm<T, N>& sh, const PlaneArgs& a, int nrows,
                                            bool listed, const cplx<T>* tw2, int tid) {
   if constexpr (N > 0) {
-    constexpr int NT = plane_threads<N>();
-    if (listed) ct_fft<T, N, DIR, N, LayRows<N + 1>, NT>(sh.plane, LayRows<N + 1>{sh.act}, nrows, sh.tw, tid);
-    else ct_fft<T, N, DIR, N, LayRowsAll<N + 1>, NT>(sh.plane, LayRowsAll<N + 1>{}, nrows, sh.tw, tid);
+    constexpr int NT = plane_threads<N>(), P = ct_plane_pitch<N>();
+    if (listed) ct_fft<T, N, DIR, N, LayRows<P>, NT>(sh.plane, LayRows<P>{sh.act}, nrows, sh.tw, tid);
+    else ct_fft<T, N, DIR, N, LayRowsAll<P>, NT>(sh.plane, LayRowsAll<P>{}, nrows, sh.tw, tid);
   } else {
     fft_lds<T, MP, DIR>(sh.plane, Lay{1, a.pitch, listed ? sh.act : nullptr}, a.p2, nrows, tw2, tid, 256);
   }
@@ -91,7 +100,8 @@ template <typename T, int N, int MP, int DIR>
 __device__ __forceinline__ void plane_cols(const PlaneShm<T, N>& sh, const PlaneArgs& a,
                                            const cplx<T>* tw1, int tid) {
   if constexpr (N > 0) {
-    ct_fft<T, N, DIR, N, LayCols<N + 1>, plane_threads<N>()>(sh.plane, LayCols<N + 1>{}, N, sh.tw, tid);
+    constexpr int P = ct_plane_pitch<N>();
+    ct_fft<T, N, DIR, N, LayCols<P>, plane_threads<N>()>(sh.plane, LayCols<P>{}, N, sh.tw, tid);
   } else {
     fft_lds<T, MP, DIR>(sh.plane, Lay{a.pitch, 1, nullptr}, a.p1, a.n2, tw1, tid, 256);
   }
@@ -101,7 +111,7 @@ template <typename T, int N>
 __device__ __forceinline__ void plane_zero_scatter(const PlaneShm<T, N>& sh, const PlaneArgs& a,
                                                    const cplx<T>* __restrict__ src, int tid) {
   const int n1 = N > 0 ? N : a.n1;
-  const int pitch = N > 0 ? N + 1 : a.pitch;
+  const int pitch = N > 0 ? ct_plane_pitch<N>() : a.pitch;
   constexpr int NT = N > 0 ? plane_threads<N>() : 256;
   for (int t = tid; t < n1 * pitch; t += NT) sh.plane[t] = czero<T>();
   __syncthreads();
@@ -381,7 +391,7 @@ __device__ __forceinline__ void plane_local_block(const cplx<T>* __restrict__ si
   constexpr int NTB = N > 0 ? plane_threads<N>() : 256;
   PlaneShm<T, N> sh(smem_raw, a, tw1, tid);
   const int n1 = N > 0 ? N : a.n1, n2 = N > 0 ? N : a.n2, n3 = N > 0 ? N : a.n3;
-  const int pitch = N > 0 ? N + 1 : a.pitch;
+  const int pitch = N > 0 ? ct_plane_pitch<N>() : a.pitch;
   const int z = vb.x, b = vb.y;
   const int64_t so = ((int64_t)b * n3 + z) * a.S;
   plane_zero_scatter<T, N>(sh, a, sin + so, tid);
@@ -445,7 +455,7 @@ __device__ __forceinline__ void plane_local_density_block(const cplx<T>* __restr
   constexpr int NTB = N > 0 ? plane_threads<N>() : 256;
   PlaneShm<T, N> sh(smem_raw, a, tw1, tid);
   const int n1 = N > 0 ? N : a.n1, n2 = N > 0 ? N : a.n2, n3 = N > 0 ? N : a.n3;
-  const int pitch = N > 0 ? N + 1 : a.pitch;
+  const int pitch = N > 0 ? ct_plane_pitch<N>() : a.pitch;
   // large planes (72^2 and 96^2 in double precision, 96^2 in single) keep the
   // running sums in dpart itself (the block's own slice, read and written by
   // the same thread in band order: the same sums, bitwise, as register
@@ -533,7 +543,7 @@ __device__ __forceinline__ void plane_to_real_block(const cplx<T>* __restrict__ 
   constexpr int NTB = N > 0 ? plane_threads<N>() : 256;
   PlaneShm<T, N> sh(smem_raw, a, tw1, tid);
   const int n1 = N > 0 ? N : a.n1, n2 = N > 0 ? N : a.n2, n3 = N > 0 ? N : a.n3;
-  const int pitch = N > 0 ? N + 1 : a.pitch;
+  const int pitch = N > 0 ? ct_plane_pitch<N>() : a.pitch;
   const int z = vb.x, b = vb.y;
   const int np = n1 * n2;
   plane_zero_scatter<T, N>(sh, a, sin + ((int64_t)b * n3 + z) * a.S, tid);
@@ -578,7 +588,7 @@ __device__ __forceinline__ void plane_vu_block(const cplx<T>* __restrict__ ur,
   constexpr int NTB = N > 0 ? plane_threads<N>() : 256;
   PlaneShm<T, N> sh(smem_raw, a, tw1, tid);
   const int n1 = N > 0 ? N : a.n1, n2 = N > 0 ? N : a.n2, n3 = N > 0 ? N : a.n3;
-  const int pitch = N > 0 ? N + 1 : a.pitch;
+  const int pitch = N > 0 ? ct_plane_pitch<N>() : a.pitch;
   const int z = vb.x, b = vb.y;
   const int np = n1 * n2;
   const cplx<T>* ub = ur + ((int64_t)b * n3 + z) * np;
@@ -632,7 +642,7 @@ __device__ __forceinline__ void hxc_planes_fwd_block(const cplx<T>* __restrict__
   constexpr int NTB = N > 0 ? plane_threads<N>() : 256;
   PlaneShm<T, N> sh(smem_raw, a, tw1, tid);
   const int n1 = N > 0 ? N : a.n1, n2 = N > 0 ? N : a.n2, n3 = N > 0 ? N : a.n3;
-  const int pitch = N > 0 ? N + 1 : a.pitch;
+  const int pitch = N > 0 ? ct_plane_pitch<N>() : a.pitch;
   const int z = vb.x;
   const int np = n1 * n2;
   const int64_t plane = (int64_t)n3 * np;
@@ -740,7 +750,7 @@ __device__ __forceinline__ void hxc_planes_inv_block(const cplx<T>* __restrict__
   constexpr int NTB = N > 0 ? plane_threads<N>() : 256;
   PlaneShm<T, N> sh(smem_raw, a, tw1, tid);
   const int n1 = N > 0 ? N : a.n1, n2 = N > 0 ? N : a.n2;
-  const int pitch = N > 0 ? N + 1 : a.pitch;
+  const int pitch = N > 0 ? ct_plane_pitch<N>() : a.pitch;
   const int z = vb.x;
   const int np = n1 * n2;
   for (int p = tid; p < np; p += NTB) {
@@ -1212,15 +1222,18 @@ void LaunchFft<T>::plane_vu(const Grid3& g, const void* ur, const void* vp, void
         if (n == 64)
           lz_launch((k_rp_vu<T, 64>), (k_rp_vu<T, 64, true>), dim3(nplanes), dim3(kRegPlaneThreads),
                     lds, s,
-                             (const cplx<T>*)ur, (const cplx<T>*)vp, (cplx<T>*)sout, reg_args(g), st);
+                             (const cplx<T>*)ur, (const cplx<T>*)vp, (cplx<T>*)sout, reg_args(g),
+                              st);
         else if (n == 72)
           lz_launch((k_rp_vu<T, 72>), (k_rp_vu<T, 72, true>), dim3(nplanes), dim3(kRegPlaneThreads),
                     lds, s,
-                             (const cplx<T>*)ur, (const cplx<T>*)vp, (cplx<T>*)sout, reg_args(g), st);
+                             (const cplx<T>*)ur, (const cplx<T>*)vp, (cplx<T>*)sout, reg_args(g),
+                              st);
         else
           lz_launch((k_rp_vu<T, 96>), (k_rp_vu<T, 96, true>), dim3(nplanes), dim3(kRegPlaneThreads),
                     lds, s,
-                             (const cplx<T>*)ur, (const cplx<T>*)vp, (cplx<T>*)sout, reg_args(g), st);
+                             (const cplx<T>*)ur, (const cplx<T>*)vp, (cplx<T>*)sout, reg_args(g),
+                              st);
         return;
       }
     }
