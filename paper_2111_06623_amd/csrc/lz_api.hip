@@ -653,6 +653,30 @@ int heuristic_group(const Instance& I, int rn) {
   return (I.nb + ng - 1) / ng;
 }
 
+// Band-group size of a density pass whose blocks (one per z-plane and group)
+// each take time in proportion to their bands, run in rounds of `slots`
+// blocks: the fewest rounds x bands per block, plus a small cost per group
+// for the partial the Hartree pass reads back (0.05 of a band's work; ties
+// go to the larger group).  On the 48^3 cell in FP64 (128 band-k products,
+// 3 blocks per compute unit) it picks 8: 768 blocks, one round.  Measured
+// there: the density pass takes the same time for groups of 4 to 13 (it is
+// not bound by the rounds), the Hartree pass reads fewer partials from
+// larger groups (36 us at 8, 41 us at 4), and 16 (two rounds) is 1.5x slower.
+int round_group(const Instance& I, int slots) {
+  int best = 1;
+  double best_t = 1e300;
+  for (int g = 1; g <= std::min(I.nb, 16); ++g) {
+    const int ng = (I.nb + g - 1) / g;
+    const int64_t blocks = (int64_t)I.n3 * ng;
+    const double t = (double)((blocks + slots - 1) / slots) * g + 0.05 * ng;
+    if (t <= best_t + 1e-9) {
+      best_t = t;
+      best = g;
+    }
+  }
+  return best;
+}
+
 std::vector<LaunchCfg> launch_candidates(Instance& I, const lz_options& opt) {
   const bool mc = opt.projector_gemm == LZ_GEMM_MFMA ||
                   (opt.projector_gemm == LZ_GEMM_AUTO && I.nbnd >= 32 && I.ptot >= 64);
@@ -663,7 +687,23 @@ std::vector<LaunchCfg> launch_candidates(Instance& I, const lz_options& opt) {
   const bool reg_avail = rn_reg != 0 || (I.fp64 && I.n1 == 48 && I.n2 == 48 && I.n3 == 48 &&
                                          I.grid.soff_c != nullptr);
   const int lds0 = opt.fft_planes == 2 ? 1 : 0;
-  const int g_reg = heuristic_group(I, rn_reg), g_lds = heuristic_group(I, 0);
+  int g_reg = heuristic_group(I, rn_reg), g_lds = heuristic_group(I, 0);
+  {
+    // the LDS density pass: groups that fill whole rounds of the blocks the
+    // device holds at once
+    const int saved = I.grid.lds_planes;
+    I.grid.lds_planes = 1;
+    const int bpc = I.fp64 ? LaunchFft<double>::density_blocks_per_cu(I.grid)
+                           : LaunchFft<float>::density_blocks_per_cu(I.grid);
+    I.grid.lds_planes = saved;
+    int dev = 0, ncu = 0;
+    if (bpc > 0 && hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+        ncu > 0)
+      g_lds = round_group(I, bpc * ncu);
+  }
+  // where no register-line kernel exists, the density pass is the LDS one in both forms
+  if (rn_reg == 0) g_reg = g_lds;
   int g0 = lds0 ? g_lds : g_reg;
   // a group size or a dot chunk the caller fixes replaces the heuristic and is not tuned
   if (opt.density_group_bands > 0) g0 = opt.density_group_bands;

@@ -451,9 +451,9 @@ __device__ __forceinline__ void plane_local_density_block(const cplx<T>* __restr
                                                           const LzDevState* st, const VBlock& vb) {
   if (st && st->status) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  const int tid = threadIdx.x;
+  const int tid0 = threadIdx.x;
   constexpr int NTB = N > 0 ? plane_threads<N>() : 256;
-  PlaneShm<T, N> sh(smem_raw, a, tw1, tid);
+  PlaneShm<T, N> sh(smem_raw, a, tw1, tid0);
   const int n1 = N > 0 ? N : a.n1, n2 = N > 0 ? N : a.n2, n3 = N > 0 ? N : a.n3;
   const int pitch = N > 0 ? ct_plane_pitch<N>() : a.pitch;
   // large planes (72^2 and 96^2 in double precision, 96^2 in single) keep the
@@ -473,6 +473,13 @@ __device__ __forceinline__ void plane_local_density_block(const cplx<T>* __restr
   for (int i = 0; i < ACC; ++i) acc[i] = czero<T>();
   const int b0 = g * gsize, b1 = min(nb, b0 + gsize);
   for (int b = b0; b < b1; ++b) {
+    // the thread index passes through an empty asm statement on every band,
+    // so that the compiler forms the transforms' LDS addresses per band
+    // instead of holding all of them in registers through the loop (FP64
+    // 48^2 planes: 138 registers instead of 232, three waves per SIMD
+    // instead of two)
+    int tid = tid0;
+    asm volatile("" : "+v"(tid));
     const int64_t so = ((int64_t)b * n3 + z) * a.S;
     plane_zero_scatter<T, N>(sh, a, sin + so, tid);
     plane_rows<T, N, MP, +1>(sh, a, a.nact, true, tw2, tid);
@@ -507,7 +514,7 @@ __device__ __forceinline__ void plane_local_density_block(const cplx<T>* __restr
   if constexpr (!GACC) {
 #pragma unroll
     for (int i = 0; i < ACC; ++i) {
-      const int p = tid + i * NTB;
+      const int p = tid0 + i * NTB;
       if (p < np) dp[p] = acc[i];
     }
   }
@@ -1190,6 +1197,28 @@ void LaunchFft<T>::plane_local_density(const Grid3& g, const void* sin, void* so
                   (const cplx<T>*)sin, (cplx<T>*)sout, (const T*)vloc, (const cplx<T>*)ur, bandw,
                   (cplx<T>*)dpart, nb, gsize, plane_args(g), (const cplx<T>*)g.tw1,
                   (const cplx<T>*)g.tw2, st);
+}
+
+template <typename T>
+int LaunchFft<T>::density_blocks_per_cu(const Grid3& g) {
+  if (reg_plane_size<T>(g) != 0) return 0;
+  const void* f = nullptr;
+  int threads = 256;
+  switch (ct_size(g)) {
+#define LZ_CASE(N)                                              \
+  case N:                                                       \
+    f = reinterpret_cast<const void*>(k_plane_local_density<T, N, 0>); \
+    threads = plane_threads<N>();                               \
+    break;
+    LZ_CT_SIZES(LZ_CASE)
+#undef LZ_CASE
+    default: return 0;
+  }
+  int nbpc = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nbpc, f, threads, plane_lds<T>(g)) !=
+      hipSuccess)
+    return 0;
+  return nbpc;
 }
 
 template <typename T>

@@ -63,6 +63,9 @@ template <typename T> struct LaunchFft {
   static void hxc(const Grid3& g, const void* dpart, int ngroups, void* nr, void* work,
                   const void* khart, const void* fxc, bool with_fxc, void* vp,
                   const LzDevState* st, hipStream_t s);
+  // blocks of the LDS density pass that one compute unit holds at once
+  // (occupancy calculator), 0 where the density pass takes another form
+  static int density_blocks_per_cu(const Grid3& g);
 };
 
 template <typename T> struct LaunchLin {

@@ -10,6 +10,7 @@ k+q.  The adiabatic LDA kernel is evaluated at the resulting density.
 from __future__ import annotations
 
 import dataclasses
+import logging
 import math
 import multiprocessing as mp
 import os
@@ -20,6 +21,7 @@ import scipy.fft as sfft
 import scipy.linalg as sla
 
 _WORKERS = -1
+_log = logging.getLogger(__name__)
 
 
 # --------------------------------------------------------------------------
@@ -234,18 +236,26 @@ class _Ham:
 
 
 def _lowest_eigenpairs(ham: _Ham, nev: int, x0: Optional[np.ndarray] = None,
-                       tol: float = 1e-10, maxit: int = 200):
-    """Lowest nev eigenpairs of a Hermitian plane-wave Hamiltonian."""
+                       tol: float = 1e-10, maxit: int = 2000):
+    """Lowest nev eigenpairs of a Hermitian plane-wave Hamiltonian; raises if
+    the block Davidson iteration leaves a wanted residual norm above 10 tol
+    (an unconverged valence set would make every reference built on it
+    differ from a converged one)."""
     npw = len(ham.kin)
     if npw <= 2600 or x0 is None:
         h = ham.dense()
         w, v = sla.eigh(h, subset_by_index=[0, nev - 1], driver="evr")
         return w, v
-    # block Davidson with a kinetic preconditioner, started from x0
+    # block Davidson with a kinetic preconditioner, started from x0; large
+    # blocks (the 128 bands of the 96^3 cell, whose top bands lie within
+    # 0.3 mHa of each other) restart thick: the Ritz block and the last
+    # corrections
     nb = x0.shape[1]
+    thick = nev > 64
     x, _ = np.linalg.qr(x0)
     hx = ham.apply(x)
     basis, hbasis = x, hx
+    last_t = None
     for _it in range(maxit):
         hs = basis.conj().T @ hbasis
         hs = 0.5 * (hs + hs.conj().T)
@@ -255,13 +265,19 @@ def _lowest_eigenpairs(ham: _Ham, nev: int, x0: Optional[np.ndarray] = None,
         hx = hbasis @ c
         res = hx - x * w[None, :]
         rn = np.linalg.norm(res, axis=0)
+        if _it % 20 == 0:
+            _log.debug("davidson it %d basis %d residual %.2e", _it, basis.shape[1], np.max(rn[:nev]))
         if np.max(rn[:nev]) < tol:
             break
         act = rn > tol * 0.1
         t = res[:, act] / (ham.kin[:, None] - w[None, act] + 1.0)
         # orthogonalise the corrections against the current Ritz block
         if basis.shape[1] + t.shape[1] > 4 * nb:
-            basis, hbasis = x, hx
+            if thick and last_t is not None:
+                q, _ = np.linalg.qr(np.concatenate([x, last_t], axis=1))
+                basis, hbasis = q, ham.apply(q)
+            else:
+                basis, hbasis = x, hx
         t -= basis @ (basis.conj().T @ t)
         t -= basis @ (basis.conj().T @ t)
         t, r = np.linalg.qr(t)
@@ -269,14 +285,21 @@ def _lowest_eigenpairs(ham: _Ham, nev: int, x0: Optional[np.ndarray] = None,
         t = t[:, keep]
         if t.shape[1] == 0:
             break
+        ht = ham.apply(t)
+        if thick:
+            last_t = t
         basis = np.concatenate([basis, t], axis=1)
-        hbasis = np.concatenate([hbasis, ham.apply(t)], axis=1)
+        hbasis = np.concatenate([hbasis, ht], axis=1)
     # final Rayleigh-Ritz on an exactly orthonormal block
     q, _ = np.linalg.qr(x)
     hq = ham.apply(q)
     hs = q.conj().T @ hq
     w, c = np.linalg.eigh(0.5 * (hs + hs.conj().T))
-    return w[:nev], (q @ c)[:, :nev]
+    v = (q @ c)[:, :nev]
+    rn = np.linalg.norm(ham.apply(v) - v * w[None, :nev], axis=0)
+    if np.max(rn) > 10 * tol:
+        raise RuntimeError(f"block Davidson: residual {np.max(rn):.1e} after {maxit} iterations")
+    return w[:nev], v
 
 
 def _solve_sphere(args):
@@ -307,9 +330,10 @@ def _solve_sphere(args):
                 break
         vlo = kb_projectors(at, mlo, kv, tau, radii) if kb_on else None
         hlo = _Ham(at, nr, vloc, mlo, kv, vlo, dkb)
-        _, vl = sla.eigh(hlo.dense(), subset_by_index=[0, nev + 7], driver="evr")
+        nbuf = 24 if nev > 64 else 8   # buffer vectors of the block
+        _, vl = sla.eigh(hlo.dense(), subset_by_index=[0, nev + nbuf - 1], driver="evr")
         pos = {int(i): j for j, i in enumerate(linear_index(mill, nr))}
-        x0 = np.zeros((len(mill), nev + 8), dtype=np.complex128)
+        x0 = np.zeros((len(mill), nev + nbuf), dtype=np.complex128)
         rows = np.array([pos[int(i)] for i in linear_index(mlo, nr)])
         x0[rows] = vl
     w, v = _lowest_eigenpairs(ham, nev, x0, tol=tol)
