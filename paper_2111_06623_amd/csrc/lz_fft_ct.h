@@ -166,13 +166,19 @@ template <int PITCH> struct LayCols {      // every column, stride PITCH
 };
 
 // One pass of a compile-time plan over nbatch <= NBMAX transforms, in place,
-// NT threads: loads into registers, barrier, stores, barrier.
+// NT threads: loads into registers, barrier, stores, barrier.  In the last
+// pass (NS R = N, so M = NS and k = j) a butterfly stores to exactly the
+// elements j + s M it loaded from, which no other butterfly touches: its
+// stores cannot overwrite what another thread has still to load, and the
+// barrier between loads and stores is left out.
 template <typename T, int N, int P, int DIR, int NBMAX, typename L, int NT = 256>
 __device__ __forceinline__ void ct_pass(cplx<T>* lds, const L& lay, int nbatch,
                                         const cplx<T>* tw, int tid) {
   constexpr int R = ct_radix(N, P);
   constexpr int NS = ct_ns(N, P);
   constexpr int M = N / R;
+  constexpr bool LAST = P + 1 == ct_npass(N);
+  static_assert(!LAST || NS == M, "the last pass of a plan maps each butterfly onto itself");
   constexpr int MAXB = (NBMAX * M + NT - 1) / NT;
   const cplx<T>* twp = tw + ct_twoff(N, P);
   const int total = nbatch * M;
@@ -201,7 +207,7 @@ __device__ __forceinline__ void ct_pass(cplx<T>* lds, const L& lay, int nbatch,
       Dft<T, R, DIR>::run(v[i]);
     }
   }
-  __syncthreads();
+  if constexpr (!LAST) __syncthreads();
 #pragma unroll
   for (int i = 0; i < MAXB; ++i) {
     const int t = tid + i * NT;
