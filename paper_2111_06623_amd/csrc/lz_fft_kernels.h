@@ -464,6 +464,12 @@ __device__ __forceinline__ void plane_local_density_block(const cplx<T>* __restr
   constexpr int NIT = N > 0 ? (N * N + NTB - 1) / NTB : MP;
   constexpr int ACC = GACC ? 1 : NIT;
   constexpr int UNR = GACC ? 4 : NIT;
+  // FP64 48^2 planes load the first NPRE of a thread's orbital values of a
+  // band before the band's transforms, which hide their latency: 6 of 9
+  // fill the registers of three waves per SIMD (168), all 9 would take 186
+  // and leave two
+  constexpr bool PRE = !GACC && N == 48 && sizeof(T) == 8;
+  constexpr int NPRE = PRE ? 6 : 0;
   const int z = vb.x, g = vb.y;
   const int np = n1 * n2;
   const T* vz = vloc + (int64_t)z * np;
@@ -476,15 +482,23 @@ __device__ __forceinline__ void plane_local_density_block(const cplx<T>* __restr
     // the thread index passes through an empty asm statement on every band,
     // so that the compiler forms the transforms' LDS addresses per band
     // instead of holding all of them in registers through the loop (FP64
-    // 48^2 planes: 138 registers instead of 232, three waves per SIMD
-    // instead of two)
+    // 48^2 planes: 138 registers instead of 232 before the orbital loads
+    // below, three waves per SIMD instead of two)
     int tid = tid0;
     asm volatile("" : "+v"(tid));
     const int64_t so = ((int64_t)b * n3 + z) * a.S;
+    const cplx<T>* ub = ur + ((int64_t)b * n3 + z) * np;
+    cplx<T> upre[PRE ? NPRE : 1];
+    if constexpr (PRE) {
+#pragma unroll
+      for (int i = 0; i < NPRE; ++i) {
+        const int p = tid + i * NTB;
+        upre[i] = p < np ? ub[p] : czero<T>();
+      }
+    }
     plane_zero_scatter<T, N>(sh, a, sin + so, tid);
     plane_rows<T, N, MP, +1>(sh, a, a.nact, true, tw2, tid);
     plane_cols<T, N, MP, +1>(sh, a, tw1, tid);
-    const cplx<T>* ub = ur + ((int64_t)b * n3 + z) * np;
     const T wb = T(bandw[b]);
 #pragma unroll UNR
     for (int i = 0; i < NIT; ++i) {
@@ -492,7 +506,10 @@ __device__ __forceinline__ void plane_local_density_block(const cplx<T>* __restr
       if (p < np) {
         const int i1 = p / n2, i2 = p - i1 * n2;
         cplx<T>& c = sh.plane[i1 * pitch + i2];
-        const cplx<T> d = cmulc<T>(ub[p], c);
+        cplx<T> u;
+        if (PRE && i < NPRE) u = upre[PRE ? i : 0];
+        else u = ub[p];
+        const cplx<T> d = cmulc<T>(u, c);
         if constexpr (GACC) {
           cplx<T> s = b == b0 ? czero<T>() : dp[p];
           s.x += wb * d.x;
