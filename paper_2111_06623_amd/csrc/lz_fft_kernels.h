@@ -37,10 +37,13 @@ template <int N> __host__ __device__ constexpr int ct_plane_pitch() {
   return N == 48 ? N + 3 : N + 1;
 }
 
-// threads of a plane block: 512 on 96^2 planes (one block per compute unit
-// fits the LDS; twice the waves hide more latency and halve the registers a
-// thread holds), else 256
-template <int N> __host__ __device__ constexpr int plane_threads() { return N == 96 ? 512 : 256; }
+// threads of a plane block, so that the blocks the LDS admits on a compute
+// unit hold about 16 waves: FP64 planes of 72^2 and 96^2 (one block per
+// unit) take 1024 threads, 64^2 (two) 512; FP32 96^2 planes (two) 512; the
+// rest 256.  More threads also mean fewer butterflies held per thread.
+template <typename T, int N> __host__ __device__ constexpr int plane_threads() {
+  return sizeof(T) == 8 ? (N >= 72 ? 1024 : N == 64 ? 512 : 256) : (N == 96 ? 512 : 256);
+}
 
 struct PlaneArgs {
   int n1, n2, n3, S, nact, pitch;
@@ -65,8 +68,8 @@ struct PlaneShm {
       cplx<T>* t = plane + N * P;
       int* r = reinterpret_cast<int*>(t + ct_twsize(N));
       const cplx<T>* tg = reinterpret_cast<const cplx<T>*>(twg);
-      for (int i = tid; i < ct_twsize(N); i += plane_threads<N>()) t[i] = tg[i];
-      for (int i = tid; i < a.nact; i += plane_threads<N>()) r[i] = a.act[i];
+      for (int i = tid; i < ct_twsize(N); i += plane_threads<T, N>()) t[i] = tg[i];
+      for (int i = tid; i < a.nact; i += plane_threads<T, N>()) r[i] = a.act[i];
       tw = t;
       act = r;
     } else {
@@ -88,7 +91,7 @@ template <typename T, int N, int MP, int DIR>
 __device__ __forceinline__ void plane_rows(const PlaneShm<T, N>& sh, const PlaneArgs& a, int nrows,
                                            bool listed, const cplx<T>* tw2, int tid) {
   if constexpr (N > 0) {
-    constexpr int NT = plane_threads<N>(), P = ct_plane_pitch<N>();
+    constexpr int NT = plane_threads<T, N>(), P = ct_plane_pitch<N>();
     if (listed) ct_fft<T, N, DIR, N, LayRows<P>, NT>(sh.plane, LayRows<P>{sh.act}, nrows, sh.tw, tid);
     else ct_fft<T, N, DIR, N, LayRowsAll<P>, NT>(sh.plane, LayRowsAll<P>{}, nrows, sh.tw, tid);
   } else {
@@ -101,7 +104,7 @@ __device__ __forceinline__ void plane_cols(const PlaneShm<T, N>& sh, const Plane
                                            const cplx<T>* tw1, int tid) {
   if constexpr (N > 0) {
     constexpr int P = ct_plane_pitch<N>();
-    ct_fft<T, N, DIR, N, LayCols<P>, plane_threads<N>()>(sh.plane, LayCols<P>{}, N, sh.tw, tid);
+    ct_fft<T, N, DIR, N, LayCols<P>, plane_threads<T, N>()>(sh.plane, LayCols<P>{}, N, sh.tw, tid);
   } else {
     fft_lds<T, MP, DIR>(sh.plane, Lay{a.pitch, 1, nullptr}, a.p1, a.n2, tw1, tid, 256);
   }
@@ -112,7 +115,7 @@ __device__ __forceinline__ void plane_zero_scatter(const PlaneShm<T, N>& sh, con
                                                    const cplx<T>* __restrict__ src, int tid) {
   const int n1 = N > 0 ? N : a.n1;
   const int pitch = N > 0 ? ct_plane_pitch<N>() : a.pitch;
-  constexpr int NT = N > 0 ? plane_threads<N>() : 256;
+  constexpr int NT = N > 0 ? plane_threads<T, N>() : 256;
   for (int t = tid; t < n1 * pitch; t += NT) sh.plane[t] = czero<T>();
   __syncthreads();
   for (int s = tid; s < a.S; s += NT) sh.plane[a.si1[s] * pitch + a.si2[s]] = src[s];
@@ -388,7 +391,7 @@ __device__ __forceinline__ void plane_local_block(const cplx<T>* __restrict__ si
   if (st && st->status) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int tid = threadIdx.x;
-  constexpr int NTB = N > 0 ? plane_threads<N>() : 256;
+  constexpr int NTB = N > 0 ? plane_threads<T, N>() : 256;
   PlaneShm<T, N> sh(smem_raw, a, tw1, tid);
   const int n1 = N > 0 ? N : a.n1, n2 = N > 0 ? N : a.n2, n3 = N > 0 ? N : a.n3;
   const int pitch = N > 0 ? ct_plane_pitch<N>() : a.pitch;
@@ -410,7 +413,7 @@ __device__ __forceinline__ void plane_local_block(const cplx<T>* __restrict__ si
 }
 
 template <typename T, int N, int MP, bool BAT = false>
-__global__ __launch_bounds__(plane_threads<N>()) void k_plane_local(PlaneLocalArgs<T> p,
+__global__ __launch_bounds__((plane_threads<T, N>())) void k_plane_local(PlaneLocalArgs<T> p,
                                                                     BatchRef br) {
   LZ_BATCHED(BAT, p, br,
              (plane_local_block<T, N, MP>(a_.sin, a_.sout, a_.vloc, a_.a, a_.tw1, a_.tw2, a_.st,
@@ -452,7 +455,7 @@ __device__ __forceinline__ void plane_local_density_block(const cplx<T>* __restr
   if (st && st->status) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int tid0 = threadIdx.x;
-  constexpr int NTB = N > 0 ? plane_threads<N>() : 256;
+  constexpr int NTB = N > 0 ? plane_threads<T, N>() : 256;
   PlaneShm<T, N> sh(smem_raw, a, tw1, tid0);
   const int n1 = N > 0 ? N : a.n1, n2 = N > 0 ? N : a.n2, n3 = N > 0 ? N : a.n3;
   const int pitch = N > 0 ? ct_plane_pitch<N>() : a.pitch;
@@ -538,7 +541,7 @@ __device__ __forceinline__ void plane_local_density_block(const cplx<T>* __restr
 }
 
 template <typename T, int N, int MP, bool BAT = false>
-__global__ __launch_bounds__(plane_threads<N>()) void k_plane_local_density(
+__global__ __launch_bounds__((plane_threads<T, N>())) void k_plane_local_density(
     PlaneLocalDensityArgs<T> p, BatchRef br) {
   LZ_BATCHED(BAT, p, br,
              (plane_local_density_block<T, N, MP>(a_.sin, a_.sout, a_.vloc, a_.ur, a_.bandw,
@@ -564,7 +567,7 @@ __device__ __forceinline__ void plane_to_real_block(const cplx<T>* __restrict__ 
                                                     const VBlock& vb) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int tid = threadIdx.x;
-  constexpr int NTB = N > 0 ? plane_threads<N>() : 256;
+  constexpr int NTB = N > 0 ? plane_threads<T, N>() : 256;
   PlaneShm<T, N> sh(smem_raw, a, tw1, tid);
   const int n1 = N > 0 ? N : a.n1, n2 = N > 0 ? N : a.n2, n3 = N > 0 ? N : a.n3;
   const int pitch = N > 0 ? ct_plane_pitch<N>() : a.pitch;
@@ -581,7 +584,7 @@ __device__ __forceinline__ void plane_to_real_block(const cplx<T>* __restrict__ 
 }
 
 template <typename T, int N, int MP, bool BAT = false>
-__global__ __launch_bounds__(plane_threads<N>()) void k_plane_to_real(PlaneToRealArgs<T> p,
+__global__ __launch_bounds__((plane_threads<T, N>())) void k_plane_to_real(PlaneToRealArgs<T> p,
                                                                       BatchRef br) {
   LZ_BATCHED(BAT, p, br,
              (plane_to_real_block<T, N, MP>(a_.sin, a_.rout, a_.a, a_.tw1, a_.tw2, vb)));
@@ -609,7 +612,7 @@ __device__ __forceinline__ void plane_vu_block(const cplx<T>* __restrict__ ur,
   if (st && st->status) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int tid = threadIdx.x;
-  constexpr int NTB = N > 0 ? plane_threads<N>() : 256;
+  constexpr int NTB = N > 0 ? plane_threads<T, N>() : 256;
   PlaneShm<T, N> sh(smem_raw, a, tw1, tid);
   const int n1 = N > 0 ? N : a.n1, n2 = N > 0 ? N : a.n2, n3 = N > 0 ? N : a.n3;
   const int pitch = N > 0 ? ct_plane_pitch<N>() : a.pitch;
@@ -632,7 +635,7 @@ __device__ __forceinline__ void plane_vu_block(const cplx<T>* __restrict__ ur,
 }
 
 template <typename T, int N, int MP, bool BAT = false>
-__global__ __launch_bounds__(plane_threads<N>()) void k_plane_vu(PlaneVuArgs<T> p, BatchRef br) {
+__global__ __launch_bounds__((plane_threads<T, N>())) void k_plane_vu(PlaneVuArgs<T> p, BatchRef br) {
   LZ_BATCHED(BAT, p, br,
              (plane_vu_block<T, N, MP>(a_.ur, a_.vp, a_.sout, a_.a, a_.tw1, a_.tw2, a_.st, vb)));
 }
@@ -663,7 +666,7 @@ __device__ __forceinline__ void hxc_planes_fwd_block(const cplx<T>* __restrict__
   if (st && st->status) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int tid = threadIdx.x;
-  constexpr int NTB = N > 0 ? plane_threads<N>() : 256;
+  constexpr int NTB = N > 0 ? plane_threads<T, N>() : 256;
   PlaneShm<T, N> sh(smem_raw, a, tw1, tid);
   const int n1 = N > 0 ? N : a.n1, n2 = N > 0 ? N : a.n2, n3 = N > 0 ? N : a.n3;
   const int pitch = N > 0 ? ct_plane_pitch<N>() : a.pitch;
@@ -688,7 +691,7 @@ __device__ __forceinline__ void hxc_planes_fwd_block(const cplx<T>* __restrict__
 }
 
 template <typename T, int N, int MP, bool BAT = false>
-__global__ __launch_bounds__(plane_threads<N>()) void k_hxc_planes_fwd(HxcPlanesFwdArgs<T> p,
+__global__ __launch_bounds__((plane_threads<T, N>())) void k_hxc_planes_fwd(HxcPlanesFwdArgs<T> p,
                                                                        BatchRef br) {
   LZ_BATCHED(BAT, p, br,
              (hxc_planes_fwd_block<T, N, MP>(a_.dpart, a_.ngroups, a_.nr, a_.work, a_.a, a_.tw1,
@@ -771,7 +774,7 @@ __device__ __forceinline__ void hxc_planes_inv_block(const cplx<T>* __restrict__
   if (st && st->status) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int tid = threadIdx.x;
-  constexpr int NTB = N > 0 ? plane_threads<N>() : 256;
+  constexpr int NTB = N > 0 ? plane_threads<T, N>() : 256;
   PlaneShm<T, N> sh(smem_raw, a, tw1, tid);
   const int n1 = N > 0 ? N : a.n1, n2 = N > 0 ? N : a.n2;
   const int pitch = N > 0 ? ct_plane_pitch<N>() : a.pitch;
@@ -798,7 +801,7 @@ __device__ __forceinline__ void hxc_planes_inv_block(const cplx<T>* __restrict__
 }
 
 template <typename T, int N, int MP, bool BAT = false>
-__global__ __launch_bounds__(plane_threads<N>()) void k_hxc_planes_inv(HxcPlanesInvArgs<T> p,
+__global__ __launch_bounds__((plane_threads<T, N>())) void k_hxc_planes_inv(HxcPlanesInvArgs<T> p,
                                                                        BatchRef br) {
   LZ_BATCHED(BAT, p, br,
              (hxc_planes_inv_block<T, N, MP>(a_.work, a_.nr, a_.fxc, a_.with_fxc, a_.vp, a_.a,
@@ -1072,13 +1075,13 @@ template <typename T> static size_t stick_lds(const Grid3& g) {
 #define LZ_PLANE_LAUNCH(KERN, T, G, GRID, LDS, STREAM, ...)                                     \
   do {                                                                                          \
     switch (ct_size(G)) {                                                                       \
-      case 24: lz_launch((KERN<T, 24, 0>), (KERN<T, 24, 0, true>), GRID, dim3(256), LDS, STREAM, __VA_ARGS__); break; \
-      case 32: lz_launch((KERN<T, 32, 0>), (KERN<T, 32, 0, true>), GRID, dim3(256), LDS, STREAM, __VA_ARGS__); break; \
-      case 40: lz_launch((KERN<T, 40, 0>), (KERN<T, 40, 0, true>), GRID, dim3(256), LDS, STREAM, __VA_ARGS__); break; \
-      case 48: lz_launch((KERN<T, 48, 0>), (KERN<T, 48, 0, true>), GRID, dim3(256), LDS, STREAM, __VA_ARGS__); break; \
-      case 64: lz_launch((KERN<T, 64, 0>), (KERN<T, 64, 0, true>), GRID, dim3(256), LDS, STREAM, __VA_ARGS__); break; \
-      case 72: lz_launch((KERN<T, 72, 0>), (KERN<T, 72, 0, true>), GRID, dim3(256), LDS, STREAM, __VA_ARGS__); break; \
-      case 96: lz_launch((KERN<T, 96, 0>), (KERN<T, 96, 0, true>), GRID, dim3(plane_threads<96>()), LDS, STREAM, __VA_ARGS__); break; \
+      case 24: lz_launch((KERN<T, 24, 0>), (KERN<T, 24, 0, true>), GRID, dim3(plane_threads<T, 24>()), LDS, STREAM, __VA_ARGS__); break; \
+      case 32: lz_launch((KERN<T, 32, 0>), (KERN<T, 32, 0, true>), GRID, dim3(plane_threads<T, 32>()), LDS, STREAM, __VA_ARGS__); break; \
+      case 40: lz_launch((KERN<T, 40, 0>), (KERN<T, 40, 0, true>), GRID, dim3(plane_threads<T, 40>()), LDS, STREAM, __VA_ARGS__); break; \
+      case 48: lz_launch((KERN<T, 48, 0>), (KERN<T, 48, 0, true>), GRID, dim3(plane_threads<T, 48>()), LDS, STREAM, __VA_ARGS__); break; \
+      case 64: lz_launch((KERN<T, 64, 0>), (KERN<T, 64, 0, true>), GRID, dim3(plane_threads<T, 64>()), LDS, STREAM, __VA_ARGS__); break; \
+      case 72: lz_launch((KERN<T, 72, 0>), (KERN<T, 72, 0, true>), GRID, dim3(plane_threads<T, 72>()), LDS, STREAM, __VA_ARGS__); break; \
+      case 96: lz_launch((KERN<T, 96, 0>), (KERN<T, 96, 0, true>), GRID, dim3(plane_threads<T, 96>()), LDS, STREAM, __VA_ARGS__); break; \
       default:                                                                                  \
         switch (plane_mp((G).n1, (G).n2)) {                                                     \
           case 12: lz_launch((KERN<T, 0, 12>), (KERN<T, 0, 12, true>), GRID, dim3(256), LDS, STREAM, __VA_ARGS__); break; \
@@ -1225,7 +1228,7 @@ int LaunchFft<T>::density_blocks_per_cu(const Grid3& g) {
 #define LZ_CASE(N)                                              \
   case N:                                                       \
     f = reinterpret_cast<const void*>(k_plane_local_density<T, N, 0>); \
-    threads = plane_threads<N>();                               \
+    threads = plane_threads<T, N>();                               \
     break;
     LZ_CT_SIZES(LZ_CASE)
 #undef LZ_CASE
