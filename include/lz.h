@@ -298,6 +298,31 @@ lz_status lz_get_tuning(lz_ctx *ctx, int32_t inst, int32_t *projector_gemm,
                         int32_t *density_group_bands, int32_t *projector_chunks,
                         int32_t *fft_planes);
 
+/* Host-side launch plan, without a system or a device: the launch
+ * parameters lz_init derives with its heuristic (before any autotuning) for
+ * a cubic grid of n points per side (n a product of 2, 3 and 5 in [2, 128],
+ * n^2 <= 9216), nbnd bands at each of nks k-points, npwx plane waves per
+ * padded row, nproj separable projectors and precision prec; for tests and
+ * tools that check the host helpers over every supported grid.  `slots` is
+ * a number of density-pass blocks resident at once (the round rule of the
+ * LDS density pass; 0 skips it).  out (host, LZ_PLAN_LEN int32, caller-owned):
+ *   [0] compile-time FFT length (0: runtime radix plans)
+ *   [1] plane length of the register-line / lane-pair kernels (0: LDS passes)
+ *   [2] density band-group size of the default schedule: the register-form
+ *       heuristic where [1] > 0, else [3]
+ *   [3] density band-group size of the LDS passes: the round rule for
+ *       `slots` when slots > 0, else the heuristic lz_init falls back to
+ *   [4] the round rule's size for `slots` (0 if slots = 0)
+ *   [5..8]  vector-ALU projector path: dot chunk (plane waves), chunks,
+ *           blocks of the output update, the same over the projector rows
+ *   [9..12] the same for the matrix-core path (split-bf16 products for
+ *           LZ_FP32_SPLITBF16)
+ *   [13] band-group size after clamping to 1..nks*nbnd, [14] groups.
+ * LZ_ERR_ARG for sizes lz_init would refuse or a NULL out; no device call. */
+#define LZ_PLAN_LEN 15
+lz_status lz_launch_plan(int32_t n, int32_t prec, int32_t nbnd, int32_t nks, int32_t npwx,
+                         int32_t nproj, int32_t slots, int32_t *out);
+
 /* Copy the right-hand side y of instance inst to a device array in the
  * caller's layout and precision (as lz_apply_liouvillian). */
 lz_status lz_get_rhs(lz_ctx *ctx, int32_t inst, void *y_out);

@@ -112,6 +112,7 @@ def load(path: str = LIB_PATH):
     lib.lz_stage_timer.argtypes = [vp, ctypes.c_int32]
     lib.lz_stage_times.argtypes = [vp, ctypes.c_int32, _dp, _ip]
     lib.lz_free.argtypes = [vp]
+    lib.lz_launch_plan.argtypes = [ctypes.c_int32] * 7 + [_ip]
     lib.lz_last_error.restype = ctypes.c_char_p
     for f in ("lz_init", "lz_apply_liouvillian", "lz_step", "lz_get_coefficients", "lz_get_gamma",
               "lz_get_tuning", "lz_ground_state", "lz_ground_density",
@@ -264,6 +265,24 @@ def lz_ground_density(system, xc="pz", device=0, stream=None):
     _check(lib.lz_ground_density(ctypes.byref(arr), XC[xc] if isinstance(xc, str) else int(xc),
                                  int(device), hs, _ptr(n0, _dp), _ptr(fxc, _dp)))
     return n0, fxc
+
+
+LZ_PLAN_LEN = 15
+PLAN_FIELDS = ("ct_size", "reg_plane", "group_reg", "group_lds", "group_round",
+               "valu_chunk", "valu_nchunk", "valu_upd_blocks", "valu_upd_blocks_proj",
+               "mfma_chunk", "mfma_nchunk", "mfma_upd_blocks", "mfma_upd_blocks_proj",
+               "gsize", "ngroups")
+
+
+def lz_launch_plan(n, prec, nbnd, nks, npwx, nproj, slots=0):
+    """Host-side launch plan of a cubic grid (lz_launch_plan; no device):
+    a dict of the LZ_PLAN_LEN fields named in PLAN_FIELDS."""
+    lib = load()
+    out = np.zeros(LZ_PLAN_LEN, dtype=np.int32)
+    _check(lib.lz_launch_plan(int(n), PREC[prec] if isinstance(prec, str) else int(prec),
+                              int(nbnd), int(nks), int(npwx), int(nproj), int(slots),
+                              _ptr(out, _ip)))
+    return dict(zip(PLAN_FIELDS, (int(v) for v in out)))
 
 
 class Context:

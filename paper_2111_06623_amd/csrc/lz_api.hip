@@ -1614,6 +1614,56 @@ lz_status lz_get_tuning(lz_ctx* c, int32_t inst, int32_t* projector_gemm,
   });
 }
 
+lz_status lz_launch_plan(int32_t n, int32_t prec, int32_t nbnd, int32_t nks, int32_t npwx,
+                         int32_t nproj, int32_t slots, int32_t* out) {
+  return guarded([&] {
+    if (!out) fail(LZ_ERR_ARG, "out is NULL");
+    if (!valid_len(n)) fail(LZ_ERR_ARG, "n must factor into 2,3,5 and lie in [2,128]");
+    if (n * n > 36 * 256) fail(LZ_ERR_ARG, "N1*N2 exceeds 9216");
+    if (prec != LZ_FP64 && prec != LZ_FP32 && prec != LZ_FP32_SPLITBF16)
+      fail(LZ_ERR_ARG, "unknown precision");
+    if (nks < 1 || nbnd < 1 || nproj < 0 || npwx < 1)
+      fail(LZ_ERR_ARG, "nks, nbnd, npwx must be >= 1 and nproj >= 0");
+    if ((int64_t)nks * nbnd > (1 << 24) || (int64_t)nbnd + nproj > (1 << 24))
+      fail(LZ_ERR_ARG, "band or projector counts too large");
+    if (slots < 0) fail(LZ_ERR_ARG, "slots must be >= 0");
+    // the fields of an instance the host-side helpers read; nothing else is set
+    Instance I;
+    I.prec = (lz_precision)prec;
+    I.fp64 = prec == LZ_FP64;
+    I.n1 = I.n2 = I.n3 = n;
+    I.N = n * n * n;
+    I.nks = nks;
+    I.nbnd = nbnd;
+    I.nproj = nproj;
+    I.npwx = npwx;
+    I.nb = nks * nbnd;
+    I.ptot = nbnd + nproj;
+    const int ct = ct_supported(n) ? n : 0;
+    const int rn = ct ? (I.fp64 ? reg_plane_len<double>(ct) : reg_plane_len<float>(ct)) : 0;
+    // as launch_candidates: the LDS form by the round rule where the slots
+    // are known, the register form's own heuristic where it exists
+    const int g_lds = slots > 0 ? round_group(I, slots) : heuristic_group(I, 0);
+    out[0] = ct;
+    out[1] = rn;
+    out[2] = rn ? heuristic_group(I, rn) : g_lds;
+    out[3] = g_lds;
+    out[4] = slots > 0 ? round_group(I, slots) : 0;
+    const LaunchCfg v = make_cfg(I, kGemmValu, out[2]);
+    const LaunchCfg m = make_cfg(I, prec == LZ_FP32_SPLITBF16 ? kGemmBf16x3 : kGemmMfma, out[2]);
+    out[5] = v.chunk;
+    out[6] = v.nchunk;
+    out[7] = v.nlzblk;
+    out[8] = v.nlzblk_nl;
+    out[9] = m.chunk;
+    out[10] = m.nchunk;
+    out[11] = m.nlzblk;
+    out[12] = m.nlzblk_nl;
+    out[13] = v.gsize;
+    out[14] = v.ngroups;
+  });
+}
+
 lz_status lz_get_gamma(lz_ctx* c, int32_t inst, int32_t first, int32_t count, double* gamma) {
   return guarded([&] {
     if (!c || inst < 0 || inst >= (int)c->inst.size()) fail(LZ_ERR_ARG, "bad context or instance");

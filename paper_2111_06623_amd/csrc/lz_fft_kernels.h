@@ -1016,11 +1016,11 @@ static inline int ct_size(const Grid3& g) {
   return (g.n1 == g.n2 && g.n2 == g.n3 && ct_supported(g.n1)) ? g.n1 : 0;
 }
 
-// size N of the register-line plane kernels for this grid (0 = not used)
+// plane length n of a register-line or lane-pair kernel in precision T
+// (0 = none: the LDS passes serve such planes)
 template <typename T>
-int reg_plane_size(const Grid3& g) {
-  if (!g.soff_f || g.lds_planes) return 0;
-  switch (ct_size(g)) {
+int reg_plane_len(int n) {
+  switch (n) {
     case 24: return reg_plane_ok<T, 24>() ? 24 : 0;
     case 32: return reg_plane_ok<T, 32>() ? 32 : 0;
     case 48: return reg_plane_ok<T, 48>() ? 48 : 0;
@@ -1029,6 +1029,15 @@ int reg_plane_size(const Grid3& g) {
     case 96: return reg_pair_ok<T>() ? 96 : 0;
     default: return 0;
   }
+}
+template int reg_plane_len<double>(int);
+template int reg_plane_len<float>(int);
+
+// size N of the register-line plane kernels for this grid (0 = not used)
+template <typename T>
+int reg_plane_size(const Grid3& g) {
+  if (!g.soff_f || g.lds_planes) return 0;
+  return reg_plane_len<T>(ct_size(g));
 }
 template int reg_plane_size<double>(const Grid3&);
 template int reg_plane_size<float>(const Grid3&);

@@ -118,6 +118,7 @@ template <typename T> struct LaunchLin {
 template <typename T> hipError_t enable_large_lds_fft();
 // grid size N served by the register-line plane kernels (0: the LDS-pass kernels)
 template <typename T> int reg_plane_size(const Grid3& g);
+template <typename T> int reg_plane_len(int n);
 
 void launch_lz_finalize(const double* partial, int nblk, LzDevState* st, double* beta, double* z,
                         int max_steps, double tol, double yscale, hipStream_t s);

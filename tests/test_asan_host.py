@@ -5,7 +5,8 @@
 compiled with -fsanitize=address; device code is not instrumented.  A child
 process with the sanitizer runtime preloaded drives every entry point down
 the paths that run before any device work: malformed options and systems,
-null arguments, bad checkpoint buffers.  Any heap or stack overflow, use
+null arguments, bad checkpoint buffers, and the host-only launch plan over
+grids and sizes from the smallest to the large cell's.  Any heap or stack overflow, use
 after free or similar error aborts the child with the sanitizer's report.
 """
 import glob
@@ -67,6 +68,12 @@ CHILD = textwrap.dedent(r"""
     expect(lib.lz_checkpoint_load(None, 0, junk, ctypes.c_uint64(4096)))
     expect(lib.lz_checkpoint_size(None, 0, ctypes.byref(n)))
     expect(lib.lz_step(None, 1, None))
+    plan = (ctypes.c_int32 * 15)()
+    for n in (2, 12, 24, 40, 48, 72, 96):
+        for prec in (0, 1, 2):
+            for sizes in ((1, 1, 1, 0, 0), (16, 8, 6500, 32, 768), (128, 4, 51443, 256, 256)):
+                assert lib.lz_launch_plan(n, prec, *sizes, plan) == lz.LZ_OK, lib.lz_last_error()
+    expect(lib.lz_launch_plan(97, 0, 4, 1, 100, 0, 0, plan))
     assert lib.lz_free(None) == lz.LZ_OK
     print("asan-host-ok", flush=True)
 """)
