@@ -38,6 +38,7 @@ OMEGA = (0.0, 2.0, 2000)
 ETA = 0.01
 GATE = 1e-4
 WINDOWS = 5
+RAW_APPLIES = 200   # raw lz_apply_liouvillian calls timed per precision
 REFERENCE = os.path.join(ROOT, "tests", "golden", "cfg2_oracle_reference.npz")
 # recursion length of each precision's configuration (the gate is taken there)
 CONFIG_STEPS = {"fp64": 1000, "fp32": 3000, "splitbf16": 3000}
@@ -140,6 +141,20 @@ def run_gpu(s, prec, applies, warmup, M, graph, autotune=True):
     dms, dcnt = ctx.stage_times()
     ctx.stage_timer(False)
     di = lz.STAGES.index(dom)
+    # raw operator applications (lz_apply_liouvillian, a D and a D+K half on
+    # device vectors), outside the recursion
+    x = torch.randn(sum(ctx.nvec), dtype=torch.complex128 if prec == "fp64" else torch.complex64,
+                    device="cuda")
+    qo, po = torch.empty_like(x), torch.empty_like(x)
+    for _ in range(5):
+        ctx.apply_liouvillian(x, x, qo, po)
+    torch.cuda.synchronize()
+    ta = time.perf_counter()
+    for _ in range(RAW_APPLIES):
+        ctx.apply_liouvillian(x, x, qo, po)
+    torch.cuda.synchronize()
+    raw_rate = RAW_APPLIES / (time.perf_counter() - ta)
+    del x, qo, po
     ctx.reset()
     ctx.step(M)
     ts = time.perf_counter()
@@ -151,7 +166,7 @@ def run_gpu(s, prec, applies, warmup, M, graph, autotune=True):
     return dict(window_s=windows, median_s=med, applies=per_window // 2,
                 rate=(per_window / 2) / med, t_spec=t_spec, stage_ms=ms, tuning=tuning,
                 stage_cnt=cnt, dom=dom, dom_ms=dms[di] / max(dcnt[di], 1),
-                dom_launches=int(dcnt[di]))
+                dom_launches=int(dcnt[di]), raw_rate=raw_rate)
 
 
 def error_profile(s, prec, ref, lengths, perturb=0.0):
@@ -721,7 +736,8 @@ def main():
                    "spectrum": "2000 frequencies in [0, 2] Ha, eta 0.01 Ha"},
         "roofline": roof,
         "rates": {p: {"applies_per_s": round(res[p]["rate"], 2),
-                      "window_ms": [round(w * 1e3, 2) for w in res[p]["window_s"]]} for p in res},
+                      "window_ms": [round(w * 1e3, 2) for w in res[p]["window_s"]],
+                      "raw_apply_liouvillian_per_s": round(res[p]["raw_rate"], 2)} for p in res},
         "gates": gates,
         "stage_ms_per_launch": {k: round(v, 5) for k, v in per_launch.items()},
         "stage_frac_of_hbm_peak_model_bytes": frac_model,
