@@ -519,7 +519,7 @@ def stage_bytes(s, prec, ngroups):
     bands, S sticks, N3 points per stick, N grid points, npw the summed
     sphere sizes over bands and k-points.
 
-    model: the survey's algorithmic count, a stick-pruned two-pass transform
+    model: the algorithmic count of a stick-pruned two-pass transform
     with the valence orbitals held as z-transformed sticks: every stick
     volume (nb N3 S c) moved once per pass -- D: inverse z 1, plane pass 2,
     forward z 1; D+K: inverse z 1, density pass 3 (x, u, V x), v'u pass 3
@@ -616,7 +616,7 @@ def cpu_baseline(s, budget_s):
 def main():
     a = _args()
     if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}), flush=True)
+        print(json.dumps({"error": "the benchmark runs on one GPU only; --gpus must be 1"}), flush=True)
         sys.exit(2)
     if a.copy_probe_mib:
         copy_probe(a.copy_probe_mib, 8)
@@ -715,7 +715,7 @@ def main():
         traffic = measured_traffic(dom, a.config, head)
         roof = {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1), "peak": 8000.0,
                 "unit": "GB/s", "frac": round(ach / 8000.0, 4), "traffic": traffic,
-                "bytes_per_launch": model[dom], "bytes_model": "survey (sticks)",
+                "bytes_per_launch": model[dom], "bytes_model": "orbitals as z-transformed sticks",
                 "impl_bytes_per_launch": impl[dom],
                 "impl_over_model": round(impl[dom] / model[dom], 3),
                 "traffic_over_model": round(traffic / model[dom], 3) if traffic else None,

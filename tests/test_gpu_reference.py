@@ -5,7 +5,7 @@ function at the workload's 1000 steps within 1e-6 (relative, floored at 1e-6
 of the maximum), the mixed path (FP32 bulk, FP64 scalars) within 1e-4 at 300
 steps; the errors at longer recursions are printed (without
 reorthogonalisation both paths drift from the oracle once Ritz values
-converge; the design doc records the figures)."""
+converge)."""
 import os
 
 import numpy as np
