@@ -467,12 +467,13 @@ __device__ __forceinline__ void plane_local_density_block(const cplx<T>* __restr
   constexpr int NIT = N > 0 ? (N * N + NTB - 1) / NTB : MP;
   constexpr int ACC = GACC ? 1 : NIT;
   constexpr int UNR = GACC ? 4 : NIT;
-  // FP64 48^2 planes load the first NPRE of a thread's orbital values of a
-  // band before the band's transforms, which hide their latency: 6 of 9
-  // fill the registers of three waves per SIMD (168), all 9 would take 186
-  // and leave two
-  constexpr bool PRE = !GACC && N == 48 && sizeof(T) == 8;
-  constexpr int NPRE = PRE ? 6 : 0;
+  // FP64 planes of 48^2 and 96^2 load the first NPRE of a thread's orbital
+  // values of a band before the band's transforms, which hide their
+  // latency: on 48^2 planes 6 of 9 fill the registers of three waves per
+  // SIMD (168; all 9 would take 186 and leave two), on 96^2 planes (1024
+  // threads, at most 128 registers) 3 of 9 fit (124)
+  constexpr bool PRE = sizeof(T) == 8 && (N == 48 || N == 96);
+  constexpr int NPRE = !PRE ? 0 : N == 48 ? 6 : 3;
   const int z = vb.x, g = vb.y;
   const int np = n1 * n2;
   const T* vz = vloc + (int64_t)z * np;
@@ -491,7 +492,7 @@ __device__ __forceinline__ void plane_local_density_block(const cplx<T>* __restr
     asm volatile("" : "+v"(tid));
     const int64_t so = ((int64_t)b * n3 + z) * a.S;
     const cplx<T>* ub = ur + ((int64_t)b * n3 + z) * np;
-    cplx<T> upre[PRE ? NPRE : 1];
+    cplx<T> upre[NPRE > 0 ? NPRE : 1];
     if constexpr (PRE) {
 #pragma unroll
       for (int i = 0; i < NPRE; ++i) {
@@ -503,28 +504,30 @@ __device__ __forceinline__ void plane_local_density_block(const cplx<T>* __restr
     plane_rows<T, N, MP, +1>(sh, a, a.nact, true, tw2, tid);
     plane_cols<T, N, MP, +1>(sh, a, tw1, tid);
     const T wb = T(bandw[b]);
-#pragma unroll UNR
-    for (int i = 0; i < NIT; ++i) {
+    // point i of the thread: the density product with the orbital value u,
+    // then the potential
+    auto point = [&](int i, const cplx<T>& u) {
       const int p = tid + i * NTB;
-      if (p < np) {
-        const int i1 = p / n2, i2 = p - i1 * n2;
-        cplx<T>& c = sh.plane[i1 * pitch + i2];
-        cplx<T> u;
-        if (PRE && i < NPRE) u = upre[PRE ? i : 0];
-        else u = ub[p];
-        const cplx<T> d = cmulc<T>(u, c);
-        if constexpr (GACC) {
-          cplx<T> s = b == b0 ? czero<T>() : dp[p];
-          s.x += wb * d.x;
-          s.y += wb * d.y;
-          dp[p] = s;
-        } else {
-          acc[i].x += wb * d.x;
-          acc[i].y += wb * d.y;
-        }
-        c = cscale<T>(c, vz[p]);
+      const int i1 = p / n2, i2 = p - i1 * n2;
+      cplx<T>& c = sh.plane[i1 * pitch + i2];
+      const cplx<T> d = cmulc<T>(u, c);
+      if constexpr (GACC) {
+        cplx<T> s = b == b0 ? czero<T>() : dp[p];
+        s.x += wb * d.x;
+        s.y += wb * d.y;
+        dp[p] = s;
+      } else {
+        acc[i].x += wb * d.x;
+        acc[i].y += wb * d.y;
       }
-    }
+      c = cscale<T>(c, vz[p]);
+    };
+#pragma unroll
+    for (int i = 0; i < NPRE; ++i)
+      if (tid + i * NTB < np) point(i, upre[i]);
+#pragma unroll UNR
+    for (int i = NPRE; i < NIT; ++i)
+      if (tid + i * NTB < np) point(i, ub[tid + i * NTB]);
     __syncthreads();
     plane_cols<T, N, MP, -1>(sh, a, tw1, tid);
     plane_rows<T, N, MP, -1>(sh, a, a.nact, true, tw2, tid);
