@@ -188,8 +188,14 @@ __device__ __forceinline__ void ct_pass(cplx<T>* lds, const L& lay, int nbatch,
   for (int i = 0; i < MAXB; ++i) {
     const int t = tid + i * NT;
     if (t < total) {
-      const int b = t / M;
-      const int j = t - b * M;
+      // butterfly j of line b, lines fastest: the lanes of a wave take the
+      // same butterfly of consecutive lines, whose elements lie a line
+      // pitch apart (odd in complex elements), so their loads and stores
+      // fall in distinct LDS banks; with the butterflies of one line on
+      // neighbouring lanes, the first pass's stores (outputs j*R + s) put
+      // the lanes of a line 16 elements apart, on the same banks
+      const int j = t / nbatch;
+      const int b = t - j * nbatch;
       const int k = j % NS;
       const int base = lay.base(b);
       bbase[i] = base;

@@ -469,11 +469,11 @@ __device__ __forceinline__ void plane_local_density_block(const cplx<T>* __restr
   constexpr int UNR = GACC ? 4 : NIT;
   // FP64 planes of 48^2 and 96^2 load the first NPRE of a thread's orbital
   // values of a band before the band's transforms, which hide their
-  // latency: on 48^2 planes 6 of 9 fill the registers of three waves per
-  // SIMD (168; all 9 would take 186 and leave two), on 96^2 planes (1024
-  // threads, at most 128 registers) 3 of 9 fit (124)
+  // latency: on 48^2 planes 5 of 9 fill the registers of three waves per
+  // SIMD (168; more leave two), on 96^2 planes (1024 threads, at most 128
+  // registers) 3 of 9 fit
   constexpr bool PRE = sizeof(T) == 8 && (N == 48 || N == 96);
-  constexpr int NPRE = !PRE ? 0 : N == 48 ? 6 : 3;
+  constexpr int NPRE = !PRE ? 0 : N == 48 ? 5 : 3;
   const int z = vb.x, g = vb.y;
   const int np = n1 * n2;
   const T* vz = vloc + (int64_t)z * np;
