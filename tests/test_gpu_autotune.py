@@ -71,3 +71,27 @@ def test_asked_for_path_is_kept():
     ctx = lz.lz_init(s, prec="fp32", max_steps=4)
     assert ctx.tuning()[0] == "valu"   # the heuristic for 16 bands
     ctx.free()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_launch_plan_matches_the_context(prec):
+    """lz_launch_plan (the host helpers alone) gives the launch parameters an
+    lz_init without autotuning takes on the benchmark cell: the density
+    band groups (for the LDS form, the round rule at some number of resident
+    blocks per compute unit, which the device decides) and the dot chunks."""
+    lz = _lz()
+    s = config_system("cfg2")
+    ctx = lz.lz_init(s, prec=prec, max_steps=4, autotune=False)
+    gemm, bands, chunks, planes = ctx.tuning()
+    ctx.free()
+    nbnd, nks, npwx, nproj = int(s.nbnd), int(s.nks), int(s.nl_kq.shape[1]), int(s.nproj)
+    n = int(s.nr[0])
+    plan0 = lz.lz_launch_plan(n, prec, nbnd, nks, npwx, nproj, 0)
+    assert chunks == (plan0["valu_nchunk"] if gemm == "valu" else plan0["mfma_nchunk"])
+    if plan0["reg_plane"]:
+        assert planes == "registers" and bands == plan0["gsize"]
+    else:
+        # LDS passes: the round rule at 1 to 8 resident blocks per compute unit
+        options = {lz.lz_launch_plan(n, prec, nbnd, nks, npwx, nproj, 256 * b)["gsize"]
+                   for b in range(1, 9)}
+        assert bands in options, (bands, options)
