@@ -8,6 +8,8 @@
 // barriers) against a radix-4 plan.  The host builds twiddle tables with the
 // same radix lists (make_plan), so table offsets agree with ct_twoff.
 #pragma once
+#include <type_traits>
+
 #include "lz_device.h"
 
 namespace lz {
@@ -171,9 +173,16 @@ template <int PITCH> struct LayCols {      // every column, stride PITCH
 // elements j + s M it loaded from, which no other butterfly touches: its
 // stores cannot overwrite what another thread has still to load, and the
 // barrier between loads and stores is left out.
-template <typename T, int N, int P, int DIR, int NBMAX, typename L, int NT = 256>
+// Pointwise work folded into the stores of a plan's last pass: no factor.
+struct NoEpilogue {
+  template <typename T>
+  __device__ __forceinline__ T load(int, int) const { return T(1); }
+};
+
+template <typename T, int N, int P, int DIR, int NBMAX, typename L, int NT = 256,
+          typename E = NoEpilogue>
 __device__ __forceinline__ void ct_pass(cplx<T>* lds, const L& lay, int nbatch,
-                                        const cplx<T>* tw, int tid) {
+                                        const cplx<T>* tw, int tid, const E& epi = E{}) {
   constexpr int R = ct_radix(N, P);
   constexpr int NS = ct_ns(N, P);
   constexpr int M = N / R;
@@ -182,7 +191,12 @@ __device__ __forceinline__ void ct_pass(cplx<T>* lds, const L& lay, int nbatch,
   constexpr int MAXB = (NBMAX * M + NT - 1) / NT;
   const cplx<T>* twp = tw + ct_twoff(N, P);
   const int total = nbatch * M;
+  // with an epilogue, the last pass scales output s of butterfly j of line b
+  // (element j + s M of the line) by epi.load(b, j + s M), loaded before the
+  // butterfly's LDS reads so that its latency overlaps them
+  constexpr bool EPI = LAST && !std::is_same<E, NoEpilogue>::value;
   cplx<T> v[MAXB][R];
+  T f[EPI ? MAXB : 1][EPI ? R : 1];
   int bbase[MAXB], bo[MAXB];
 #pragma unroll
   for (int i = 0; i < MAXB; ++i) {
@@ -200,6 +214,10 @@ __device__ __forceinline__ void ct_pass(cplx<T>* lds, const L& lay, int nbatch,
       const int base = lay.base(b);
       bbase[i] = base;
       bo[i] = (j / NS) * NS * R + k;
+      if constexpr (EPI) {
+#pragma unroll
+        for (int s = 0; s < R; ++s) f[i][s] = epi.template load<T>(b, j + s * M);
+      }
 #pragma unroll
       for (int r = 0; r < R; ++r) v[i][r] = lds[base + (j + r * M) * L::stride];
       if constexpr (NS > 1) {
@@ -218,6 +236,10 @@ __device__ __forceinline__ void ct_pass(cplx<T>* lds, const L& lay, int nbatch,
   for (int i = 0; i < MAXB; ++i) {
     const int t = tid + i * NT;
     if (t < total) {
+      if constexpr (EPI) {
+#pragma unroll
+        for (int s = 0; s < R; ++s) v[i][s] = cscale<T>(v[i][s], f[i][s]);
+      }
 #pragma unroll
       for (int s = 0; s < R; ++s) lds[bbase[i] + (bo[i] + s * NS) * L::stride] = v[i][s];
     }
@@ -225,13 +247,14 @@ __device__ __forceinline__ void ct_pass(cplx<T>* lds, const L& lay, int nbatch,
   __syncthreads();
 }
 
-template <typename T, int N, int DIR, int NBMAX, typename L, int NT = 256>
+template <typename T, int N, int DIR, int NBMAX, typename L, int NT = 256,
+          typename E = NoEpilogue>
 __device__ __forceinline__ void ct_fft(cplx<T>* lds, const L& lay, int nbatch, const cplx<T>* tw,
-                                       int tid) {
+                                       int tid, const E& epi = E{}) {
   static_assert(ct_supported(N), "no compile-time plan for this length");
-  ct_pass<T, N, 0, DIR, NBMAX, L, NT>(lds, lay, nbatch, tw, tid);
-  if constexpr (ct_npass(N) > 1) ct_pass<T, N, 1, DIR, NBMAX, L, NT>(lds, lay, nbatch, tw, tid);
-  if constexpr (ct_npass(N) > 2) ct_pass<T, N, 2, DIR, NBMAX, L, NT>(lds, lay, nbatch, tw, tid);
+  ct_pass<T, N, 0, DIR, NBMAX, L, NT, E>(lds, lay, nbatch, tw, tid, epi);
+  if constexpr (ct_npass(N) > 1) ct_pass<T, N, 1, DIR, NBMAX, L, NT, E>(lds, lay, nbatch, tw, tid, epi);
+  if constexpr (ct_npass(N) > 2) ct_pass<T, N, 2, DIR, NBMAX, L, NT, E>(lds, lay, nbatch, tw, tid, epi);
 }
 
 }  // namespace lz

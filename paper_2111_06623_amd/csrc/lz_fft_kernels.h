@@ -110,6 +110,16 @@ __device__ __forceinline__ void plane_cols(const PlaneShm<T, N>& sh, const Plane
   }
 }
 
+// the local potential of a z-plane as a last-pass epilogue of the inverse
+// column transforms: element i1 of column i2 is scaled by V(i1, i2)
+template <typename T>
+struct PotentialEpilogue {
+  const T* vz;
+  int n2;
+  template <typename U>
+  __device__ __forceinline__ U load(int col, int row) const { return vz[row * n2 + col]; }
+};
+
 template <typename T, int N>
 __device__ __forceinline__ void plane_zero_scatter(const PlaneShm<T, N>& sh, const PlaneArgs& a,
                                                    const cplx<T>* __restrict__ src, int tid) {
@@ -399,14 +409,21 @@ __device__ __forceinline__ void plane_local_block(const cplx<T>* __restrict__ si
   const int64_t so = ((int64_t)b * n3 + z) * a.S;
   plane_zero_scatter<T, N>(sh, a, sin + so, tid);
   plane_rows<T, N, MP, +1>(sh, a, a.nact, true, tw2, tid);
-  plane_cols<T, N, MP, +1>(sh, a, tw1, tid);
   const T* vz = vloc + (int64_t)z * n1 * n2;
-  for (int p = tid; p < n1 * n2; p += NTB) {
-    const int i1 = p / n2, i2 = p - i1 * n2;
-    cplx<T>& c = sh.plane[i1 * pitch + i2];
-    c = cscale<T>(c, vz[p]);
+  if constexpr (N > 0) {
+    // the potential multiplies the outputs of the last inverse column pass
+    // as they are stored: no separate sweep over the plane
+    ct_fft<T, N, +1, N, LayCols<ct_plane_pitch<N>()>, plane_threads<T, N>()>(
+        sh.plane, LayCols<ct_plane_pitch<N>()>{}, N, sh.tw, tid, PotentialEpilogue<T>{vz, N});
+  } else {
+    plane_cols<T, N, MP, +1>(sh, a, tw1, tid);
+    for (int p = tid; p < n1 * n2; p += NTB) {
+      const int i1 = p / n2, i2 = p - i1 * n2;
+      cplx<T>& c = sh.plane[i1 * pitch + i2];
+      c = cscale<T>(c, vz[p]);
+    }
+    __syncthreads();
   }
-  __syncthreads();
   plane_cols<T, N, MP, -1>(sh, a, tw1, tid);
   plane_rows<T, N, MP, -1>(sh, a, a.nact, true, tw2, tid);
   for (int s = tid; s < a.S; s += NTB) sout[so + s] = sh.plane[a.si1[s] * pitch + a.si2[s]];
